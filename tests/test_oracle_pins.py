@@ -1,0 +1,318 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (no GPU).
+
+Each test names what it pins.  None of them re-types an oracle formula: they compare the oracle with
+textbook results (dense inverses, closed-form spectra, convergence orders, exact Fourier identities) or
+compare two independent computations (explicit time marching vs the algebraic transfer matrix).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import dense, gradient, iteration, operators, stepping
+
+# A small, stable GL problem on [-15, 15] (32 nodes) shared by several pins.
+N_T, XL_T, XR_T = 32, -15.0, 15.0
+MU0_T, MU2_T = 0.20, -0.01
+H_T, P_T = 0.05, 400
+
+
+def tiny_gl(mu0=MU0_T, mu2=MU2_T, n=N_T):
+    L, x = operators.gl_operator(n, mu0, mu2, xl=XL_T, xr=XR_T)
+    return L, x
+
+
+def forcing(seed, nw, k, n):
+    g = np.random.default_rng(seed)
+    return g.standard_normal((nw, k, n)) + 1j * g.standard_normal((nw, k, n))
+
+
+def test_tiny_gl_is_stable():
+    L, _ = tiny_gl()
+    assert np.linalg.eigvals(L.toarray()).real.max() < -0.05
+
+
+# ---------------------------------------------------------------------------------------------
+# Operators: each PDE term against its analytic action on a smooth function (pins signs and indices).
+# ---------------------------------------------------------------------------------------------
+def test_gl_operator_matches_pde_on_smooth_function():
+    # g vanishes at both ends; L g must approach -nu g' + gamma g'' + mu g at second order in dx.
+    errs = []
+    for n in (200, 400):
+        L, x = operators.gl_operator(n, 0.3, -0.01)
+        a = np.pi / 100.0
+        g = np.sin(a * (x + 50.0)) ** 2
+        gp = 2 * a * np.sin(a * (x + 50.0)) * np.cos(a * (x + 50.0))
+        gpp = 2 * a * a * np.cos(2 * a * (x + 50.0))
+        mu = (0.3 - 0.04) - 0.005 * x * x
+        exact = -(2 + 0.4j) * gp + (1 - 1j) * gpp + mu * g
+        errs.append(np.abs(L @ g - exact).max())
+    assert errs[0] < 1e-3 and 3.5 < errs[0] / errs[1] < 4.5  # second-order
+
+
+def test_gl_constant_mu_spectrum_is_tridiagonal_toeplitz():
+    # Dirichlet tridiagonal Toeplitz (sub a, diag b, super c): lambda_m = b + 2 sqrt(a c) cos(m pi/(n+1)).
+    n = 60
+    L, x = operators.gl_operator(n, 0.1, 0.0)
+    dx = x[1] - x[0]
+    nu, gam = 2 + 0.4j, 1 - 1j
+    a = nu / (2 * dx) + gam / dx ** 2
+    c = -nu / (2 * dx) + gam / dx ** 2
+    b = -2 * gam / dx ** 2 + (0.1 - 0.04)
+    m = np.arange(1, n + 1)
+    ref = b + 2 * np.sqrt(a * c) * np.cos(m * np.pi / (n + 1))
+    got = np.linalg.eigvals(L.toarray())
+    assert np.abs(np.sort_complex(got) - np.sort_complex(ref)).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_adr2d_operator_matches_pde_on_smooth_function():
+    errs = []
+    for (nx, ny) in ((64, 32), (128, 64)):
+        mu = None
+        L, f = operators.adr2d_operator(nx, ny, Re=200.0, mu=mu)
+        X, Y = f["X"], f["Y"]
+        ax, ay = np.pi / 40.0, np.pi / 20.0
+        g = np.sin(ax * X) ** 2 * np.sin(ay * (Y + 10)) ** 2
+        gx = 2 * ax * np.sin(ax * X) * np.cos(ax * X) * np.sin(ay * (Y + 10)) ** 2
+        gxx = 2 * ax * ax * np.cos(2 * ax * X) * np.sin(ay * (Y + 10)) ** 2
+        gyy = 2 * ay * ay * np.cos(2 * ay * (Y + 10)) * np.sin(ax * X) ** 2
+        exact = -np.tanh(Y) * gx + (gxx + gyy) / 200.0 + (f["mu"] - f["sponge"]) * g
+        errs.append(np.abs((L @ g.ravel()).reshape(ny, nx) - exact).max())
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+def test_adr3d3c_operator_matches_pde_on_smooth_function():
+    wake = dict(amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+    errs = []
+    for n in ((24, 16, 16), (48, 32, 32)):
+        nx, ny, nz = n
+        L, f = operators.adr3d3c_operator(nx, ny, nz, wake, Re=200.0)
+        X, Y, Z = f["X"], f["Y"], f["Z"]
+        a, b = np.pi / 40.0, np.pi / 20.0
+        sx, sy, sz = np.sin(a * X) ** 2, np.sin(b * (Y + 10)) ** 2, np.sin(b * (Z + 10)) ** 2
+        g = sx * sy * sz
+        gx = 2 * a * np.sin(a * X) * np.cos(a * X) * sy * sz
+        lap = (2 * a * a * np.cos(2 * a * X) * sy * sz + 2 * b * b * np.cos(2 * b * (Y + 10)) * sx * sz
+               + 2 * b * b * np.cos(2 * b * (Z + 10)) * sx * sy)
+        Ug = 1 - 0.5 * np.exp(-((Y - 0.2) ** 2 + (Z + 0.3) ** 2) / 4.0)
+        Uy = 0.5 * np.exp(-((Y - 0.2) ** 2 + (Z + 0.3) ** 2) / 4.0) * 2 * (Y - 0.2) / 4.0
+        Uz = 0.5 * np.exp(-((Y - 0.2) ** 2 + (Z + 0.3) ** 2) / 4.0) * 2 * (Z + 0.3) / 4.0
+        scal = -Ug * gx + lap / 200.0 + (-0.05 - f["sponge"]) * g
+        # components (u, v, w) = (g, 2g, 3g)
+        q = np.concatenate([g.ravel(), 2 * g.ravel(), 3 * g.ravel()])
+        out = (L @ q).reshape(3, nz, ny, nx)
+        ex = np.stack([scal - 2 * g * Uy - 3 * g * Uz, 2 * scal, 3 * scal])
+        errs.append(np.abs(out - ex).max())
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+# ---------------------------------------------------------------------------------------------
+# Dense ground truth against closed forms.
+# ---------------------------------------------------------------------------------------------
+def test_diagonal_operator_gains_closed_form():
+    mu = np.array([-0.3, -1.0, -0.05 + 0.2j, -2.0])
+    w = 0.7
+    s, U, V = dense.gains_and_modes(dense.resolvent(np.diag(mu), w))
+    assert np.allclose(s, np.sort(1 / np.abs(1j * w - mu))[::-1], rtol=1e-13)
+
+
+def test_circulant_operator_gains_closed_form_and_iteration():
+    # Periodic constant-coefficient stencil: normal operator, Fourier eigenvectors,
+    # lambda_m = b + a e^{-i theta_m} + c e^{+i theta_m}; gains = 1/|i w - lambda_m|.
+    n = 40
+    a, b, c = 0.9 + 0.3j, -2.5 + 0.1j, 1.1 - 0.3j
+    L = (np.diag(np.full(n, b)) + np.diag(np.full(n - 1, a), -1) + np.diag(np.full(n - 1, c), 1)).astype(complex)
+    L[0, -1] = a
+    L[-1, 0] = c
+    th = 2 * np.pi * np.arange(n) / n
+    lam = b + a * np.exp(-1j * th) + c * np.exp(1j * th)
+    w = 0.4
+    ref = np.sort(1 / np.abs(1j * w - lam))[::-1]
+    s, _, _ = dense.gains_and_modes(dense.resolvent(L, w))
+    assert np.allclose(s, ref, rtol=1e-12)
+    # the block power iteration on the continuous resolvent recovers the top 3
+    R = dense.resolvent(L, w)
+    ap = lambda F: np.stack([(R @ F[0].T).T])
+    ad = lambda G: np.stack([(R.conj().T @ G[0].T).T])
+    g, V, U, _ = iteration.block_power_iteration(ap, ad, forcing(3, 1, 3, n), 200)
+    assert np.allclose(g[0], ref[:3], rtol=1e-10)
+
+
+def test_rk4_transfer_converges_at_fourth_order():
+    # R_d(w) -> (i w I - L)^{-1} as h^4: the gain error drops by ~16 per halving of h.
+    L, _ = tiny_gl()
+    w = -0.3
+    s0 = dense.gains_and_modes(dense.resolvent(L, w), 1)[0][0]
+    errs = [abs(dense.gains_and_modes(dense.resolvent_rk4(L, w, h), 1)[0][0] / s0 - 1)
+            for h in (0.1, 0.05, 0.025)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 14.5 < r1 < 17.5 and 14.5 < r2 < 17.5
+
+
+def test_rk4_amplification_is_taylor_of_exponential():
+    # P(z) agrees with e^z to fourth order: |P(z) - e^z| ~ |z|^5/120.
+    for z in (0.01 + 0.02j, -0.02 + 0.01j):
+        p = dense.rk4_amplification(np.array([[z]]))[0, 0]
+        assert abs(p - np.exp(z)) < 2 * abs(z) ** 5 / 120
+
+
+# ---------------------------------------------------------------------------------------------
+# Time stepping: explicit runs against the algebraic transfer matrix and the continuous resolvent.
+# ---------------------------------------------------------------------------------------------
+def _grid3():
+    dw = 2 * np.pi / (P_T * H_T)
+    return -0.3, dw, stepping.frequencies(-0.3, dw, 3)
+
+
+def test_periodic_run_equals_rk4_transfer_matrix():
+    L, _ = tiny_gl()
+    w0, dw, om = _grid3()
+    F = forcing(1, 3, 2, N_T)
+    Ustep = stepping.run(L, H_T, w0, dw, F, "periodic", periods=14)
+    for j, w in enumerate(om):
+        ref = (dense.resolvent_rk4(L, w, H_T) @ F[j].T).T
+        assert np.linalg.norm(Ustep[j] - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_transient_run_equals_rk4_transfer_matrix():
+    L, _ = tiny_gl()
+    w0, dw, om = _grid3()
+    F = forcing(2, 3, 1, N_T)
+    U, uend = stepping.transient_run(L, H_T, om, F, P_T, 13 * P_T)
+    assert np.linalg.norm(uend) < 1e-13 * np.linalg.norm(F)
+    for j, w in enumerate(om):
+        ref = (dense.resolvent_rk4(L, w, H_T) @ F[j].T).T
+        assert np.linalg.norm(U[j] - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_stepped_response_converges_to_continuous_resolvent_at_fourth_order():
+    # Independent of the algebraic transfer matrix: marched response vs (i w I - L)^{-1} F.
+    L, _ = tiny_gl()
+    F = forcing(4, 1, 1, N_T)
+    errs = []
+    for h, P in ((0.1, 100), (0.05, 200)):
+        dw = 2 * np.pi / (P * h)
+        U = stepping.run(L, h, -0.4, dw, F, "periodic", periods=20)
+        ref = np.linalg.solve(1j * (-0.4) * np.eye(N_T) - L.toarray(), F[0, 0])
+        errs.append(np.linalg.norm(U[0, 0] - ref) / np.linalg.norm(ref))
+    assert errs[0] < 1e-5 and 13 < errs[0] / errs[1] < 19
+
+
+def test_adjoint_run_is_hermitian_transpose():
+    # Sec. 2.1 adjoint relations: the adjoint run realises R_d^H and <R f, g> = <f, R^H g>.
+    L, _ = tiny_gl()
+    w0, dw, om = _grid3()
+    F = forcing(5, 3, 1, N_T)
+    G = forcing(6, 3, 1, N_T)
+    RF = stepping.run(L, H_T, w0, dw, F, "periodic", periods=14)
+    RHG = stepping.run(L, H_T, w0, dw, G, "periodic", periods=14, adjoint=True)
+    for j, w in enumerate(om):
+        Rd = dense.resolvent_rk4(L, w, H_T)
+        assert np.linalg.norm(RHG[j, 0] - Rd.conj().T @ G[j, 0]) / np.linalg.norm(RHG[j, 0]) < 1e-12
+        lhs = np.vdot(G[j, 0], RF[j, 0])
+        rhs = np.vdot(RHG[j, 0], F[j, 0])
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_subsampled_projection_is_exact_for_steady_state():
+    L, _ = tiny_gl()
+    w0, dw, om = _grid3()
+    F = forcing(7, 3, 1, N_T)
+    full = stepping.run(L, H_T, w0, dw, F, "periodic", periods=14, stride=1)
+    sub = stepping.run(L, H_T, w0, dw, F, "periodic", periods=14, stride=100)  # 4 samples >= 3 freqs
+    assert np.linalg.norm(full - sub) / np.linalg.norm(full) < 1e-12
+
+
+def test_grid_snapping_and_commensurability():
+    w0, dw, P = stepping.snap_grid(-3.0, 3.0, 256, 0.001, stride=256)
+    assert P % 256 == 0 and abs(dw * P * 0.001 - 2 * np.pi) < 1e-12
+    assert abs(w0 + 255 * dw - 3.0) < 2e-3
+    with pytest.raises(ValueError):
+        stepping.period_steps(0.0123456, 0.001)
+
+
+def test_real_operator_gains_symmetric_in_frequency():
+    # Real L: R(-w) = conj(R(w)), so the gains at +-w coincide; the stepped runs respect it.
+    L = operators.gl_operator(N_T, 0.2, -0.01, nu=1.5, gamma=1.0, xl=XL_T, xr=XR_T)[0]
+    h, P = 0.05, 400
+    dw = 2 * np.pi / (P * h)
+    w = 3 * dw  # +w and -w both on the grid starting at -w
+    apply, adj = iteration.stepped_applies(L, h, -w, dw, "periodic", periods=8, stride=50)
+    F = forcing(8, 7, 2, N_T)
+    g, _, _, _ = iteration.block_power_iteration(apply, adj, F, 16)
+    assert abs(g[0, 0] / g[6, 0] - 1) < 1e-11
+
+
+# ---------------------------------------------------------------------------------------------
+# Block power iteration (Appendix A) against the SVD.
+# ---------------------------------------------------------------------------------------------
+def test_block_iteration_converges_to_svd_of_transfer_matrix():
+    L, _ = tiny_gl()
+    om = np.array([-0.3, 0.0, 0.5])
+    apply, adj = iteration.dense_rk4_applies(L, H_T, om)
+    F0 = forcing(9, 3, 3, N_T)
+    g, V, U, hist = iteration.block_power_iteration(apply, adj, F0, 60)
+    for j, w in enumerate(om):
+        Rd = dense.resolvent_rk4(L, w, H_T)
+        s, Us, Vs = dense.gains_and_modes(Rd, 3)
+        assert np.allclose(g[j], s, rtol=1e-10)
+        for i in range(2):  # modes up to phase
+            assert abs(abs(np.vdot(Vs[:, i], V[j, i])) - 1) < 1e-8
+            assert abs(abs(np.vdot(Us[:, i], U[j, i])) - 1) < 1e-8
+            assert np.linalg.norm(Rd @ V[j, i] - g[j, i] * U[j, i]) < 1e-8 * g[j, i]
+    # both estimators in the history agree with sigma once converged (eq. tildeSig)
+    assert np.allclose(hist[-1, :, 0, 1], g[:, 0], rtol=1e-8)
+
+
+def test_power_iteration_error_decays_at_gain_ratio_rate():
+    # Appendix A: with k = 1 the force-mode error falls like (sigma_2/sigma_1)^{2n}; the Rayleigh-Ritz gain
+    # error, quadratic in the mode error, like (sigma_2/sigma_1)^{4n}.
+    L, _ = tiny_gl()
+    w = 0.3
+    apply, adj = iteration.dense_rk4_applies(L, H_T, np.array([w]))
+    s = dense.gains_and_modes(dense.resolvent_rk4(L, w, H_T), 2)[0]
+    rate = (s[1] / s[0]) ** 4
+    _, _, _, hist = iteration.block_power_iteration(apply, adj, forcing(10, 1, 1, N_T), 8)
+    err = np.abs(hist[:, 0, 0, 0] / s[0] - 1)
+    ratios = err[3:7] / err[2:6]
+    assert np.all(np.abs(ratios / rate - 1) < 0.2)
+
+
+def test_stepped_iteration_matches_dense_iteration():
+    L, _ = tiny_gl()
+    w0, dw, om = _grid3()
+    F0 = forcing(11, 3, 2, N_T)
+    a1, d1 = iteration.stepped_applies(L, H_T, w0, dw, "transient", tail=13 * P_T)
+    a2, d2 = iteration.dense_rk4_applies(L, H_T, om)
+    g1 = iteration.block_power_iteration(a1, d1, F0, 3)[0]
+    g2 = iteration.block_power_iteration(a2, d2, F0, 3)[0]
+    assert np.allclose(g1, g2, rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------------------------
+# Gain sensitivity (gradient) pins.
+# ---------------------------------------------------------------------------------------------
+def test_leading_gain_sensitivity_closed_form_matches_finite_differences():
+    n = 24
+    x, _ = operators.uniform_interior_grid(n, XL_T, XR_T)
+    mu = operators.gl_mu(x, 0.2, -0.01)
+    Lmu = lambda m: operators.gl_operator(n, mu=m, xl=XL_T, xr=XR_T)[0].toarray()
+    w = -0.2
+    sig = lambda m: dense.gains_and_modes(dense.resolvent(Lmu(m), w), 1)[0][0]
+    fd = gradient.central_difference_gradient(sig, mu, 1e-6)
+    cf = gradient.leading_gain_sensitivity(Lmu(mu), w)
+    assert np.linalg.norm(cf - fd) < 1e-7 * np.linalg.norm(fd)
+
+
+def test_discrete_objective_gradient_tends_to_continuous_sensitivity():
+    # With V the leading force mode of R_d, dJ/dmu of the discrete objective approaches the continuous closed
+    # form as h -> 0 (both are sigma_1 sensitivities; they differ by the RK4 error only).
+    n = 24
+    x, _ = operators.uniform_interior_grid(n, XL_T, XR_T)
+    mu = operators.gl_mu(x, 0.2, -0.01)
+    Lmu = lambda m: operators.gl_operator(n, mu=m, xl=XL_T, xr=XR_T)[0].toarray()
+    w, h = -0.2, 0.01
+    V1 = dense.gains_and_modes(dense.resolvent_rk4(Lmu(mu), w, h), 1)[2][:, 0]
+    J = lambda m: gradient.discrete_objective(Lmu, m, h, [w], V1[None, :], np.array([1.0]))
+    fd = gradient.central_difference_gradient(J, mu, 1e-6)
+    cf = gradient.leading_gain_sensitivity(Lmu(mu), w)
+    assert np.linalg.norm(cf - fd) < 1e-5 * np.linalg.norm(cf)
