@@ -1,0 +1,180 @@
+/*
+ * resolvent.h -- C ABI of the MI355X time-stepping resolvent library.
+ *
+ * The library computes the action of the resolvent of a stable linear system du/dt = L u + f on forcings
+ * at many frequencies at once by time marching (Martini, Rodriguez, Towne & Cavalieri, "Efficient
+ * computation of global resolvent modes", Sec. 2), and the optimal and suboptimal gains and modes by a block
+ * power iteration on R^H R (Appendix A).  Conventions:
+ *
+ *   - the paper's system du/dt + A u = B f, y = C u (Sec. 2.1, eq. system) with L = -A and B = C = I;
+ *   - forcing f(t) = sum_j F_j exp(+i w_j t) on the uniform grid w_j = w0 + j dw, j = 0..n_w-1, with
+ *     dw = 2 pi / (P h) for an integer P (Sec. 2.3: w_k = 2 pi k / T, T = P h);  the response amplitudes are
+ *     U_j = R_d(w_j) F_j, where R_d is the resolvent (i w I - L)^{-1} of the RK4-discretised system
+ *     (it converges to the continuous resolvent at fourth order in h);
+ *   - the adjoint (Sec. 2.1, eqs. adsystem and adsystemFreqDomain) is taken in the Euclidean inner product:
+ *     resolvent_adjoint_apply returns R_d(w_j)^H G_j;
+ *   - complex arrays are interleaved (re, im), row-major, [n_w][k][N] with N the number of state unknowns
+ *     (all instances of a batch back to back); complex128 for RES_FP64 operators and complex64 for
+ *     RES_MIXED operators.  Gains are always double.
+ *
+ * All compute calls are asynchronous on the HIP stream passed in (NULL = the default stream); device
+ * arrays are owned by the caller and must stay valid until the stream reaches the call.  Calls that return
+ * host data (resolvent_modes, resolvent_op_create's decay probe, resolvent_op_check) synchronise the stream.
+ * A handle must not be used from two host threads at once, and calls on one handle must not overlap on
+ * different streams (they share the handle's device workspace).
+ */
+#ifndef RESOLVENT_H
+#define RESOLVENT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------------------------- */
+enum {
+  RES_OK = 0,
+  RES_EINVAL = 1,      /* invalid argument (NULL pointer, bad size, unsupported combination)            */
+  RES_EGRID = 2,       /* frequency grid not commensurate with the step: |dw| P h != 2 pi, or n_w > P,   */
+                       /* or the periodic projection stride does not divide P / leaves fewer than n_w    */
+                       /* samples per period                                                             */
+  RES_ESTEP = 3,       /* the decay probe diverged at a rate only an unstable RK4 step explains           */
+  RES_EUNSTABLE = 4,   /* the decay probe did not decay: the operator is not stable (Sec. 2.1 assumes it) */
+  RES_ENONFINITE = 5,  /* a result contained NaN or Inf                                                   */
+  RES_ENOMEM = 6,      /* device allocation failed                                                        */
+  RES_EHIP = 7,        /* HIP runtime error (message in resolvent_last_error)                             */
+  RES_ENOTSUP = 8      /* operation not supported for this operator kind                                  */
+};
+
+/* ---- operator kinds, precisions, methods ---------------------------------------------------------- */
+enum {
+  RES_OP_TRIDIAG = 1,  /* 1-D three-point operator, complex coefficients, instances back to back        */
+  RES_OP_ADR2D = 2,    /* 2-D five-point operator, real coefficients, one complex unknown per node       */
+  RES_OP_ADR3D3C = 3   /* 3-D seven-point operator, real coefficients, three coupled unknowns per node   */
+};
+enum { RES_FP64 = 0, RES_MIXED = 1 };
+/* RES_TRANSIENT: transient-response method with a one-window forcing (Sec. 2.2): force for P steps, march a
+ *   further `tail` steps while the response decays, project every step.
+ * RES_PERIODIC: steady-state-response method (Sec. 2.3): force for `periods` periods, project the last
+ *   period every `stride` steps. */
+enum { RES_TRANSIENT = 0, RES_PERIODIC = 1 };
+
+typedef struct resolvent_op resolvent_op;
+
+/* Operator description.  All arrays are host arrays, read during resolvent_op_create only.
+ *
+ * RES_OP_TRIDIAG:  (L u)_i = lower_i u_{i-1} + diag_i u_i + upper_i u_{i+1}, complex (interleaved re,im),
+ *   length n_total = inst_offsets[ninst].  Instances [inst_offsets[m], inst_offsets[m+1]) are independent:
+ *   lower at an instance's first unknown and upper at its last are ignored (treated as 0: homogeneous
+ *   Dirichlet values outside each instance).  ninst = 1 with inst_offsets = NULL means one instance of
+ *   length nx.
+ * RES_OP_ADR2D / RES_OP_ADR3D3C: grid nx * ny * nz nodes, x fastest (nz = 1 in 2-D), homogeneous Dirichlet
+ *   values outside the grid.  For node (x, y, z) with line index l = z*ny + y and component c:
+ *     (L q)_c = cxm[l] q_c(x-1) + cxp[l] q_c(x+1) + cym[l] q_c(y-1) + cyp[l] q_c(y+1)
+ *             + czm[l] q_c(z-1) + czp[l] q_c(z+1) + dfield[node] q_c + sum_c' coupling[l][c][c'] q_c'
+ *   (czm, czp and coupling are ignored in 2-D; coupling[l] is a row-major 3x3 real matrix whose diagonal
+ *   adds to dfield).  Unknowns are component-major: [c][z][y][x].
+ */
+typedef struct {
+  int32_t kind;              /* RES_OP_*                                                             */
+  int32_t precision;         /* RES_FP64 or RES_MIXED (FP32 stepping and phase GEMMs, FP64 QR/gains)  */
+  double h;                  /* RK4 step                                                              */
+  int32_t ninst;             /* RES_OP_TRIDIAG: number of instances (>= 1)                             */
+  const int64_t* inst_offsets; /* [ninst + 1] or NULL                                                 */
+  const double* lower;       /* RES_OP_TRIDIAG: complex [n_total]                                     */
+  const double* diag;        /* RES_OP_TRIDIAG: complex [n_total]                                     */
+  const double* upper;       /* RES_OP_TRIDIAG: complex [n_total]                                     */
+  int64_t nx, ny, nz;        /* grid sizes (RES_OP_TRIDIAG with inst_offsets == NULL: nx = n_total)    */
+  const double* cxm; const double* cxp;  /* [ny * nz]                                                 */
+  const double* cym; const double* cyp;  /* [ny * nz]                                                 */
+  const double* czm; const double* czp;  /* [ny * nz] (3-D)                                          */
+  const double* dfield;      /* [nz * ny * nx]                                                        */
+  const double* coupling;    /* [ny * nz][3][3] (3-D)                                                 */
+  /* Decay probe (Sec. 2.3: the transient time is estimated from a prior run in which the norm of a random
+   * initial condition falls to a prescribed small value).  probe = 0 skips it. */
+  int32_t probe;
+  double probe_tol;          /* relative norm to reach (e.g. 1e-9)                                     */
+  double probe_tmax;         /* give up (RES_EUNSTABLE) after this much time                           */
+  uint64_t probe_seed;       /* seed of the SplitMix64 stream of the random initial condition          */
+} resolvent_op_desc;
+
+/* Frequency grid w_j = omega0 + j * domega, j = 0 .. n_omega-1; |domega| P h must equal 2 pi for an integer
+ * P (relative tolerance 1e-9) and n_omega <= P, else RES_EGRID. */
+typedef struct {
+  double omega0;
+  double domega;
+  int32_t n_omega;
+} resolvent_grid;
+
+/* Schedule of one run (one application of R_d or R_d^H). */
+typedef struct {
+  int32_t method;            /* RES_TRANSIENT or RES_PERIODIC                                          */
+  int64_t tail;              /* RES_TRANSIENT: steps marched after the forcing window                  */
+  int32_t periods;           /* RES_PERIODIC: periods marched (>= 1); the last one is projected        */
+  int64_t stride;            /* RES_PERIODIC: projection stride (divides P, P/stride >= n_omega)       */
+} resolvent_run;
+
+/* Create / destroy.  Uploads the operator, builds the RK4 step stencils of L and L^H, and runs the decay
+ * probe when asked (synchronising `stream`).  On failure *out is NULL. */
+int resolvent_op_create(const resolvent_op_desc* desc, void* stream, resolvent_op** out);
+void resolvent_op_destroy(resolvent_op* op);
+
+/* Number of unknowns of one column (n_total of the description). */
+int64_t resolvent_op_size(const resolvent_op* op);
+/* Probe result: time (in time units) the random initial condition took to fall below probe_tol, or -1. */
+double resolvent_op_decay_time(const resolvent_op* op);
+
+/* Replace the diagonal (the reaction field): RES_OP_TRIDIAG takes complex [n_total] (the new diag),
+ * ADR kinds take real [nz*ny*nx] (the new dfield).  `on_device` = 1 if the array is device memory.
+ * Stream-ordered; the array must stay valid until the stream reaches the call. */
+int resolvent_op_set_diagonal(resolvent_op* op, const double* values, int32_t on_device, void* stream);
+
+/* u_hat[j] = R_d(w_j) f_hat[j]  for every frequency j and every one of the k columns, in ONE time-marched run
+ * (Sec. 2.1: all frequencies from one direct run).  f_hat, u_hat: device [n_omega][k][N] complex (dtype per
+ * precision, see above); they may not alias. */
+int resolvent_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                    const void* f_hat, void* u_hat, void* stream);
+
+/* z_hat[j] = R_d(w_j)^H g_hat[j]: the adjoint run (Sec. 2.1, eq. adsystemFreqDomain): L^H marched with the
+ * frequencies negated (equivalent to the paper's backward integration in reversed time). */
+int resolvent_adjoint_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                            const void* g_hat, void* z_hat, void* stream);
+
+/* Block power iteration (Appendix A, eqs. iteration, powerMethod, arDec) with per-frequency normalisation and
+ * orthogonalisation of the Fourier coefficients (Sec. 2.3), `iters` iterations of a direct and an adjoint run:
+ *   F = Q(QR(F_hat));  Y = R_d F = Q_Y R_Y;  R_Y = Phi Sigma Psi^H;  gains = Sigma, V = F Psi, U = Q_Y Phi;
+ *   F_hat <- R_d^H Q_Y R_Y Psi.
+ * f0_hat: device [n_omega][k][N] initial forcings (caller-generated, e.g. random).
+ * gains:  host double [ninst][n_omega][k], descending per frequency (the last iteration's estimates).
+ * V, U:   device [n_omega][k][N] force and response modes (each up to a common unit-modulus factor), or NULL.
+ * hist:   host double [iters][ninst][n_omega][k][2] or NULL: per iteration the Rayleigh-Ritz gains and the
+ *         norm-ratio estimate sqrt(||F_hat_i||) of eq. tildeSig.
+ * Synchronises `stream`.  k <= 8. */
+int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                    int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                    void* stream);
+
+/* Gradient of a real objective J(u_hat) of u_hat = resolvent_apply(f_hat) through the time-stepped run
+ * (discrete adjoint of the RK4 march, recomputing the forward trajectory from checkpoints taken every
+ * `checkpoint_every` steps).  g_hat = dJ/du_hat (device, same layout/dtype as u_hat, with the convention
+ * dJ/dRe + i dJ/dIm).  Outputs: f_grad (device, same layout as f_hat, same convention) if not NULL, and
+ * mu_grad (device double, RES_OP_TRIDIAG: [n_total], ADR kinds: [nz*ny*nx]) = dJ/d(real part of the diagonal)
+ * if not NULL.  Supported for RES_TRANSIENT and RES_PERIODIC runs. */
+int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                             const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
+                             int32_t checkpoint_every, void* stream);
+
+/* Synchronise `stream` and report RES_ENONFINITE if any result produced since the last check held NaN/Inf. */
+int resolvent_op_check(resolvent_op* op, void* stream);
+
+/* Static message for a status code. */
+const char* resolvent_strerror(int status);
+/* Detail of the last error on this host thread (empty if none). */
+const char* resolvent_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RESOLVENT_H */

@@ -1,0 +1,148 @@
+"""Python face of the resolvent library: a handle class over the C ABI.  PyTorch provides device memory and the
+stream; the computation is entirely in libresolvent.so (no CPU fallback: without the library or a GPU the
+calls raise)."""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import Grid, OpDesc, Run, check
+
+_METHODS = {"transient": _lib.RES_TRANSIENT, "periodic": _lib.RES_PERIODIC}
+_PREC = {"fp64": _lib.RES_FP64, "mixed": _lib.RES_MIXED}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the resolvent library needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+class ResolventOp:
+    """A linear operator L with its RK4 step h, uploaded to the GPU.
+
+    precision: "fp64" (complex128 I/O, FP64 everywhere) or "mixed" (complex64 I/O, FP32 stepping and phase
+    GEMMs with FP64 accumulation, FP64 QR and gains)."""
+
+    def __init__(self, desc, keep, precision, stream=None):
+        self._lib = _lib.load()
+        torch = _torch()
+        self.precision = precision
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self._keep = keep
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(self._lib.resolvent_op_create(ctypes.byref(desc), self._stream_ptr(), ctypes.byref(h)))
+        self._h = h
+        self.n = int(self._lib.resolvent_op_size(h))
+        self.h = desc.h
+        self.ninst = int(desc.ninst)
+        self.offsets = np.array(keep.get("offsets", [0, self.n]), dtype=np.int64)
+
+    # ---- construction helpers ---------------------------------------------------------------------------
+    @classmethod
+    def tridiagonal(cls, lower, diag, upper, h, precision="fp64", offsets=None, probe=False, probe_tol=1e-9,
+                    probe_tmax=2000.0, probe_seed=12345, stream=None):
+        lower = np.ascontiguousarray(np.asarray(lower, np.complex128)).view(np.float64)
+        diag = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
+        upper = np.ascontiguousarray(np.asarray(upper, np.complex128)).view(np.float64)
+        n = diag.size // 2
+        keep = dict(lower=lower, diag=diag, upper=upper)
+        d = OpDesc()
+        d.kind = _lib.RES_OP_TRIDIAG
+        d.precision = _PREC[precision]
+        d.h = float(h)
+        if offsets is not None:
+            off = np.ascontiguousarray(np.asarray(offsets, np.int64))
+            keep["offsets"] = off
+            d.ninst = len(off) - 1
+            d.inst_offsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        else:
+            d.ninst = 1
+            d.nx = n
+        d.lower, d.diag, d.upper = _dptr(lower), _dptr(diag), _dptr(upper)
+        d.probe = 1 if probe else 0
+        d.probe_tol = probe_tol
+        d.probe_tmax = probe_tmax
+        d.probe_seed = probe_seed
+        return cls(d, keep, precision, stream)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.resolvent_op_destroy(h)
+            self._h = None
+
+    def _stream_ptr(self):
+        torch = _torch()
+        s = self._stream if self._stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    @property
+    def decay_time(self):
+        return float(self._lib.resolvent_op_decay_time(self._h))
+
+    # ---- arguments ----------------------------------------------------------------------------------------
+    @staticmethod
+    def grid(omega0, domega, n_omega):
+        return Grid(float(omega0), float(domega), int(n_omega))
+
+    @staticmethod
+    def run(method, tail=0, periods=1, stride=1):
+        return Run(_METHODS[method], int(tail), int(periods), int(stride))
+
+    def _check_io(self, x, nw, k):
+        torch = _torch()
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.cdtype and x.is_contiguous()):
+            raise TypeError("expected a contiguous %s CUDA tensor" % self.cdtype)
+        if tuple(x.shape) != (nw, k, self.n):
+            raise ValueError("expected shape (n_omega, k, N) = %s, got %s" % ((nw, k, self.n), tuple(x.shape)))
+
+    # ---- calls ------------------------------------------------------------------------------------------------
+    def apply(self, f_hat, grid, run, out=None):
+        """u_hat[j] = R_d(w_j) f_hat[j] for all frequencies in one direct run."""
+        return self._apply(f_hat, grid, run, out, adjoint=False)
+
+    def adjoint_apply(self, g_hat, grid, run, out=None):
+        """z_hat[j] = R_d(w_j)^H g_hat[j] in one adjoint run."""
+        return self._apply(g_hat, grid, run, out, adjoint=True)
+
+    def _apply(self, x, grid, run, out, adjoint):
+        torch = _torch()
+        nw, k = grid.n_omega, x.shape[1]
+        self._check_io(x, nw, k)
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_io(out, nw, k)
+        fn = self._lib.resolvent_adjoint_apply if adjoint else self._lib.resolvent_apply
+        check(fn(self._h, ctypes.byref(grid), ctypes.byref(run), k, ctypes.c_void_p(x.data_ptr()),
+                 ctypes.c_void_p(out.data_ptr()), self._stream_ptr()))
+        return out
+
+    def modes(self, f0_hat, grid, run, iters, want_modes=True, want_hist=True):
+        """Block power iteration; returns (gains [ninst, nw, k], V, U, hist [iters, ninst, nw, k, 2])."""
+        torch = _torch()
+        nw, k = grid.n_omega, f0_hat.shape[1]
+        self._check_io(f0_hat, nw, k)
+        gains = np.zeros((self.ninst, nw, k))
+        hist = np.zeros((iters, self.ninst, nw, k, 2)) if want_hist else None
+        V = torch.empty_like(f0_hat) if want_modes else None
+        U = torch.empty_like(f0_hat) if want_modes else None
+        check(self._lib.resolvent_modes(
+            self._h, ctypes.byref(grid), ctypes.byref(run), k, int(iters), ctypes.c_void_p(f0_hat.data_ptr()),
+            _dptr(gains), ctypes.c_void_p(V.data_ptr()) if V is not None else None,
+            ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
+        return gains, V, U, hist
+
+    def set_diagonal(self, diag):
+        """Replace the operator's diagonal (host array): complex [N] for a tridiagonal operator."""
+        d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
+        check(self._lib.resolvent_op_set_diagonal(self._h, _dptr(d), 0, self._stream_ptr()))
+
+    def check(self):
+        check(self._lib.resolvent_op_check(self._h, self._stream_ptr()))

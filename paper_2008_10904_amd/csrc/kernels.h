@@ -1,0 +1,82 @@
+// Kernel launchers of the resolvent library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace res {
+
+// ---- 1-D stepper --------------------------------------------------------------------------------------
+constexpr int kStep1DConfigs = 10;
+struct Step1DArgs {
+  int fp64;
+  int cfg;                 // index into the (threads, unknowns per thread, prefetch depth) table
+  const Seg1D* segs;
+  int64_t nseg;
+  const void* band;        // [N][9] complex (working precision)
+  void* state;             // [ncol][N]
+  int64_t N, row_len;      // row_len = ncol * N
+  int64_t n_steps;
+  const void* frc;         // forcing rows or null
+  int64_t frc_row0, frc_period;
+  double phi_re, phi_im;
+  void* snap;              // snapshot rows or null
+  int64_t snap_first, snap_stride, snap_count, snap_row0;
+};
+int step1d_capacity(int cfg);
+int launch_step1d(const Step1DArgs& a, hipStream_t st);
+int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
+                      int out_fp64, int64_t N, int k, int nw, double sw0h, double sdwh, double h, int pass,
+                      hipStream_t st);
+
+// ---- 2-D / 3-D stencils -------------------------------------------------------------------------------
+struct GridOp {
+  int dim;                 // 2 or 3
+  int ncomp;               // 1 or 3
+  int64_t nx, ny, nz;
+  const double* cxm; const double* cxp; const double* cym; const double* cyp; const double* czm; const double* czp;
+  const double* dfield;    // [nz*ny*nx]
+  const double* coupling;  // [ny*nz][3][3] or null
+};
+// y = alpha * (Z x) + beta * x + gamma_j * f  (Z = h L applied per column/frequency block; see stencil.hip)
+int launch_grid_stage(const GridOp& op, int fp64, const void* x, const void* u, void* y, int64_t nblocks,
+                      double h, double stage_scale, hipStream_t st);
+int launch_grid_horner(const GridOp& op, const cx<double>* yin, const void* F, int f_fp64, void* yout, int out_fp64,
+                       int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
+int launch_grid_axpy_forcing(int fp64, void* u, const void* frc, int64_t count, double phi_re, double phi_im,
+                             hipStream_t st);
+
+// ---- phase GEMMs --------------------------------------------------------------------------------------
+struct PhaseGemmArgs {
+  int mode;                // 0 synthesis, 1 projection
+  int64_t M, Ncols, K;
+  const void* btab;        // [P] complex (working precision): e^{2 pi i m / P}
+  int64_t P;
+  int sigma;               // +1 direct, -1 adjoint
+  double w0h;              // omega0 * h
+  int64_t s0, stride;      // synthesis: first step; projection: step of sample 0 and sample spacing
+  const void* bmat;        // [K][Ncols]
+  void* out;               // synthesis: [M][Ncols] working precision; projection: FP64 accumulator [M][Ncols]
+  double scale;            // projection scale
+  int64_t k_per_split;     // K entries per split (projection), >= K for no split
+  void* partial;           // projection split partials (FP64) or null
+};
+int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st);
+int launch_reduce_partials(const void* part, void* acc, int64_t count, int nsplit, double scale, hipStream_t st);
+
+// ---- per-frequency QR / SVD ----------------------------------------------------------------------------
+int gram_km(int k);
+int launch_gram(const void* X, int x_fp64, int64_t N, int k, const int64_t* off, int ninst, int nw, int nsplit,
+                void* part, int* flag, hipStream_t st);
+int launch_chol(const void* part, int nsplit, int k, int nw, int ninst, void* rout, void* rinv, const void* rprev,
+                void* rtot, double* hist, int* flag, hipStream_t st);
+int launch_rmul(const void* Xin, int in_fp64, void* Xout, int out_fp64, int64_t N, int k, const int64_t* off,
+                int ninst, int nw, int nsplit, const void* M, hipStream_t st);
+int launch_svd(const void* A, int k, int nw, int ninst, void* phi, void* psi, void* apsi, double* gains,
+               double* hist, hipStream_t st);
+int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t st);
+int launch_convert(const void* x, int in_fp64, void* y, int out_fp64, int64_t count, double scale, hipStream_t st);
+
+}  // namespace res

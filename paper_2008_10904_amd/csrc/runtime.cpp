@@ -1,0 +1,903 @@
+// Host runtime of the resolvent library: the C ABI of include/resolvent.h, operator set-up (RK4 step stencils
+// of L and L^H), run scheduling (synthesis table or tiles, stepper launches, projection flushes), the block
+// power iteration driver and the decay probe.  All device work is stream-ordered on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/resolvent.h"
+#include "kernels.h"
+
+using namespace res;
+typedef std::complex<double> cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess) return fail(RES_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+double env_double(const char* name, double dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atof(v) : dflt;
+}
+long env_long(const char* name, long dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atol(v) : dflt;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Banded matrix: m[i][d + r] = M_{i, i + d}, |d| <= r.
+struct Band {
+  int64_t n = 0;
+  int r = 0;
+  std::vector<cd> m;
+  Band() {}
+  Band(int64_t n_, int r_) : n(n_), r(r_), m((size_t)n_ * (2 * r_ + 1), cd(0, 0)) {}
+  cd& at(int64_t i, int d) { return m[(size_t)i * (2 * r + 1) + (d + r)]; }
+  cd get(int64_t i, int d) const {
+    if (d < -r || d > r) return cd(0, 0);
+    return m[(size_t)i * (2 * r + 1) + (d + r)];
+  }
+};
+
+Band band_mul(const Band& A, const Band& B) {
+  Band C(A.n, A.r + B.r);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int e = -A.r; e <= A.r; ++e) {
+      const int64_t k = i + e;
+      if (k < 0 || k >= A.n) continue;
+      const cd a = A.get(i, e);
+      if (a == cd(0, 0)) continue;
+      for (int f = -B.r; f <= B.r; ++f) {
+        const int64_t jcol = k + f;
+        if (jcol < 0 || jcol >= A.n) continue;
+        C.at(i, e + f) += a * B.get(k, f);
+      }
+    }
+  return C;
+}
+
+}  // namespace
+
+struct resolvent_op {
+  int kind = 0, prec = 0;
+  double h = 0;
+  int64_t N = 0;  // unknowns per column
+  int ninst = 1;
+  std::vector<int64_t> off;
+  int64_t* d_off = nullptr;
+  // 1-D three-point operator
+  std::vector<cd> zl, zd, zu;  // Z = h L (instance boundaries zeroed)
+  void* d_tri[2] = {nullptr, nullptr};   // FP64 [N][3] of Z (0) and Z^H (1)
+  void* d_band[2] = {nullptr, nullptr};  // working precision [N][9] of P(Z), P(Z^H)
+  std::vector<Seg1D> segs;               // segments of one column
+  std::vector<Seg1D> segs_k;             // segments of all k columns of the current run (upload source)
+  int step_cfg = -1;
+  // workspace and caches
+  std::map<std::string, DevBuf> ws;
+  std::map<int64_t, void*> btab;
+  int* d_flag = nullptr;
+  double decay_time = -1;
+  bool fp64() const { return prec == RES_FP64; }
+  size_t wsize() const { return fp64() ? 16 : 8; }  // bytes per complex in working precision
+};
+
+namespace {
+
+int ws_get(resolvent_op* op, const std::string& name, size_t bytes, void** out) {
+  DevBuf& b = op->ws[name];
+  if (b.bytes < bytes) {
+    if (b.p) HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      b.p = nullptr;
+      (void)hipGetLastError();
+      return fail(RES_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + name + " failed");
+    }
+    b.bytes = bytes;
+  }
+  *out = b.p;
+  return RES_OK;
+}
+
+#define RES_TRY(expr)          \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != RES_OK) return rc_; \
+  } while (0)
+
+int upload(void** dst, const void* src, size_t bytes) {
+  HIP_TRY(hipMalloc(dst, bytes));
+  HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return RES_OK;
+}
+
+// P(Z) = I + Z + Z^2/2 + Z^3/6 + Z^4/24 of a tridiagonal Z, as a radius-4 band.
+Band rk4_step_band(const std::vector<cd>& zl, const std::vector<cd>& zd, const std::vector<cd>& zu) {
+  const int64_t n = (int64_t)zd.size();
+  Band Z(n, 1);
+  for (int64_t i = 0; i < n; ++i) {
+    Z.at(i, -1) = zl[i];
+    Z.at(i, 0) = zd[i];
+    Z.at(i, 1) = zu[i];
+  }
+  Band Z2 = band_mul(Z, Z), Z3 = band_mul(Z2, Z), Z4 = band_mul(Z3, Z);
+  Band P(n, kBandRadius);
+  for (int64_t i = 0; i < n; ++i) {
+    P.at(i, 0) += 1.0;
+    for (int d = -1; d <= 1; ++d) P.at(i, d) += Z.get(i, d);
+    for (int d = -2; d <= 2; ++d) P.at(i, d) += Z2.get(i, d) / 2.0;
+    for (int d = -3; d <= 3; ++d) P.at(i, d) += Z3.get(i, d) / 6.0;
+    for (int d = -4; d <= 4; ++d) P.at(i, d) += Z4.get(i, d) / 24.0;
+  }
+  return P;
+}
+
+int build_1d_stencils(resolvent_op* op) {
+  const int64_t n = op->N;
+  // adjoint tridiagonal: (Z^H)_{i,i-1} = conj(Z_{i-1,i}), (Z^H)_{i,i+1} = conj(Z_{i+1,i})
+  std::vector<cd> al(n), ad(n), au(n);
+  for (int64_t i = 0; i < n; ++i) {
+    ad[i] = std::conj(op->zd[i]);
+    al[i] = i > 0 ? std::conj(op->zu[i - 1]) : cd(0, 0);
+    au[i] = i + 1 < n ? std::conj(op->zl[i + 1]) : cd(0, 0);
+  }
+  const std::vector<cd>* L3[2][3] = {{&op->zl, &op->zd, &op->zu}, {&al, &ad, &au}};
+  for (int s = 0; s < 2; ++s) {
+    std::vector<cd> tri((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i) {
+      tri[3 * i + 0] = (*L3[s][0])[i];
+      tri[3 * i + 1] = (*L3[s][1])[i];
+      tri[3 * i + 2] = (*L3[s][2])[i];
+    }
+    if (op->d_tri[s]) HIP_TRY(hipFree(op->d_tri[s]));
+    op->d_tri[s] = nullptr;
+    RES_TRY(upload(&op->d_tri[s], tri.data(), tri.size() * sizeof(cd)));
+    Band P = rk4_step_band(*L3[s][0], *L3[s][1], *L3[s][2]);
+    if (op->d_band[s]) HIP_TRY(hipFree(op->d_band[s]));
+    op->d_band[s] = nullptr;
+    if (op->fp64()) {
+      RES_TRY(upload(&op->d_band[s], P.m.data(), P.m.size() * sizeof(cd)));
+    } else {
+      std::vector<std::complex<float>> pf(P.m.size());
+      for (size_t i = 0; i < P.m.size(); ++i) pf[i] = std::complex<float>((float)P.m[i].real(), (float)P.m[i].imag());
+      RES_TRY(upload(&op->d_band[s], pf.data(), pf.size() * sizeof(std::complex<float>)));
+    }
+  }
+  return RES_OK;
+}
+
+// Segments of one column: consecutive whole instances packed greedily up to the stepper capacity.
+int plan_1d_segments(resolvent_op* op) {
+  int64_t maxlen = 0;
+  for (int m = 0; m < op->ninst; ++m) maxlen = std::max(maxlen, op->off[m + 1] - op->off[m]);
+  const int64_t cap_max = 2048;
+  if (maxlen > cap_max)
+    return fail(RES_ENOTSUP, "1-D instances longer than " + std::to_string(cap_max) + " unknowns are not supported");
+  // smallest capacity class holding the largest instance
+  int64_t cap = 64;
+  while (cap < maxlen) cap *= 2;
+  op->segs.clear();
+  Seg1D cur{0, 0, op->off[0], 0};
+  for (int m = 0; m < op->ninst; ++m) {
+    const int64_t len = op->off[m + 1] - op->off[m];
+    if (cur.ndof + len > cap && cur.ndof > 0) {
+      op->segs.push_back(cur);
+      cur = Seg1D{0, 0, op->off[m], 0};
+    }
+    cur.ndof += len;
+  }
+  if (cur.ndof > 0) op->segs.push_back(cur);
+  int64_t seglen = 0;
+  for (auto& s : op->segs) seglen = std::max(seglen, s.ndof);
+  // default configuration per capacity class (overridable for tuning)
+  int cfg;
+  if (seglen <= 64) cfg = 0;
+  else if (seglen <= 128) cfg = 1;
+  else if (seglen <= 256) cfg = 2;
+  else if (seglen <= 512) cfg = 3;
+  else if (seglen <= 1024) cfg = 8;
+  else cfg = 6;
+  const long forced = env_long("RESOLVENT_STEP1D_CFG", -1);
+  if (forced >= 0 && forced < kStep1DConfigs && step1d_capacity((int)forced) >= seglen) cfg = (int)forced;
+  op->step_cfg = cfg;
+  return RES_OK;
+}
+
+int phase_table(resolvent_op* op, int64_t P, void** out) {
+  auto it = op->btab.find(P);
+  if (it != op->btab.end()) {
+    *out = it->second;
+    return RES_OK;
+  }
+  void* d = nullptr;
+  if (op->fp64()) {
+    std::vector<cd> t((size_t)P);
+    for (int64_t m = 0; m < P; ++m) t[m] = std::polar(1.0, 2.0 * M_PI * (double)m / (double)P);
+    RES_TRY(upload(&d, t.data(), t.size() * sizeof(cd)));
+  } else {
+    std::vector<std::complex<float>> t((size_t)P);
+    for (int64_t m = 0; m < P; ++m) {
+      const cd z = std::polar(1.0, 2.0 * M_PI * (double)m / (double)P);
+      t[m] = std::complex<float>((float)z.real(), (float)z.imag());
+    }
+    RES_TRY(upload(&d, t.data(), t.size() * sizeof(std::complex<float>)));
+  }
+  op->btab[P] = d;
+  *out = d;
+  return RES_OK;
+}
+
+struct Plan {
+  double w0, dw;
+  int nw;
+  int64_t P;
+  int method;
+  int64_t S;                               // total steps
+  int64_t forced_end;                      // forcing active for s < forced_end
+  int64_t pfirst, pstride, pcount;         // projected steps pfirst + m*pstride, m < pcount
+  double scale;                            // projection normalisation
+};
+
+int make_plan(const resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, Plan* pl) {
+  if (!g || !r) return fail(RES_EINVAL, "grid and run must not be NULL");
+  if (g->n_omega < 1) return fail(RES_EINVAL, "n_omega must be >= 1");
+  if (!(std::fabs(g->domega) > 0)) return fail(RES_EGRID, "domega must be nonzero");
+  const double Pd = 2.0 * M_PI / (std::fabs(g->domega) * op->h);
+  const int64_t P = (int64_t)std::llround(Pd);
+  if (P < 1 || std::fabs(std::fabs(g->domega) * (double)P * op->h - 2.0 * M_PI) > 1e-9 * 2.0 * M_PI)
+    return fail(RES_EGRID, "|domega| * P * h != 2 pi for integer P (P ~ " + std::to_string(Pd) + ")");
+  if (g->n_omega > P) return fail(RES_EGRID, "more frequencies than steps per period (aliasing)");
+  pl->w0 = g->omega0;
+  pl->dw = g->domega;
+  pl->nw = g->n_omega;
+  pl->P = P;
+  pl->method = r->method;
+  if (r->method == RES_TRANSIENT) {
+    if (r->tail < 0) return fail(RES_EINVAL, "tail must be >= 0");
+    pl->S = P + r->tail;
+    pl->forced_end = P;
+    pl->pfirst = 0;
+    pl->pstride = 1;
+    pl->pcount = pl->S;
+    pl->scale = 1.0 / (double)P;
+  } else if (r->method == RES_PERIODIC) {
+    if (r->periods < 1) return fail(RES_EINVAL, "periods must be >= 1");
+    const int64_t D = r->stride < 1 ? 1 : r->stride;
+    if (P % D != 0 || P / D < g->n_omega)
+      return fail(RES_EGRID, "projection stride must divide P and leave at least n_omega samples per period");
+    pl->S = (int64_t)r->periods * P;
+    pl->forced_end = pl->S;
+    pl->pfirst = (int64_t)(r->periods - 1) * P;
+    pl->pstride = D;
+    pl->pcount = P / D;
+    pl->scale = (double)D / (double)P;
+  } else {
+    return fail(RES_EINVAL, "unknown method");
+  }
+  return RES_OK;
+}
+
+int nsplit_for(int64_t maxlen) {
+  int64_t s = (maxlen + 2047) / 2048;
+  if (s < 1) s = 1;
+  if (s > 1024) s = 1024;
+  return (int)s;
+}
+
+int64_t max_instance_len(const resolvent_op* op) {
+  int64_t m = 0;
+  for (int i = 0; i < op->ninst; ++i) m = std::max(m, op->off[i + 1] - op->off[i]);
+  return m;
+}
+
+// Flush `rows` buffered snapshot rows (the first being projected sample m_first) into acc.
+void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStream_t st);
+
+int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* btab, const void* snap,
+                     int64_t m_first, int64_t rows, double* acc, hipStream_t st) {
+  if (rows <= 0) return RES_OK;
+  trace_norm("snapshots", snap, rows * (int64_t)k * op->N, op->fp64(), st);
+  const int64_t ncols = (int64_t)k * op->N;
+  PhaseGemmArgs a{};
+  a.mode = 1;
+  a.M = pl.nw;
+  a.Ncols = ncols;
+  a.K = rows;
+  a.btab = btab;
+  a.P = pl.P;
+  a.sigma = sigma;
+  a.w0h = pl.w0 * op->h;
+  a.s0 = pl.pfirst + m_first * pl.pstride;
+  a.stride = pl.pstride;
+  a.bmat = snap;
+  a.out = acc;
+  a.scale = pl.scale;
+  // split K so that the grid has enough workgroups
+  const int64_t tiles = ((pl.nw + 63) / 64) * ((ncols + 63) / 64);
+  int64_t nsplit = 1;
+  if (tiles < 1024) nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, (rows + 63) / 64);
+  if (nsplit < 1) nsplit = 1;
+  const int64_t kps = ((rows + nsplit - 1) / nsplit + 15) / 16 * 16;
+  nsplit = (rows + kps - 1) / kps;
+  a.k_per_split = kps;
+  if (nsplit > 1) {
+    void* part = nullptr;
+    RES_TRY(ws_get(op, "proj_partial", (size_t)nsplit * pl.nw * ncols * sizeof(cd), &part));
+    a.partial = part;
+    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "projection GEMM launch");
+    launch_reduce_partials(part, acc, (int64_t)pl.nw * ncols, (int)nsplit, pl.scale, st);
+  } else {
+    a.partial = nullptr;
+    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "projection GEMM launch");
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+// Opt-in diagnostics (RESOLVENT_TRACE=1): synchronise and print the 2-norm of a device complex array.
+void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStream_t st) {
+  static const bool on = env_long("RESOLVENT_TRACE", 0) != 0;
+  if (!on || p == nullptr) return;
+  (void)hipStreamSynchronize(st);
+  double s = 0;
+  if (fp64) {
+    std::vector<cd> h(count);
+    (void)hipMemcpy(h.data(), p, count * sizeof(cd), hipMemcpyDeviceToHost);
+    for (auto& z : h) s += std::norm(z);
+  } else {
+    std::vector<std::complex<float>> h(count);
+    (void)hipMemcpy(h.data(), p, count * sizeof(std::complex<float>), hipMemcpyDeviceToHost);
+    for (auto& z : h) s += std::norm(std::complex<double>(z.real(), z.imag()));
+  }
+  std::fprintf(stderr, "[resolvent trace] %-28s count=%lld norm=%.6e err=%s\n", what, (long long)count,
+               std::sqrt(s), hipGetErrorString(hipGetLastError()));
+}
+
+int zero_device(void* p, size_t bytes, hipStream_t st) {
+  HIP_TRY(hipMemsetAsync(p, 0, bytes, st));
+  return RES_OK;
+}
+
+// One time-marched run: acc[j][c][:] = R_d(sigma w_j)-run of in[j][c][:], with L (sigma = +1) or L^H (sigma = -1).
+// `in` is [nw][k][N] complex of dtype in_fp64; acc is FP64 [nw][k][N] and is overwritten.
+int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
+           hipStream_t st) {
+  const int64_t N = op->N;
+  const int64_t ncols = (int64_t)k * N;
+  const int nw = pl.nw;
+  const int s = sigma > 0 ? 0 : 1;
+  const size_t ws = op->wsize();
+  void *y1, *y2, *G, *state, *btab;
+  RES_TRY(ws_get(op, "horner_a", (size_t)nw * ncols * sizeof(cd), &y1));
+  RES_TRY(ws_get(op, "horner_b", (size_t)nw * ncols * sizeof(cd), &y2));
+  RES_TRY(ws_get(op, "G", (size_t)nw * ncols * ws, &G));
+  RES_TRY(ws_get(op, "state", (size_t)ncols * ws, &state));
+  RES_TRY(phase_table(op, pl.P, &btab));
+  // G_j = h Q_j(Z) F_j  (three Horner passes)
+  const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
+  const cx<double>* tri = (const cx<double>*)op->d_tri[s];
+  launch_tri_horner(tri, nullptr, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 0, st);
+  launch_tri_horner(tri, (const cx<double>*)y1, in, in_fp64, y2, 1, N, k, nw, sw0h, sdwh, op->h, 1, st);
+  launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
+  HIP_TRY(hipGetLastError());
+  trace_norm("run input", in, (int64_t)nw * ncols, in_fp64, st);
+  trace_norm("horner pass 0", y1, (int64_t)nw * ncols, 1, st);
+  trace_norm("G = hQ(Z) F", G, (int64_t)nw * ncols, op->fp64(), st);
+  RES_TRY(zero_device(state, (size_t)ncols * ws, st));
+  RES_TRY(zero_device(acc, (size_t)nw * ncols * sizeof(cd), st));
+
+  // forcing rows: whole first period as a table when it fits, else tiles
+  const double table_budget = env_double("RESOLVENT_TABLE_BUDGET_GB", 48.0) * 1073741824.0;
+  const int64_t table_rows = std::min<int64_t>(pl.P, pl.forced_end);
+  const bool table_mode = (double)table_rows * (double)ncols * (double)ws <= table_budget;
+  int64_t tile_rows = 0;
+  void* frc = nullptr;
+  if (table_mode) {
+    RES_TRY(ws_get(op, "forcing", (size_t)table_rows * ncols * ws, &frc));
+    PhaseGemmArgs a{};
+    a.mode = 0;
+    a.M = table_rows;
+    a.Ncols = ncols;
+    a.K = nw;
+    a.btab = btab;
+    a.P = pl.P;
+    a.sigma = sigma;
+    a.w0h = pl.w0 * op->h;
+    a.s0 = 0;
+    a.stride = 1;
+    a.bmat = G;
+    a.out = frc;
+    a.k_per_split = nw;
+    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
+    HIP_TRY(hipGetLastError());
+    trace_norm("forcing table", frc, table_rows * ncols, op->fp64(), st);
+  } else {
+    const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
+    tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));
+    RES_TRY(ws_get(op, "forcing", (size_t)tile_rows * ncols * ws, &frc));
+  }
+  // snapshot buffer
+  const double snap_budget = env_double("RESOLVENT_SNAP_BUDGET_GB", 2.0) * 1073741824.0;
+  int64_t snap_cap = std::max<int64_t>(64, (int64_t)(snap_budget / ((double)ncols * ws)));
+  snap_cap = std::min<int64_t>(snap_cap, pl.pcount);
+  void* snap = nullptr;
+  RES_TRY(ws_get(op, "snapshots", (size_t)snap_cap * ncols * ws, &snap));
+
+  // segments for all k columns (host copy kept in the handle: the upload is asynchronous)
+  std::vector<Seg1D>& segs = op->segs_k;
+  segs.clear();
+  for (int c = 0; c < k; ++c)
+    for (auto sg : op->segs) {
+      sg.col = c;
+      segs.push_back(sg);
+    }
+  void* dsegs;
+  RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), &dsegs));
+  HIP_TRY(hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
+
+  int64_t buffered = 0, buf_m0 = 0;  // rows in the snapshot buffer and the sample index of the first
+  int64_t s0 = 0;
+  while (s0 < pl.S) {
+    // chunk end: period boundary (table mode), tile size (tile mode), forcing switch-off
+    int64_t e = pl.S;
+    if (table_mode) e = std::min(e, (s0 / pl.P + 1) * pl.P);
+    else e = std::min(e, s0 + tile_rows);
+    if (s0 < pl.forced_end) e = std::min(e, pl.forced_end);
+    // projected samples in [s0, e): m in [ma, mb)
+    auto first_m_at_or_after = [&](int64_t t) -> int64_t {
+      if (t <= pl.pfirst) return 0;
+      return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
+    };
+    int64_t ma = first_m_at_or_after(s0), mb = first_m_at_or_after(e);
+    if (mb - ma > snap_cap - buffered) {
+      mb = ma + (snap_cap - buffered);
+      e = pl.pfirst + (mb - 1) * pl.pstride + 1;  // stop right after the last sample that fits
+    }
+    const bool forced = s0 < pl.forced_end;
+    Step1DArgs a{};
+    a.fp64 = op->fp64();
+    a.cfg = op->step_cfg;
+    a.segs = (const Seg1D*)dsegs;
+    a.nseg = (int64_t)segs.size();
+    a.band = op->d_band[s];
+    a.state = state;
+    a.N = N;
+    a.row_len = ncols;
+    a.n_steps = e - s0;
+    a.phi_re = 1.0;
+    a.phi_im = 0.0;
+    if (forced) {
+      if (table_mode) {
+        a.frc = frc;
+        a.frc_row0 = s0 % pl.P;
+        a.frc_period = std::min<int64_t>(pl.P, table_rows);
+        // e^{i sigma w0 q P h} for the period q of this chunk (table rows hold the period-0 phases)
+        const int64_t q = s0 / pl.P;
+        const cd phi = std::polar(1.0, sigma * pl.w0 * op->h * (double)pl.P * (double)q);
+        a.phi_re = phi.real();
+        a.phi_im = phi.imag();
+      } else {
+        PhaseGemmArgs g{};
+        g.mode = 0;
+        g.M = e - s0;
+        g.Ncols = ncols;
+        g.K = nw;
+        g.btab = btab;
+        g.P = pl.P;
+        g.sigma = sigma;
+        g.w0h = pl.w0 * op->h;
+        g.s0 = s0;
+        g.stride = 1;
+        g.bmat = G;
+        g.out = frc;
+        g.k_per_split = nw;
+        if (launch_phase_gemm(g, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
+        a.frc = frc;
+        a.frc_row0 = 0;
+        a.frc_period = 0;
+      }
+    } else {
+      a.frc = nullptr;
+    }
+    if (mb > ma) {
+      a.snap = snap;
+      a.snap_first = pl.pfirst + ma * pl.pstride - s0;
+      a.snap_stride = pl.pstride;
+      a.snap_count = mb - ma;
+      a.snap_row0 = buffered;
+      if (buffered == 0) buf_m0 = ma;
+      buffered += mb - ma;
+    } else {
+      a.snap = nullptr;
+    }
+    if (launch_step1d(a, st)) return fail(RES_EINVAL, "stepper launch");
+    HIP_TRY(hipGetLastError());
+    trace_norm("state after chunk", state, ncols, op->fp64(), st);
+    if (buffered == snap_cap || (buffered > 0 && (e >= pl.S || mb >= pl.pcount))) {
+      RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, buf_m0, buffered, acc, st));
+      buffered = 0;
+    }
+    s0 = e;
+  }
+  if (buffered > 0) RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, buf_m0, buffered, acc, st));
+  return RES_OK;
+}
+
+int run_any(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
+            hipStream_t st) {
+  if (op->kind == RES_OP_TRIDIAG) return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);
+  return fail(RES_ENOTSUP, "operator kind not supported yet");
+}
+
+int apply_common(resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, int k, const void* in, void* out,
+                 int sigma, hipStream_t st) {
+  if (!op || !in || !out) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
+  Plan pl;
+  RES_TRY(make_plan(op, g, r, &pl));
+  const int64_t count = (int64_t)pl.nw * k * op->N;
+  double* acc;
+  if (op->fp64()) {
+    acc = (double*)out;
+  } else {
+    void* p;
+    RES_TRY(ws_get(op, "acc_io", (size_t)count * sizeof(cd), &p));
+    acc = (double*)p;
+  }
+  RES_TRY(run_any(op, pl, k, in, op->fp64(), acc, sigma, st));
+  if (!op->fp64()) launch_convert(acc, 1, out, 0, count, 1.0, st);
+  launch_finite(acc, 1, count, op->d_flag, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+// CholeskyQR2 of X [nw][k][N] (FP64, in place): X <- Q; rtot receives R.  norm_hist (may be null) gets the
+// column-norm estimator from the first Gram.
+int cholqr2(resolvent_op* op, int nw, int k, double* X, void* rtot, double* norm_hist, hipStream_t st) {
+  const int nsplit = nsplit_for(max_instance_len(op));
+  const int km = gram_km(k);
+  const size_t np = (size_t)km * (km + 1) / 2;
+  void *part, *r1, *r1i, *r2i;
+  const size_t mats = (size_t)nw * op->ninst * 64 * sizeof(cd);
+  RES_TRY(ws_get(op, "gram_part", (size_t)nw * op->ninst * nsplit * np * sizeof(cd), &part));
+  RES_TRY(ws_get(op, "qr_r1", mats, &r1));
+  RES_TRY(ws_get(op, "qr_r1i", mats, &r1i));
+  RES_TRY(ws_get(op, "qr_r2i", mats, &r2i));
+  launch_gram(X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, part, op->d_flag, st);
+  launch_chol(part, nsplit, k, nw, op->ninst, r1, r1i, nullptr, nullptr, norm_hist, op->d_flag, st);
+  launch_rmul(X, 1, X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, r1i, st);
+  launch_gram(X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, part, op->d_flag, st);
+  launch_chol(part, nsplit, k, nw, op->ninst, nullptr, r2i, r1, rtot, nullptr, op->d_flag, st);
+  launch_rmul(X, 1, X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, r2i, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Decay probe: march a random initial condition without forcing until its norm falls below tol (stable),
+// diverges (RES_ESTEP) or tmax passes (RES_EUNSTABLE).
+int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
+  const int64_t N = op->N;
+  const size_t ws = op->wsize();
+  void* state;
+  RES_TRY(ws_get(op, "state", (size_t)N * ws, &state));
+  uint64_t sx = d->probe_seed;
+  std::vector<cd> u0(N);
+  for (int64_t i = 0; i < N; ++i) {
+    const double a = (double)(splitmix64(sx) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    const double b = (double)(splitmix64(sx) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    u0[i] = cd(a, b);
+  }
+  if (op->fp64()) {
+    HIP_TRY(hipMemcpyAsync(state, u0.data(), N * sizeof(cd), hipMemcpyHostToDevice, st));
+  } else {
+    std::vector<std::complex<float>> f(N);
+    for (int64_t i = 0; i < N; ++i) f[i] = std::complex<float>((float)u0[i].real(), (float)u0[i].imag());
+    HIP_TRY(hipMemcpyAsync(state, f.data(), N * sizeof(std::complex<float>), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  double n0 = 0;
+  for (auto& z : u0) n0 += std::norm(z);
+  n0 = std::sqrt(n0);
+  std::vector<Seg1D>& segs = op->segs_k;
+  segs = op->segs;
+  void *dsegs, *part;
+  RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), &dsegs));
+  HIP_TRY(hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
+  const int nsplit = nsplit_for(max_instance_len(op));
+  RES_TRY(ws_get(op, "probe_part", (size_t)op->ninst * nsplit * sizeof(cd), &part));
+  const double tol = d->probe_tol > 0 ? d->probe_tol : 1e-9;
+  const double tmax = d->probe_tmax > 0 ? d->probe_tmax : 2000.0;
+  const int64_t chunk = std::max<int64_t>(1, (int64_t)std::ceil(tmax / 50.0 / op->h));
+  std::vector<cd> hpart((size_t)op->ninst * nsplit);
+  int64_t steps = 0;
+  while (true) {
+    Step1DArgs a{};
+    a.fp64 = op->fp64();
+    a.cfg = op->step_cfg;
+    a.segs = (const Seg1D*)dsegs;
+    a.nseg = (int64_t)segs.size();
+    a.band = op->d_band[0];
+    a.state = state;
+    a.N = N;
+    a.row_len = N;
+    a.n_steps = chunk;
+    if (launch_step1d(a, st)) return fail(RES_EINVAL, "stepper launch");
+    steps += chunk;
+    launch_gram(state, op->fp64(), N, 1, op->d_off, op->ninst, 1, nsplit, part, op->d_flag, st);
+    HIP_TRY(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double nn = 0;
+    for (auto& z : hpart) nn += z.real();
+    const double nrm = std::sqrt(std::max(nn, 0.0));
+    const double t = steps * op->h;
+    if (!std::isfinite(nrm) || nrm > 1e30 * n0) {
+      int zero = 0;
+      HIP_TRY(hipMemcpy(op->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+      return fail(RES_ESTEP, "decay probe diverged after " + std::to_string(steps) +
+                                 " steps: the RK4 step h is outside the stability region of L");
+    }
+    if (nrm <= tol * n0) {
+      op->decay_time = t;
+      return RES_OK;
+    }
+    if (t >= tmax)
+      return fail(RES_EUNSTABLE, "decay probe: norm ratio " + std::to_string(nrm / n0) + " after t = " +
+                                     std::to_string(t) + " (operator not stable, or decay slower than probe_tmax)");
+  }
+}
+
+}  // namespace
+
+// =====================================================================================================
+// C ABI
+// =====================================================================================================
+extern "C" {
+
+const char* resolvent_strerror(int s) {
+  switch (s) {
+    case RES_OK: return "success";
+    case RES_EINVAL: return "invalid argument";
+    case RES_EGRID: return "frequency grid not commensurate with the time step";
+    case RES_ESTEP: return "RK4 step unstable for this operator";
+    case RES_EUNSTABLE: return "operator is not stable (decay probe did not decay)";
+    case RES_ENONFINITE: return "non-finite values in a result";
+    case RES_ENOMEM: return "device allocation failed";
+    case RES_EHIP: return "HIP runtime error";
+    case RES_ENOTSUP: return "not supported for this operator";
+    default: return "unknown status";
+  }
+}
+
+const char* resolvent_last_error(void) { return g_last_error.c_str(); }
+
+int resolvent_op_create(const resolvent_op_desc* d, void* stream, resolvent_op** out) {
+  g_last_error.clear();
+  if (!out) return fail(RES_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(RES_EINVAL, "desc is NULL");
+  if (!(d->h > 0) || !std::isfinite(d->h)) return fail(RES_EINVAL, "h must be positive");
+  if (d->precision != RES_FP64 && d->precision != RES_MIXED) return fail(RES_EINVAL, "bad precision");
+  hipStream_t st = (hipStream_t)stream;
+  resolvent_op* op = new resolvent_op();
+  op->kind = d->kind;
+  op->prec = d->precision;
+  op->h = d->h;
+  auto bail = [&](int rc) {
+    resolvent_op_destroy(op);
+    return rc;
+  };
+  if (d->kind == RES_OP_TRIDIAG) {
+    if (!d->lower || !d->diag || !d->upper) return bail(fail(RES_EINVAL, "tridiagonal arrays are NULL"));
+    op->ninst = d->ninst < 1 ? 1 : d->ninst;
+    if (d->inst_offsets) {
+      op->off.assign(d->inst_offsets, d->inst_offsets + op->ninst + 1);
+    } else {
+      if (op->ninst != 1) return bail(fail(RES_EINVAL, "inst_offsets required when ninst > 1"));
+      op->off = {0, d->nx};
+    }
+    if (op->off[0] != 0) return bail(fail(RES_EINVAL, "inst_offsets[0] must be 0"));
+    for (int m = 0; m < op->ninst; ++m)
+      if (op->off[m + 1] <= op->off[m]) return bail(fail(RES_EINVAL, "instances must be non-empty"));
+    op->N = op->off[op->ninst];
+    const int64_t n = op->N;
+    op->zl.resize(n);
+    op->zd.resize(n);
+    op->zu.resize(n);
+    std::vector<char> first(n, 0), last(n, 0);
+    for (int m = 0; m < op->ninst; ++m) {
+      first[op->off[m]] = 1;
+      last[op->off[m + 1] - 1] = 1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      const cd l(d->lower[2 * i], d->lower[2 * i + 1]), c(d->diag[2 * i], d->diag[2 * i + 1]),
+          u(d->upper[2 * i], d->upper[2 * i + 1]);
+      if (!std::isfinite(l.real()) || !std::isfinite(l.imag()) || !std::isfinite(c.real()) ||
+          !std::isfinite(c.imag()) || !std::isfinite(u.real()) || !std::isfinite(u.imag()))
+        return bail(fail(RES_EINVAL, "non-finite operator coefficient"));
+      op->zl[i] = first[i] ? cd(0, 0) : d->h * l;
+      op->zd[i] = d->h * c;
+      op->zu[i] = last[i] ? cd(0, 0) : d->h * u;
+    }
+    int rc = plan_1d_segments(op);
+    if (rc) return bail(rc);
+    rc = build_1d_stencils(op);
+    if (rc) return bail(rc);
+  } else {
+    return bail(fail(RES_ENOTSUP, "operator kind not supported"));
+  }
+  if (upload((void**)&op->d_off, op->off.data(), op->off.size() * sizeof(int64_t))) return bail(RES_EHIP);
+  if (hipMalloc(&op->d_flag, sizeof(int)) != hipSuccess) return bail(fail(RES_ENOMEM, "flag"));
+  if (hipMemset(op->d_flag, 0, sizeof(int)) != hipSuccess) return bail(fail(RES_EHIP, "flag memset"));
+  if (d->probe) {
+    int rc = decay_probe(op, d, st);
+    if (rc) return bail(rc);
+  }
+  *out = op;
+  return RES_OK;
+}
+
+void resolvent_op_destroy(resolvent_op* op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : op->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : op->btab)
+    if (kv.second) (void)hipFree(kv.second);
+  for (int s = 0; s < 2; ++s) {
+    if (op->d_tri[s]) (void)hipFree(op->d_tri[s]);
+    if (op->d_band[s]) (void)hipFree(op->d_band[s]);
+  }
+  if (op->d_off) (void)hipFree(op->d_off);
+  if (op->d_flag) (void)hipFree(op->d_flag);
+  delete op;
+}
+
+int64_t resolvent_op_size(const resolvent_op* op) { return op ? op->N : -1; }
+double resolvent_op_decay_time(const resolvent_op* op) { return op ? op->decay_time : -1; }
+
+int resolvent_op_set_diagonal(resolvent_op* op, const double* values, int32_t on_device, void* stream) {
+  if (!op || !values) return fail(RES_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (op->kind == RES_OP_TRIDIAG) {
+    std::vector<double> hv(2 * op->N);
+    if (on_device) {
+      HIP_TRY(hipMemcpyAsync(hv.data(), values, hv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    } else {
+      std::memcpy(hv.data(), values, hv.size() * sizeof(double));
+    }
+    for (int64_t i = 0; i < op->N; ++i) op->zd[i] = op->h * cd(hv[2 * i], hv[2 * i + 1]);
+    HIP_TRY(hipStreamSynchronize(st));  // kernels in flight may still read the old stencils
+    return build_1d_stencils(op);
+  }
+  return fail(RES_ENOTSUP, "operator kind not supported");
+}
+
+int resolvent_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                    const void* f_hat, void* u_hat, void* stream) {
+  g_last_error.clear();
+  return apply_common(op, grid, run, k, f_hat, u_hat, +1, (hipStream_t)stream);
+}
+
+int resolvent_adjoint_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                            const void* g_hat, void* z_hat, void* stream) {
+  g_last_error.clear();
+  return apply_common(op, grid, run, k, g_hat, z_hat, -1, (hipStream_t)stream);
+}
+
+int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                    int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                    void* stream) {
+  g_last_error.clear();
+  if (!op || !f0_hat || !gains) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1 || k > 8) return fail(RES_EINVAL, "k must be in 1..8");
+  if (iters < 1) return fail(RES_EINVAL, "iters must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  Plan pl;
+  RES_TRY(make_plan(op, grid, run, &pl));
+  const int nw = pl.nw;
+  const int64_t count = (int64_t)nw * k * op->N;
+  const size_t mats = (size_t)nw * op->ninst * 64 * sizeof(cd);
+  void *Fh, *Y, *Z, *rY, *phi, *psi, *apsi, *dg, *dh = nullptr;
+  RES_TRY(ws_get(op, "modes_F", count * sizeof(cd), &Fh));
+  RES_TRY(ws_get(op, "modes_Y", count * sizeof(cd), &Y));
+  RES_TRY(ws_get(op, "modes_Z", count * sizeof(cd), &Z));
+  RES_TRY(ws_get(op, "modes_rY", mats, &rY));
+  RES_TRY(ws_get(op, "modes_phi", mats, &phi));
+  RES_TRY(ws_get(op, "modes_psi", mats, &psi));
+  RES_TRY(ws_get(op, "modes_apsi", mats, &apsi));
+  const size_t gcount = (size_t)op->ninst * nw * k;
+  RES_TRY(ws_get(op, "modes_gains", gcount * sizeof(double), &dg));
+  if (hist) RES_TRY(ws_get(op, "modes_hist", (size_t)iters * gcount * 2 * sizeof(double), &dh));
+  launch_convert(f0_hat, op->fp64(), Fh, 1, count, 1.0, st);
+  for (int it = 0; it < iters; ++it) {
+    double* hprev = (hist && it > 0) ? (double*)dh + (size_t)(it - 1) * gcount * 2 : nullptr;
+    double* hcur = hist ? (double*)dh + (size_t)it * gcount * 2 : nullptr;
+    // 1. F = Q(QR(F_hat))
+    RES_TRY(cholqr2(op, nw, k, (double*)Fh, rY, hprev, st));
+    // 2. Y = R_d F
+    RES_TRY(run_any(op, pl, k, Fh, 1, (double*)Y, +1, st));
+    // 3. Y = Q_Y R_Y, R_Y = Phi Sigma Psi^H
+    RES_TRY(cholqr2(op, nw, k, (double*)Y, rY, nullptr, st));
+    launch_svd(rY, k, nw, op->ninst, phi, psi, apsi, (double*)dg, hcur, st);
+    if (it == iters - 1) {
+      if (U) launch_rmul(Y, 1, U, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), phi, st);
+      if (V) launch_rmul(Fh, 1, V, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), psi, st);
+    }
+    // 4. Z = R_d^H Q_Y
+    RES_TRY(run_any(op, pl, k, Y, 1, (double*)Z, -1, st));
+    // 5. F_hat = Z R_Y Psi
+    launch_rmul(Z, 1, Fh, 1, op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), apsi, st);
+    HIP_TRY(hipGetLastError());
+  }
+  if (hist) {
+    // norm estimate of the last iteration from the Gram of the final F_hat
+    const int nsplit = nsplit_for(max_instance_len(op));
+    const int km = gram_km(k);
+    void *part, *r1, *r1i;
+    RES_TRY(ws_get(op, "gram_part", (size_t)nw * op->ninst * nsplit * km * (km + 1) / 2 * sizeof(cd), &part));
+    RES_TRY(ws_get(op, "qr_r1", mats, &r1));
+    RES_TRY(ws_get(op, "qr_r1i", mats, &r1i));
+    launch_gram(Fh, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, part, op->d_flag, st);
+    launch_chol(part, nsplit, k, nw, op->ninst, r1, r1i, nullptr, nullptr,
+                (double*)dh + (size_t)(iters - 1) * gcount * 2, op->d_flag, st);
+    HIP_TRY(hipMemcpyAsync(hist, dh, (size_t)iters * gcount * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipMemcpyAsync(gains, dg, gcount * sizeof(double), hipMemcpyDeviceToHost, st));
+  return resolvent_op_check(op, stream);
+}
+
+int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                             const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
+                             int32_t checkpoint_every, void* stream) {
+  (void)op; (void)grid; (void)run; (void)k; (void)f_hat; (void)g_hat; (void)f_grad; (void)mu_grad;
+  (void)checkpoint_every; (void)stream;
+  return fail(RES_ENOTSUP, "backward not implemented yet");
+}
+
+int resolvent_op_check(resolvent_op* op, void* stream) {
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  int flag = 0;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(&flag, op->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    int zero = 0;
+    HIP_TRY(hipMemcpy(op->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (flag & 2) return fail(RES_ENONFINITE, "rank-deficient or non-finite block in the per-frequency QR");
+    return fail(RES_ENONFINITE, "non-finite values in a result");
+  }
+  return RES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+"""GPU parity of the 1-D (three-point) path against the CPU oracle, element by element on seeded inputs.
+
+Tolerances: the FP64 path must match the oracle's explicit RK4 runs to within rounding (relative 1e-10 per
+frequency vector; the arithmetic differs only in order: fused step stencil vs four stages), gains to 1e-8
+(spec FP64 target); the mixed path to 1e-4 relative per gain (spec mixed target) and 1e-3 per
+response vector.
+"""
+import numpy as np
+import pytest
+
+from _helpers import gpu_tensor, mode_alignment, per_freq_relerr, relerr, say
+from oracle import iteration as O_it
+from oracle import operators as O_ops
+from oracle import stepping as O_st
+
+pytestmark = pytest.mark.gpu
+
+N_T, XL_T, XR_T = 32, -15.0, 15.0
+
+
+def gpu_gl(n, mu0, mu2, h, precision="fp64", xl=XL_T, xr=XR_T, **kw):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    lo, d, up = gl_coefficients(n, mu0, mu2, xl=xl, xr=xr)
+    return ResolventOp.tridiagonal(lo, d, up, h, precision=precision, **kw)
+
+
+def forcing(seed, nw, k, n):
+    g = np.random.default_rng(seed)
+    return g.standard_normal((nw, k, n)) + 1j * g.standard_normal((nw, k, n))
+
+
+def to_np(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("stride", [1, 100])
+def test_periodic_apply_matches_oracle(stride):
+    import torch
+    say("case: periodic apply tiny GL N=32 h=0.05 P=400 stride", stride)
+    h, P, nw, k, periods = 0.05, 400, 3, 2, 14
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F = forcing(1, nw, k, N_T)
+    ref = O_st.run(L, h, -0.3, dw, F, "periodic", periods=periods, stride=stride)
+    op = gpu_gl(N_T, 0.2, -0.01, h)
+    out = op.apply(gpu_tensor(F), op.grid(-0.3, dw, nw), op.run("periodic", periods=periods, stride=stride))
+    torch.cuda.synchronize()
+    err = per_freq_relerr(to_np(out), ref)
+    say("  per-frequency rel err", err)
+    assert err < 1e-10
+
+
+def test_transient_apply_matches_oracle():
+    import torch
+    say("case: transient apply tiny GL N=32 h=0.05 P=400 tail=3000")
+    h, P, nw, k, tail = 0.05, 400, 5, 1, 3000
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F = forcing(2, nw, k, N_T)
+    ref = O_st.run(L, h, -0.5, dw, F, "transient", tail=tail)
+    op = gpu_gl(N_T, 0.2, -0.01, h)
+    out = op.apply(gpu_tensor(F), op.grid(-0.5, dw, nw), op.run("transient", tail=tail))
+    torch.cuda.synchronize()
+    err = per_freq_relerr(to_np(out), ref)
+    say("  per-frequency rel err", err)
+    assert err < 1e-10
+
+
+def test_adjoint_apply_matches_oracle_and_identity():
+    import torch
+    say("case: adjoint apply tiny GL")
+    h, P, nw, k, periods = 0.05, 400, 4, 2, 14
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F = forcing(3, nw, k, N_T)
+    G = forcing(4, nw, k, N_T)
+    ref = O_st.run(L, h, 0.1, dw, G, "periodic", periods=periods, adjoint=True)
+    op = gpu_gl(N_T, 0.2, -0.01, h)
+    grid, run = op.grid(0.1, dw, nw), op.run("periodic", periods=periods)
+    z = to_np(op.adjoint_apply(gpu_tensor(G), grid, run))
+    u = to_np(op.apply(gpu_tensor(F), grid, run))
+    torch.cuda.synchronize()
+    assert per_freq_relerr(z, ref) < 1e-10
+    lhs = np.sum(np.conj(G) * u, axis=-1)
+    rhs = np.sum(np.conj(z) * F, axis=-1)
+    say("  adjoint identity max rel", np.abs(lhs - rhs).max() / np.abs(lhs).max())
+    assert np.abs(lhs - rhs).max() < 1e-11 * np.abs(lhs).max()
+
+
+def test_modes_match_oracle_block_iteration():
+    import torch
+    say("case: modes tiny GL k=3 periodic")
+    h, P, nw, k, periods, iters = 0.05, 400, 3, 3, 10, 4
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F0 = forcing(5, nw, k, N_T)
+    a, ad = O_it.stepped_applies(L, h, -0.2, dw, "periodic", periods=periods, stride=100)
+    g_ref, V_ref, U_ref, H_ref = O_it.block_power_iteration(a, ad, F0, iters)
+    op = gpu_gl(N_T, 0.2, -0.01, h)
+    g, V, U, H = op.modes(gpu_tensor(F0), op.grid(-0.2, dw, nw), op.run("periodic", periods=periods, stride=100),
+                          iters)
+    torch.cuda.synchronize()
+    say("  gains rel err", np.abs(g[0] / g_ref - 1).max())
+    assert np.abs(g[0] / g_ref - 1).max() < 1e-8
+    assert np.abs(H[:, 0] / H_ref - 1).max() < 1e-8
+    # leading modes agree up to a phase (suboptimals of an unconverged iteration are subspace-defined)
+    assert mode_alignment(to_np(V)[:, :1], V_ref[:, :1]) > 1 - 1e-8
+    assert mode_alignment(to_np(U)[:, :1], U_ref[:, :1]) > 1 - 1e-8
+
+
+def test_batched_instances_match_per_instance_oracle():
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_batched_coefficients
+    say("case: batched 3 instances N=(24,40,17)")
+    inst = [(24, 0.2, -0.01), (40, 0.15, -0.02), (17, 0.12, -0.012)]  # all stable (max Re eig < -0.08)
+    h, P, nw, k, periods = 0.05, 400, 3, 2, 20
+    dw = 2 * np.pi / (P * h)
+    lo, d, up, off = gl_batched_coefficients(inst, xl=XL_T, xr=XR_T)
+    op = ResolventOp.tridiagonal(lo, d, up, h, offsets=off)
+    F = forcing(6, nw, k, int(off[-1]))
+    out = to_np(op.apply(gpu_tensor(F), op.grid(0.0, dw, nw), op.run("periodic", periods=periods, stride=50)))
+    g, _, _, _ = op.modes(gpu_tensor(F), op.grid(0.0, dw, nw), op.run("periodic", periods=periods, stride=50), 3,
+                          want_modes=False, want_hist=False)
+    torch.cuda.synchronize()
+    for m, (n, mu0, mu2) in enumerate(inst):
+        L, _ = O_ops.gl_operator(n, mu0, mu2, xl=XL_T, xr=XR_T)
+        sl = slice(int(off[m]), int(off[m + 1]))
+        ref = O_st.run(L, h, 0.0, dw, F[:, :, sl], "periodic", periods=periods, stride=50)
+        assert per_freq_relerr(out[:, :, sl], ref) < 1e-10
+        a, ad = O_it.stepped_applies(L, h, 0.0, dw, "periodic", periods=periods, stride=50)
+        g_ref = O_it.block_power_iteration(a, ad, F[:, :, sl], 3)[0]
+        say("  instance", m, "gain err", np.abs(g[m] / g_ref - 1).max())
+        assert np.abs(g[m] / g_ref - 1).max() < 1e-8
+
+
+def test_mixed_precision_error_vs_fp64_oracle():
+    import torch
+    say("case: mixed precision tiny GL")
+    h, P, nw, k, periods, iters = 0.05, 400, 3, 2, 10, 4
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F0 = forcing(7, nw, k, N_T)
+    ref = O_st.run(L, h, -0.2, dw, F0, "periodic", periods=periods, stride=100)
+    a, ad = O_it.stepped_applies(L, h, -0.2, dw, "periodic", periods=periods, stride=100)
+    g_ref = O_it.block_power_iteration(a, ad, F0, iters)[0]
+    op = gpu_gl(N_T, 0.2, -0.01, h, precision="mixed")
+    grid, run = op.grid(-0.2, dw, nw), op.run("periodic", periods=periods, stride=100)
+    out = to_np(op.apply(gpu_tensor(F0, torch.complex64), grid, run))
+    g, _, _, _ = op.modes(gpu_tensor(F0, torch.complex64), grid, run, iters)
+    torch.cuda.synchronize()
+    say("  mixed apply err", per_freq_relerr(out, ref), "gain err", np.abs(g[0] / g_ref - 1).max())
+    assert per_freq_relerr(out, ref) < 1e-3
+    assert np.abs(g[0] / g_ref - 1).max() < 1e-4
+
+
+def test_single_frequency_single_column_edge():
+    import torch
+    say("case: n_omega=1, k=1, N=5")
+    h, P = 0.05, 400
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(5, 0.2, -0.01, xl=-3.0, xr=3.0)
+    F = forcing(8, 1, 1, 5)
+    ref = O_st.run(L, h, 0.7, dw, F, "periodic", periods=6)
+    op = gpu_gl(5, 0.2, -0.01, h, xl=-3.0, xr=3.0)
+    out = to_np(op.apply(gpu_tensor(F), op.grid(0.7, dw, 1), op.run("periodic", periods=6)))
+    torch.cuda.synchronize()
+    assert per_freq_relerr(out, ref) < 1e-10
+
+
+def test_error_paths():
+    from paper_2008_10904_amd import ResolventError
+    from paper_2008_10904_amd import _lib as L
+    say("case: error paths (grid, stride)")
+    op = gpu_gl(N_T, 0.2, -0.01, 0.05)
+    import torch
+    F = gpu_tensor(forcing(9, 3, 1, N_T))
+    with pytest.raises(ResolventError) as e:
+        op.apply(F, op.grid(0.0, 0.3123, 3), op.run("periodic", periods=2))
+    assert e.value.code == L.RES_EGRID
+    dw = 2 * np.pi / (400 * 0.05)
+    with pytest.raises(ResolventError) as e:
+        op.apply(F, op.grid(0.0, dw, 3), op.run("periodic", periods=2, stride=7))
+    assert e.value.code == L.RES_EGRID
+    torch.cuda.synchronize()
+
+
+def test_decay_probe_classifies_operators():
+    from paper_2008_10904_amd import ResolventError
+    from paper_2008_10904_amd import _lib as L
+    say("case: decay probe stable / unstable (literal mu0=0.38 at N=200) / RK4-unstable step")
+    op = gpu_gl(N_T, 0.2, -0.01, 0.05, probe=True, probe_tmax=2000.0)
+    assert 0 < op.decay_time < 2000.0
+    with pytest.raises(ResolventError) as e:
+        gpu_gl(200, 0.38, -0.01, 0.01, xl=-50.0, xr=50.0, probe=True, probe_tmax=3000.0)
+    assert e.value.code == L.RES_EUNSTABLE
+    with pytest.raises(ResolventError) as e:
+        gpu_gl(2000, 0.38, -0.01, 0.005, xl=-50.0, xr=50.0, probe=True, probe_tmax=50.0)
+    assert e.value.code == L.RES_ESTEP
