@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Resolvent sweeps/s of the time-stepping resolvent method on one MI355X.
+
+Workload: linearised Ginzburg-Landau, N = 2000 unknowns, k = 4 forcing columns per frequency, 256 frequencies in
+[-3, 3], steady-state-response (periodic) method with 10 forcing periods per run (the last one projected every
+256 steps), RK4 with h = 0.001 (P = 267,008 steps per period), complex128.  One benchmark step is one iteration
+of the block power iteration: a direct run, an adjoint run, two per-frequency QR factorisations and the k x k
+SVDs.  Sweeps/s = N * k * n_omega * (time steps of the direct and adjoint runs) / seconds.
+
+The same step is also timed in the mixed form (FP32 stepping and phase GEMMs, FP64 accumulation/QR/gains), with
+the largest relative gain difference to the FP64 GPU run reported beside it.  The CPU baseline is the FP64
+oracle marching the same operator and forcing for a bounded number of steps (the oracle is slow; its rate is
+scaled to the same unit).  Inputs are synthetic and seeded; no data set is involved.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9  # CUs x SIMDs x FP64 lanes x (FMA = 2 flop) x clock = 78.6 TFLOP/s
+STEP_FLOP_PER_UNKNOWN = 9 * 8 + 8  # nine complex multiply-adds of the step stencil + the forcing term
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def build_op(cfg, precision):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    lo, d, up = gl_coefficients(cfg["N"], cfg["mu0"], cfg["mu2"])
+    return ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=precision)
+
+
+def time_steps(op, f0, grid, run, K, W):
+    import torch
+    from paper_2008_10904_amd import _lib as L
+    for _ in range(W):
+        g, _, _, _ = op.modes(f0, grid, run, 1, want_modes=False, want_hist=False)
+    torch.cuda.synchronize()
+    op.set_timing(True)
+    for kind in range(4):
+        op.timing(kind)  # reset the counters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g, _, _, _ = op.modes(f0, grid, run, 1, want_modes=False, want_hist=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
+                                                   ("synthesis", L.RES_TIMING_SYNTHESIS),
+                                                   ("projection", L.RES_TIMING_PROJECTION),
+                                                   ("qr", L.RES_TIMING_QR))}
+    op.set_timing(False)
+    return (t1 - t0) / K, g, kt
+
+
+def cpu_baseline(cfg, w0, dw, F, seconds):
+    """The oracle's explicit RK4 march of the same operator and forcing, timed for a bounded sample of steps."""
+    import numpy as np
+    from oracle import operators as O_ops
+    L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
+    om = w0 + dw * np.arange(cfg["n_omega"])
+    from oracle.stepping import march
+    # calibrate on a few steps, then run a sample sized to `seconds`
+    t = time.perf_counter()
+    march(L, cfg["h"], om, F, 5, lambda s: True, lambda s: False, 1.0)
+    per = (time.perf_counter() - t) / 5
+    n = max(10, int(seconds / max(per, 1e-6)))
+    t = time.perf_counter()
+    march(L, cfg["h"], om, F, n, lambda s: True, lambda s: False, 1.0)
+    dt = time.perf_counter() - t
+    sweeps = cfg["N"] * cfg["k"] * cfg["n_omega"] * n / dt
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or str(os.cpu_count())
+    return dict(value=sweeps, unit="resolvent sweeps/s", cores=int(threads), kind="oracle",
+                sample="%d forced RK4 steps of the N=2000, k=4, 256-frequency periodic run (FP64 NumPy/SciPy), "
+                       "%.1f s" % (n, dt))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd.operators import snap_grid
+
+    cfg = W.GL_PERIODIC
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+    steps_per_run = cfg["periods"] * P
+    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
+    sweeps_per_step = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
+
+    op = build_op(cfg, "fp64")
+    grid = op.grid(w0, dw, cfg["n_omega"])
+    run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+    f64 = torch.from_numpy(F).cuda()
+    dt, gains64, kt = time_steps(op, f64, grid, run, args.steps, args.warmup)
+    stepper_ms, stepper_n = kt["stepper"]
+    avg_launch_s = stepper_ms / 1e3 / max(stepper_n, 1)
+    steps_per_launch = 2 * steps_per_run * args.steps / max(stepper_n, 1)
+    flop_per_launch = STEP_FLOP_PER_UNKNOWN * cfg["N"] * cfg["k"] * steps_per_launch
+    achieved = flop_per_launch / avg_launch_s / 1e12
+    peak = FP64_VECTOR_PEAK / 1e12
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)",
+        "value": sweeps_per_step / dt,
+        "unit": "resolvent sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": cfg["N"], "k": cfg["k"], "n_omega": cfg["n_omega"],
+                   "omega0": w0, "domega": dw, "P": P, "h": cfg["h"], "method": "periodic",
+                   "periods": cfg["periods"], "stride": cfg["stride"], "step": "one block-power iteration",
+                   "time_steps_per_step": 2 * steps_per_run},
+        "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
+                     "steps_per_launch": steps_per_launch},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+    }
+    del op, f64
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        opm = build_op(cfg, "mixed")
+        f32 = torch.from_numpy(F).to(torch.complex64).cuda()
+        dtm, gainsm, ktm = time_steps(opm, f32, grid, run, args.steps, args.warmup)
+        out["mixed"] = {"value": sweeps_per_step / dtm, "ms_per_step": dtm * 1e3, "dtype": "f32 step/GEMM, f64 acc",
+                        "max_rel_gain_diff_vs_fp64": float(np.abs(gainsm / gains64 - 1).max()),
+                        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()}}
+        del opm, f32
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, w0, dw, F, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

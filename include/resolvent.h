@@ -165,6 +165,14 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);
 
+/* Opt-in kernel timing: while enabled, the library records HIP events on the caller's stream around each of its
+ * kernel launches.  resolvent_op_get_timing synchronises the stream, returns the summed device time (ms) and
+ * the number of launches of one kernel class since the last query, and resets that class.  Classes:
+ * 0 = time stepper, 1 = forcing synthesis GEMM, 2 = Fourier projection GEMM, 3 = per-frequency QR/SVD. */
+enum { RES_TIMING_STEPPER = 0, RES_TIMING_SYNTHESIS = 1, RES_TIMING_PROJECTION = 2, RES_TIMING_QR = 3 };
+int resolvent_op_set_timing(resolvent_op* op, int32_t enable);
+int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, int64_t* launches);
+
 /* Synchronise `stream` and report RES_ENONFINITE if any result produced since the last check held NaN/Inf. */
 int resolvent_op_check(resolvent_op* op, void* stream);
 

@@ -11,6 +11,7 @@ RES_OK, RES_EINVAL, RES_EGRID, RES_ESTEP, RES_EUNSTABLE, RES_ENONFINITE, RES_ENO
 RES_OP_TRIDIAG, RES_OP_ADR2D, RES_OP_ADR3D3C = 1, 2, 3
 RES_FP64, RES_MIXED = 0, 1
 RES_TRANSIENT, RES_PERIODIC = 0, 1
+RES_TIMING_STEPPER, RES_TIMING_SYNTHESIS, RES_TIMING_PROJECTION, RES_TIMING_QR = 0, 1, 2, 3
 
 _dp = POINTER(c_double)
 
@@ -47,6 +48,8 @@ SIGNATURES = {
     "resolvent_apply_backward": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                            c_void_p, _dp, c_int32, c_void_p]),
     "resolvent_op_check": (c_int32, [c_void_p, c_void_p]),
+    "resolvent_op_set_timing": (c_int32, [c_void_p, c_int32]),
+    "resolvent_op_get_timing": (c_int32, [c_void_p, c_int32, _dp, POINTER(c_int64)]),
     "resolvent_strerror": (ctypes.c_char_p, [c_int32]),
     "resolvent_last_error": (ctypes.c_char_p, []),
 }

@@ -144,5 +144,15 @@ class ResolventOp:
         d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
         check(self._lib.resolvent_op_set_diagonal(self._h, _dptr(d), 0, self._stream_ptr()))
 
+    def set_timing(self, enable=True):
+        check(self._lib.resolvent_op_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self, kind):
+        """(total device ms, launches) of a kernel class since the last query (synchronises the stream)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(self._lib.resolvent_op_get_timing(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def check(self):
         check(self._lib.resolvent_op_check(self._h, self._stream_ptr()))

@@ -41,6 +41,11 @@ template <typename R> __host__ __device__ __forceinline__ cx<R> cfma_conj(cx<R> 
 }
 template <typename R> __host__ __device__ __forceinline__ cx<R> cconj(cx<R> a) { return mk<R>(a.re, -a.im); }
 
+// Component-wise select (a ternary on the whole struct can be lowered through a stack slot).
+template <typename R> __host__ __device__ __forceinline__ cx<R> csel(bool c, cx<R> a, cx<R> b) {
+  return mk<R>(c ? a.re : b.re, c ? a.im : b.im);
+}
+
 template <typename To, typename From> __host__ __device__ __forceinline__ cx<To> ccast(cx<From> a) {
   return mk<To>((To)a.re, (To)a.im);
 }
@@ -58,13 +63,26 @@ template <> __device__ __forceinline__ cx<float> load_nt<float>(const cx<float>*
   return mk<float>(t.x, t.y);
 }
 
-// One contiguous run of unknowns marched by one workgroup of the 1-D stepper: column `col`, unknowns
-// [dof0, dof0 + ndof) of that column.  Every instance lies entirely inside one segment.
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not wait for outstanding global
+// loads, so loads issued ahead of time (prefetched forcing rows) stay in flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Work of one workgroup of the 1-D stepper: column `col`, a region [dof0, dof0 + ndof) of that column that it
+// marches, and inside it the owned unknowns [dof0 + own0, dof0 + own0 + nown) whose values it publishes.  Outside
+// an instance the step stencil has no couplings, so regions may span instances; when the region is cut inside
+// an instance, the cut must lie at least 4 unknowns per step away from the owned range (the step stencil has
+// radius 4), so that the owned values are exact after the launch's steps.
 struct Seg1D {
   int32_t col;
-  int32_t pad;
+  int32_t own0;
   int64_t dof0;
-  int64_t ndof;
+  int32_t ndof;
+  int32_t nown;
+  int32_t left, right;  // workgroups owning the halo on either side (-1: none); used by the persistent stepper
 };
 
 // Radius of the one-step propagator stencil of a three-point operator: P(Z) = sum_{m<=4} Z^m/m! couples

@@ -9,22 +9,33 @@
 namespace res {
 
 // ---- 1-D stepper --------------------------------------------------------------------------------------
-constexpr int kStep1DConfigs = 10;
+constexpr int kStep1DConfigs = 16;
 struct Step1DArgs {
   int fp64;
   int cfg;                 // index into the (threads, unknowns per thread, prefetch depth) table
   const Seg1D* segs;
   int64_t nseg;
   const void* band;        // [N][9] complex (working precision)
-  void* state;             // [ncol][N]
+  const void* state_in;    // [ncol][N]
+  void* state_out;         // [ncol][N] (may equal state_in when every region is owned entirely)
   int64_t N, row_len;      // row_len = ncol * N
   int64_t n_steps;
   const void* frc;         // forcing rows or null
   int64_t frc_row0, frc_period;
   double phi_re, phi_im;
-  void* snap;              // snapshot rows or null
-  int64_t snap_first, snap_stride, snap_count, snap_row0;
+  void* snap;              // snapshot rows (length snap_ld >= row_len + 1) or null
+  int64_t snap_ld, snap_first, snap_stride, snap_count, snap_row0;
+  // persistent variant: blocks of `block` steps with neighbour exchange through xbuf (2 rows) and flags
+  int persist;
+  void* xbuf;
+  uint32_t* flags;
+  uint32_t epoch;
+  int64_t block;
+  uint64_t spin_ns;
+  int* err;
 };
+int step1d_coresident(int fp64, int cfg, int device);
+int step1d_prefetch(int cfg);
 int step1d_capacity(int cfg);
 int launch_step1d(const Step1DArgs& a, hipStream_t st);
 int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
@@ -57,7 +68,8 @@ struct PhaseGemmArgs {
   int sigma;               // +1 direct, -1 adjoint
   double w0h;              // omega0 * h
   int64_t s0, stride;      // synthesis: first step; projection: step of sample 0 and sample spacing
-  const void* bmat;        // [K][Ncols]
+  const void* bmat;        // [K][ldb] (ldb >= Ncols; 0 means Ncols)
+  int64_t ldb;
   void* out;               // synthesis: [M][Ncols] working precision; projection: FP64 accumulator [M][Ncols]
   double scale;            // projection scale
   int64_t k_per_split;     // K entries per split (projection), >= K for no split

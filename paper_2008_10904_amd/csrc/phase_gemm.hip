@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   const cx<R>* __restrict__ btab = (const cx<R>*)a.btab;
   const cx<R>* __restrict__ B = (const cx<R>*)a.bmat;
   const double sig = (double)a.sigma;
+  const int64_t ldb = a.ldb > 0 ? a.ldb : a.Ncols;
 
   // K range of this split
   const int64_t kb = (int64_t)blockIdx.z * a.k_per_split;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
       for (int q = 0; q < 4; ++q) {
         const int64_t n = n0 + nc + q;
         cx<R> v = mk<R>(0, 0);
-        if (kk < ke && n < a.Ncols) v = B[kk * a.Ncols + n];
+        if (kk < ke && n < a.Ncols) v = B[kk * ldb + n];
         Bs[0][kr][nc + q] = v.re;
         Bs[1][kr][nc + q] = v.im;
       }

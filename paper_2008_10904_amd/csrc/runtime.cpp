@@ -92,9 +92,20 @@ struct resolvent_op {
   std::vector<cd> zl, zd, zu;  // Z = h L (instance boundaries zeroed)
   void* d_tri[2] = {nullptr, nullptr};   // FP64 [N][3] of Z (0) and Z^H (1)
   void* d_band[2] = {nullptr, nullptr};  // working precision [N][9] of P(Z), P(Z^H)
-  std::vector<Seg1D> segs;               // segments of one column
-  std::vector<Seg1D> segs_k;             // segments of all k columns of the current run (upload source)
-  int step_cfg = -1;
+  std::vector<Seg1D> segs;               // workgroup regions of one column
+  std::vector<Seg1D> segs_k;             // regions of all k columns of the current run (upload source)
+  int step_cfg = -1;                     // stepper kernel configuration
+  int64_t step_block = 0;                // steps per launch when regions carry halos (0: unlimited)
+  int64_t step_chunk = 0;                // owned unknowns per workgroup (0: whole column in one workgroup)
+  int cur_state = 0;                     // which of the two state buffers holds the current state
+  bool step_persist = false;             // one cooperative launch per march, neighbour exchange in-kernel
+  uint32_t* d_flags = nullptr;           // per-workgroup block counters of the persistent stepper
+  size_t nflags = 0;
+  uint32_t flag_epoch = 1;               // flags only grow; each launch starts above every value written
+  // opt-in timing: event pairs per kernel class
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[4];
+  const void* march_band = nullptr;      // step stencil used by march_1d (L or L^H)
   // workspace and caches
   std::map<std::string, DevBuf> ws;
   std::map<int64_t, void*> btab;
@@ -122,6 +133,27 @@ int ws_get(resolvent_op* op, const std::string& name, size_t bytes, void** out) 
   *out = b.p;
   return RES_OK;
 }
+
+// Opt-in timing of one launch (or launch group) of kernel class `kind`.
+struct TimedLaunch {
+  resolvent_op* op;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(resolvent_op* o, int k, hipStream_t s) : op(o), kind(k), st(s) {
+    if (!op->timing) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, st);
+  }
+  ~TimedLaunch() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    op->tev[kind].push_back({a, b});
+  }
+};
 
 #define RES_TRY(expr)          \
   do {                         \
@@ -190,40 +222,76 @@ int build_1d_stencils(resolvent_op* op) {
   return RES_OK;
 }
 
-// Segments of one column: consecutive whole instances packed greedily up to the stepper capacity.
-int plan_1d_segments(resolvent_op* op) {
-  int64_t maxlen = 0;
-  for (int m = 0; m < op->ninst; ++m) maxlen = std::max(maxlen, op->off[m + 1] - op->off[m]);
-  const int64_t cap_max = 2048;
-  if (maxlen > cap_max)
-    return fail(RES_ENOTSUP, "1-D instances longer than " + std::to_string(cap_max) + " unknowns are not supported");
-  // smallest capacity class holding the largest instance
-  int64_t cap = 64;
-  while (cap < maxlen) cap *= 2;
-  op->segs.clear();
-  Seg1D cur{0, 0, op->off[0], 0};
-  for (int m = 0; m < op->ninst; ++m) {
-    const int64_t len = op->off[m + 1] - op->off[m];
-    if (cur.ndof + len > cap && cur.ndof > 0) {
-      op->segs.push_back(cur);
-      cur = Seg1D{0, 0, op->off[m], 0};
-    }
-    cur.ndof += len;
+// Workgroup regions of one column.  chunk == 0: the whole column in one workgroup (no halo, any number of
+// steps per launch).  Otherwise owned chunks of `chunk` unknowns with a halo of 4 * block unknowns on each side
+// (the step stencil's radius times the steps per launch), clipped to the column.
+void plan_1d_regions(resolvent_op* op, int64_t chunk, int64_t block, std::vector<Seg1D>* out) {
+  out->clear();
+  const int64_t n = op->N;
+  if (chunk <= 0 || chunk >= n) {
+    out->push_back(Seg1D{0, 0, 0, (int32_t)n, (int32_t)n, -1, -1});
+    return;
   }
-  if (cur.ndof > 0) op->segs.push_back(cur);
-  int64_t seglen = 0;
-  for (auto& s : op->segs) seglen = std::max(seglen, s.ndof);
-  // default configuration per capacity class (overridable for tuning)
+  const int64_t halo = (int64_t)kBandRadius * block;
+  for (int64_t o0 = 0; o0 < n; o0 += chunk) {
+    const int64_t o1 = std::min(n, o0 + chunk);
+    const int64_t r0 = std::max<int64_t>(0, o0 - halo), r1 = std::min(n, o1 + halo);
+    const int32_t i = (int32_t)out->size();
+    out->push_back(Seg1D{0, (int32_t)(o0 - r0), r0, (int32_t)(r1 - r0), (int32_t)(o1 - o0), i - 1, -1});
+  }
+  out->front().left = -1;
+  for (size_t i = 0; i + 1 < out->size(); ++i) (*out)[i].right = (int32_t)(i + 1);
+}
+
+int smallest_cfg(int64_t len) {
+  static const int order[] = {0, 1, 2, 3, 4, 6};  // one default per capacity 64 .. 2048
+  for (int c : order)
+    if (step1d_capacity(c) >= len) return c;
+  return -1;
+}
+
+// Default stepper plan: a column of up to 256 unknowns in one workgroup; longer columns in owned chunks of 128
+// with a halo of 64 (16 steps per block), marched by one persistent cooperative launch with in-kernel neighbour
+// exchange when the grid is co-resident, else by relaunches every 16 steps.
+// RESOLVENT_STEP1D="cfg,chunk,block[,persist]" overrides it.
+int plan_1d_default(resolvent_op* op) {
   int cfg;
-  if (seglen <= 64) cfg = 0;
-  else if (seglen <= 128) cfg = 1;
-  else if (seglen <= 256) cfg = 2;
-  else if (seglen <= 512) cfg = 3;
-  else if (seglen <= 1024) cfg = 8;
-  else cfg = 6;
-  const long forced = env_long("RESOLVENT_STEP1D_CFG", -1);
-  if (forced >= 0 && forced < kStep1DConfigs && step1d_capacity((int)forced) >= seglen) cfg = (int)forced;
+  int64_t chunk = 0, block = 0;
+  int persist = 1;
+  if (op->N <= 256) {
+    cfg = smallest_cfg(op->N);
+  } else {
+    block = 16;
+    chunk = 128;
+    cfg = 12;  // 256 threads x 1 unknown, prefetch 8
+  }
+  if (const char* e = std::getenv("RESOLVENT_STEP1D")) {
+    int c = -1, pe = 1;
+    long ch = 0, bl = 0;
+    const int got = std::sscanf(e, "%d,%ld,%ld,%d", &c, &ch, &bl, &pe);
+    if (got >= 3 && c >= 0 && c < kStep1DConfigs) {
+      cfg = c;
+      chunk = ch;
+      block = bl;
+      persist = got >= 4 ? pe : 1;
+    }
+  }
+  std::vector<Seg1D> regs;
+  plan_1d_regions(op, chunk, block, &regs);
+  int64_t maxlen = 0;
+  for (auto& r : regs) maxlen = std::max<int64_t>(maxlen, r.ndof);
+  if (step1d_capacity(cfg) < maxlen) {
+    const int c = smallest_cfg(maxlen);
+    if (c < 0) return fail(RES_ENOTSUP, "stepper region of " + std::to_string(maxlen) + " unknowns is too long");
+    cfg = c;
+  }
+  op->segs = regs;
   op->step_cfg = cfg;
+  op->step_chunk = (chunk > 0 && chunk < op->N) ? chunk : 0;
+  op->step_block = op->step_chunk ? block : 0;
+  // persistent exchange needs the halo inside the immediate neighbours and blocks made of whole prefetch rounds
+  op->step_persist = persist && op->step_chunk > 0 && (int64_t)kBandRadius * block <= chunk &&
+                     block % step1d_prefetch(cfg) == 0;
   return RES_OK;
 }
 
@@ -318,9 +386,9 @@ int64_t max_instance_len(const resolvent_op* op) {
 void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStream_t st);
 
 int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* btab, const void* snap,
-                     int64_t m_first, int64_t rows, double* acc, hipStream_t st) {
+                     int64_t snap_ld, int64_t m_first, int64_t rows, double* acc, hipStream_t st) {
   if (rows <= 0) return RES_OK;
-  trace_norm("snapshots", snap, rows * (int64_t)k * op->N, op->fp64(), st);
+  trace_norm("snapshots", snap, rows * snap_ld, op->fp64(), st);
   const int64_t ncols = (int64_t)k * op->N;
   PhaseGemmArgs a{};
   a.mode = 1;
@@ -334,6 +402,7 @@ int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* b
   a.s0 = pl.pfirst + m_first * pl.pstride;
   a.stride = pl.pstride;
   a.bmat = snap;
+  a.ldb = snap_ld;
   a.out = acc;
   a.scale = pl.scale;
   // split K so that the grid has enough workgroups
@@ -344,6 +413,7 @@ int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* b
   const int64_t kps = ((rows + nsplit - 1) / nsplit + 15) / 16 * 16;
   nsplit = (rows + kps - 1) / kps;
   a.k_per_split = kps;
+  TimedLaunch tl(op, RES_TIMING_PROJECTION, st);
   if (nsplit > 1) {
     void* part = nullptr;
     RES_TRY(ws_get(op, "proj_partial", (size_t)nsplit * pl.nw * ncols * sizeof(cd), &part));
@@ -382,6 +452,117 @@ int zero_device(void* p, size_t bytes, hipStream_t st) {
   return RES_OK;
 }
 
+struct ForceSpec {
+  const void* frc = nullptr;   // forcing rows or null (unforced)
+  int64_t row0 = 0, period = 0;
+  cd phi = cd(1, 0);
+};
+struct SnapSpec {
+  void* snap = nullptr;        // snapshot rows or null
+  int64_t ld = 0, first = 0, stride = 1, count = 0, row0 = 0;
+};
+
+// March n steps of all k columns from the current state buffer.  With halo regions the march is cut into
+// launches of op->step_block steps, the state ping-ponging between two buffers; otherwise one launch.
+int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const SnapSpec& ss, const void* dsegs,
+             int64_t nseg, hipStream_t st) {
+  const int64_t ncols = (int64_t)k * op->N;
+  void* sb[2];
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * op->wsize(), &sb[0]));
+  RES_TRY(ws_get(op, "state1", (size_t)ncols * op->wsize(), &sb[1]));
+  const bool halo = op->step_block > 0;
+  bool persist = op->step_persist;
+  void* xbuf = nullptr;
+  if (persist) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (step1d_coresident(op->fp64(), op->step_cfg, dev) < nseg) persist = false;
+  }
+  if (persist) {
+    RES_TRY(ws_get(op, "xbuf", (size_t)2 * ncols * op->wsize(), &xbuf));
+    if (op->nflags < (size_t)nseg) {
+      if (op->d_flags) HIP_TRY(hipFree(op->d_flags));
+      HIP_TRY(hipMalloc((void**)&op->d_flags, (size_t)nseg * sizeof(uint32_t)));
+      HIP_TRY(hipMemsetAsync(op->d_flags, 0, (size_t)nseg * sizeof(uint32_t), st));
+      op->nflags = (size_t)nseg;
+      op->flag_epoch = 1;
+    }
+    const int64_t nblk = (n + op->step_block - 1) / op->step_block;
+    if ((uint64_t)op->flag_epoch + (uint64_t)nblk + 2 >= 0xF0000000ull) {
+      HIP_TRY(hipMemsetAsync(op->d_flags, 0, op->nflags * sizeof(uint32_t), st));
+      op->flag_epoch = 1;
+    }
+  }
+  const int64_t blk = (halo && !persist) ? op->step_block : n;
+  for (int64_t b0 = 0; b0 < n; b0 += blk) {
+    const int64_t nb = std::min(blk, n - b0);
+    Step1DArgs a{};
+    a.fp64 = op->fp64();
+    a.cfg = op->step_cfg;
+    a.segs = (const Seg1D*)dsegs;
+    a.nseg = nseg;
+    a.band = op->march_band;
+    a.state_in = sb[op->cur_state];
+    a.state_out = (halo && !persist) ? sb[1 - op->cur_state] : sb[op->cur_state];
+    a.N = op->N;
+    a.row_len = ncols;
+    a.n_steps = nb;
+    a.frc = fs.frc;
+    a.frc_row0 = fs.row0 + b0;
+    a.frc_period = fs.period;
+    a.phi_re = fs.phi.real();
+    a.phi_im = fs.phi.imag();
+    if (ss.snap != nullptr && ss.count > 0) {
+      // samples m with first + m*stride in [b0, b0 + nb)
+      const int64_t mlo = b0 <= ss.first ? 0 : (b0 - ss.first + ss.stride - 1) / ss.stride;
+      const int64_t last = b0 + nb - 1;
+      const int64_t mhi = last < ss.first ? 0 : std::min(ss.count, (last - ss.first) / ss.stride + 1);
+      if (mhi > mlo) {
+        a.snap = ss.snap;
+        a.snap_ld = ss.ld;
+        a.snap_first = ss.first + mlo * ss.stride - b0;
+        a.snap_stride = ss.stride;
+        a.snap_count = mhi - mlo;
+        a.snap_row0 = ss.row0 + mlo;
+      }
+    }
+    a.persist = persist ? 1 : 0;
+    a.xbuf = xbuf;
+    a.flags = op->d_flags;
+    a.epoch = op->flag_epoch;
+    a.block = persist ? op->step_block : nb;
+    a.spin_ns = 2000000000ull;
+    a.err = op->d_flag;
+    int rc;
+    {
+      TimedLaunch tl(op, RES_TIMING_STEPPER, st);
+      rc = launch_step1d(a, st);
+    }
+    if (rc) return fail(RES_EHIP, "stepper launch failed (" + std::to_string(rc) + ")");
+    if (persist) op->flag_epoch += (uint32_t)((nb + op->step_block - 1) / op->step_block) + 1;
+    if (halo && !persist) op->cur_state = 1 - op->cur_state;
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStream_t st) {
+  std::vector<Seg1D>& segs = op->segs_k;  // kept in the handle: the upload is asynchronous
+  segs.clear();
+  const int32_t g = (int32_t)op->segs.size();
+  for (int c = 0; c < k; ++c)
+    for (auto sg : op->segs) {
+      sg.col = c;
+      if (sg.left >= 0) sg.left += c * g;
+      if (sg.right >= 0) sg.right += c * g;
+      segs.push_back(sg);
+    }
+  RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), dsegs));
+  HIP_TRY(hipMemcpyAsync(*dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
+  *nseg = (int64_t)segs.size();
+  return RES_OK;
+}
+
 // One time-marched run: acc[j][c][:] = R_d(sigma w_j)-run of in[j][c][:], with L (sigma = +1) or L^H (sigma = -1).
 // `in` is [nw][k][N] complex of dtype in_fp64; acc is FP64 [nw][k][N] and is overwritten.
 int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
@@ -391,11 +572,10 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   const int nw = pl.nw;
   const int s = sigma > 0 ? 0 : 1;
   const size_t ws = op->wsize();
-  void *y1, *y2, *G, *state, *btab;
+  void *y1, *y2, *G, *btab;
   RES_TRY(ws_get(op, "horner_a", (size_t)nw * ncols * sizeof(cd), &y1));
   RES_TRY(ws_get(op, "horner_b", (size_t)nw * ncols * sizeof(cd), &y2));
   RES_TRY(ws_get(op, "G", (size_t)nw * ncols * ws, &G));
-  RES_TRY(ws_get(op, "state", (size_t)ncols * ws, &state));
   RES_TRY(phase_table(op, pl.P, &btab));
   // G_j = h Q_j(Z) F_j  (three Horner passes)
   const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
@@ -405,10 +585,15 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
   HIP_TRY(hipGetLastError());
   trace_norm("run input", in, (int64_t)nw * ncols, in_fp64, st);
-  trace_norm("horner pass 0", y1, (int64_t)nw * ncols, 1, st);
   trace_norm("G = hQ(Z) F", G, (int64_t)nw * ncols, op->fp64(), st);
-  RES_TRY(zero_device(state, (size_t)ncols * ws, st));
+  void* st0;
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
+  RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &st0));
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
+  op->cur_state = 0;
+  RES_TRY(zero_device(st0, (size_t)ncols * ws, st));
   RES_TRY(zero_device(acc, (size_t)nw * ncols * sizeof(cd), st));
+  op->march_band = op->d_band[s];
 
   // forcing rows: whole first period as a table when it fits, else tiles
   const double table_budget = env_double("RESOLVENT_TABLE_BUDGET_GB", 48.0) * 1073741824.0;
@@ -416,134 +601,99 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   const bool table_mode = (double)table_rows * (double)ncols * (double)ws <= table_budget;
   int64_t tile_rows = 0;
   void* frc = nullptr;
+  PhaseGemmArgs syn{};
+  syn.mode = 0;
+  syn.Ncols = ncols;
+  syn.K = nw;
+  syn.btab = btab;
+  syn.P = pl.P;
+  syn.sigma = sigma;
+  syn.w0h = pl.w0 * op->h;
+  syn.stride = 1;
+  syn.bmat = G;
+  syn.ldb = ncols;
+  syn.k_per_split = nw;
   if (table_mode) {
     RES_TRY(ws_get(op, "forcing", (size_t)table_rows * ncols * ws, &frc));
-    PhaseGemmArgs a{};
-    a.mode = 0;
-    a.M = table_rows;
-    a.Ncols = ncols;
-    a.K = nw;
-    a.btab = btab;
-    a.P = pl.P;
-    a.sigma = sigma;
-    a.w0h = pl.w0 * op->h;
-    a.s0 = 0;
-    a.stride = 1;
-    a.bmat = G;
-    a.out = frc;
-    a.k_per_split = nw;
-    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
+    syn.M = table_rows;
+    syn.s0 = 0;
+    syn.out = frc;
+    TimedLaunch tl(op, RES_TIMING_SYNTHESIS, st);
+    if (launch_phase_gemm(syn, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
     HIP_TRY(hipGetLastError());
     trace_norm("forcing table", frc, table_rows * ncols, op->fp64(), st);
   } else {
     const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
     tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));
-    RES_TRY(ws_get(op, "forcing", (size_t)tile_rows * ncols * ws, &frc));
+    RES_TRY(ws_get(op, "forcing", (size_t)(tile_rows + 16) * ncols * ws, &frc));  // + prefetch padding rows
   }
-  // snapshot buffer
+  // snapshot rows: ncols values and one scratch slot
+  const int64_t snap_ld = ncols + 1;
   const double snap_budget = env_double("RESOLVENT_SNAP_BUDGET_GB", 2.0) * 1073741824.0;
-  int64_t snap_cap = std::max<int64_t>(64, (int64_t)(snap_budget / ((double)ncols * ws)));
+  int64_t snap_cap = std::max<int64_t>(64, (int64_t)(snap_budget / ((double)snap_ld * ws)));
   snap_cap = std::min<int64_t>(snap_cap, pl.pcount);
   void* snap = nullptr;
-  RES_TRY(ws_get(op, "snapshots", (size_t)snap_cap * ncols * ws, &snap));
+  RES_TRY(ws_get(op, "snapshots", (size_t)snap_cap * snap_ld * ws, &snap));
 
-  // segments for all k columns (host copy kept in the handle: the upload is asynchronous)
-  std::vector<Seg1D>& segs = op->segs_k;
-  segs.clear();
-  for (int c = 0; c < k; ++c)
-    for (auto sg : op->segs) {
-      sg.col = c;
-      segs.push_back(sg);
-    }
   void* dsegs;
-  RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), &dsegs));
-  HIP_TRY(hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
+  int64_t nseg;
+  RES_TRY(upload_regions(op, k, &dsegs, &nseg, st));
 
   int64_t buffered = 0, buf_m0 = 0;  // rows in the snapshot buffer and the sample index of the first
   int64_t s0 = 0;
+  auto first_m_at_or_after = [&](int64_t t) -> int64_t {
+    if (t <= pl.pfirst) return 0;
+    return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
+  };
   while (s0 < pl.S) {
-    // chunk end: period boundary (table mode), tile size (tile mode), forcing switch-off
+    // chunk end: period boundary (table mode), tile size (tile mode), forcing switch-off, snapshot capacity
     int64_t e = pl.S;
     if (table_mode) e = std::min(e, (s0 / pl.P + 1) * pl.P);
     else e = std::min(e, s0 + tile_rows);
     if (s0 < pl.forced_end) e = std::min(e, pl.forced_end);
-    // projected samples in [s0, e): m in [ma, mb)
-    auto first_m_at_or_after = [&](int64_t t) -> int64_t {
-      if (t <= pl.pfirst) return 0;
-      return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
-    };
     int64_t ma = first_m_at_or_after(s0), mb = first_m_at_or_after(e);
     if (mb - ma > snap_cap - buffered) {
       mb = ma + (snap_cap - buffered);
       e = pl.pfirst + (mb - 1) * pl.pstride + 1;  // stop right after the last sample that fits
     }
-    const bool forced = s0 < pl.forced_end;
-    Step1DArgs a{};
-    a.fp64 = op->fp64();
-    a.cfg = op->step_cfg;
-    a.segs = (const Seg1D*)dsegs;
-    a.nseg = (int64_t)segs.size();
-    a.band = op->d_band[s];
-    a.state = state;
-    a.N = N;
-    a.row_len = ncols;
-    a.n_steps = e - s0;
-    a.phi_re = 1.0;
-    a.phi_im = 0.0;
-    if (forced) {
+    ForceSpec fs;
+    if (s0 < pl.forced_end) {
       if (table_mode) {
-        a.frc = frc;
-        a.frc_row0 = s0 % pl.P;
-        a.frc_period = std::min<int64_t>(pl.P, table_rows);
-        // e^{i sigma w0 q P h} for the period q of this chunk (table rows hold the period-0 phases)
-        const int64_t q = s0 / pl.P;
-        const cd phi = std::polar(1.0, sigma * pl.w0 * op->h * (double)pl.P * (double)q);
-        a.phi_re = phi.real();
-        a.phi_im = phi.imag();
+        fs.frc = frc;
+        fs.row0 = s0 % pl.P;
+        fs.period = table_rows;
+        // table rows hold period-0 phases; period q adds e^{i sigma w0 q P h}
+        fs.phi = std::polar(1.0, sigma * pl.w0 * op->h * (double)pl.P * (double)(s0 / pl.P));
       } else {
-        PhaseGemmArgs g{};
-        g.mode = 0;
-        g.M = e - s0;
-        g.Ncols = ncols;
-        g.K = nw;
-        g.btab = btab;
-        g.P = pl.P;
-        g.sigma = sigma;
-        g.w0h = pl.w0 * op->h;
-        g.s0 = s0;
-        g.stride = 1;
-        g.bmat = G;
-        g.out = frc;
-        g.k_per_split = nw;
-        if (launch_phase_gemm(g, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
-        a.frc = frc;
-        a.frc_row0 = 0;
-        a.frc_period = 0;
+        syn.M = e - s0;
+        syn.s0 = s0;
+        syn.out = frc;
+        TimedLaunch tl(op, RES_TIMING_SYNTHESIS, st);
+        if (launch_phase_gemm(syn, op->fp64(), st)) return fail(RES_EINVAL, "synthesis GEMM launch");
+        fs.frc = frc;
+        fs.row0 = 0;
+        fs.period = 0;
       }
-    } else {
-      a.frc = nullptr;
     }
+    SnapSpec ss;
     if (mb > ma) {
-      a.snap = snap;
-      a.snap_first = pl.pfirst + ma * pl.pstride - s0;
-      a.snap_stride = pl.pstride;
-      a.snap_count = mb - ma;
-      a.snap_row0 = buffered;
+      ss.snap = snap;
+      ss.ld = snap_ld;
+      ss.first = pl.pfirst + ma * pl.pstride - s0;
+      ss.stride = pl.pstride;
+      ss.count = mb - ma;
+      ss.row0 = buffered;
       if (buffered == 0) buf_m0 = ma;
       buffered += mb - ma;
-    } else {
-      a.snap = nullptr;
     }
-    if (launch_step1d(a, st)) return fail(RES_EINVAL, "stepper launch");
-    HIP_TRY(hipGetLastError());
-    trace_norm("state after chunk", state, ncols, op->fp64(), st);
+    RES_TRY(march_1d(op, k, e - s0, fs, ss, dsegs, nseg, st));
     if (buffered == snap_cap || (buffered > 0 && (e >= pl.S || mb >= pl.pcount))) {
-      RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, buf_m0, buffered, acc, st));
+      RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, snap_ld, buf_m0, buffered, acc, st));
       buffered = 0;
     }
     s0 = e;
   }
-  if (buffered > 0) RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, buf_m0, buffered, acc, st));
+  if (buffered > 0) RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, snap_ld, buf_m0, buffered, acc, st));
   return RES_OK;
 }
 
@@ -587,6 +737,7 @@ int cholqr2(resolvent_op* op, int nw, int k, double* X, void* rtot, double* norm
   RES_TRY(ws_get(op, "qr_r1", mats, &r1));
   RES_TRY(ws_get(op, "qr_r1i", mats, &r1i));
   RES_TRY(ws_get(op, "qr_r2i", mats, &r2i));
+  TimedLaunch tl(op, RES_TIMING_QR, st);
   launch_gram(X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, part, op->d_flag, st);
   launch_chol(part, nsplit, k, nw, op->ninst, r1, r1i, nullptr, nullptr, norm_hist, op->d_flag, st);
   launch_rmul(X, 1, X, 1, op->N, k, op->d_off, op->ninst, nw, nsplit, r1i, st);
@@ -609,8 +760,10 @@ uint64_t splitmix64(uint64_t& x) {
 int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
   const int64_t N = op->N;
   const size_t ws = op->wsize();
-  void* state;
-  RES_TRY(ws_get(op, "state", (size_t)N * ws, &state));
+  void *sb0, *sb1;
+  RES_TRY(ws_get(op, "state0", (size_t)N * ws, &sb0));
+  RES_TRY(ws_get(op, "state1", (size_t)N * ws, &sb1));
+  op->cur_state = 0;
   uint64_t sx = d->probe_seed;
   std::vector<cd> u0(N);
   for (int64_t i = 0; i < N; ++i) {
@@ -619,42 +772,32 @@ int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
     u0[i] = cd(a, b);
   }
   if (op->fp64()) {
-    HIP_TRY(hipMemcpyAsync(state, u0.data(), N * sizeof(cd), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpy(sb0, u0.data(), N * sizeof(cd), hipMemcpyHostToDevice));
   } else {
     std::vector<std::complex<float>> f(N);
     for (int64_t i = 0; i < N; ++i) f[i] = std::complex<float>((float)u0[i].real(), (float)u0[i].imag());
-    HIP_TRY(hipMemcpyAsync(state, f.data(), N * sizeof(std::complex<float>), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(sb0, f.data(), N * sizeof(std::complex<float>), hipMemcpyHostToDevice));
   }
   double n0 = 0;
   for (auto& z : u0) n0 += std::norm(z);
   n0 = std::sqrt(n0);
-  std::vector<Seg1D>& segs = op->segs_k;
-  segs = op->segs;
   void *dsegs, *part;
-  RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), &dsegs));
-  HIP_TRY(hipMemcpyAsync(dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
+  int64_t nseg;
+  RES_TRY(upload_regions(op, 1, &dsegs, &nseg, st));
   const int nsplit = nsplit_for(max_instance_len(op));
   RES_TRY(ws_get(op, "probe_part", (size_t)op->ninst * nsplit * sizeof(cd), &part));
   const double tol = d->probe_tol > 0 ? d->probe_tol : 1e-9;
   const double tmax = d->probe_tmax > 0 ? d->probe_tmax : 2000.0;
   const int64_t chunk = std::max<int64_t>(1, (int64_t)std::ceil(tmax / 50.0 / op->h));
   std::vector<cd> hpart((size_t)op->ninst * nsplit);
+  op->march_band = op->d_band[0];
   int64_t steps = 0;
   while (true) {
-    Step1DArgs a{};
-    a.fp64 = op->fp64();
-    a.cfg = op->step_cfg;
-    a.segs = (const Seg1D*)dsegs;
-    a.nseg = (int64_t)segs.size();
-    a.band = op->d_band[0];
-    a.state = state;
-    a.N = N;
-    a.row_len = N;
-    a.n_steps = chunk;
-    if (launch_step1d(a, st)) return fail(RES_EINVAL, "stepper launch");
+    RES_TRY(march_1d(op, 1, chunk, ForceSpec(), SnapSpec(), dsegs, nseg, st));
     steps += chunk;
-    launch_gram(state, op->fp64(), N, 1, op->d_off, op->ninst, 1, nsplit, part, op->d_flag, st);
+    void* cur;
+    RES_TRY(ws_get(op, op->cur_state ? "state1" : "state0", (size_t)N * ws, &cur));
+    launch_gram(cur, op->fp64(), N, 1, op->d_off, op->ninst, 1, nsplit, part, op->d_flag, st);
     HIP_TRY(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     double nn = 0;
@@ -749,7 +892,7 @@ int resolvent_op_create(const resolvent_op_desc* d, void* stream, resolvent_op**
       op->zd[i] = d->h * c;
       op->zu[i] = last[i] ? cd(0, 0) : d->h * u;
     }
-    int rc = plan_1d_segments(op);
+    int rc = plan_1d_default(op);
     if (rc) return bail(rc);
     rc = build_1d_stencils(op);
     if (rc) return bail(rc);
@@ -779,6 +922,12 @@ void resolvent_op_destroy(resolvent_op* op) {
     if (op->d_band[s]) (void)hipFree(op->d_band[s]);
   }
   if (op->d_off) (void)hipFree(op->d_off);
+  if (op->d_flags) (void)hipFree(op->d_flags);
+  for (int c = 0; c < 4; ++c)
+    for (auto& e : op->tev[c]) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
   if (op->d_flag) (void)hipFree(op->d_flag);
   delete op;
 }
@@ -886,6 +1035,29 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
   return fail(RES_ENOTSUP, "backward not implemented yet");
 }
 
+int resolvent_op_set_timing(resolvent_op* op, int32_t enable) {
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  op->timing = enable != 0;
+  return RES_OK;
+}
+
+int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!op || kind < 0 || kind > 3 || !total_ms || !launches) return fail(RES_EINVAL, "bad argument");
+  double tot = 0;
+  for (auto& e : op->tev[kind]) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  *total_ms = tot;
+  *launches = (int64_t)op->tev[kind].size();
+  op->tev[kind].clear();
+  return RES_OK;
+}
+
 int resolvent_op_check(resolvent_op* op, void* stream) {
   if (!op) return fail(RES_EINVAL, "NULL op");
   int flag = 0;
@@ -894,6 +1066,11 @@ int resolvent_op_check(resolvent_op* op, void* stream) {
   if (flag) {
     int zero = 0;
     HIP_TRY(hipMemcpy(op->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+    if (flag & 8) {
+      if (op->d_flags) HIP_TRY(hipMemset(op->d_flags, 0, op->nflags * sizeof(uint32_t)));
+      op->flag_epoch = 1;
+      return fail(RES_EHIP, "persistent stepper: neighbour synchronisation timed out");
+    }
     if (flag & 2) return fail(RES_ENONFINITE, "rank-deficient or non-finite block in the per-frequency QR");
     return fail(RES_ENONFINITE, "non-finite values in a result");
   }

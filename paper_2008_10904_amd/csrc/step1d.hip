@@ -16,39 +16,61 @@
 
 namespace res {
 
-// One workgroup marches one segment (a column's run of whole instances) for n_steps steps.  Thread t owns V
-// consecutive unknowns held in registers together with their nine stencil coefficients; the state is
-// exchanged through a double-buffered LDS row once per step (one barrier per step).  Forcing rows are
-// prefetched PD steps ahead into a register ring.
+// One workgroup marches its region for n_steps steps.  Thread t holds V consecutive unknowns of the region in
+// registers together with their nine stencil coefficients; the state is exchanged through a double-buffered LDS
+// row once per step (one LDS-only barrier per step).  Forcing rows are prefetched PD steps ahead into a register
+// ring.  Threads past the region end work on a clamped copy of its last unknown with zero coefficients, so every
+// load is in bounds and no branch depends on the lane.
 //
 // Forcing of local step t: phi * frc[row][col*N + i] with row = frc_row0 + t (mod frc_period if > 0).
-// Snapshot rows: u_t (the state BEFORE step t's update) is written to snap[snap_row0 + m] for
-// t = snap_first + m*snap_stride, m < snap_count.
-template <typename R, int NT, int V, int PD>
+// Snapshots (u_t, the state BEFORE step t's update) of the owned unknowns go to rows of length snap_ld whose last
+// element is a scratch slot that non-owned lanes overwrite, keeping every snapshot store unconditional.
+// SNAP: 0 = none, 1 = every step into row snap_row0 + t, 2 = steps snap_first + m*snap_stride into row
+// snap_row0 + m.  Keeping the store pattern a compile-time property lets the compiler count outstanding memory
+// operations exactly, so the prefetched loads are waited for with partial counts.
+//
+// PERSIST: the launch marches all n_steps in blocks of `block` steps (a multiple of PD).  After each block a
+// workgroup publishes its owned values to xbuf[b & 1], raises flags[blockIdx.x] to epoch + b + 1 (release at
+// agent scope), waits until both halo neighbours have done the same (relaxed spin, then acquire) and reloads its
+// halo from their published values.  Double buffering is safe: a neighbour can only overwrite xbuf[b & 1] again
+// after this workgroup has published block b + 1, i.e. after it finished reading.  Every wait is bounded by
+// `spin_ns` of wall-clock time: on expiry the workgroup poisons its flag, sets *err and returns, so every wave
+// of the grid terminates.  The grid must be co-resident (the launcher uses a cooperative launch).
+template <typename R, int NT, int V, int PD, bool FORCED, int SNAP, bool PERSIST>
 __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ segs, const cx<R>* __restrict__ band,
-                                                    cx<R>* __restrict__ state, int64_t N, int64_t row_len,
-                                                    int64_t n_steps, const cx<R>* __restrict__ frc,
-                                                    int64_t frc_row0, int64_t frc_period, R phi_re, R phi_im,
-                                                    cx<R>* __restrict__ snap, int64_t snap_first,
-                                                    int64_t snap_stride, int64_t snap_count, int64_t snap_row0) {
+                                                    const cx<R>* __restrict__ state_in, cx<R>* __restrict__ state_out,
+                                                    int64_t N, int64_t row_len, int64_t n_steps,
+                                                    const cx<R>* __restrict__ frc, int64_t frc_row0,
+                                                    int64_t frc_period, R phi_re, R phi_im, cx<R>* __restrict__ snap,
+                                                    int64_t snap_ld, int64_t snap_first, int64_t snap_stride,
+                                                    int64_t snap_count, int64_t snap_row0, cx<R>* xbuf,
+                                                    uint32_t* flags, uint32_t epoch, int64_t block,
+                                                    uint64_t spin_ns, int* err) {
   constexpr int W = NT * V + 2 * kBandRadius;
   __shared__ cx<R> buf[2][W];
   const Seg1D sg = segs[blockIdx.x];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)sg.col * N + sg.dof0;
+  const int64_t cbase = (int64_t)sg.col * N + sg.dof0;
   const cx<R> zero = mk<R>(0, 0);
   const cx<R> phi = mk<R>(phi_re, phi_im);
 
   cx<R> p[V][kBandWidth];
   cx<R> u[V];
-  bool valid[V];
+  int lc[V];
+  bool valid[V], own[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int64_t l = (int64_t)tid * V + v;
+    const int l = tid * V + v;
     valid[v] = l < sg.ndof;
-    u[v] = valid[v] ? state[base + l] : zero;
+    own[v] = valid[v] && l >= sg.own0 && l < sg.own0 + sg.nown;
+    lc[v] = valid[v] ? l : sg.ndof - 1;
+    const cx<R> s0 = state_in[cbase + lc[v]];
+    u[v] = csel(valid[v], s0, zero);
 #pragma unroll
-    for (int d = 0; d < kBandWidth; ++d) p[v][d] = valid[v] ? band[(sg.dof0 + l) * kBandWidth + d] : zero;
+    for (int d = 0; d < kBandWidth; ++d) {
+      const cx<R> c = band[(sg.dof0 + lc[v]) * kBandWidth + d];
+      p[v][d] = csel(valid[v], c, zero);
+    }
   }
   if (tid < kBandRadius) {
     buf[0][tid] = zero;
@@ -57,57 +79,163 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
     buf[1][W - 1 - tid] = zero;
   }
 
-  cx<R> f[PD][V];
-  // Forcing rows are loaded strictly in step order, so the (wrapping) row index advances by one per load.
-  int64_t lrow = frc_period > 0 ? frc_row0 % frc_period : frc_row0;
-  auto load_forcing = [&](int64_t t, cx<R>* dst) {
-    if (frc == nullptr || t >= n_steps) {
-#pragma unroll
-      for (int v = 0; v < V; ++v) dst[v] = zero;
-      return;
-    }
-    const cx<R>* src = frc + lrow * row_len + base + (int64_t)tid * V;
-    if (++lrow == frc_period) lrow = 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) dst[v] = valid[v] ? load_nt<R>(src + v) : zero;
+  // Forcing rows are consumed strictly in step order; `lrow` is the (wrapping) row of the next load.  Rows travel
+  // by value (a pointer to the ring would force it into scratch memory).
+  struct FRow {
+    cx<R> v[V];
   };
+  int64_t lrow = frc_period > 0 ? frc_row0 % frc_period : frc_row0;
+  const cx<R>* fbase = FORCED ? frc + cbase : nullptr;
+  auto load_row = [&]() -> FRow {
+    FRow r;
+    const cx<R>* src = fbase + lrow * row_len;
 #pragma unroll
-  for (int q = 0; q < PD; ++q) load_forcing(q, f[q]);
+    for (int v = 0; v < V; ++v) r.v[v] = load_nt<R>(src + lc[v]);
+    if (++lrow == frc_period) lrow = 0;
+    return r;
+  };
 
-  int64_t next_snap = (snap != nullptr && snap_count > 0) ? snap_first : -1;
+  int64_t next_snap = (SNAP == 2 && snap_count > 0) ? snap_first : -1;
   int64_t snap_m = 0;
+  int64_t sidx[V];  // snapshot column of each lane: owned unknown or the row's scratch slot
+#pragma unroll
+  for (int v = 0; v < V; ++v) sidx[v] = own[v] ? cbase + lc[v] : snap_ld - 1;
 
-  for (int64_t t0 = 0; t0 < n_steps; t0 += PD) {
+  // one step: exchange through LDS, snapshot of u_t, u <- P(Z) u + phi f
+  auto step = [&](int64_t t, const FRow f) {
+    cx<R>* row = buf[t & 1];
 #pragma unroll
-    for (int q = 0; q < PD; ++q) {
-      const int64_t t = t0 + q;
-      if (t < n_steps) {
-        cx<R>* row = buf[t & 1];
+    for (int v = 0; v < V; ++v) row[kBandRadius + tid * V + v] = u[v];
+    lds_barrier();
+    if (SNAP == 1) {
+      cx<R>* dst = snap + (snap_row0 + t) * snap_ld;
 #pragma unroll
-        for (int v = 0; v < V; ++v) row[kBandRadius + tid * V + v] = u[v];
+      for (int v = 0; v < V; ++v) dst[sidx[v]] = u[v];
+    } else if (SNAP == 2 && t == next_snap) {
+      cx<R>* dst = snap + (snap_row0 + snap_m) * snap_ld;
+#pragma unroll
+      for (int v = 0; v < V; ++v) dst[sidx[v]] = u[v];
+      ++snap_m;
+      next_snap = (snap_m < snap_count) ? next_snap + snap_stride : -1;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      // two partial sums shorten the dependent FMA chain
+      cx<R> a0 = FORCED ? cmul(phi, f.v[v]) : zero;
+      cx<R> a1 = zero;
+#pragma unroll
+      for (int d = 0; d < kBandWidth; ++d) {
+        if (d & 1) a1 = cfma(p[v][d], row[tid * V + v + d], a1);
+        else a0 = cfma(p[v][d], row[tid * V + v + d], a0);
+      }
+      const cx<R> acc = cadd(a0, a1);
+      u[v] = csel(valid[v], acc, zero);
+    }
+  };
+
+  if (PERSIST) {
+    // blocks of `block` steps (multiple of PD), neighbour exchange between blocks
+    __shared__ int abort_flag;
+    const int64_t nblk = (n_steps + block - 1) / block;
+    FRow f[PD];
+    if (FORCED) {
+#pragma unroll
+      for (int q = 0; q < PD; ++q) f[q] = load_row();
+    }
+    int64_t t = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+      if (b > 0) {
+        // publish the owned values of the state after block b-1, then fetch the halo from the neighbours
+        cx<R>* pub = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (own[v]) pub[lc[v]] = u[v];
         __syncthreads();
-        if (t == next_snap) {
-          cx<R>* dst = snap + (snap_row0 + snap_m) * row_len + base + (int64_t)tid * V;
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-            if (valid[v]) dst[v] = u[v];
-          ++snap_m;
-          next_snap = (snap_m < snap_count) ? next_snap + snap_stride : -1;
+        if (tid == 0) {
+          abort_flag = 0;
+          const uint32_t target = epoch + (uint32_t)b;
+          __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t t0 = wall_clock64();
+          const uint64_t limit = spin_ns / 10;  // wall_clock64 ticks at 100 MHz
+          const int nb[2] = {sg.left, sg.right};
+          for (int side = 0; side < 2; ++side) {
+            if (nb[side] < 0) continue;
+            while (true) {
+              const uint32_t fv = __hip_atomic_load(flags + nb[side], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (fv == 0xffffffffu) { abort_flag = 1; break; }
+              if ((int32_t)(fv - target) >= 0) break;
+              if (wall_clock64() - t0 > limit) { abort_flag = 1; break; }
+              __builtin_amdgcn_s_sleep(1);
+            }
+          }
+          if (abort_flag) {
+            atomicOr(err, 8);
+            __hip_atomic_store(flags + blockIdx.x, 0xffffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        __syncthreads();
+        if (abort_flag) return;
+        const cx<R>* src = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          cx<R> acc = cmul(phi, f[q][v]);
+        for (int v = 0; v < V; ++v)
+          if (valid[v] && !own[v]) u[v] = src[lc[v]];
+      }
+      const int64_t te = (t + block < n_steps) ? t + block : n_steps;
+      if (FORCED) {
+        for (; t + PD <= te; t += PD) {
 #pragma unroll
-          for (int d = 0; d < kBandWidth; ++d) acc = cfma(p[v][d], row[tid * V + v + d], acc);
-          u[v] = acc;
+          for (int q = 0; q < PD; ++q) {
+            step(t + q, f[q]);
+            __builtin_amdgcn_sched_barrier(0);
+            f[q] = load_row();  // refills past the last step read padding rows
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
-        load_forcing(t + PD, f[q]);
+        // the launch's last steps when n_steps is not a multiple of PD (blocks are multiples of PD)
+#pragma unroll
+        for (int q = 0; q < PD; ++q)
+          if (t + q < te) step(t + q, f[q]);
+        t = te;
+      } else {
+        FRow none;
+#pragma unroll
+        for (int v = 0; v < V; ++v) none.v[v] = zero;
+        for (; t < te; ++t) step(t, none);
       }
     }
+  } else {
+  const int64_t n_main = FORCED ? (n_steps / PD) * PD : n_steps;
+  int64_t t = 0;
+  if (FORCED) {
+    // prefetch ring: f[q] holds the row of step t0 + q; it is refilled with step t0 + q + PD right after use
+    FRow f[PD];
+#pragma unroll
+    for (int q = 0; q < PD; ++q) f[q] = load_row();
+    for (; t < n_main; t += PD) {
+#pragma unroll
+      for (int q = 0; q < PD; ++q) {
+        step(t + q, f[q]);
+        // keep the refill of slot q after the step that consumes it (hoisting it would force a copy of the
+        // slot and a full wait on the loads in flight).  Refills past the last step read padding rows.
+        __builtin_amdgcn_sched_barrier(0);
+        f[q] = load_row();
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PD; ++q)
+      if (t + q < n_steps) step(t + q, f[q]);
+  } else {
+    FRow none;
+#pragma unroll
+    for (int v = 0; v < V; ++v) none.v[v] = zero;
+    for (; t < n_steps; ++t) step(t, none);
+  }
   }
 #pragma unroll
   for (int v = 0; v < V; ++v)
-    if (valid[v]) state[base + (int64_t)tid * V + v] = u[v];
+    if (own[v]) state_out[cbase + lc[v]] = u[v];
 }
 
 // One Horner pass of G = h Q_j(Z) F over [n_w][k][N] (three passes build G):
@@ -166,37 +294,110 @@ __global__ __launch_bounds__(256) void tri_horner_kernel(const cx<double>* __res
 // ---------------------------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------------------------
-template <typename R, int NT, int V, int PD>
-static void launch_step1d_cfg(const Step1DArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((step1d_kernel<R, NT, V, PD>), dim3(a.nseg), dim3(NT), 0, st, a.segs,
-                     (const cx<R>*)a.band, (cx<R>*)a.state, a.N, a.row_len, a.n_steps, (const cx<R>*)a.frc,
-                     a.frc_row0, a.frc_period, (R)a.phi_re, (R)a.phi_im, (cx<R>*)a.snap, a.snap_first,
-                     a.snap_stride, a.snap_count, a.snap_row0);
+template <typename R, int NT, int V, int PD, bool F, int S, bool PERSIST>
+static int launch_step1d_one(const Step1DArgs& a, hipStream_t st) {
+  const cx<R>* band = (const cx<R>*)a.band;
+  const cx<R>* sin = (const cx<R>*)a.state_in;
+  cx<R>* sout = (cx<R>*)a.state_out;
+  const cx<R>* frc = (const cx<R>*)a.frc;
+  R phr = (R)a.phi_re, phi = (R)a.phi_im;
+  cx<R>* snap = (cx<R>*)a.snap;
+  cx<R>* xbuf = (cx<R>*)a.xbuf;
+  auto kern = step1d_kernel<R, NT, V, PD, F, S, PERSIST>;
+  if (!PERSIST) {
+    hipLaunchKernelGGL(kern, dim3(a.nseg), dim3(NT), 0, st, a.segs, band, sin, sout, a.N, a.row_len, a.n_steps, frc,
+                       a.frc_row0, a.frc_period, phr, phi, snap, a.snap_ld, a.snap_first, a.snap_stride,
+                       a.snap_count, a.snap_row0, xbuf, a.flags, a.epoch, a.block, a.spin_ns, a.err);
+    return 0;
+  }
+  void* args[] = {(void*)&a.segs, (void*)&band, (void*)&sin, (void*)&sout, (void*)&a.N, (void*)&a.row_len,
+                  (void*)&a.n_steps, (void*)&frc, (void*)&a.frc_row0, (void*)&a.frc_period, (void*)&phr,
+                  (void*)&phi, (void*)&snap, (void*)&a.snap_ld, (void*)&a.snap_first, (void*)&a.snap_stride,
+                  (void*)&a.snap_count, (void*)&a.snap_row0, (void*)&xbuf, (void*)&a.flags, (void*)&a.epoch,
+                  (void*)&a.block, (void*)&a.spin_ns, (void*)&a.err};
+  return hipLaunchCooperativeKernel((const void*)kern, dim3(a.nseg), dim3(NT), args, 0, st) == hipSuccess ? 0 : -2;
 }
+
+template <typename R, int NT, int V, int PD>
+static int launch_step1d_cfg(const Step1DArgs& a, hipStream_t st) {
+  // snapshot mode: every step when the launch projects each of its steps from row snap_row0 on
+  const int mode = (a.snap == nullptr || a.snap_count <= 0) ? 0
+                   : (a.snap_first == 0 && a.snap_stride == 1 && a.snap_count == a.n_steps) ? 1 : 2;
+#define RES_STEP(F, S) \
+  return a.persist ? launch_step1d_one<R, NT, V, PD, F, S, true>(a, st) : launch_step1d_one<R, NT, V, PD, F, S, false>(a, st)
+  if (a.frc != nullptr) {
+    if (mode == 0) RES_STEP(true, 0); else if (mode == 1) RES_STEP(true, 1); else RES_STEP(true, 2);
+  } else {
+    if (mode == 0) RES_STEP(false, 0); else if (mode == 1) RES_STEP(false, 1); else RES_STEP(false, 2);
+  }
+#undef RES_STEP
+}
+
+// Largest grid of this configuration that is co-resident on the device (for the persistent variant).
+template <typename R, int NT, int V, int PD>
+static int coresident_cfg(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step1d_kernel<R, NT, V, PD, true, 2, true>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+#define RES_CFGS(X)               \
+  X(0, 64, 1, 4)                  \
+  X(1, 128, 1, 4)                 \
+  X(2, 256, 1, 4)                 \
+  X(3, 256, 2, 4)                 \
+  X(4, 256, 4, 2)                 \
+  X(5, 256, 8, 2)                 \
+  X(6, 512, 4, 2)                 \
+  X(7, 1024, 2, 2)                \
+  X(8, 512, 2, 4)                 \
+  X(9, 1024, 1, 4)                \
+  X(10, 512, 1, 4)                \
+  X(11, 128, 2, 4)                \
+  X(12, 256, 1, 8)                \
+  X(13, 512, 1, 8)                \
+  X(14, 128, 1, 8)                \
+  X(15, 256, 2, 8)
 
 template <typename R> static int launch_step1d_t(const Step1DArgs& a, hipStream_t st) {
   switch (a.cfg) {
-    case 0: launch_step1d_cfg<R, 64, 1, 4>(a, st); break;
-    case 1: launch_step1d_cfg<R, 128, 1, 4>(a, st); break;
-    case 2: launch_step1d_cfg<R, 256, 1, 4>(a, st); break;
-    case 3: launch_step1d_cfg<R, 256, 2, 4>(a, st); break;
-    case 4: launch_step1d_cfg<R, 256, 4, 2>(a, st); break;
-    case 5: launch_step1d_cfg<R, 256, 8, 2>(a, st); break;
-    case 6: launch_step1d_cfg<R, 512, 4, 2>(a, st); break;
-    case 7: launch_step1d_cfg<R, 1024, 2, 2>(a, st); break;
-    case 8: launch_step1d_cfg<R, 512, 2, 4>(a, st); break;
-    case 9: launch_step1d_cfg<R, 1024, 1, 4>(a, st); break;
+#define RES_CASE(I, NT, V, PD) \
+  case I: return launch_step1d_cfg<R, NT, V, PD>(a, st);
+    RES_CFGS(RES_CASE)
+#undef RES_CASE
     default: return -1;
   }
-  return 0;
+}
+
+template <typename R> static int coresident_t(int cfg, int device) {
+  switch (cfg) {
+#define RES_CASE(I, NT, V, PD) \
+  case I: return coresident_cfg<R, NT, V, PD>(device);
+    RES_CFGS(RES_CASE)
+#undef RES_CASE
+    default: return 0;
+  }
+}
+
+int step1d_coresident(int fp64, int cfg, int device) {
+  return fp64 ? coresident_t<double>(cfg, device) : coresident_t<float>(cfg, device);
+}
+
+int step1d_prefetch(int cfg) {
+  static const int pd[] = {4, 4, 4, 4, 2, 2, 2, 2, 4, 4, 4, 4, 8, 8, 8, 8};
+  return (cfg >= 0 && cfg < kStep1DConfigs) ? pd[cfg] : 0;
 }
 
 int step1d_capacity(int cfg) {
-  static const int cap[] = {64, 128, 256, 512, 1024, 2048, 2048, 2048, 1024, 1024};
+  static const int cap[] = {64, 128, 256, 512, 1024, 2048, 2048, 2048, 1024, 1024, 512, 256, 256, 512, 128, 512};
   return (cfg >= 0 && cfg < kStep1DConfigs) ? cap[cfg] : 0;
 }
 
 int launch_step1d(const Step1DArgs& a, hipStream_t st) {
+  if (a.persist && (a.block <= 0 || a.block % step1d_prefetch(a.cfg) != 0)) return -3;
   return a.fp64 ? launch_step1d_t<double>(a, st) : launch_step1d_t<float>(a, st);
 }
 

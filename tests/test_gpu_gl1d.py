@@ -198,3 +198,31 @@ def test_decay_probe_classifies_operators():
     with pytest.raises(ResolventError) as e:
         gpu_gl(2000, 0.38, -0.01, 0.005, xl=-50.0, xr=50.0, probe=True, probe_tmax=50.0)
     assert e.value.code == L.RES_ESTEP
+
+
+@pytest.mark.parametrize("plan", ["1,40,4,0", "2,17,7", "0,8,1", "12,40,8,0", "13,100,20", "1,40,4", "12,40,8", "14,32,8", "13,64,16"])
+def test_halo_regions_match_oracle(plan, monkeypatch):
+    """Multi-workgroup marching (owned chunks + redundant halos, state exchanged between launches) is exact."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_batched_coefficients
+    say("case: halo regions plan", plan)
+    monkeypatch.setenv("RESOLVENT_STEP1D", plan)
+    inst = [(50, 0.2, -0.01), (37, 0.15, -0.02), (33, 0.12, -0.012)]
+    h, P, nw, k = 0.05, 400, 3, 2
+    dw = 2 * np.pi / (P * h)
+    lo, d, up, off = gl_batched_coefficients(inst, xl=XL_T, xr=XR_T)
+    op = ResolventOp.tridiagonal(lo, d, up, h, offsets=off)
+    F = forcing(10, nw, k, int(off[-1]))
+    grid = op.grid(-0.1, dw, nw)
+    outp = to_np(op.apply(gpu_tensor(F), grid, op.run("periodic", periods=12, stride=50)))
+    outt = to_np(op.adjoint_apply(gpu_tensor(F), grid, op.run("transient", tail=2000)))
+    torch.cuda.synchronize()
+    for m, (n, mu0, mu2) in enumerate(inst):
+        L, _ = O_ops.gl_operator(n, mu0, mu2, xl=XL_T, xr=XR_T)
+        sl = slice(int(off[m]), int(off[m + 1]))
+        refp = O_st.run(L, h, -0.1, dw, F[:, :, sl], "periodic", periods=12, stride=50)
+        reft = O_st.run(L, h, -0.1, dw, F[:, :, sl], "transient", tail=2000, adjoint=True)
+        say("  inst", m, per_freq_relerr(outp[:, :, sl], refp), per_freq_relerr(outt[:, :, sl], reft))
+        assert per_freq_relerr(outp[:, :, sl], refp) < 1e-10
+        assert per_freq_relerr(outt[:, :, sl], reft) < 1e-10
