@@ -74,13 +74,12 @@ def cpu_baseline(cfg, w0, dw, F, seconds):
     L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
     om = w0 + dw * np.arange(cfg["n_omega"])
     from oracle.stepping import march
-    # calibrate on a few steps, then run a sample sized to `seconds`
-    t = time.perf_counter()
-    march(L, cfg["h"], om, F, 5, lambda s: True, lambda s: False, 1.0)
-    per = (time.perf_counter() - t) / 5
-    n = max(10, int(seconds / max(per, 1e-6)))
-    t = time.perf_counter()
-    march(L, cfg["h"], om, F, n, lambda s: True, lambda s: False, 1.0)
+    march(L, cfg["h"], om, F, 3, lambda s: True, lambda s: False, 1.0)  # warm caches and BLAS threads
+    # time-boxed sample: chunks of 200 forced steps until `seconds` have elapsed
+    n, t = 0, time.perf_counter()
+    while time.perf_counter() - t < seconds:
+        march(L, cfg["h"], om, F, 200, lambda s: True, lambda s: False, 1.0)
+        n += 200
     dt = time.perf_counter() - t
     sweeps = cfg["N"] * cfg["k"] * cfg["n_omega"] * n / dt
     threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or str(os.cpu_count())
