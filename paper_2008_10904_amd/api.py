@@ -72,6 +72,33 @@ class ResolventOp:
         d.probe_seed = probe_seed
         return cls(d, keep, precision, stream)
 
+    @classmethod
+    def grid_operator(cls, kind, nx, ny, nz, coef, h, precision="fp64", probe=False, probe_tol=1e-9,
+                      probe_tmax=2000.0, probe_seed=12345, stream=None):
+        """2-D five-point (kind "adr2d") or 3-D three-component (kind "adr3d3c") operator from the coefficient
+        dict of ``operators.adr2d_coefficients`` / ``operators.adr3d3c_coefficients``."""
+        three = kind == "adr3d3c"
+        keep = {}
+        d = OpDesc()
+        d.kind = _lib.RES_OP_ADR3D3C if three else _lib.RES_OP_ADR2D
+        d.precision = _PREC[precision]
+        d.h = float(h)
+        d.ninst = 1
+        d.nx, d.ny, d.nz = int(nx), int(ny), int(nz if three else 1)
+        for name in ("cxm", "cxp", "cym", "cyp", "czm", "czp", "dfield", "coupling"):
+            if name in coef and (three or name not in ("czm", "czp", "coupling")):
+                a = np.ascontiguousarray(np.asarray(coef[name], np.float64)).ravel()
+                keep[name] = a
+                setattr(d, name, _dptr(a))
+        d.probe = 1 if probe else 0
+        d.probe_tol = probe_tol
+        d.probe_tmax = probe_tmax
+        d.probe_seed = probe_seed
+        op = cls(d, keep, precision, stream)
+        op.grid_shape = (int(nz if three else 1), int(ny), int(nx))
+        op.ncomp = 3 if three else 1
+        return op
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -140,8 +167,12 @@ class ResolventOp:
         return gains, V, U, hist
 
     def set_diagonal(self, diag):
-        """Replace the operator's diagonal (host array): complex [N] for a tridiagonal operator."""
-        d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
+        """Replace the operator's diagonal (host array): complex [N] for a tridiagonal operator, real
+        [nz*ny*nx] (the dfield) for a grid operator."""
+        if hasattr(self, "grid_shape"):
+            d = np.ascontiguousarray(np.asarray(diag, np.float64)).ravel()
+        else:
+            d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
         check(self._lib.resolvent_op_set_diagonal(self._h, _dptr(d), 0, self._stream_ptr()))
 
     def set_timing(self, enable=True):

@@ -43,21 +43,20 @@ int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* 
                       hipStream_t st);
 
 // ---- 2-D / 3-D stencils -------------------------------------------------------------------------------
-struct GridOp {
-  int dim;                 // 2 or 3
-  int ncomp;               // 1 or 3
+// Device coefficients of Z = h L on an nx*ny*nz grid (real, working precision or FP64): per x-line
+// neighbour coefficients [ny*nz], diagonal [nodes], 3x3 component coupling per line [ny*nz][3][3] or null.
+struct GridOpDev {
+  int ncomp;
   int64_t nx, ny, nz;
-  const double* cxm; const double* cxp; const double* cym; const double* cyp; const double* czm; const double* czp;
-  const double* dfield;    // [nz*ny*nx]
-  const double* coupling;  // [ny*nz][3][3] or null
+  const void* cxm; const void* cxp; const void* cym; const void* cyp; const void* czm; const void* czp;
+  const void* d;
+  const void* K;
 };
-// y = alpha * (Z x) + beta * x + gamma_j * f  (Z = h L applied per column/frequency block; see stencil.hip)
-int launch_grid_stage(const GridOp& op, int fp64, const void* x, const void* u, void* y, int64_t nblocks,
-                      double h, double stage_scale, hipStream_t st);
-int launch_grid_horner(const GridOp& op, const cx<double>* yin, const void* F, int f_fp64, void* yout, int out_fp64,
-                       int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
-int launch_grid_axpy_forcing(int fp64, void* u, const void* frc, int64_t count, double phi_re, double phi_im,
-                             hipStream_t st);
+// One Horner stage of the RK4 step for all k columns (see stencil.hip).
+int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
+                      const void* frc, double phr, double phi, void* snap, hipStream_t st);
+int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
+                       int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
 
 // ---- phase GEMMs --------------------------------------------------------------------------------------
 struct PhaseGemmArgs {

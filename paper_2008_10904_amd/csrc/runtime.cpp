@@ -102,10 +102,19 @@ struct resolvent_op {
   uint32_t* d_flags = nullptr;           // per-workgroup block counters of the persistent stepper
   size_t nflags = 0;
   uint32_t flag_epoch = 1;               // flags only grow; each launch starts above every value written
+  // 2-D / 3-D structured-grid operator: host coefficients of Z = h L (FP64) and device copies of Z and Z^H
+  int ncomp = 1;
+  int64_t nx = 0, ny = 1, nz = 1;
+  std::vector<double> gx[6];             // cxm, cxp, cym, cyp, czm, czp per x-line (times h)
+  std::vector<double> gd;                // diagonal per node (times h)
+  std::vector<double> gK;                // coupling per x-line [3][3] (times h), 3-component operators
+  std::vector<void*> gbufs;              // device allocations of the grid coefficients
+  GridOpDev g64[2], gw[2];               // FP64 and working-precision coefficient sets of Z (0) and Z^H (1)
   // opt-in timing: event pairs per kernel class
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[4];
   const void* march_band = nullptr;      // step stencil used by march_1d (L or L^H)
+  const GridOpDev* march_grid = nullptr; // coefficient set used by march_grid (L or L^H)
   // workspace and caches
   std::map<std::string, DevBuf> ws;
   std::map<int64_t, void*> btab;
@@ -219,6 +228,71 @@ int build_1d_stencils(resolvent_op* op) {
       RES_TRY(upload(&op->d_band[s], pf.data(), pf.size() * sizeof(std::complex<float>)));
     }
   }
+  return RES_OK;
+}
+
+bool is_grid(const resolvent_op* op) { return op->kind == RES_OP_ADR2D || op->kind == RES_OP_ADR3D3C; }
+
+// Device coefficient sets of Z and Z^H (real coefficients, so Z^H = Z^T): x-neighbour coefficients swap (they are
+// constant along x), y/z-neighbour coefficients move to the neighbouring line, the coupling matrix transposes.
+int build_grid_coefficients(resolvent_op* op) {
+  for (void* b : op->gbufs) (void)hipFree(b);
+  op->gbufs.clear();
+  const int64_t nl = op->ny * op->nz, nn = nl * op->nx;
+  std::vector<double> tx[6];
+  for (int a = 0; a < 6; ++a) tx[a].assign(nl, 0.0);
+  std::vector<double> tK(op->gK.size(), 0.0);
+  for (int64_t l = 0; l < nl; ++l) {
+    const int64_t iy = l % op->ny, iz = l / op->ny;
+    tx[0][l] = op->gx[1][l];
+    tx[1][l] = op->gx[0][l];
+    tx[2][l] = iy > 0 ? op->gx[3][l - 1] : 0.0;             // cym' = cyp of the line below
+    tx[3][l] = iy + 1 < op->ny ? op->gx[2][l + 1] : 0.0;    // cyp' = cym of the line above
+    tx[4][l] = iz > 0 ? op->gx[5][l - op->ny] : 0.0;
+    tx[5][l] = iz + 1 < op->nz ? op->gx[4][l + op->ny] : 0.0;
+    if (!op->gK.empty())
+      for (int c = 0; c < 3; ++c)
+        for (int cp = 0; cp < 3; ++cp) tK[l * 9 + c * 3 + cp] = op->gK[l * 9 + cp * 3 + c];
+  }
+  auto up = [&](const std::vector<double>& v, bool f64, const void** dst) -> int {
+    *dst = nullptr;
+    if (v.empty()) return RES_OK;
+    void* d = nullptr;
+    if (f64) {
+      RES_TRY(upload(&d, v.data(), v.size() * sizeof(double)));
+    } else {
+      std::vector<float> f(v.begin(), v.end());
+      RES_TRY(upload(&d, f.data(), f.size() * sizeof(float)));
+    }
+    op->gbufs.push_back(d);
+    *dst = d;
+    return RES_OK;
+  };
+  for (int s = 0; s < 2; ++s) {
+    const std::vector<double>* X = s == 0 ? op->gx : tx;
+    const std::vector<double>& K = s == 0 ? op->gK : tK;
+    for (int pass = 0; pass < 2; ++pass) {
+      const bool f64 = pass == 0;
+      if (!f64 && op->fp64()) {
+        op->gw[s] = op->g64[s];
+        continue;
+      }
+      GridOpDev& g = f64 ? op->g64[s] : op->gw[s];
+      g.ncomp = op->ncomp;
+      g.nx = op->nx;
+      g.ny = op->ny;
+      g.nz = op->nz;
+      RES_TRY(up(X[0], f64, &g.cxm));
+      RES_TRY(up(X[1], f64, &g.cxp));
+      RES_TRY(up(X[2], f64, &g.cym));
+      RES_TRY(up(X[3], f64, &g.cyp));
+      RES_TRY(up(X[4], f64, &g.czm));
+      RES_TRY(up(X[5], f64, &g.czp));
+      RES_TRY(up(op->gd, f64, &g.d));
+      RES_TRY(up(K, f64, &g.K));
+    }
+  }
+  (void)nn;
   return RES_OK;
 }
 
@@ -546,9 +620,48 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
   return RES_OK;
 }
 
+// March n steps of all k columns of a grid operator: four Horner-stage launches per step (Z or Z^H chosen by
+// op->march_band's twin op->march_grid).
+int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const SnapSpec& ss, hipStream_t st) {
+  const int64_t ncols = (int64_t)k * op->N;
+  const size_t ws = op->wsize();
+  void *u, *v1, *v2;
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &u));
+  RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v1));
+  RES_TRY(ws_get(op, "gv2", (size_t)ncols * ws, &v2));
+  const GridOpDev& g = *op->march_grid;
+  TimedLaunch tl(op, RES_TIMING_STEPPER, st);
+  int64_t next = (ss.snap != nullptr && ss.count > 0) ? ss.first : -1, m = 0;
+  for (int64_t t = 0; t < n; ++t) {
+    const void* frow = nullptr;
+    if (fs.frc != nullptr) {
+      int64_t row = fs.row0 + t;
+      if (fs.period > 0) row %= fs.period;
+      frow = (const char*)fs.frc + (size_t)row * ncols * ws;
+    }
+    void* srow = nullptr;
+    if (t == next) {
+      srow = (char*)ss.snap + (size_t)(ss.row0 + m) * ss.ld * ws;
+      ++m;
+      next = m < ss.count ? next + ss.stride : -1;
+    }
+    launch_grid_stage(g, op->fp64(), k, u, u, v1, 0.25, 0, nullptr, 0, 0, nullptr, st);
+    launch_grid_stage(g, op->fp64(), k, u, v1, v2, 1.0 / 3.0, 0, nullptr, 0, 0, nullptr, st);
+    launch_grid_stage(g, op->fp64(), k, u, v2, v1, 0.5, 0, nullptr, 0, 0, nullptr, st);
+    launch_grid_stage(g, op->fp64(), k, u, v1, nullptr, 1.0, 1, frow, fs.phi.real(), fs.phi.imag(), srow, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStream_t st) {
   std::vector<Seg1D>& segs = op->segs_k;  // kept in the handle: the upload is asynchronous
   segs.clear();
+  if (is_grid(op)) {
+    *dsegs = nullptr;
+    *nseg = 0;
+    return RES_OK;
+  }
   const int32_t g = (int32_t)op->segs.size();
   for (int c = 0; c < k; ++c)
     for (auto sg : op->segs) {
@@ -579,10 +692,19 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   RES_TRY(phase_table(op, pl.P, &btab));
   // G_j = h Q_j(Z) F_j  (three Horner passes)
   const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
-  const cx<double>* tri = (const cx<double>*)op->d_tri[s];
-  launch_tri_horner(tri, nullptr, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 0, st);
-  launch_tri_horner(tri, (const cx<double>*)y1, in, in_fp64, y2, 1, N, k, nw, sw0h, sdwh, op->h, 1, st);
-  launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
+  if (is_grid(op)) {
+    const GridOpDev& g = op->g64[s];
+    if (launch_grid_horner(g, nullptr, in, in_fp64, y1, 1, k, nw, sw0h, sdwh, op->h, 0, st) ||
+        launch_grid_horner(g, (const cx<double>*)y1, in, in_fp64, y2, 1, k, nw, sw0h, sdwh, op->h, 1, st) ||
+        launch_grid_horner(g, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), k, nw, sw0h, sdwh, op->h, 2, st))
+      return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
+    op->march_grid = &op->gw[s];
+  } else {
+    const cx<double>* tri = (const cx<double>*)op->d_tri[s];
+    launch_tri_horner(tri, nullptr, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 0, st);
+    launch_tri_horner(tri, (const cx<double>*)y1, in, in_fp64, y2, 1, N, k, nw, sw0h, sdwh, op->h, 1, st);
+    launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
+  }
   HIP_TRY(hipGetLastError());
   trace_norm("run input", in, (int64_t)nw * ncols, in_fp64, st);
   trace_norm("G = hQ(Z) F", G, (int64_t)nw * ncols, op->fp64(), st);
@@ -686,7 +808,8 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
       if (buffered == 0) buf_m0 = ma;
       buffered += mb - ma;
     }
-    RES_TRY(march_1d(op, k, e - s0, fs, ss, dsegs, nseg, st));
+    if (is_grid(op)) RES_TRY(march_grid(op, k, e - s0, fs, ss, st));
+    else RES_TRY(march_1d(op, k, e - s0, fs, ss, dsegs, nseg, st));
     if (buffered == snap_cap || (buffered > 0 && (e >= pl.S || mb >= pl.pcount))) {
       RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, snap_ld, buf_m0, buffered, acc, st));
       buffered = 0;
@@ -699,8 +822,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
 
 int run_any(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
             hipStream_t st) {
-  if (op->kind == RES_OP_TRIDIAG) return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);
-  return fail(RES_ENOTSUP, "operator kind not supported yet");
+  return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);  // one driver; the march dispatches on the operator kind
 }
 
 int apply_common(resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, int k, const void* in, void* out,
@@ -792,8 +914,10 @@ int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
   std::vector<cd> hpart((size_t)op->ninst * nsplit);
   op->march_band = op->d_band[0];
   int64_t steps = 0;
+  op->march_grid = &op->gw[0];
   while (true) {
-    RES_TRY(march_1d(op, 1, chunk, ForceSpec(), SnapSpec(), dsegs, nseg, st));
+    if (is_grid(op)) RES_TRY(march_grid(op, 1, chunk, ForceSpec(), SnapSpec(), st));
+    else RES_TRY(march_1d(op, 1, chunk, ForceSpec(), SnapSpec(), dsegs, nseg, st));
     steps += chunk;
     void* cur;
     RES_TRY(ws_get(op, op->cur_state ? "state1" : "state0", (size_t)N * ws, &cur));
@@ -896,6 +1020,36 @@ int resolvent_op_create(const resolvent_op_desc* d, void* stream, resolvent_op**
     if (rc) return bail(rc);
     rc = build_1d_stencils(op);
     if (rc) return bail(rc);
+  } else if (d->kind == RES_OP_ADR2D || d->kind == RES_OP_ADR3D3C) {
+    const bool three = d->kind == RES_OP_ADR3D3C;
+    op->ncomp = three ? 3 : 1;
+    op->nx = d->nx;
+    op->ny = d->ny;
+    op->nz = three ? d->nz : 1;
+    if (op->nx < 1 || op->ny < 1 || op->nz < 1) return bail(fail(RES_EINVAL, "grid sizes must be >= 1"));
+    if (!d->cxm || !d->cxp || !d->cym || !d->cyp || !d->dfield || (three && (!d->czm || !d->czp)))
+      return bail(fail(RES_EINVAL, "grid coefficient arrays are NULL"));
+    const int64_t nl = op->ny * op->nz, nn = nl * op->nx;
+    const double* src[6] = {d->cxm, d->cxp, d->cym, d->cyp, three ? d->czm : nullptr, three ? d->czp : nullptr};
+    for (int a = 0; a < 6; ++a) {
+      op->gx[a].assign(nl, 0.0);
+      if (src[a])
+        for (int64_t l = 0; l < nl; ++l) op->gx[a][l] = d->h * src[a][l];
+    }
+    op->gd.resize(nn);
+    for (int64_t i = 0; i < nn; ++i) op->gd[i] = d->h * d->dfield[i];
+    if (three && d->coupling) {
+      op->gK.resize(nl * 9);
+      for (int64_t i = 0; i < nl * 9; ++i) op->gK[i] = d->h * d->coupling[i];
+    }
+    for (int a = 0; a < 6; ++a)
+      for (double v : op->gx[a])
+        if (!std::isfinite(v)) return bail(fail(RES_EINVAL, "non-finite operator coefficient"));
+    op->N = (int64_t)op->ncomp * nn;
+    op->ninst = 1;
+    op->off = {0, op->N};
+    int rc = build_grid_coefficients(op);
+    if (rc) return bail(rc);
   } else {
     return bail(fail(RES_ENOTSUP, "operator kind not supported"));
   }
@@ -923,6 +1077,7 @@ void resolvent_op_destroy(resolvent_op* op) {
   }
   if (op->d_off) (void)hipFree(op->d_off);
   if (op->d_flags) (void)hipFree(op->d_flags);
+  for (void* b : op->gbufs) (void)hipFree(b);
   for (int c = 0; c < 4; ++c)
     for (auto& e : op->tev[c]) {
       (void)hipEventDestroy(e.first);
@@ -949,6 +1104,18 @@ int resolvent_op_set_diagonal(resolvent_op* op, const double* values, int32_t on
     for (int64_t i = 0; i < op->N; ++i) op->zd[i] = op->h * cd(hv[2 * i], hv[2 * i + 1]);
     HIP_TRY(hipStreamSynchronize(st));  // kernels in flight may still read the old stencils
     return build_1d_stencils(op);
+  }
+  if (is_grid(op)) {
+    const int64_t nn = op->nx * op->ny * op->nz;
+    std::vector<double> hv(nn);
+    if (on_device) {
+      HIP_TRY(hipMemcpyAsync(hv.data(), values, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+    } else {
+      std::memcpy(hv.data(), values, nn * sizeof(double));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < nn; ++i) op->gd[i] = op->h * hv[i];
+    return build_grid_coefficients(op);
   }
   return fail(RES_ENOTSUP, "operator kind not supported");
 }

@@ -55,3 +55,68 @@ def snap_grid(wmin, wmax, n_omega, h, stride=1):
     dw_nom = (wmax - wmin) / (n_omega - 1)
     P = stride * int(round(2.0 * np.pi / (dw_nom * h * stride)))
     return float(wmin), 2.0 * np.pi / (P * h), P
+
+
+# ------------------------------------------------------------------------------------------------------------
+# 2-D advection-diffusion-reaction and 3-D three-component advection-diffusion with shear coupling
+# ------------------------------------------------------------------------------------------------------------
+def _ramp(s, lo, hi, frac=0.1):
+    """Sponge ramp: 0 away from the ends of [lo, hi], rising linearly to 1 over the last `frac` of each end."""
+    w = frac * (hi - lo)
+    return np.clip((w - np.minimum(s - lo, hi - s)) / w, 0.0, 1.0)
+
+
+def adr2d_coefficients(nx, ny, Re=200.0, mu=None, mu_base=-0.1, mu_amp=0.08, mu_xc=10.0, mu_w2=4.0, nu_s=1.0,
+                       Lx=40.0, ylo=-10.0, yhi=10.0):
+    """Five-point coefficients of  L q = -U(y) q_x + (q_xx + q_yy)/Re + (mu(x,y) - sponge(x,y)) q,  U = tanh(y),
+    on nx * ny interior nodes of [0, Lx] x [ylo, yhi] with q = 0 on the boundary (x fastest).
+
+    mu: array (ny, nx) or None for mu_base + mu_amp exp(-((x - mu_xc)^2 + y^2)/mu_w2).  The sponge is
+    nu_s * max(rx, ry)^2 with rx, ry the linear ramps over the outer tenth of each direction.
+    Returns dict(cxm, cxp, cym, cyp [ny], dfield [ny*nx], mu [ny, nx])."""
+    dx = Lx / (nx + 1)
+    dy = (yhi - ylo) / (ny + 1)
+    x = dx * (1.0 + np.arange(nx))
+    y = ylo + dy * (1.0 + np.arange(ny))
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    if mu is None:
+        mu = mu_base + mu_amp * np.exp(-((X - mu_xc) ** 2 + Y ** 2) / mu_w2)
+    sponge = nu_s * np.maximum(_ramp(X, 0.0, Lx), _ramp(Y, ylo, yhi)) ** 2
+    U = np.tanh(y)
+    dif_x, dif_y = 1.0 / (Re * dx * dx), 1.0 / (Re * dy * dy)
+    return dict(cxm=U / (2 * dx) + dif_x, cxp=-U / (2 * dx) + dif_x, cym=np.full(ny, dif_y), cyp=np.full(ny, dif_y),
+                dfield=(-2 * dif_x - 2 * dif_y + np.asarray(mu) - sponge).ravel(), mu=np.asarray(mu), sponge=sponge)
+
+
+def wake_profile(y, z, amp, delta, y0, z0):
+    """U = 1 - amp exp(-((y - y0)^2 + (z - z0)^2)/delta^2) with its analytic derivatives (U, dU/dy, dU/dz)."""
+    g = np.exp(-((y - y0) ** 2 + (z - z0) ** 2) / delta ** 2)
+    return 1.0 - amp * g, 2.0 * amp * g * (y - y0) / delta ** 2, 2.0 * amp * g * (z - z0) / delta ** 2
+
+
+def adr3d3c_coefficients(nx, ny, nz, wake, Re=200.0, mu=None, mu_const=-0.05, nu_s=1.0, Lx=40.0, lo=-10.0,
+                         hi=10.0):
+    """Seven-point coefficients of the three-component operator on (nz, ny, nx) interior nodes, q = 0 on the
+    boundary:  du/dt = -U u_x - U_y v - U_z w + lap(u)/Re + (mu - s) u,  dv/dt = -U v_x + lap(v)/Re + (mu - s) v,
+    dw/dt = -U w_x + lap(w)/Re + (mu - s) w,  with U(y, z) the wake profile of ``wake``.
+    Returns dict(cxm, cxp, cym, cyp, czm, czp [nz*ny], dfield [nz*ny*nx], coupling [nz*ny, 3, 3], mu)."""
+    dx = Lx / (nx + 1)
+    dy = (hi - lo) / (ny + 1)
+    dz = (hi - lo) / (nz + 1)
+    x = dx * (1.0 + np.arange(nx))
+    y = lo + dy * (1.0 + np.arange(ny))
+    z = lo + dz * (1.0 + np.arange(nz))
+    Zl, Yl = np.meshgrid(z, y, indexing="ij")  # line index l = iz * ny + iy
+    U, Uy, Uz = wake_profile(Yl, Zl, **wake)
+    Z3, Y3, X3 = np.meshgrid(z, y, x, indexing="ij")
+    if mu is None:
+        mu = np.full((nz, ny, nx), mu_const)
+    sponge = nu_s * np.maximum(np.maximum(_ramp(X3, 0.0, Lx), _ramp(Y3, lo, hi)), _ramp(Z3, lo, hi)) ** 2
+    ax, ay, az = 1.0 / (Re * dx * dx), 1.0 / (Re * dy * dy), 1.0 / (Re * dz * dz)
+    nl = ny * nz
+    K = np.zeros((nl, 3, 3))
+    K[:, 0, 1] = -Uy.ravel()
+    K[:, 0, 2] = -Uz.ravel()
+    return dict(cxm=(U / (2 * dx) + ax).ravel(), cxp=(-U / (2 * dx) + ax).ravel(), cym=np.full(nl, ay),
+                cyp=np.full(nl, ay), czm=np.full(nl, az), czp=np.full(nl, az),
+                dfield=(-2 * (ax + ay + az) + np.asarray(mu) - sponge).ravel(), coupling=K, mu=np.asarray(mu))

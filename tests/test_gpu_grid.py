@@ -1,0 +1,127 @@
+"""GPU parity of the 2-D (five-point) and 3-D three-component (seven-point, shear-coupled) paths against the
+CPU oracle on small grids, element by element on seeded inputs.  Tolerances as for the 1-D path: FP64 runs
+within 1e-10 per frequency vector (only the order of the arithmetic differs), gains within 1e-8; mixed runs
+within 1e-3 per vector and 1e-4 per gain."""
+import numpy as np
+import pytest
+
+from _helpers import gpu_tensor, mode_alignment, per_freq_relerr, say
+from oracle import iteration as O_it
+from oracle import operators as O_ops
+from oracle import stepping as O_st
+
+pytestmark = pytest.mark.gpu
+
+WAKE = dict(amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+
+
+def forcing(seed, nw, k, n):
+    g = np.random.default_rng(seed)
+    return g.standard_normal((nw, k, n)) + 1j * g.standard_normal((nw, k, n))
+
+
+def to_np(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def mu2d(nx, ny, seed=0):
+    f = O_ops.adr2d_fields(nx, ny)
+    return O_ops.adr2d_mu_default(f["X"], f["Y"], base=-0.3, amp=0.08)
+
+
+def make2d(nx, ny, h, precision="fp64", mu=None):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    mu = mu2d(nx, ny) if mu is None else mu
+    c = adr2d_coefficients(nx, ny, mu=mu)
+    op = ResolventOp.grid_operator("adr2d", nx, ny, 1, c, h, precision=precision)
+    L, _ = O_ops.adr2d_operator(nx, ny, mu=mu)
+    return op, L
+
+
+def make3d(nx, ny, nz, h, precision="fp64", mu=None):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr3d3c_coefficients
+    mu = np.full((nz, ny, nx), -0.2) if mu is None else mu
+    c = adr3d3c_coefficients(nx, ny, nz, WAKE, mu=mu)
+    op = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, c, h, precision=precision)
+    L, _ = O_ops.adr3d3c_operator(nx, ny, nz, WAKE, mu=mu)
+    return op, L
+
+
+CASES = {"2d": lambda p="fp64", mu=None: make2d(24, 16, 0.1, p, mu),
+         "3d": lambda p="fp64", mu=None: make3d(12, 8, 8, 0.1, p, mu)}
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_apply_adjoint_and_transient_match_oracle(case):
+    import torch
+    say("case: grid", case, "apply / adjoint / transient")
+    op, L = CASES[case]()
+    h, P, nw, k = 0.1, 200, 3, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(21, nw, k, op.n)
+    grid = op.grid(0.1, dw, nw)
+    up = to_np(op.apply(gpu_tensor(F), grid, op.run("periodic", periods=8, stride=50)))
+    za = to_np(op.adjoint_apply(gpu_tensor(F), grid, op.run("periodic", periods=8, stride=50)))
+    ut = to_np(op.apply(gpu_tensor(F), grid, op.run("transient", tail=800)))
+    torch.cuda.synchronize()
+    rp = O_st.run(L, h, 0.1, dw, F, "periodic", periods=8, stride=50)
+    ra = O_st.run(L, h, 0.1, dw, F, "periodic", periods=8, stride=50, adjoint=True)
+    rt = O_st.run(L, h, 0.1, dw, F, "transient", tail=800)
+    e = (per_freq_relerr(up, rp), per_freq_relerr(za, ra), per_freq_relerr(ut, rt))
+    say("  errors", e)
+    assert max(e) < 1e-10
+    # adjoint identity on the GPU results
+    lhs = np.sum(np.conj(F) * up, axis=-1)
+    rhs = np.sum(np.conj(za) * F, axis=-1)
+    assert np.abs(lhs - rhs).max() < 1e-10 * np.abs(lhs).max()
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_modes_match_oracle(case):
+    import torch
+    say("case: grid", case, "modes")
+    op, L = CASES[case]()
+    h, P, nw, k, iters = 0.1, 200, 2, 2, 3
+    dw = 2 * np.pi / (P * h)
+    F0 = forcing(22, nw, k, op.n)
+    g, V, U, H = op.modes(gpu_tensor(F0), op.grid(0.0, dw, nw), op.run("periodic", periods=8, stride=50), iters)
+    torch.cuda.synchronize()
+    a, ad = O_it.stepped_applies(L, h, 0.0, dw, "periodic", periods=8, stride=50)
+    g_ref, V_ref, U_ref, _ = O_it.block_power_iteration(a, ad, F0, iters)
+    say("  gains err", np.abs(g[0] / g_ref - 1).max())
+    assert np.abs(g[0] / g_ref - 1).max() < 1e-8
+    assert mode_alignment(to_np(V)[:, :1], V_ref[:, :1]) > 1 - 1e-8
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_mixed_precision_error(case):
+    import torch
+    say("case: grid", case, "mixed")
+    op, L = CASES[case]("mixed")
+    h, P, nw, k = 0.1, 200, 3, 1
+    dw = 2 * np.pi / (P * h)
+    F = forcing(23, nw, k, op.n)
+    out = to_np(op.apply(gpu_tensor(F, torch.complex64), op.grid(0.2, dw, nw), op.run("periodic", periods=8, stride=50)))
+    torch.cuda.synchronize()
+    ref = O_st.run(L, h, 0.2, dw, F, "periodic", periods=8, stride=50)
+    say("  mixed err", per_freq_relerr(out, ref))
+    assert per_freq_relerr(out, ref) < 1e-3
+
+
+def test_set_diagonal_grid():
+    import torch
+    say("case: grid 2d set_diagonal")
+    nx, ny, h, P, nw = 24, 16, 0.1, 200, 2
+    dw = 2 * np.pi / (P * h)
+    op, _ = make2d(nx, ny, h)
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    mu_new = mu2d(nx, ny) - 0.05 * np.random.default_rng(3).random((ny, nx))
+    op.set_diagonal(adr2d_coefficients(nx, ny, mu=mu_new)["dfield"])
+    F = forcing(24, nw, 1, op.n)
+    out = to_np(op.apply(gpu_tensor(F), op.grid(0.0, dw, nw), op.run("periodic", periods=8, stride=50)))
+    torch.cuda.synchronize()
+    L, _ = O_ops.adr2d_operator(nx, ny, mu=mu_new)
+    ref = O_st.run(L, h, 0.0, dw, F, "periodic", periods=8, stride=50)
+    assert per_freq_relerr(out, ref) < 1e-10
