@@ -316,3 +316,60 @@ def test_discrete_objective_gradient_tends_to_continuous_sensitivity():
     fd = gradient.central_difference_gradient(J, mu, 1e-6)
     cf = gradient.leading_gain_sensitivity(Lmu(mu), w)
     assert np.linalg.norm(cf - fd) < 1e-5 * np.linalg.norm(cf)
+
+
+# ---------------------------------------------------------------------------------------------
+# Reverse mode of the time-stepped run (the references for the GPU backward pass).
+# ---------------------------------------------------------------------------------------------
+def _small_gl(mu0):
+    return operators.gl_operator(12, mu0, -0.01, xl=XL_T, xr=XR_T)[0]
+
+
+@pytest.mark.parametrize("method,kw", [("transient", dict(tail=90)), ("periodic", dict(periods=3, stride=6))])
+def test_stepped_vjp_is_the_adjoint_of_the_run(method, kw):
+    # <A^H G, d> = <G, A d> for independent random d: a dropped conjugate, a transposed transfer matrix or a
+    # wrong unit-forcing index breaks it.
+    L = _small_gl(0.2)
+    h, P = 0.1, 60
+    dw = 2 * np.pi / (P * h)
+    G = forcing(31, 3, 2, 12)
+    vjp = gradient.stepped_vjp(L, h, -0.4, dw, G, method, **kw)
+    for seed in (32, 33):
+        d = forcing(seed, 3, 2, 12)
+        Ad = stepping.run(L, h, -0.4, dw, d, method, **kw)
+        lhs, rhs = np.vdot(vjp, d), np.vdot(G, Ad)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_stepped_vjp_tends_to_dense_adjoint_in_steady_state():
+    # Periodic run long after the transient: A is block diagonal with blocks R_d(w_j), so A^H G = R_d^H G.
+    L = _small_gl(-0.5)
+    h, P = 0.1, 60
+    dw = 2 * np.pi / (P * h)
+    G = forcing(34, 3, 1, 12)
+    vjp = gradient.stepped_vjp(L, h, -0.4, dw, G, "periodic", periods=12, stride=6)
+    for j, w in enumerate(stepping.frequencies(-0.4, dw, 3)):
+        ref = dense.resolvent_rk4(L, w, h).conj().T @ G[j, 0]
+        assert np.linalg.norm(vjp[j, 0] - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_stepped_mu_gradient_of_diagonal_operator_matches_closed_form():
+    # L = diag(lambda): each unknown is a scalar RK4 recurrence whose steady response to F e^{i w t} is
+    # r(z) F with r(z) = h q(z) / (e^{i w h} - p(z)), z = h (lambda + mu), p the RK4 step polynomial and q its
+    # forcing polynomial; then dJ/dmu_x = Re sum conj(G) h r'(z) F with r' from the quotient rule.
+    n, h, P = 6, 0.1, 60
+    lam = -0.6 + 1j * np.linspace(-1.0, 1.0, n)
+    L0 = sp.diags(lam).tocsr()
+    dw = 2 * np.pi / (P * h)
+    F, G = forcing(35, 3, 2, n), forcing(36, 3, 2, n)
+    fd = gradient.stepped_mu_gradient(L0, np.zeros(n), h, -0.4, dw, F, G, "periodic", eps=1e-5, periods=14,
+                                      stride=6)
+    p = np.polynomial.Polynomial([1.0, 1.0, 1 / 2, 1 / 6, 1 / 24])
+    ref = np.zeros(n)
+    for j, w in enumerate(stepping.frequencies(-0.4, dw, 3)):
+        a, b = np.exp(0.5j * w * h), np.exp(1j * w * h)
+        q = h * np.polynomial.Polynomial([(1 + 4 * a + b) / 6, (1 + 2 * a) / 6, (1 + a) / 12, 1 / 24])
+        z = h * lam
+        dr = (q.deriv()(z) * (b - p(z)) + q(z) * p.deriv()(z)) / (b - p(z)) ** 2
+        ref += np.real(np.sum(np.conj(G[j]) * h * dr * F[j], axis=0))
+    assert np.abs(fd - ref).max() < 1e-7 * np.abs(ref).max()
