@@ -11,6 +11,9 @@ def __getattr__(name):
     if name in ("ResolventOp",):
         from .api import ResolventOp
         return ResolventOp
+    if name in ("ResolventApply", "resolvent_apply"):
+        from . import autograd
+        return getattr(autograd, name)
     if name in ("ResolventError",):
         from ._lib import ResolventError
         return ResolventError

@@ -71,6 +71,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libresolvent.so is not built: run `python -m paper_2008_10904_amd.build` "
                           "(the resolvent path has no CPU fallback)")
+    # PyTorch ships its own HIP runtime.  Importing it first makes the loader resolve the library's
+    # libamdhip64.so.7 to that same, already loaded runtime; loaded the other way round the process would hold
+    # two HIP runtimes, and the one not initialised by torch reports no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

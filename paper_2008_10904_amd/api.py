@@ -166,6 +166,32 @@ class ResolventOp:
             ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
         return gains, V, U, hist
 
+    def diag_size(self):
+        """Length of the diagonal that set_diagonal and the reverse mode address: N for a tridiagonal operator,
+        nz*ny*nx (one value per node, shared by the components) for a grid operator."""
+        if hasattr(self, "grid_shape"):
+            nz, ny, nx = self.grid_shape
+            return nz * ny * nx
+        return self.n
+
+    def apply_backward(self, f_hat, g_hat, grid, run, checkpoint_every=0, want_f=True, want_mu=True):
+        """Reverse mode of apply(f_hat, grid, run): given g_hat = dJ/du_hat of a real objective J (convention
+        dJ/dRe + i dJ/dIm), returns (f_grad like f_hat or None, mu_grad float64 [diag_size()] or None) with
+        mu_grad = dJ/d(real part of L's diagonal).  The forward trajectory is recomputed from checkpoints taken
+        every `checkpoint_every` steps (0: about sqrt of the run length)."""
+        torch = _torch()
+        nw, k = grid.n_omega, f_hat.shape[1]
+        self._check_io(f_hat, nw, k)
+        self._check_io(g_hat, nw, k)
+        f_grad = torch.empty_like(f_hat) if want_f else None
+        mu_grad = torch.empty(self.diag_size(), dtype=torch.float64, device=f_hat.device) if want_mu else None
+        mu_ptr = ctypes.cast(ctypes.c_void_p(mu_grad.data_ptr()), ctypes.POINTER(ctypes.c_double)) if want_mu else None
+        check(self._lib.resolvent_apply_backward(
+            self._h, ctypes.byref(grid), ctypes.byref(run), k, ctypes.c_void_p(f_hat.data_ptr()),
+            ctypes.c_void_p(g_hat.data_ptr()), ctypes.c_void_p(f_grad.data_ptr()) if want_f else None, mu_ptr,
+            int(checkpoint_every), self._stream_ptr()))
+        return f_grad, mu_grad
+
     def set_diagonal(self, diag):
         """Replace the operator's diagonal (host array): complex [N] for a tridiagonal operator, real
         [nz*ny*nx] (the dfield) for a grid operator."""

@@ -1,0 +1,167 @@
+// Discrete adjoint of the RK4 march (reverse-mode differentiation of a time-stepped run), FP64.
+//
+// With Z = h L, K_i = Z y_i + h f_i and the classical stages y_1 = u, y_2 = u + K_1/2, y_3 = u + K_2/2,
+// y_4 = u + K_3, u' = u + (K_1 + 2 K_2 + 2 K_3 + K_4)/6, the gradient lambda' = dJ/du' (convention dJ/dRe + i dJ/dIm)
+// propagates back as
+//
+//   Kb_4 = lambda'/6,                 yb_4 = Z^H Kb_4,
+//   Kb_3 = lambda'/3 + yb_4,          yb_3 = Z^H Kb_3,
+//   Kb_2 = lambda'/3 + yb_3/2,        yb_2 = Z^H Kb_2,
+//   Kb_1 = lambda'/6 + yb_2/2,        yb_1 = Z^H Kb_1,
+//   lambda = lambda' + yb_4 + yb_3 + yb_2 + yb_1   (+ the projection's injection at sampled steps),
+//
+// and a real perturbation d mu of L's diagonal (dZ = h diag(d mu)) contributes h Re(conj(Kb_i) y_i) per node and
+// stage.  The forward stages y_i are recomputed from the state u_s (from checkpoints).  One launch per stage; a
+// thread owns one site (unknown of the three-point operator, or grid node with all its components) and all k
+// columns, so the reaction-field gradient of a node is accumulated without atomics.
+#include "common.h"
+#include "gridz.h"
+#include "kernels.h"
+
+namespace res {
+
+// (Z x)[site] for column base x.  KIND 0: three-point complex operator (tri = [N][3]); KIND 1: structured grid.
+template <int KIND, int NC>
+__device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __restrict__ x, int64_t p,
+                                      cx<double> out[NC]) {
+  if (KIND == 0) {
+    const cx<double>* tri = (const cx<double>*)op.tri;
+    cx<double> acc = cmul(tri[3 * p + 1], x[p]);
+    if (p > 0) acc = cfma(tri[3 * p], x[p - 1], acc);
+    if (p + 1 < op.nsite) acc = cfma(tri[3 * p + 2], x[p + 1], acc);
+    out[0] = acc;
+  } else {
+    GridCoef<double> c;
+    c.cxm = (const double*)op.g.cxm; c.cxp = (const double*)op.g.cxp; c.cym = (const double*)op.g.cym;
+    c.cyp = (const double*)op.g.cyp; c.czm = (const double*)op.g.czm; c.czp = (const double*)op.g.czp;
+    c.d = (const double*)op.g.d; c.K = (const double*)op.g.K;
+    const int64_t nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
+    const int64_t ix = p % nx, l = p / nx, iy = l % ny, iz = l / ny;
+    apply_z<double, NC>(c, x, op.nsite, nx, ny, nz, ix, iy, iz, p, l, out);
+  }
+}
+
+// Forward stage m (1..4):  K = Z yin + h f;  m=1: yout = u + K/2, acc = K;  m=2: yout = u + K/2, acc += 2K;
+// m=3: yout = u + K, acc += 2K;  m=4: uout = u + (acc + K)/6 (uout may equal u).  acc may be null when only the
+// stage values are wanted (m < 4); f null means no forcing.
+template <int KIND, int NC>
+__global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int m, const cx<double>* u,
+                                                        cx<double>* uout, const cx<double>* __restrict__ yin,
+                                                        cx<double>* yout,
+                                                        cx<double>* acc, const cx<double>* __restrict__ f, double h) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= op.nsite) return;
+  const int64_t blk = (int64_t)NC * op.nsite;
+  for (int b = 0; b < k; ++b) {
+    cx<double> z[NC];
+    zsite<KIND, NC>(op, yin + b * blk, p, z);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t e = b * blk + c * op.nsite + p;
+      cx<double> K = z[c];
+      if (f != nullptr) {
+        K.re += h * f[e].re;
+        K.im += h * f[e].im;
+      }
+      const cx<double> uu = u[e];
+      if (m == 4) {
+        const cx<double> a = acc[e];
+        uout[e] = mk<double>(uu.re + (a.re + K.re) / 6.0, uu.im + (a.im + K.im) / 6.0);
+      } else {
+        const double w = m == 3 ? 1.0 : 0.5;
+        yout[e] = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
+        if (acc != nullptr) {
+          if (m == 1) acc[e] = K;
+          else {
+            const cx<double> a = acc[e];
+            acc[e] = mk<double>(a.re + 2.0 * K.re, a.im + 2.0 * K.im);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Reverse stage m (4..1) with opH = Z^H; see the header comment.  lam holds lambda' (read for the lambda'/3 and
+// lambda'/6 terms, m > 1); lam_out receives lambda at m = 1 (it must not alias lam or ubar).  kin = Kb_m
+// (m < 4), kout = Kb_{m-1}, ubar the running lambda' + sum yb, mu += h Re(conj(Kb_m) y_m) (mu null: skipped),
+// inj added to lambda at m = 1 (null: none).
+template <int KIND, int NC>
+__global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int m,
+                                                        const cx<double>* __restrict__ lam,
+                                                        cx<double>* __restrict__ lam_out,
+                                                        const cx<double>* __restrict__ kin,
+                                                        const cx<double>* __restrict__ y, cx<double>* kout,
+                                                        cx<double>* ubar, double* __restrict__ mu,
+                                                        const cx<double>* __restrict__ inj, double h) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= opH.nsite) return;
+  const int64_t blk = (int64_t)NC * opH.nsite;
+  double musum = 0.0;
+  for (int b = 0; b < k; ++b) {
+    cx<double> z[NC];
+    zsite<KIND, NC>(opH, (m == 4 ? lam : kin) + b * blk, p, z);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t e = b * blk + c * opH.nsite + p;
+      const cx<double> lp = m > 1 ? lam[e] : mk<double>(0.0, 0.0);
+      cx<double> kb;  // Kb_m at this point
+      if (m == 4) {
+        kb = mk<double>(lp.re / 6.0, lp.im / 6.0);
+        z[c] = mk<double>(z[c].re / 6.0, z[c].im / 6.0);  // Z^H (lambda'/6)
+        kout[e] = mk<double>(lp.re / 3.0 + z[c].re, lp.im / 3.0 + z[c].im);
+        ubar[e] = mk<double>(lp.re + z[c].re, lp.im + z[c].im);
+      } else {
+        kb = kin[e];
+        const cx<double> ub = ubar[e];
+        if (m == 1) {
+          cx<double> l = mk<double>(ub.re + z[c].re, ub.im + z[c].im);
+          if (inj != nullptr) {
+            l.re += inj[e].re;
+            l.im += inj[e].im;
+          }
+          lam_out[e] = l;
+        } else {
+          const double w = m == 3 ? 1.0 / 3.0 : 1.0 / 6.0;
+          kout[e] = mk<double>(w * lp.re + 0.5 * z[c].re, w * lp.im + 0.5 * z[c].im);
+          ubar[e] = mk<double>(ub.re + z[c].re, ub.im + z[c].im);
+        }
+      }
+      if (mu != nullptr) {
+        const cx<double> yy = y[e];
+        musum += kb.re * yy.re + kb.im * yy.im;  // Re(conj(kb) y)
+      }
+    }
+  }
+  if (mu != nullptr) mu[p] += h * musum;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
+                     void* acc, const void* f, double h, hipStream_t st) {
+  const dim3 grid((unsigned)((op.nsite + 255) / 256));
+#define RES_F(KIND, NC)                                                                                          \
+  hipLaunchKernelGGL((fwd_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, op, k, m, (const cx<double>*)u,      \
+                     (cx<double>*)uout, (const cx<double>*)yin, (cx<double>*)yout, (cx<double>*)acc, (const cx<double>*)f, h)
+  if (op.kind == 0) RES_F(0, 1);
+  else if (op.ncomp == 3) RES_F(1, 3);
+  else RES_F(1, 1);
+#undef RES_F
+  return 0;
+}
+
+int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
+                     const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st) {
+  const dim3 grid((unsigned)((opH.nsite + 255) / 256));
+#define RES_R(KIND, NC)                                                                                            \
+  hipLaunchKernelGGL((rev_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, opH, k, m,                          \
+                     (const cx<double>*)lam, (cx<double>*)lam_out, (const cx<double>*)kin, (const cx<double>*)y,     \
+                     (cx<double>*)kout, (cx<double>*)ubar, mu, (const cx<double>*)inj, h)
+  if (opH.kind == 0) RES_R(0, 1);
+  else if (opH.ncomp == 3) RES_R(1, 3);
+  else RES_R(1, 1);
+#undef RES_R
+  return 0;
+}
+
+}  // namespace res

@@ -58,6 +58,21 @@ int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* 
 int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                        int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
 
+// ---- discrete adjoint (reverse-mode) stage kernels, FP64 -----------------------------------------------
+// kind 0: three-point complex operator, tri = [nsite][3] (lower, diag, upper) of Z (or Z^H); kind 1: grid
+// operator g (FP64 coefficients), nsite = nodes, ncomp components per node.  Columns are [k][ncomp][nsite].
+struct AdjOpDev {
+  int kind;
+  int ncomp;
+  int64_t nsite;
+  const void* tri;
+  GridOpDev g;
+};
+int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
+                     void* acc, const void* f, double h, hipStream_t st);
+int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
+                     const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
+
 // ---- phase GEMMs --------------------------------------------------------------------------------------
 struct PhaseGemmArgs {
   int mode;                // 0 synthesis, 1 projection

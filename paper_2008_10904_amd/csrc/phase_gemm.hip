@@ -1,7 +1,7 @@
 // Forcing synthesis and Fourier projection as complex GEMMs on MFMA (FP64 16x16x4 or FP32 16x16x4).
 //
 //   synthesis  (Sec. 2.3, eq. forceFseries, complex branch):  out[r][n] = sum_j e^{i sw_j t_s} G[j][n],
-//              s = s0 + r, t_s = s h  -- the rows are the forcing samples of consecutive time steps;
+//              s = s0 + r*stride, t_s = s h  -- the rows are forcing samples of (usually consecutive) steps;
 //   projection (eq. fourier, evaluated as a finite sum):     acc[j][n] += scale * sum_m e^{-i sw_j t_m} X[m][n],
 //              t_m = (s0 + m*stride) h  -- the rows of X are state snapshots.
 //
@@ -71,8 +71,8 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   int64_t idx = 0, step = 0, step16 = 0;
   bool arow_ok;
   if (MODE == 0) {
-    // row = time sample s = s0 + m0 + ar; column kk = frequency j: index (j * smod) mod P
-    const int64_t s = a.s0 + m0 + ar;
+    // row = time sample s = s0 + (m0 + ar) * stride; column kk = frequency j: index (j * smod) mod P
+    const int64_t s = a.s0 + (m0 + ar) * (a.stride > 0 ? a.stride : 1);
     arow_ok = (m0 + ar) < a.M;
     const int64_t smod = s % P;
     step = smod;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   }
 
   if (MODE == 0 && tid < GBM) {
-    const int64_t s = a.s0 + m0 + tid;
+    const int64_t s = a.s0 + (m0 + tid) * (a.stride > 0 ? a.stride : 1);
     double sn, cs;
     sincos(sig * a.w0h * (double)s, &sn, &cs);
     ph_re[tid] = cs;

@@ -118,6 +118,7 @@ struct resolvent_op {
   // workspace and caches
   std::map<std::string, DevBuf> ws;
   std::map<int64_t, void*> btab;
+  std::map<int64_t, void*> btab64;        // FP64 phase tables of the mixed-precision operator (reverse mode)
   int* d_flag = nullptr;
   double decay_time = -1;
   bool fp64() const { return prec == RES_FP64; }
@@ -393,6 +394,23 @@ int phase_table(resolvent_op* op, int64_t P, void** out) {
   return RES_OK;
 }
 
+// FP64 table e^{2 pi i m / P} whatever the working precision (the reverse mode always runs in FP64).
+int phase_table64(resolvent_op* op, int64_t P, void** out) {
+  if (op->fp64()) return phase_table(op, P, out);
+  auto it = op->btab64.find(P);
+  if (it != op->btab64.end()) {
+    *out = it->second;
+    return RES_OK;
+  }
+  std::vector<cd> t((size_t)P);
+  for (int64_t m = 0; m < P; ++m) t[m] = std::polar(1.0, 2.0 * M_PI * (double)m / (double)P);
+  void* d = nullptr;
+  RES_TRY(upload(&d, t.data(), t.size() * sizeof(cd)));
+  op->btab64[P] = d;
+  *out = d;
+  return RES_OK;
+}
+
 struct Plan {
   double w0, dw;
   int nw;
@@ -459,47 +477,81 @@ int64_t max_instance_len(const resolvent_op* op) {
 // Flush `rows` buffered snapshot rows (the first being projected sample m_first) into acc.
 void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStream_t st);
 
+// acc[j][n] += scale * sum_m e^{-i sigma w_j t_m} rows[m][n] for m < count, t_m = (s0 + m*stride) h,
+// w_j = w0 + j dw, dw = 2 pi / (P h); rows have leading dimension ld; the GEMM runs in FP64 if fp64 != 0.
+int project_rows(resolvent_op* op, int fp64, int nw, int64_t P, double w0h, int sigma, void* btab, const void* rows,
+                 int64_t ld, int64_t ncols, int64_t s0, int64_t stride, int64_t count, double scale, double* acc,
+                 hipStream_t st) {
+  if (count <= 0) return RES_OK;
+  PhaseGemmArgs a{};
+  a.mode = 1;
+  a.M = nw;
+  a.Ncols = ncols;
+  a.K = count;
+  a.btab = btab;
+  a.P = P;
+  a.sigma = sigma;
+  a.w0h = w0h;
+  a.s0 = s0;
+  a.stride = stride;
+  a.bmat = rows;
+  a.ldb = ld;
+  a.out = acc;
+  a.scale = scale;
+  // split K so that the grid has enough workgroups
+  const int64_t tiles = ((nw + 63) / 64) * ((ncols + 63) / 64);
+  int64_t nsplit = 1;
+  if (tiles < 1024) nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, (count + 63) / 64);
+  if (nsplit < 1) nsplit = 1;
+  const int64_t kps = ((count + nsplit - 1) / nsplit + 15) / 16 * 16;
+  nsplit = (count + kps - 1) / kps;
+  a.k_per_split = kps;
+  if (nsplit > 1) {
+    void* part = nullptr;
+    RES_TRY(ws_get(op, "proj_partial", (size_t)nsplit * nw * ncols * sizeof(cd), &part));
+    a.partial = part;
+    if (launch_phase_gemm(a, fp64, st)) return fail(RES_EINVAL, "projection GEMM launch");
+    launch_reduce_partials(part, acc, (int64_t)nw * ncols, (int)nsplit, scale, st);
+  } else {
+    a.partial = nullptr;
+    if (launch_phase_gemm(a, fp64, st)) return fail(RES_EINVAL, "projection GEMM launch");
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+// out[r][n] = sum_j e^{i sigma w_j t_r} G[j][n] for r < M, t_r = (s0 + r*stride) hs with w0h = w0 hs and a
+// table of period P (dw hs = 2 pi / P); G is [nw][ncols].
+int synth_rows(int fp64, int nw, int64_t P, double w0h, int sigma, const void* btab, const void* G, int64_t ncols,
+               int64_t s0, int64_t stride, int64_t M, void* out, hipStream_t st) {
+  if (M <= 0) return RES_OK;
+  PhaseGemmArgs a{};
+  a.mode = 0;
+  a.M = M;
+  a.Ncols = ncols;
+  a.K = nw;
+  a.btab = btab;
+  a.P = P;
+  a.sigma = sigma;
+  a.w0h = w0h;
+  a.s0 = s0;
+  a.stride = stride;
+  a.bmat = G;
+  a.ldb = ncols;
+  a.out = out;
+  a.k_per_split = nw;
+  if (launch_phase_gemm(a, fp64, st)) return fail(RES_EINVAL, "synthesis GEMM launch");
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* btab, const void* snap,
                      int64_t snap_ld, int64_t m_first, int64_t rows, double* acc, hipStream_t st) {
   if (rows <= 0) return RES_OK;
   trace_norm("snapshots", snap, rows * snap_ld, op->fp64(), st);
-  const int64_t ncols = (int64_t)k * op->N;
-  PhaseGemmArgs a{};
-  a.mode = 1;
-  a.M = pl.nw;
-  a.Ncols = ncols;
-  a.K = rows;
-  a.btab = btab;
-  a.P = pl.P;
-  a.sigma = sigma;
-  a.w0h = pl.w0 * op->h;
-  a.s0 = pl.pfirst + m_first * pl.pstride;
-  a.stride = pl.pstride;
-  a.bmat = snap;
-  a.ldb = snap_ld;
-  a.out = acc;
-  a.scale = pl.scale;
-  // split K so that the grid has enough workgroups
-  const int64_t tiles = ((pl.nw + 63) / 64) * ((ncols + 63) / 64);
-  int64_t nsplit = 1;
-  if (tiles < 1024) nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, (rows + 63) / 64);
-  if (nsplit < 1) nsplit = 1;
-  const int64_t kps = ((rows + nsplit - 1) / nsplit + 15) / 16 * 16;
-  nsplit = (rows + kps - 1) / kps;
-  a.k_per_split = kps;
   TimedLaunch tl(op, RES_TIMING_PROJECTION, st);
-  if (nsplit > 1) {
-    void* part = nullptr;
-    RES_TRY(ws_get(op, "proj_partial", (size_t)nsplit * pl.nw * ncols * sizeof(cd), &part));
-    a.partial = part;
-    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "projection GEMM launch");
-    launch_reduce_partials(part, acc, (int64_t)pl.nw * ncols, (int)nsplit, pl.scale, st);
-  } else {
-    a.partial = nullptr;
-    if (launch_phase_gemm(a, op->fp64(), st)) return fail(RES_EINVAL, "projection GEMM launch");
-  }
-  HIP_TRY(hipGetLastError());
-  return RES_OK;
+  return project_rows(op, op->fp64(), pl.nw, pl.P, pl.w0 * op->h, sigma, btab, snap, snap_ld, (int64_t)k * op->N,
+                      pl.pfirst + m_first * pl.pstride, pl.pstride, rows, pl.scale, acc, st);
 }
 
 // Opt-in diagnostics (RESOLVENT_TRACE=1): synchronise and print the 2-norm of a device complex array.
@@ -944,6 +996,181 @@ int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
   }
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// Reverse mode: gradient of a real objective of u_hat = resolvent_apply(f_hat) with respect to f_hat and to a real
+// perturbation of L's diagonal, by the exact discrete adjoint of the classical four-stage march (see adjoint.hip).
+//
+// The forward trajectory is marched once in stage form (FP64, raw forcing sampled at the stage times t_s,
+// t_s + h/2, t_s + h, synthesised on the half-step grid) keeping the state every C steps; the segments are then
+// visited in reverse: the states of the segment are recomputed from its checkpoint, and each step runs three
+// stage recomputations and four reverse stages.  The adjoint state lambda_s = dJ/du_s receives the projection's
+// seed scale * sum_j e^{+i w_j t_s} g_j at the sampled steps.  The forcing gradient uses the single-step form
+// u_{s+1} = P(Z) u_s + sum_j e^{i w_j t_s} h Q_j(Z) F_j:  F_grad_j = (h Q_j(Z))^H sum_{forced s} e^{-i w_j t_s}
+// lambda_{s+1}, i.e. a Fourier projection of the lambda rows followed by the forcing pre-filter of Z^H at the
+// negated frequencies ((h Q_w(Z))^H = h Q_{-w}(Z^H)).
+AdjOpDev adj_op(const resolvent_op* op, int s) {
+  AdjOpDev a{};
+  if (is_grid(op)) {
+    a.kind = 1;
+    a.ncomp = op->ncomp;
+    a.nsite = op->nx * op->ny * op->nz;
+    a.g = op->g64[s];
+  } else {
+    a.kind = 0;
+    a.ncomp = 1;
+    a.nsite = op->N;
+    a.tri = op->d_tri[s];
+  }
+  return a;
+}
+
+int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const void* g_hat, void* f_grad,
+             double* mu_grad, int64_t C, hipStream_t st) {
+  const int64_t N = op->N, ncols = (int64_t)k * N, S = pl.S;
+  const int nw = pl.nw;
+  const size_t rowb = (size_t)ncols * sizeof(cd);
+  const double h = op->h;
+  if (C <= 0) C = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)S)));
+  C = std::min<int64_t>(C, S);
+  const int64_t ncp = (S + C - 1) / C;
+  const AdjOpDev fwd = adj_op(op, 0), rev = adj_op(op, 1);
+  const int64_t nsite = fwd.nsite;
+
+  // inputs in FP64: F (as given when FP64), seed G = scale * g
+  const void* F = f_hat;
+  if (!op->fp64()) {
+    void* p;
+    RES_TRY(ws_get(op, "bw_F", (size_t)nw * rowb, &p));
+    launch_convert(f_hat, 0, p, 1, (int64_t)nw * ncols, 1.0, st);
+    F = p;
+  }
+  void *G, *frow, *cps, *seg, *u, *acc, *y2, *y3, *y4, *ka, *kb, *ub, *lrows, *carry, *inj, *facc = nullptr;
+  void *btab_half, *btab;
+  RES_TRY(ws_get(op, "bw_G", (size_t)nw * rowb, &G));
+  launch_convert(g_hat, op->fp64(), G, 1, (int64_t)nw * ncols, pl.scale, st);
+  RES_TRY(ws_get(op, "bw_frow", (size_t)(2 * C + 1) * rowb, &frow));
+  RES_TRY(ws_get(op, "bw_ckpt", (size_t)ncp * rowb, &cps));
+  RES_TRY(ws_get(op, "bw_seg", (size_t)C * rowb, &seg));
+  RES_TRY(ws_get(op, "bw_u", rowb, &u));
+  RES_TRY(ws_get(op, "bw_acc", rowb, &acc));
+  RES_TRY(ws_get(op, "bw_y2", rowb, &y2));
+  RES_TRY(ws_get(op, "bw_y3", rowb, &y3));
+  RES_TRY(ws_get(op, "bw_y4", rowb, &y4));
+  RES_TRY(ws_get(op, "bw_ka", rowb, &ka));
+  RES_TRY(ws_get(op, "bw_kb", rowb, &kb));
+  RES_TRY(ws_get(op, "bw_ub", rowb, &ub));
+  RES_TRY(ws_get(op, "bw_lrows", (size_t)C * rowb, &lrows));
+  RES_TRY(ws_get(op, "bw_carry", rowb, &carry));
+  RES_TRY(ws_get(op, "bw_inj", (size_t)C * rowb, &inj));
+  if (f_grad) {
+    RES_TRY(ws_get(op, "bw_facc", (size_t)nw * rowb, &facc));
+    RES_TRY(zero_device(facc, (size_t)nw * rowb, st));
+  }
+  RES_TRY(phase_table64(op, 2 * pl.P, &btab_half));
+  RES_TRY(phase_table64(op, pl.P, &btab));
+  if (mu_grad) RES_TRY(zero_device(mu_grad, (size_t)nsite * sizeof(double), st));
+  auto row = [&](void* base, int64_t r) { return (void*)((char*)base + (size_t)r * rowb); };
+  // raw forcing of steps [sa, sb): half-step samples 2 sa .. 2 sb
+  auto synth_segment = [&](int64_t sa, int64_t sb) -> int {
+    if (sa >= pl.forced_end) return RES_OK;
+    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa, 1, 2 * (sb - sa) + 1,
+                      frow, st);
+  };
+  auto frc = [&](int64_t s, int64_t r, int half) -> const void* {
+    return s < pl.forced_end ? row(frow, 2 * r + half) : nullptr;
+  };
+  auto first_m_at_or_after = [&](int64_t t) -> int64_t {
+    if (t <= pl.pfirst) return 0;
+    return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
+  };
+
+  // 1. forward march with checkpoints
+  RES_TRY(zero_device(u, rowb, st));
+  for (int64_t c = 0; c < ncp; ++c) {
+    const int64_t sa = c * C, sb = std::min(S, sa + C);
+    HIP_TRY(hipMemcpyAsync(row(cps, c), u, rowb, hipMemcpyDeviceToDevice, st));
+    if (c == ncp - 1) break;  // the state after the last step is not needed
+    RES_TRY(synth_segment(sa, sb));
+    for (int64_t s = sa; s < sb; ++s) {
+      const int64_t r = s - sa;
+      launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, frc(s, r, 0), h, st);
+      launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 4, u, u, y2, nullptr, acc, frc(s, r, 2), h, st);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+
+  // 2. reverse sweep over the segments
+  RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
+  for (int64_t c = ncp - 1; c >= 0; --c) {
+    const int64_t sa = c * C, sb = std::min(S, sa + C), len = sb - sa;
+    RES_TRY(synth_segment(sa, sb));
+    // states u_sa .. u_{sb-1}
+    HIP_TRY(hipMemcpyAsync(row(seg, 0), row(cps, c), rowb, hipMemcpyDeviceToDevice, st));
+    for (int64_t s = sa; s + 1 < sb; ++s) {
+      const int64_t r = s - sa;
+      void* us = row(seg, r);
+      launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, acc, frc(s, r, 0), h, st);
+      launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y2, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 4, us, row(seg, r + 1), y2, nullptr, acc, frc(s, r, 2), h, st);
+    }
+    // projection seeds of the sampled steps in [sa, sb)
+    const int64_t ma = first_m_at_or_after(sa), mb = first_m_at_or_after(sb);
+    if (mb > ma)
+      RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, G, ncols, pl.pfirst + ma * pl.pstride, pl.pstride, mb - ma,
+                         inj, st));
+    // lambda rows: lrows[r] = lambda_{sa + r + 1}
+    HIP_TRY(hipMemcpyAsync(row(lrows, len - 1), carry, rowb, hipMemcpyDeviceToDevice, st));
+    for (int64_t s = sb - 1; s >= sa; --s) {
+      const int64_t r = s - sa;
+      void* us = row(seg, r);
+      launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st);
+      launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st);
+      const void* lp = row(lrows, r);
+      const void* seed = nullptr;
+      if (s >= pl.pfirst && (s - pl.pfirst) % pl.pstride == 0) {
+        const int64_t m = (s - pl.pfirst) / pl.pstride;
+        if (m < pl.pcount) seed = row(inj, m - ma);
+      }
+      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, y4, ka, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 3, lp, nullptr, ka, y3, kb, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 2, lp, nullptr, kb, y2, ka, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lrows, r - 1) : carry, ka, us, nullptr, ub, mu_grad, seed, h, st);
+    }
+    HIP_TRY(hipGetLastError());
+    // forcing gradient: Fourier sums of lambda_{s+1} over the forced steps of the segment
+    const int64_t nf = std::min(sb, pl.forced_end) - sa;
+    if (f_grad && nf > 0)
+      RES_TRY(project_rows(op, 1, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, sa, 1, nf, 1.0,
+                           (double*)facc, st));
+  }
+  // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j
+  if (f_grad) {
+    void *ya, *yb;
+    RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
+    RES_TRY(ws_get(op, "horner_b", (size_t)nw * rowb, &yb));
+    const double sw0h = -pl.w0 * h, sdwh = -pl.dw * h;
+    if (is_grid(op)) {
+      const GridOpDev& g = op->g64[1];
+      if (launch_grid_horner(g, nullptr, facc, 1, ya, 1, k, nw, sw0h, sdwh, h, 0, st) ||
+          launch_grid_horner(g, (const cx<double>*)ya, facc, 1, yb, 1, k, nw, sw0h, sdwh, h, 1, st) ||
+          launch_grid_horner(g, (const cx<double>*)yb, facc, 1, f_grad, op->fp64(), k, nw, sw0h, sdwh, h, 2, st))
+        return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
+    } else {
+      const cx<double>* tri = (const cx<double>*)op->d_tri[1];
+      launch_tri_horner(tri, nullptr, facc, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 0, st);
+      launch_tri_horner(tri, (const cx<double>*)ya, facc, 1, yb, 1, N, k, nw, sw0h, sdwh, h, 1, st);
+      launch_tri_horner(tri, (const cx<double>*)yb, facc, 1, f_grad, op->fp64(), N, k, nw, sw0h, sdwh, h, 2, st);
+    }
+    launch_finite(facc, 1, (int64_t)nw * ncols, op->d_flag, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 }  // namespace
 
 // =====================================================================================================
@@ -1071,6 +1298,8 @@ void resolvent_op_destroy(resolvent_op* op) {
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : op->btab)
     if (kv.second) (void)hipFree(kv.second);
+  for (auto& kv : op->btab64)
+    if (kv.second) (void)hipFree(kv.second);
   for (int s = 0; s < 2; ++s) {
     if (op->d_tri[s]) (void)hipFree(op->d_tri[s]);
     if (op->d_band[s]) (void)hipFree(op->d_band[s]);
@@ -1197,9 +1426,14 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
 int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream) {
-  (void)op; (void)grid; (void)run; (void)k; (void)f_hat; (void)g_hat; (void)f_grad; (void)mu_grad;
-  (void)checkpoint_every; (void)stream;
-  return fail(RES_ENOTSUP, "backward not implemented yet");
+  g_last_error.clear();
+  if (!op || !f_hat || !g_hat) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
+  if (checkpoint_every < 0) return fail(RES_EINVAL, "checkpoint_every must be >= 0");
+  Plan pl;
+  RES_TRY(make_plan(op, grid, run, &pl));
+  if (!f_grad && !mu_grad) return RES_OK;
+  return backward(op, pl, k, f_hat, g_hat, f_grad, mu_grad, checkpoint_every, (hipStream_t)stream);
 }
 
 int resolvent_op_set_timing(resolvent_op* op, int32_t enable) {
