@@ -34,7 +34,20 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: 2^30 bytes read and 2^30 bytes written per launch, three launches."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}), flush=True)
 
 
 def build_op(cfg, precision):
@@ -42,6 +55,31 @@ def build_op(cfg, precision):
     from paper_2008_10904_amd.operators import gl_coefficients
     lo, d, up = gl_coefficients(cfg["N"], cfg["mu0"], cfg["mu2"])
     return ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=precision)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step1d_gl_periodic_n2000_traffic.md")
+STEPPER_SOURCES = ("step1d.hip", "common.h", "kernels.h")
+
+
+def measured_traffic():
+    """HBM bytes per stepper launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
+    stepper's sources have changed since those counters were taken (their hash is recorded beside the figure)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEPPER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2008_10904_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    value, digest = None, None
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("traffic_bytes_per_launch:"):
+                    value = float(line.split(":", 1)[1])
+                elif line.startswith("source-sha256"):
+                    digest = line.rsplit(":", 1)[1].strip()
+    except OSError:
+        return None
+    return value if digest == h.hexdigest() else None
 
 
 def time_steps(op, f0, grid, run, K, W):
@@ -93,6 +131,9 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: the build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import numpy as np
     import torch
 
@@ -135,7 +176,7 @@ def main():
                    "time_steps_per_step": 2 * steps_per_run},
         "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
+                     "traffic": measured_traffic(), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
                      "steps_per_launch": steps_per_launch},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
     }
