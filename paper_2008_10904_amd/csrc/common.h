@@ -63,6 +63,10 @@ template <> __device__ __forceinline__ cx<float> load_nt<float>(const cx<float>*
   return mk<float>(t.x, t.y);
 }
 
+// s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8) that waits for
+// every outstanding vector-memory operation and leaves the other counters alone.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Workgroup barrier that orders LDS only: unlike __syncthreads() it does not wait for outstanding global
 // loads, so loads issued ahead of time (prefetched forcing rows) stay in flight across the barrier.
 __device__ __forceinline__ void lds_barrier() {

@@ -99,8 +99,10 @@ struct resolvent_op {
   int64_t step_chunk = 0;                // owned unknowns per workgroup (0: whole column in one workgroup)
   int cur_state = 0;                     // which of the two state buffers holds the current state
   bool step_persist = false;             // one cooperative launch per march, neighbour exchange in-kernel
-  uint32_t* d_flags = nullptr;           // per-workgroup block counters of the persistent stepper
+  uint32_t* d_flags = nullptr;           // per-workgroup block counters of the persistent stepper (in xch)
   size_t nflags = 0;
+  void* xch = nullptr;                   // uncached exchange area: flags, then two rows of published values
+  size_t xch_bytes = 0, xch_flag_bytes = 0;
   uint32_t flag_epoch = 1;               // flags only grow; each launch starts above every value written
   // 2-D / 3-D structured-grid operator: host coefficients of Z = h L (FP64) and device copies of Z and Z^H
   int ncomp = 1;
@@ -126,6 +128,12 @@ struct resolvent_op {
 };
 
 namespace {
+
+// Uncached exchange areas that are no longer used; kept allocated until the process ends.
+std::vector<void*>& retired_exchange_areas() {
+  static std::vector<void*> v;
+  return v;
+}
 
 int ws_get(resolvent_op* op, const std::string& name, size_t bytes, void** out) {
   DevBuf& b = op->ws[name];
@@ -605,14 +613,25 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     if (step1d_coresident(op->fp64(), op->step_cfg, dev) < nseg) persist = false;
   }
   if (persist) {
-    RES_TRY(ws_get(op, "xbuf", (size_t)2 * ncols * op->wsize(), &xbuf));
-    if (op->nflags < (size_t)nseg) {
-      if (op->d_flags) HIP_TRY(hipFree(op->d_flags));
-      HIP_TRY(hipMalloc((void**)&op->d_flags, (size_t)nseg * sizeof(uint32_t)));
-      HIP_TRY(hipMemsetAsync(op->d_flags, 0, (size_t)nseg * sizeof(uint32_t), st));
+    // Exchange area (flags, then two rows of published values) in uncached device memory: every access of the
+    // persistent stepper's neighbour exchange then goes to the device-coherent level, across XCDs, without L2
+    // write-back/invalidate fences.  Uncached memory is never freed once a kernel has used it (an outgrown
+    // area is retired, not released); it is reclaimed when the process ends.
+    const size_t flag_bytes = ((size_t)nseg * sizeof(uint32_t) + 255) / 256 * 256;
+    const size_t need = flag_bytes + (size_t)2 * ncols * op->wsize();
+    if (op->xch_bytes < need || op->nflags < (size_t)nseg) {
+      void* p = nullptr;
+      HIP_TRY(hipExtMallocWithFlags(&p, need, hipDeviceMallocUncached));
+      if (op->xch) retired_exchange_areas().push_back(op->xch);
+      op->xch = p;
+      op->xch_bytes = need;
+      op->d_flags = (uint32_t*)p;
       op->nflags = (size_t)nseg;
+      op->xch_flag_bytes = flag_bytes;
+      HIP_TRY(hipMemsetAsync(op->d_flags, 0, flag_bytes, st));
       op->flag_epoch = 1;
     }
+    xbuf = (char*)op->xch + op->xch_flag_bytes;
     const int64_t nblk = (n + op->step_block - 1) / op->step_block;
     if ((uint64_t)op->flag_epoch + (uint64_t)nblk + 2 >= 0xF0000000ull) {
       HIP_TRY(hipMemsetAsync(op->d_flags, 0, op->nflags * sizeof(uint32_t), st));
@@ -1305,7 +1324,7 @@ void resolvent_op_destroy(resolvent_op* op) {
     if (op->d_band[s]) (void)hipFree(op->d_band[s]);
   }
   if (op->d_off) (void)hipFree(op->d_off);
-  if (op->d_flags) (void)hipFree(op->d_flags);
+  if (op->xch) retired_exchange_areas().push_back(op->xch);  // uncached memory is not freed (see march_1d)
   for (void* b : op->gbufs) (void)hipFree(b);
   for (int c = 0; c < 4; ++c)
     for (auto& e : op->tev[c]) {

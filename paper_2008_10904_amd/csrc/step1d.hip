@@ -30,9 +30,13 @@ namespace res {
 // operations exactly, so the prefetched loads are waited for with partial counts.
 //
 // PERSIST: the launch marches all n_steps in blocks of `block` steps (a multiple of PD).  After each block a
-// workgroup publishes its owned values to xbuf[b & 1], raises flags[blockIdx.x] to epoch + b + 1 (release at
-// agent scope), waits until both halo neighbours have done the same (relaxed spin, then acquire) and reloads its
-// halo from their published values.  Double buffering is safe: a neighbour can only overwrite xbuf[b & 1] again
+// workgroup publishes its owned values to xbuf[b & 1], raises flags[blockIdx.x] to epoch + b + 1, waits until
+// both halo neighbours have done the same and reloads its halo from their published values.  Every access to
+// xbuf and flags is an agent-scope atomic (a device-coherent access) to uncached memory.  The order "data
+// stores complete, then flag store" comes from an explicit vmcnt(0) wait in every wave before the barrier that
+// precedes the flag store, and "flag observed, then data loads" from the barrier after tid 0's spin.  This
+// avoids the agent-scope release/acquire fences, which write back and invalidate the L2 of the XCD at every
+// exchange (measured: about a quarter of the step time).  Double buffering is safe: a neighbour can only overwrite xbuf[b & 1] again
 // after this workgroup has published block b + 1, i.e. after it finished reading.  Every wait is bounded by
 // `spin_ns` of wall-clock time: on expiry the workgroup poisons its flag, sets *err and returns, so every wave
 // of the grid terminates.  The grid must be co-resident (the launcher uses a cooperative launch).
@@ -134,74 +138,94 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
   };
 
   if (PERSIST) {
-    // blocks of `block` steps (multiple of PD), neighbour exchange between blocks
+    // Blocks of `block` steps (a multiple of PD) with a neighbour exchange before every block but the first.
+    // exchange(b) publishes the owned values of the state after block b-1, waits for both neighbours to have
+    // published theirs and reloads the halo; it returns false when the wait was abandoned (the grid drains).
     __shared__ int abort_flag;
-    const int64_t nblk = (n_steps + block - 1) / block;
-    FRow f[PD];
+    auto exchange = [&](int64_t b) -> bool {
+      cx<R>* pub = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (own[v]) {
+          __hip_atomic_store(&pub[lc[v]].re, u[v].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&pub[lc[v]].im, u[v].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      // __syncthreads() alone does not wait for outstanding global stores (its workgroup-scope release needs no
+      // vmcnt wait), so the flag store below could overtake another wave's data stores: wait for them here.
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __syncthreads();
+      if (tid == 0) {
+        abort_flag = 0;
+        const uint32_t target = epoch + (uint32_t)b;
+        __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        const uint64_t limit = spin_ns / 10;  // wall_clock64 ticks at 100 MHz
+        const int nb[2] = {sg.left, sg.right};
+        for (int side = 0; side < 2; ++side) {
+          if (nb[side] < 0) continue;
+          while (true) {
+            const uint32_t fv = __hip_atomic_load(flags + nb[side], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (fv == 0xffffffffu) { abort_flag = 1; break; }
+            if ((int32_t)(fv - target) >= 0) break;
+            if (wall_clock64() - t0 > limit) { abort_flag = 1; break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        if (abort_flag) {
+          atomicOr(err, 8);
+          __hip_atomic_store(flags + blockIdx.x, 0xffffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      __syncthreads();  // the halo loads below are issued after tid 0 has seen both neighbours' flags
+      if (abort_flag) return false;
+      cx<R>* src = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (valid[v] && !own[v]) {
+          u[v].re = __hip_atomic_load(&src[lc[v]].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          u[v].im = __hip_atomic_load(&src[lc[v]].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      // Complete every outstanding load here, so that the loads still in flight when the step code resumes are
+      // exactly the forcing ring's, in ring order, whichever path led there: the compiler then waits for each
+      // ring slot with an exact count instead of draining the ring (vmcnt(0)) at every round.
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      return true;
+    };
     if (FORCED) {
+      // One flat loop over rounds of PD steps (the ring's period); the exchange is a uniform branch inside it.
+      FRow f[PD];
 #pragma unroll
       for (int q = 0; q < PD; ++q) f[q] = load_row();
-    }
-    int64_t t = 0;
-    for (int64_t b = 0; b < nblk; ++b) {
-      if (b > 0) {
-        // publish the owned values of the state after block b-1, then fetch the halo from the neighbours
-        cx<R>* pub = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-          if (own[v]) pub[lc[v]] = u[v];
-        __syncthreads();
-        if (tid == 0) {
-          abort_flag = 0;
-          const uint32_t target = epoch + (uint32_t)b;
-          __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          const uint64_t t0 = wall_clock64();
-          const uint64_t limit = spin_ns / 10;  // wall_clock64 ticks at 100 MHz
-          const int nb[2] = {sg.left, sg.right};
-          for (int side = 0; side < 2; ++side) {
-            if (nb[side] < 0) continue;
-            while (true) {
-              const uint32_t fv = __hip_atomic_load(flags + nb[side], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              if (fv == 0xffffffffu) { abort_flag = 1; break; }
-              if ((int32_t)(fv - target) >= 0) break;
-              if (wall_clock64() - t0 > limit) { abort_flag = 1; break; }
-              __builtin_amdgcn_s_sleep(1);
-            }
-          }
-          if (abort_flag) {
-            atomicOr(err, 8);
-            __hip_atomic_store(flags + blockIdx.x, 0xffffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int64_t n_main = (n_steps / PD) * PD;
+      const int64_t rounds_per_block = block / PD;
+      int64_t t = 0, b = 0, until_exchange = rounds_per_block;
+      for (; t < n_main; t += PD) {
+        if (until_exchange == 0) {
+          if (!exchange(++b)) return;
+          until_exchange = rounds_per_block;
         }
-        __syncthreads();
-        if (abort_flag) return;
-        const cx<R>* src = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+        --until_exchange;
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-          if (valid[v] && !own[v]) u[v] = src[lc[v]];
+        for (int q = 0; q < PD; ++q) {
+          step(t + q, f[q]);
+          __builtin_amdgcn_sched_barrier(0);
+          f[q] = load_row();  // refills past the last step read padding rows
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
-      const int64_t te = (t + block < n_steps) ? t + block : n_steps;
-      if (FORCED) {
-        for (; t + PD <= te; t += PD) {
-#pragma unroll
-          for (int q = 0; q < PD; ++q) {
-            step(t + q, f[q]);
-            __builtin_amdgcn_sched_barrier(0);
-            f[q] = load_row();  // refills past the last step read padding rows
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        }
-        // the launch's last steps when n_steps is not a multiple of PD (blocks are multiples of PD)
+      if (t < n_steps) {
+        if (until_exchange == 0 && !exchange(++b)) return;
 #pragma unroll
         for (int q = 0; q < PD; ++q)
-          if (t + q < te) step(t + q, f[q]);
-        t = te;
-      } else {
-        FRow none;
+          if (t + q < n_steps) step(t + q, f[q]);
+      }
+    } else {
+      FRow none;
 #pragma unroll
-        for (int v = 0; v < V; ++v) none.v[v] = zero;
-        for (; t < te; ++t) step(t, none);
+      for (int v = 0; v < V; ++v) none.v[v] = zero;
+      for (int64_t t = 0; t < n_steps; ++t) {
+        if (t > 0 && t % block == 0 && !exchange(t / block)) return;
+        step(t, none);
       }
     }
   } else {

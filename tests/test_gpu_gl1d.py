@@ -226,3 +226,34 @@ def test_halo_regions_match_oracle(plan, monkeypatch):
         say("  inst", m, per_freq_relerr(outp[:, :, sl], refp), per_freq_relerr(outt[:, :, sl], reft))
         assert per_freq_relerr(outp[:, :, sl], refp) < 1e-10
         assert per_freq_relerr(outt[:, :, sl], reft) < 1e-10
+
+
+_SCALE_REF = {}
+
+
+@pytest.mark.parametrize("plan", ["12,96,8", "2,96,16", "12,128,16", "13,256,32"])
+def test_persistent_exchange_at_scale(plan, monkeypatch):
+    """Many workgroups exchanging halos every 8-32 steps (GL N=2000, k=2, up to 84 workgroups, 8,192 steps):
+    the persistent launch must agree bit for bit with the relaunch form of the same plan, and with the oracle.
+    Regression test: the neighbour flag was once raised before other waves' published values had landed."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    say("case: persistent exchange at scale, plan", plan)
+    n, h, P, nw, k = 2000, 0.001, 4096, 4, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(12, nw, k, n)
+    lo, d, up = gl_coefficients(n, 0.38, -0.01)
+    outs = []
+    for form in (plan, plan + ",0"):
+        monkeypatch.setenv("RESOLVENT_STEP1D", form)
+        op = ResolventOp.tridiagonal(lo, d, up, h)
+        outs.append(to_np(op.apply(gpu_tensor(F), op.grid(-3.0, dw, nw), op.run("periodic", periods=2, stride=64))))
+        torch.cuda.synchronize()
+    if "ref" not in _SCALE_REF:
+        L, _ = O_ops.gl_operator(n, 0.38, -0.01)
+        _SCALE_REF["ref"] = O_st.run(L, h, -3.0, dw, F, "periodic", periods=2, stride=64)
+    err = per_freq_relerr(outs[0], _SCALE_REF["ref"])
+    say("  persistent vs relaunch identical:", np.array_equal(outs[0], outs[1]), " vs oracle", err)
+    assert np.array_equal(outs[0], outs[1])
+    assert err < 1e-10
