@@ -25,11 +25,10 @@ struct Step1DArgs {
   double phi_re, phi_im;
   void* snap;              // snapshot rows (length snap_ld >= row_len + 1) or null
   int64_t snap_ld, snap_first, snap_stride, snap_count, snap_row0;
-  // persistent variant: blocks of `block` steps with neighbour exchange through xbuf (2 rows) and flags
+  // persistent variant: blocks of `block` steps with neighbour exchange through xbuf ([2][2][row_len] complex
+  // slots in uncached memory, every slot empty at launch: launch_fill_empty)
   int persist;
   void* xbuf;
-  uint32_t* flags;
-  uint32_t epoch;
   int64_t block;
   uint64_t spin_ns;
   int* err;
@@ -38,6 +37,7 @@ int step1d_coresident(int fp64, int cfg, int device);
 int step1d_prefetch(int cfg);
 int step1d_capacity(int cfg);
 int launch_step1d(const Step1DArgs& a, hipStream_t st);
+int launch_fill_empty(void* xbuf, int fp64, int64_t count, hipStream_t st);
 int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                       int out_fp64, int64_t N, int k, int nw, double sw0h, double sdwh, double h, int pass,
                       hipStream_t st);

@@ -99,11 +99,8 @@ struct resolvent_op {
   int64_t step_chunk = 0;                // owned unknowns per workgroup (0: whole column in one workgroup)
   int cur_state = 0;                     // which of the two state buffers holds the current state
   bool step_persist = false;             // one cooperative launch per march, neighbour exchange in-kernel
-  uint32_t* d_flags = nullptr;           // per-workgroup block counters of the persistent stepper (in xch)
-  size_t nflags = 0;
-  void* xch = nullptr;                   // uncached exchange area: flags, then two rows of published values
-  size_t xch_bytes = 0, xch_flag_bytes = 0;
-  uint32_t flag_epoch = 1;               // flags only grow; each launch starts above every value written
+  void* xch = nullptr;                   // uncached exchange rows of the persistent stepper
+  size_t xch_bytes = 0;
   // 2-D / 3-D structured-grid operator: host coefficients of Z = h L (FP64) and device copies of Z and Z^H
   int ncomp = 1;
   int64_t nx = 0, ny = 1, nz = 1;
@@ -613,30 +610,20 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     if (step1d_coresident(op->fp64(), op->step_cfg, dev) < nseg) persist = false;
   }
   if (persist) {
-    // Exchange area (flags, then two rows of published values) in uncached device memory: every access of the
-    // persistent stepper's neighbour exchange then goes to the device-coherent level, across XCDs, without L2
-    // write-back/invalidate fences.  Uncached memory is never freed once a kernel has used it (an outgrown
-    // area is retired, not released); it is reclaimed when the process ends.
-    const size_t flag_bytes = ((size_t)nseg * sizeof(uint32_t) + 255) / 256 * 256;
-    const size_t need = flag_bytes + (size_t)2 * ncols * op->wsize();
-    if (op->xch_bytes < need || op->nflags < (size_t)nseg) {
+    // Exchange rows in uncached device memory: every access of the persistent stepper's neighbour exchange then
+    // goes to the device-coherent level, across XCDs, without L2 write-back/invalidate fences.  Uncached memory
+    // is never freed once a kernel has used it (an outgrown area is retired, not released); it is reclaimed when
+    // the process ends.  Every slot starts empty for each launch.
+    const size_t need = (size_t)4 * ncols * op->wsize();  // [2 buffers][2 directions][ncols]
+    if (op->xch_bytes < need) {
       void* p = nullptr;
       HIP_TRY(hipExtMallocWithFlags(&p, need, hipDeviceMallocUncached));
       if (op->xch) retired_exchange_areas().push_back(op->xch);
       op->xch = p;
       op->xch_bytes = need;
-      op->d_flags = (uint32_t*)p;
-      op->nflags = (size_t)nseg;
-      op->xch_flag_bytes = flag_bytes;
-      HIP_TRY(hipMemsetAsync(op->d_flags, 0, flag_bytes, st));
-      op->flag_epoch = 1;
     }
-    xbuf = (char*)op->xch + op->xch_flag_bytes;
-    const int64_t nblk = (n + op->step_block - 1) / op->step_block;
-    if ((uint64_t)op->flag_epoch + (uint64_t)nblk + 2 >= 0xF0000000ull) {
-      HIP_TRY(hipMemsetAsync(op->d_flags, 0, op->nflags * sizeof(uint32_t), st));
-      op->flag_epoch = 1;
-    }
+    xbuf = op->xch;
+    launch_fill_empty(xbuf, op->fp64(), 4 * ncols, st);
   }
   const int64_t blk = (halo && !persist) ? op->step_block : n;
   for (int64_t b0 = 0; b0 < n; b0 += blk) {
@@ -673,8 +660,6 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     }
     a.persist = persist ? 1 : 0;
     a.xbuf = xbuf;
-    a.flags = op->d_flags;
-    a.epoch = op->flag_epoch;
     a.block = persist ? op->step_block : nb;
     a.spin_ns = 2000000000ull;
     a.err = op->d_flag;
@@ -684,7 +669,6 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
       rc = launch_step1d(a, st);
     }
     if (rc) return fail(RES_EHIP, "stepper launch failed (" + std::to_string(rc) + ")");
-    if (persist) op->flag_epoch += (uint32_t)((nb + op->step_block - 1) / op->step_block) + 1;
     if (halo && !persist) op->cur_state = 1 - op->cur_state;
   }
   HIP_TRY(hipGetLastError());
@@ -1486,11 +1470,7 @@ int resolvent_op_check(resolvent_op* op, void* stream) {
   if (flag) {
     int zero = 0;
     HIP_TRY(hipMemcpy(op->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice));
-    if (flag & 8) {
-      if (op->d_flags) HIP_TRY(hipMemset(op->d_flags, 0, op->nflags * sizeof(uint32_t)));
-      op->flag_epoch = 1;
-      return fail(RES_EHIP, "persistent stepper: neighbour synchronisation timed out");
-    }
+    if (flag & 8) return fail(RES_EHIP, "persistent stepper: neighbour synchronisation timed out");
     if (flag & 2) return fail(RES_ENONFINITE, "rank-deficient or non-finite block in the per-frequency QR");
     return fail(RES_ENONFINITE, "non-finite values in a result");
   }

@@ -11,10 +11,29 @@
 // nine-point stencil (radius 4); the host builds it once per operator.  The stepper therefore does ONE
 // neighbour exchange and nine complex multiply-adds per unknown and step instead of four exchanges and
 // twelve; the forcing sum is a precomputed row of the synthesis GEMM.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace res {
+
+// Empty mark of an exchange slot: a signalling-NaN bit pattern that no arithmetic produces (computed NaNs are
+// quiet), compared as raw bits.
+template <typename R> struct EmptyMark;
+template <> struct EmptyMark<double> {
+  typedef unsigned long long U;
+  static constexpr U bits = 0x7FF4DEAD5EA1ED00ull;
+};
+template <> struct EmptyMark<float> {
+  typedef unsigned int U;
+  static constexpr U bits = 0x7FA5EA1Du;
+};
+
+template <typename R> __global__ void fill_empty_kernel(typename EmptyMark<R>::U* p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = EmptyMark<R>::bits;
+}
 
 // One workgroup marches its region for n_steps steps.  Thread t holds V consecutive unknowns of the region in
 // registers together with their nine stencil coefficients; the state is exchanged through a double-buffered LDS
@@ -29,17 +48,18 @@ namespace res {
 // snap_row0 + m.  Keeping the store pattern a compile-time property lets the compiler count outstanding memory
 // operations exactly, so the prefetched loads are waited for with partial counts.
 //
-// PERSIST: the launch marches all n_steps in blocks of `block` steps (a multiple of PD).  After each block a
-// workgroup publishes its owned values to xbuf[b & 1], raises flags[blockIdx.x] to epoch + b + 1, waits until
-// both halo neighbours have done the same and reloads its halo from their published values.  Every access to
-// xbuf and flags is an agent-scope atomic (a device-coherent access) to uncached memory.  The order "data
-// stores complete, then flag store" comes from an explicit vmcnt(0) wait in every wave before the barrier that
-// precedes the flag store, and "flag observed, then data loads" from the barrier after tid 0's spin.  This
-// avoids the agent-scope release/acquire fences, which write back and invalidate the L2 of the XCD at every
-// exchange (measured: about a quarter of the step time).  Double buffering is safe: a neighbour can only overwrite xbuf[b & 1] again
-// after this workgroup has published block b + 1, i.e. after it finished reading.  Every wait is bounded by
-// `spin_ns` of wall-clock time: on expiry the workgroup poisons its flag, sets *err and returns, so every wave
-// of the grid terminates.  The grid must be co-resident (the launcher uses a cooperative launch).
+// PERSIST: the launch marches all n_steps in blocks of `block` steps (a multiple of PD).  Between blocks each
+// workgroup publishes the owned values its neighbours need (the 4*block nearest each end of its owned range, in
+// one row per direction) into rows (b - 1) & 1 of xbuf and takes its halo from the neighbours' rows.  Every slot
+// has one writer and one reader and holds either a value or the empty mark (a NaN bit pattern no arithmetic
+// produces): a halo lane polls its own slot until the neighbour's value has replaced the mark, takes it and
+// re-arms the slot, so the data itself carries the ready signal and no flag round trip is needed.  A
+// workgroup rewrites a row only after it has seen the neighbours' values of the following block, which they
+// publish only after their re-arming stores have completed (the vmcnt(0) wait that opens every exchange), so a
+// value is never overwritten by a late re-arm.  All slot accesses are agent-scope atomics (device-coherent) to
+// uncached memory; rows start empty (launch_fill_empty before each persistent launch).  Every wait is bounded
+// by `spin_ns` of wall-clock time: on expiry the workgroup sets *err and returns, and its neighbours then time
+// out in turn, so every wave of the grid terminates.  The grid must be co-resident (cooperative launch).
 template <typename R, int NT, int V, int PD, bool FORCED, int SNAP, bool PERSIST>
 __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ segs, const cx<R>* __restrict__ band,
                                                     const cx<R>* __restrict__ state_in, cx<R>* __restrict__ state_out,
@@ -48,8 +68,7 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
                                                     int64_t frc_period, R phi_re, R phi_im, cx<R>* __restrict__ snap,
                                                     int64_t snap_ld, int64_t snap_first, int64_t snap_stride,
                                                     int64_t snap_count, int64_t snap_row0, cx<R>* xbuf,
-                                                    uint32_t* flags, uint32_t epoch, int64_t block,
-                                                    uint64_t spin_ns, int* err) {
+                                                    int64_t block, uint64_t spin_ns, int* err) {
   constexpr int W = NT * V + 2 * kBandRadius;
   __shared__ cx<R> buf[2][W];
   const Seg1D sg = segs[blockIdx.x];
@@ -142,53 +161,58 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
     // exchange(b) publishes the owned values of the state after block b-1, waits for both neighbours to have
     // published theirs and reloads the halo; it returns false when the wait was abandoned (the grid drains).
     __shared__ int abort_flag;
+    if (tid == 0) abort_flag = 0;  // ordered before any exchange by the first step's barrier
+    typedef typename EmptyMark<R>::U U;
+    const int halo = kBandRadius * (int)block;  // halo width of a region = owned values a neighbour reads
     auto exchange = [&](int64_t b) -> bool {
-      cx<R>* pub = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+      // rows: [(b - 1) & 1][side], side 0 = values near the owner's left end (read by its left neighbour),
+      // side 1 = values near its right end (read by its right neighbour); every slot has one writer, one reader
+      U* rows = reinterpret_cast<U*>(xbuf + (int64_t)((b - 1) & 1) * 2 * row_len + cbase);
+      U* to_left = rows;
+      U* to_right = rows + 2 * row_len;
+      // The slots this workgroup re-armed at the previous exchange must be empty again before a neighbour can
+      // see this block's values: it rewrites them only after it has seen these.
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 #pragma unroll
       for (int v = 0; v < V; ++v)
         if (own[v]) {
-          __hip_atomic_store(&pub[lc[v]].re, u[v].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&pub[lc[v]].im, u[v].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      // __syncthreads() alone does not wait for outstanding global stores (its workgroup-scope release needs no
-      // vmcnt wait), so the flag store below could overtake another wave's data stores: wait for them here.
-      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-      __syncthreads();
-      if (tid == 0) {
-        abort_flag = 0;
-        const uint32_t target = epoch + (uint32_t)b;
-        __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t t0 = wall_clock64();
-        const uint64_t limit = spin_ns / 10;  // wall_clock64 ticks at 100 MHz
-        const int nb[2] = {sg.left, sg.right};
-        for (int side = 0; side < 2; ++side) {
-          if (nb[side] < 0) continue;
-          while (true) {
-            const uint32_t fv = __hip_atomic_load(flags + nb[side], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (fv == 0xffffffffu) { abort_flag = 1; break; }
-            if ((int32_t)(fv - target) >= 0) break;
-            if (wall_clock64() - t0 > limit) { abort_flag = 1; break; }
-            __builtin_amdgcn_s_sleep(1);
+          const int pos = lc[v] - sg.own0;
+          const U re = __builtin_bit_cast(U, u[v].re), im = __builtin_bit_cast(U, u[v].im);
+          if (pos < halo) {
+            __hip_atomic_store(to_left + 2 * lc[v], re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(to_left + 2 * lc[v] + 1, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          if (sg.nown - 1 - pos < halo) {
+            __hip_atomic_store(to_right + 2 * lc[v], re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(to_right + 2 * lc[v] + 1, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        if (abort_flag) {
-          atomicOr(err, 8);
-          __hip_atomic_store(flags + blockIdx.x, 0xffffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      __syncthreads();  // the halo loads below are issued after tid 0 has seen both neighbours' flags
-      if (abort_flag) return false;
-      cx<R>* src = xbuf + (int64_t)((b - 1) & 1) * row_len + cbase;
+      const uint64_t t0 = wall_clock64();
+      const uint64_t limit = spin_ns / 10;  // wall_clock64 ticks at 100 MHz
+      bool late = false;
 #pragma unroll
       for (int v = 0; v < V; ++v)
         if (valid[v] && !own[v]) {
-          u[v].re = __hip_atomic_load(&src[lc[v]].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          u[v].im = __hip_atomic_load(&src[lc[v]].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // a halo value left of the owned range is the left neighbour's right-end value, and vice versa
+          U* slot = (lc[v] < sg.own0 ? to_right : to_left) + 2 * lc[v];
+          U re, im;
+          while (true) {
+            re = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            im = __hip_atomic_load(slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (re != EmptyMark<R>::bits && im != EmptyMark<R>::bits) break;
+            if (wall_clock64() - t0 > limit) { late = true; break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          __hip_atomic_store(slot, EmptyMark<R>::bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(slot + 1, EmptyMark<R>::bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          u[v] = mk<R>(__builtin_bit_cast(R, re), __builtin_bit_cast(R, im));
         }
-      // Complete every outstanding load here, so that the loads still in flight when the step code resumes are
-      // exactly the forcing ring's, in ring order, whichever path led there: the compiler then waits for each
-      // ring slot with an exact count instead of draining the ring (vmcnt(0)) at every round.
-      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      if (late) abort_flag = 1;
+      __syncthreads();
+      if (abort_flag) {
+        if (tid == 0) atomicOr(err, 8);
+        return false;
+      }
       return true;
     };
     if (FORCED) {
@@ -331,14 +355,14 @@ static int launch_step1d_one(const Step1DArgs& a, hipStream_t st) {
   if (!PERSIST) {
     hipLaunchKernelGGL(kern, dim3(a.nseg), dim3(NT), 0, st, a.segs, band, sin, sout, a.N, a.row_len, a.n_steps, frc,
                        a.frc_row0, a.frc_period, phr, phi, snap, a.snap_ld, a.snap_first, a.snap_stride,
-                       a.snap_count, a.snap_row0, xbuf, a.flags, a.epoch, a.block, a.spin_ns, a.err);
+                       a.snap_count, a.snap_row0, xbuf, a.block, a.spin_ns, a.err);
     return 0;
   }
   void* args[] = {(void*)&a.segs, (void*)&band, (void*)&sin, (void*)&sout, (void*)&a.N, (void*)&a.row_len,
                   (void*)&a.n_steps, (void*)&frc, (void*)&a.frc_row0, (void*)&a.frc_period, (void*)&phr,
                   (void*)&phi, (void*)&snap, (void*)&a.snap_ld, (void*)&a.snap_first, (void*)&a.snap_stride,
-                  (void*)&a.snap_count, (void*)&a.snap_row0, (void*)&xbuf, (void*)&a.flags, (void*)&a.epoch,
-                  (void*)&a.block, (void*)&a.spin_ns, (void*)&a.err};
+                  (void*)&a.snap_count, (void*)&a.snap_row0, (void*)&xbuf, (void*)&a.block, (void*)&a.spin_ns,
+                  (void*)&a.err};
   return hipLaunchCooperativeKernel((const void*)kern, dim3(a.nseg), dim3(NT), args, 0, st) == hipSuccess ? 0 : -2;
 }
 
@@ -355,6 +379,14 @@ static int launch_step1d_cfg(const Step1DArgs& a, hipStream_t st) {
     if (mode == 0) RES_STEP(false, 0); else if (mode == 1) RES_STEP(false, 1); else RES_STEP(false, 2);
   }
 #undef RES_STEP
+}
+
+int launch_fill_empty(void* xbuf, int fp64, int64_t count, hipStream_t st) {
+  const int64_t words = 2 * count;  // re and im of `count` complex slots
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, (words + 255) / 256);
+  if (fp64) hipLaunchKernelGGL(fill_empty_kernel<double>, dim3(grid), dim3(256), 0, st, (EmptyMark<double>::U*)xbuf, words);
+  else hipLaunchKernelGGL(fill_empty_kernel<float>, dim3(grid), dim3(256), 0, st, (EmptyMark<float>::U*)xbuf, words);
+  return 0;
 }
 
 // Largest grid of this configuration that is co-resident on the device (for the persistent variant).
