@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="gl_periodic_n2000", choices=["gl_periodic_n2000", "gl_batched_64"],
+                    help="gl_periodic_n2000 (default, the headline line) or gl_batched_64 (64 uneven GL instances, "
+                         "mixed precision, reported beside its FP64 form)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -126,6 +129,57 @@ def cpu_baseline(cfg, w0, dw, F, seconds):
                        "%.1f s" % (n, dt))
 
 
+def bench_batched(args):
+    """One block-power iteration of the batched workload (64 GL instances packed back to back, k = 2, 128
+    frequencies, periodic method, mixed precision), with the FP64 form of the same iteration beside it."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_batched_coefficients, snap_grid
+
+    cfg = W.GL_BATCHED
+    inst = W.batched_instances()
+    lo, d, up, off = gl_batched_coefficients(inst)
+    ntot = int(off[-1])
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+    steps_per_run = cfg["periods"] * P
+    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], ntot)
+    sweeps_per_step = ntot * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
+    from paper_2008_10904_amd import autotune
+    res, plans = {}, {}
+    for prec, dtype in (("mixed", torch.complex64), ("fp64", torch.complex128)):
+        op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=prec, offsets=off)
+        plans[prec], _ = autotune.tuned(op, cfg["k"])
+        grid = op.grid(w0, dw, cfg["n_omega"])
+        run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+        f = torch.from_numpy(F).to(dtype).cuda()
+        res[prec] = time_steps(op, f, grid, run, args.steps, args.warmup)
+        del op, f
+        torch.cuda.empty_cache()
+    dtm, gm, ktm = res["mixed"]
+    dt64, g64, kt64 = res["fp64"]
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)",
+        "value": sweeps_per_step / dtm,
+        "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dtm * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 step/GEMM, f64 acc",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "instances": len(inst), "N_total": ntot, "k": cfg["k"],
+                   "n_omega": cfg["n_omega"], "P": P, "h": cfg["h"], "method": "periodic",
+                   "periods": cfg["periods"], "stride": cfg["stride"], "step": "one block-power iteration",
+                   "time_steps_per_step": 2 * steps_per_run},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()},
+        "fp64": {"value": sweeps_per_step / dt64, "ms_per_step": dt64 * 1e3, "dtype": "f64",
+                 "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt64.items()}},
+        "max_rel_gain_diff_mixed_vs_fp64": float(np.abs(gm / g64 - 1).max()),
+        "stepper_plan": {k: list(v) for k, v in plans.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -133,6 +187,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "gl_batched_64":
+        bench_batched(args)
         return
     import numpy as np
     import torch
@@ -146,7 +203,9 @@ def main():
     F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
     sweeps_per_step = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
 
+    from paper_2008_10904_amd import autotune
     op = build_op(cfg, "fp64")
+    plan64, _ = autotune.tuned(op, cfg["k"])  # set-up: the stepper plan (cached after the first run)
     grid = op.grid(w0, dw, cfg["n_omega"])
     run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
     f64 = torch.from_numpy(F).cuda()
@@ -179,16 +238,19 @@ def main():
                      "traffic": measured_traffic(), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
                      "steps_per_launch": steps_per_launch},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "stepper_plan": list(plan64),
     }
     del op, f64
     torch.cuda.empty_cache()
     if not args.no_mixed:
         opm = build_op(cfg, "mixed")
+        planm, _ = autotune.tuned(opm, cfg["k"])
         f32 = torch.from_numpy(F).to(torch.complex64).cuda()
         dtm, gainsm, ktm = time_steps(opm, f32, grid, run, args.steps, args.warmup)
         out["mixed"] = {"value": sweeps_per_step / dtm, "ms_per_step": dtm * 1e3, "dtype": "f32 step/GEMM, f64 acc",
                         "max_rel_gain_diff_vs_fp64": float(np.abs(gainsm / gains64 - 1).max()),
-                        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()}}
+                        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()},
+                        "stepper_plan": list(planm)}
         del opm, f32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, w0, dw, F, args.cpu_seconds)

@@ -165,6 +165,24 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);
 
+/* Stepper plan of a RES_OP_TRIDIAG operator (how the time march is laid out on the device; results do not
+ * depend on it, bit for bit): plan[0] = kernel configuration (0..15: threads per workgroup, unknowns per
+ * thread and forcing prefetch depth), plan[1] = owned unknowns per workgroup (0: each column in one
+ * workgroup), plan[2] = steps between neighbour exchanges (the halo is 4 * plan[2] unknowns per side),
+ * plan[3] = 1 for one persistent launch per march with in-kernel exchange, 0 for a relaunch per exchange.
+ * set_plan raises the configuration to the smallest that holds the longest region and drops persistence when
+ * the plan cannot exchange in-kernel; get_plan returns what is in effect.  RES_ENOTSUP for grid operators,
+ * RES_EINVAL for a malformed plan.  These are layout choices of this implementation, not of the paper. */
+int resolvent_op_get_plan(const resolvent_op* op, int32_t plan[4]);
+int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]);
+
+/* Stepper autotuner for RES_OP_TRIDIAG operators: times every candidate plan on `steps` forced steps of k
+ * columns on `stream` (the handle's state buffers are overwritten; run results are unaffected), keeps the
+ * fastest, and writes it to plan_out and its time per step in microseconds to us_per_step (each may be NULL).
+ * Synchronises the stream.  steps >= 16.  RES_ENOTSUP for grid operators. */
+int resolvent_op_tune(resolvent_op* op, int32_t k, int32_t steps, int32_t plan_out[4], double* us_per_step,
+                      void* stream);
+
 /* Opt-in kernel timing: while enabled, the library records HIP events on the caller's stream around each of its
  * kernel launches.  resolvent_op_get_timing synchronises the stream, returns the summed device time (ms) and
  * the number of launches of one kernel class since the last query, and resets that class.  Classes:

@@ -201,6 +201,25 @@ class ResolventOp:
             d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
         check(self._lib.resolvent_op_set_diagonal(self._h, _dptr(d), 0, self._stream_ptr()))
 
+    # ---- stepper plan and autotuner (1-D operators) ------------------------------------------------------------
+    def get_plan(self):
+        """(configuration, owned unknowns per workgroup, steps between exchanges, persistent) in effect."""
+        p = (ctypes.c_int32 * 4)()
+        check(self._lib.resolvent_op_get_plan(self._h, p))
+        return tuple(int(x) for x in p)
+
+    def set_plan(self, plan):
+        p = (ctypes.c_int32 * 4)(*[int(x) for x in plan])
+        check(self._lib.resolvent_op_set_plan(self._h, p))
+        return self.get_plan()
+
+    def tune(self, k, steps=2048):
+        """Time every candidate stepper plan for k columns and keep the fastest; returns (plan, us per step)."""
+        p = (ctypes.c_int32 * 4)()
+        us = ctypes.c_double()
+        check(self._lib.resolvent_op_tune(self._h, int(k), int(steps), p, ctypes.byref(us), self._stream_ptr()))
+        return tuple(int(x) for x in p), us.value
+
     def set_timing(self, enable=True):
         check(self._lib.resolvent_op_set_timing(self._h, 1 if enable else 0))
 

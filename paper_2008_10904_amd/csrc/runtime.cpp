@@ -334,6 +334,35 @@ int smallest_cfg(int64_t len) {
 // with a halo of 64 (16 steps per block), marched by one persistent cooperative launch with in-kernel neighbour
 // exchange when the grid is co-resident, else by relaunches every 16 steps.
 // RESOLVENT_STEP1D="cfg,chunk,block[,persist]" overrides it.
+// Apply a stepper plan: regions of one column, the kernel configuration (raised to the smallest that holds the
+// longest region when needed) and whether the march runs as one persistent launch.
+int apply_plan(resolvent_op* op, int cfg, int64_t chunk, int64_t block, int persist) {
+  if (cfg < 0 || cfg >= kStep1DConfigs) return fail(RES_EINVAL, "stepper configuration out of range");
+  if (chunk < 0 || block < 0) return fail(RES_EINVAL, "negative chunk or block");
+  if (chunk > 0 && chunk < op->N && block < 1) return fail(RES_EINVAL, "a chunked plan needs block >= 1");
+  std::vector<Seg1D> regs;
+  plan_1d_regions(op, chunk, block, &regs);
+  int64_t maxlen = 0;
+  for (auto& r : regs) maxlen = std::max<int64_t>(maxlen, r.ndof);
+  if (step1d_capacity(cfg) < maxlen) {
+    const int c = smallest_cfg(maxlen);
+    if (c < 0) return fail(RES_ENOTSUP, "stepper region of " + std::to_string(maxlen) + " unknowns is too long");
+    cfg = c;
+  }
+  op->segs = regs;
+  op->step_cfg = cfg;
+  op->step_chunk = (chunk > 0 && chunk < op->N) ? chunk : 0;
+  op->step_block = op->step_chunk ? block : 0;
+  // persistent exchange needs the halo inside the immediate neighbours and blocks made of whole prefetch rounds
+  op->step_persist = persist && op->step_chunk > 0 && (int64_t)kBandRadius * block <= chunk &&
+                     block % step1d_prefetch(cfg) == 0;
+  return RES_OK;
+}
+
+// Default stepper plan: a column of up to 256 unknowns in one workgroup; longer columns in owned chunks of 128
+// with a halo of 64 (16 steps per block), marched by one persistent cooperative launch with in-kernel neighbour
+// exchange when the grid is co-resident, else by relaunches every 16 steps.
+// RESOLVENT_STEP1D="cfg,chunk,block[,persist]" overrides it; resolvent_op_tune searches for a faster one.
 int plan_1d_default(resolvent_op* op) {
   int cfg;
   int64_t chunk = 0, block = 0;
@@ -356,23 +385,7 @@ int plan_1d_default(resolvent_op* op) {
       persist = got >= 4 ? pe : 1;
     }
   }
-  std::vector<Seg1D> regs;
-  plan_1d_regions(op, chunk, block, &regs);
-  int64_t maxlen = 0;
-  for (auto& r : regs) maxlen = std::max<int64_t>(maxlen, r.ndof);
-  if (step1d_capacity(cfg) < maxlen) {
-    const int c = smallest_cfg(maxlen);
-    if (c < 0) return fail(RES_ENOTSUP, "stepper region of " + std::to_string(maxlen) + " unknowns is too long");
-    cfg = c;
-  }
-  op->segs = regs;
-  op->step_cfg = cfg;
-  op->step_chunk = (chunk > 0 && chunk < op->N) ? chunk : 0;
-  op->step_block = op->step_chunk ? block : 0;
-  // persistent exchange needs the halo inside the immediate neighbours and blocks made of whole prefetch rounds
-  op->step_persist = persist && op->step_chunk > 0 && (int64_t)kBandRadius * block <= chunk &&
-                     block % step1d_prefetch(cfg) == 0;
-  return RES_OK;
+  return apply_plan(op, cfg, chunk, block, persist);
 }
 
 int phase_table(resolvent_op* op, int64_t P, void** out) {
@@ -772,10 +785,22 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   RES_TRY(zero_device(acc, (size_t)nw * ncols * sizeof(cd), st));
   op->march_band = op->d_band[s];
 
-  // forcing rows: whole first period as a table when it fits, else tiles
-  const double table_budget = env_double("RESOLVENT_TABLE_BUDGET_GB", 48.0) * 1073741824.0;
+  // Forcing rows: the whole first period as one table when it fits in device memory (it is then synthesised
+  // once per run and reused by every period), else tiles synthesised as the march goes.  The default budget
+  // is the free device memory (plus the table this handle already holds) minus a reserve for the rest of the
+  // run; RESOLVENT_TABLE_BUDGET_GB overrides it.
+  double table_budget;
+  if (std::getenv("RESOLVENT_TABLE_BUDGET_GB")) {
+    table_budget = env_double("RESOLVENT_TABLE_BUDGET_GB", 0.0) * 1073741824.0;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const auto held = op->ws.find("forcing");
+    const double reserve = 6.0 * 1073741824.0;
+    table_budget = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0) - reserve;
+  }
   const int64_t table_rows = std::min<int64_t>(pl.P, pl.forced_end);
-  const bool table_mode = (double)table_rows * (double)ncols * (double)ws <= table_budget;
+  bool table_mode = (double)table_rows * (double)ncols * (double)ws <= table_budget;
   int64_t tile_rows = 0;
   void* frc = nullptr;
   PhaseGemmArgs syn{};
@@ -790,8 +815,11 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   syn.bmat = G;
   syn.ldb = ncols;
   syn.k_per_split = nw;
+  if (table_mode && ws_get(op, "forcing", (size_t)table_rows * ncols * ws, &frc) != RES_OK) {
+    g_last_error.clear();
+    table_mode = false;  // the allocation failed after all: fall back to tiles
+  }
   if (table_mode) {
-    RES_TRY(ws_get(op, "forcing", (size_t)table_rows * ncols * ws, &frc));
     syn.M = table_rows;
     syn.s0 = 0;
     syn.out = frc;
@@ -997,6 +1025,100 @@ int decay_probe(resolvent_op* op, const resolvent_op_desc* d, hipStream_t st) {
       return fail(RES_EUNSTABLE, "decay probe: norm ratio " + std::to_string(nrm / n0) + " after t = " +
                                      std::to_string(t) + " (operator not stable, or decay slower than probe_tmax)");
   }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Stepper autotuner (1-D operators): candidate plans are owned-chunk sizes x steps-between-exchanges x kernel
+// configurations whose capacity holds the region (chunk + two halos of 4*block) without leaving more than half
+// of the threads idle, plus the single-region plans when a column fits one workgroup.  Each candidate marches
+// `steps` forced steps of k columns three times on the caller's stream; the faster of the last two (timed with
+// HIP events) is its time, and the fastest plan is kept.
+struct PlanCand {
+  int cfg;
+  int64_t chunk, block;
+  int persist;
+};
+
+std::vector<PlanCand> plan_candidates(const resolvent_op* op) {
+  std::vector<PlanCand> c;
+  const int64_t n = op->N;
+  for (int cfg = 0; cfg < kStep1DConfigs; ++cfg) {
+    const int64_t cap = step1d_capacity(cfg);
+    if (cap >= n && cap < 2 * n) c.push_back({cfg, 0, 0, 1});
+  }
+  static const int64_t chunks[] = {64, 96, 128, 160, 192, 256, 384, 512, 768, 1024, 1536};
+  static const int64_t blocks[] = {4, 8, 12, 16, 24, 32, 48, 64};
+  for (int64_t chunk : chunks) {
+    if (chunk >= n) continue;
+    for (int64_t block : blocks) {
+      if ((int64_t)kBandRadius * block > chunk) continue;
+      const int64_t region = chunk + 2 * (int64_t)kBandRadius * block;
+      for (int cfg = 0; cfg < kStep1DConfigs; ++cfg) {
+        const int64_t cap = step1d_capacity(cfg);
+        if (cap < region || cap >= 2 * region) continue;
+        c.push_back({cfg, chunk, block, block % step1d_prefetch(cfg) == 0 ? 1 : 0});
+      }
+    }
+  }
+  return c;
+}
+
+int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best_us, hipStream_t st) {
+  const int64_t ncols = (int64_t)k * op->N;
+  const size_t ws = op->wsize();
+  void *frc, *s0, *s1;
+  RES_TRY(ws_get(op, "forcing", (size_t)(steps + 16) * ncols * ws, &frc));
+  RES_TRY(zero_device(frc, (size_t)(steps + 16) * ncols * ws, st));
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &s0));
+  RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &s1));
+  RES_TRY(zero_device(s0, (size_t)ncols * ws, st));
+  RES_TRY(zero_device(s1, (size_t)ncols * ws, st));
+  op->march_band = op->d_band[0];
+  ForceSpec fs;
+  fs.frc = frc;
+  fs.row0 = 0;
+  fs.period = 0;
+  const bool timing = op->timing;
+  op->timing = false;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best_ms = -1;
+  int rc = RES_OK;
+  for (const PlanCand& c : plan_candidates(op)) {
+    if (apply_plan(op, c.cfg, c.chunk, c.block, c.persist) != RES_OK) {
+      g_last_error.clear();
+      continue;
+    }
+    void* dsegs;
+    int64_t nseg;
+    if ((rc = upload_regions(op, k, &dsegs, &nseg, st)) != RES_OK) break;
+    if ((rc = march_1d(op, k, steps, fs, SnapSpec(), dsegs, nseg, st)) != RES_OK) break;  // warm-up
+    double ms = -1;
+    for (int rep = 0; rep < 2 && rc == RES_OK; ++rep) {  // the faster of two timed marches
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(RES_EHIP, "event record"); break; }
+      if ((rc = march_1d(op, k, steps, fs, SnapSpec(), dsegs, nseg, st)) != RES_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(RES_EHIP, "event timing");
+        break;
+      }
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (ms < 0 || t < ms) ms = t;
+    }
+    if (rc != RES_OK) break;
+    if (best_ms < 0 || ms < best_ms) {
+      best_ms = ms;
+      *best = {op->step_cfg, op->step_chunk, op->step_block, op->step_persist ? 1 : 0};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  op->timing = timing;
+  if (rc != RES_OK) return rc;
+  if (best_ms < 0) return fail(RES_ENOTSUP, "no stepper plan fits this operator");
+  *best_us = best_ms * 1e3 / (double)steps;
+  return apply_plan(op, best->cfg, best->chunk, best->block, best->persist);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -1437,6 +1559,37 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
   RES_TRY(make_plan(op, grid, run, &pl));
   if (!f_grad && !mu_grad) return RES_OK;
   return backward(op, pl, k, f_hat, g_hat, f_grad, mu_grad, checkpoint_every, (hipStream_t)stream);
+}
+
+int resolvent_op_get_plan(const resolvent_op* op, int32_t plan[4]) {
+  if (!op || !plan) return fail(RES_EINVAL, "NULL argument");
+  if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators have no stepper plan");
+  plan[0] = op->step_cfg;
+  plan[1] = (int32_t)op->step_chunk;
+  plan[2] = (int32_t)op->step_block;
+  plan[3] = op->step_persist ? 1 : 0;
+  return RES_OK;
+}
+
+int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]) {
+  g_last_error.clear();
+  if (!op || !plan) return fail(RES_EINVAL, "NULL argument");
+  if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators have no stepper plan");
+  return apply_plan(op, plan[0], plan[1], plan[2], plan[3]);
+}
+
+int resolvent_op_tune(resolvent_op* op, int32_t k, int32_t steps, int32_t plan_out[4], double* us_per_step,
+                      void* stream) {
+  g_last_error.clear();
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators have no stepper plan");
+  if (k < 1 || steps < 16) return fail(RES_EINVAL, "k must be >= 1 and steps >= 16");
+  PlanCand best{};
+  double us = 0;
+  RES_TRY(tune_1d(op, k, steps, &best, &us, (hipStream_t)stream));
+  if (plan_out) RES_TRY(resolvent_op_get_plan(op, plan_out));
+  if (us_per_step) *us_per_step = us;
+  return RES_OK;
 }
 
 int resolvent_op_set_timing(resolvent_op* op, int32_t enable) {

@@ -257,3 +257,37 @@ def test_persistent_exchange_at_scale(plan, monkeypatch):
     say("  persistent vs relaunch identical:", np.array_equal(outs[0], outs[1]), " vs oracle", err)
     assert np.array_equal(outs[0], outs[1])
     assert err < 1e-10
+
+
+def test_autotuner_plan_roundtrip_and_bitwise_results(tmp_path, monkeypatch):
+    """The tuner picks some plan; results under it are bit for bit those of the default plan (and match the
+    oracle); set_plan/get_plan round-trip; malformed plans and grid operators are rejected."""
+    import torch
+    from paper_2008_10904_amd import ResolventError, ResolventOp
+    from paper_2008_10904_amd import autotune
+    from paper_2008_10904_amd.operators import gl_coefficients
+    monkeypatch.delenv("RESOLVENT_STEP1D", raising=False)
+    say("case: autotuner, GL N=2000 k=2")
+    n, h, P, nw, k = 2000, 0.001, 4096, 4, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(13, nw, k, n)
+    lo, d, up = gl_coefficients(n, 0.38, -0.01)
+    op = ResolventOp.tridiagonal(lo, d, up, h)
+    grid, run = op.grid(-3.0, dw, nw), op.run("periodic", periods=2, stride=64)
+    default_plan = op.get_plan()
+    ref = to_np(op.apply(gpu_tensor(F), grid, run))
+    plan, us = autotune.tuned(op, k, steps=256, device="test", path=str(tmp_path / "plans.json"))
+    say("  default plan", default_plan, "tuned plan", plan, "us/step %.4f" % us)
+    assert op.get_plan() == plan and us > 0
+    out = to_np(op.apply(gpu_tensor(F), grid, run))
+    torch.cuda.synchronize()
+    assert np.array_equal(out, ref)
+    assert op.set_plan(default_plan) == default_plan
+    plan2, us2 = autotune.tuned(op, k, device="test", path=str(tmp_path / "plans.json"))
+    assert plan2 == plan and us2 is None
+    with pytest.raises(ResolventError):
+        op.set_plan((99, 128, 16, 1))
+    with pytest.raises(ResolventError):
+        op.set_plan((12, 128, 0, 1))
+    L, _ = O_ops.gl_operator(n, 0.38, -0.01)
+    assert per_freq_relerr(out, O_st.run(L, h, -3.0, dw, F, "periodic", periods=2, stride=64)) < 1e-10

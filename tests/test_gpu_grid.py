@@ -125,3 +125,13 @@ def test_set_diagonal_grid():
     L, _ = O_ops.adr2d_operator(nx, ny, mu=mu_new)
     ref = O_st.run(L, h, 0.0, dw, F, "periodic", periods=8, stride=50)
     assert per_freq_relerr(out, ref) < 1e-10
+
+
+def test_grid_operator_has_no_stepper_plan():
+    from paper_2008_10904_amd import ResolventError
+    say("case: grid operator plan calls")
+    op, _ = make2d(8, 6, 0.1)
+    with pytest.raises(ResolventError):
+        op.get_plan()
+    with pytest.raises(ResolventError):
+        op.tune(1)
