@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="gl_periodic_n2000", choices=["gl_periodic_n2000", "gl_batched_64"],
+    ap.add_argument("--workload", default="gl_periodic_n2000",
+                    choices=["gl_periodic_n2000", "gl_batched_64", "adr2d_1024x512", "adr3d3c_256x128x128"],
                     help="gl_periodic_n2000 (default, the headline line) or gl_batched_64 (64 uneven GL instances, "
                          "mixed precision, reported beside its FP64 form)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -180,6 +181,102 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def grid_op(cfg, precision):
+    import numpy as np
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients, adr3d3c_coefficients
+    if cfg["kind"] == "adr2d":
+        c = adr2d_coefficients(cfg["nx"], cfg["ny"], Re=cfg["Re"], mu_base=cfg["mu_base"], mu_amp=cfg["mu_amp"],
+                               mu_xc=cfg["mu_xc"], mu_w2=cfg["mu_w2"], nu_s=cfg["nu_s"])
+        return ResolventOp.grid_operator("adr2d", cfg["nx"], cfg["ny"], 1, c, cfg["h"], precision=precision)
+    wake = W.wake_parameters(cfg["seed"])
+    c = adr3d3c_coefficients(cfg["nx"], cfg["ny"], cfg["nz"], wake, Re=cfg["Re"],
+                             mu=np.full((cfg["nz"], cfg["ny"], cfg["nx"]), cfg["mu_const"]), nu_s=cfg["nu_s"])
+    return ResolventOp.grid_operator("adr3d3c", cfg["nx"], cfg["ny"], cfg["nz"], c, cfg["h"], precision=precision)
+
+
+def bench_grid(args):
+    """Grid workloads.  adr2d_1024x512: one full block-power iteration (transient method, mixed precision).
+    adr3d3c_256x128x128: the full-size state does not leave room for a whole iteration's FP64 blocks in one GPU's
+    memory, so the stepping is measured alone: one apply of 64 forced steps at the full grid (8 frequencies,
+    P = 64), reported per step; the Fourier work scales with the frequency count and is reported separately by
+    the iteration of the 2-D workload.  Both report the HBM roofline of the Horner-stage kernel against the
+    algorithmic bytes of a step (read and write the state, read one forcing row)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.operators import snap_grid
+
+    cfg = W.ADR2D if args.workload == "adr2d_1024x512" else W.ADR3D
+    op = grid_op(cfg, cfg["precision"])
+    ncomp = 3 if cfg["kind"] == "adr3d3c" else 1
+    nodes = cfg["nx"] * cfg["ny"] * cfg.get("nz", 1)
+    N = ncomp * nodes
+    k = cfg["k"]
+    csize = 8  # complex64 state
+    if cfg["kind"] == "adr2d":
+        w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+        nw = cfg["n_omega"]
+        run = op.run("transient", tail=cfg["tail"])
+        steps_per_run = P + cfg["tail"]
+        F = W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)
+        f = torch.from_numpy(F).cuda()
+        grid = op.grid(w0, dw, nw)
+        dt, gains, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
+        time_steps_total = 2 * steps_per_run * args.steps
+        value = N * k * nw * 2 * steps_per_run / dt
+        step_desc = "one block-power iteration"
+    else:
+        nw, P = 8, 64
+        dw = 2 * np.pi / (P * cfg["h"])
+        F = W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)
+        f = torch.from_numpy(F).cuda()
+        del F
+        grid = op.grid(cfg["wmin"], dw, nw)
+        run = op.run("transient", tail=0)
+        out = op.apply(f, grid, run)
+        torch.cuda.synchronize()
+        op.set_timing(True)
+        for kind in range(4):
+            op.timing(kind)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.apply(f, grid, run, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
+                                                       ("synthesis", L.RES_TIMING_SYNTHESIS),
+                                                       ("projection", L.RES_TIMING_PROJECTION))}
+        op.set_timing(False)
+        time_steps_total = P * args.steps
+        steps_per_run = P
+        value = N * k * cfg["n_omega"] * P / (kt["stepper"][0] / 1e3 / args.steps)
+        step_desc = "stepping of one 64-step apply (value: sweeps/s of the stepping alone at 96 frequencies)"
+    step_s = kt["stepper"][0] / 1e3 / time_steps_total
+    alg_bytes = 3 * csize * N * k  # read u, write u, read one forcing row
+    achieved = alg_bytes / step_s
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)", "value": value, "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 step/GEMM, f64 acc",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["ny"], cfg.get("nz", 1)], "components": ncomp,
+                   "k": k, "n_omega": nw, "P": P, "h": cfg["h"], "step": step_desc,
+                   "time_steps_per_step": time_steps_total // args.steps},
+        "roofline": {"bound": "hbm", "kernel": "grid_stage_kernel x4 (one RK4 step)", "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                     "us_per_time_step": step_s * 1e6, "algorithmic_bytes_per_step": alg_bytes},
+        "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -190,6 +287,9 @@ def main():
         return
     if args.workload == "gl_batched_64":
         bench_batched(args)
+        return
+    if args.workload in ("adr2d_1024x512", "adr3d3c_256x128x128"):
+        bench_grid(args)
         return
     import numpy as np
     import torch

@@ -55,6 +55,9 @@ struct GridOpDev {
 // One Horner stage of the RK4 step for all k columns (see stencil.hip).
 int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
                       const void* frc, double phr, double phi, void* snap, hipStream_t st);
+// Whole RK4 step of a 2-D one-component operator in one launch (LDS temporal blocking); uout != uin.
+int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
+                       double phi, void* snap, hipStream_t st);
 int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                        int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
 

@@ -698,6 +698,13 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
   RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v1));
   RES_TRY(ws_get(op, "gv2", (size_t)ncols * ws, &v2));
   const GridOpDev& g = *op->march_grid;
+  // 2-D one-component operators: one fused launch per step, the state ping-ponging between state0 and state1
+  const bool fused = g.ncomp == 1 && g.nz == 1;
+  void* sb[2] = {u, nullptr};
+  if (fused) {
+    RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &sb[1]));
+    RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &sb[0]));
+  }
   TimedLaunch tl(op, RES_TIMING_STEPPER, st);
   int64_t next = (ss.snap != nullptr && ss.count > 0) ? ss.first : -1, m = 0;
   for (int64_t t = 0; t < n; ++t) {
@@ -712,6 +719,13 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
       srow = (char*)ss.snap + (size_t)(ss.row0 + m) * ss.ld * ws;
       ++m;
       next = m < ss.count ? next + ss.stride : -1;
+    }
+    if (fused) {
+      if (launch_grid_step2d(g, op->fp64(), k, sb[op->cur_state], sb[1 - op->cur_state], frow, fs.phi.real(),
+                             fs.phi.imag(), srow, st))
+        return fail(RES_EINVAL, "2-D step launch");
+      op->cur_state = 1 - op->cur_state;
+      continue;
     }
     launch_grid_stage(g, op->fp64(), k, u, u, v1, 0.25, 0, nullptr, 0, 0, nullptr, st);
     launch_grid_stage(g, op->fp64(), k, u, v1, v2, 1.0 / 3.0, 0, nullptr, 0, 0, nullptr, st);

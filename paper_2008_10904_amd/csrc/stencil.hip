@@ -57,6 +57,95 @@ __global__ __launch_bounds__(256) void grid_stage_kernel(GridCoef<R> Cf, int64_t
   }
 }
 
+// Whole RK4 step of the 2-D five-point operator in one launch (temporal blocking).  A workgroup of 4 x 64
+// threads owns a 56 x 32 tile of one column and works on the 64 x 40 window around it (halo 4 = the radius of
+// P(Z)).  Lane l of strip w holds window column l, rows 10w .. 10w+9, in registers (the state u, the diagonal,
+// the current stage values); each stage publishes the stage input to one of two LDS windows, so x-neighbours
+// and the strip-end y-neighbours come from LDS and the other y-neighbours from the thread's own registers.  The
+// valid region shrinks by one node per stage; values outside the grid are zero (homogeneous Dirichlet).  The
+// new state goes to uout (a different buffer: neighbouring tiles read this step's u as their halo).  HBM
+// traffic per step: the state once (plus halo rows, mostly from L2), the forcing row once, the new state once.
+template <typename R>
+__global__ __launch_bounds__(256) void grid_step2d_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny,
+                                                          const cx<R>* __restrict__ uin, cx<R>* __restrict__ uout,
+                                                          const cx<R>* __restrict__ frc, R phr, R phi,
+                                                          cx<R>* __restrict__ snap) {
+  constexpr int H = 4, WX = 64, WY = 40, TX = WX - 2 * H, TY = WY - 2 * H, RS = WY / 4;
+  __shared__ cx<R> Lw[2][WY][WX];
+  __shared__ R cxm[WY], cxp[WY], cym[WY], cyp[WY];
+  const int tid = threadIdx.x;
+  const int lx = tid & 63, ly0 = (tid >> 6) * RS;
+  const int64_t x0 = (int64_t)blockIdx.x * TX - H, y0 = (int64_t)blockIdx.y * TY - H;
+  const int64_t cb = (int64_t)blockIdx.z * nx * ny;  // column offset
+  const int64_t ix = x0 + lx;
+  const bool xin = ix >= 0 && ix < nx;
+  if (tid < WY) {
+    const int64_t iy = y0 + tid;
+    const bool in = iy >= 0 && iy < ny;
+    cxm[tid] = in ? Cf.cxm[iy] : R(0);
+    cxp[tid] = in ? Cf.cxp[iy] : R(0);
+    cym[tid] = in ? Cf.cym[iy] : R(0);
+    cyp[tid] = in ? Cf.cyp[iy] : R(0);
+  }
+  cx<R> u[RS], x[RS];
+  R d[RS];
+  bool in[RS];
+#pragma unroll
+  for (int r = 0; r < RS; ++r) {
+    const int64_t iy = y0 + ly0 + r;
+    in[r] = xin && iy >= 0 && iy < ny;
+    const int64_t p = iy * nx + ix;
+    u[r] = in[r] ? uin[cb + p] : mk<R>(R(0), R(0));
+    d[r] = in[r] ? Cf.d[p] : R(0);
+    x[r] = u[r];
+  }
+  // stage m = 1..4: y = u + s (Z x) on the valid region (m <= lx < WX - m, m <= ly < WY - m), zero elsewhere;
+  // the last stage has s = 1 and adds the forcing.  Operation order as apply_z: diagonal, -x, +x, -y, +y.
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    cx<R>(*Lm)[WX] = Lw[m & 1];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) Lm[ly0 + r][lx] = x[r];
+    __syncthreads();
+    const R s = m == 1 ? R(0.25) : m == 2 ? R(1) / R(3) : m == 3 ? R(0.5) : R(1);
+    const bool xok = lx >= m && lx < WX - m;
+    cx<R> y[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int ly = ly0 + r;
+      y[r] = mk<R>(R(0), R(0));
+      if (!(xok && ly >= m && ly < WY - m && in[r])) continue;
+      const cx<R> lf = Lm[ly][lx - 1], rt = Lm[ly][lx + 1];
+      const cx<R> dn = r > 0 ? x[r - 1] : Lm[ly - 1][lx];
+      const cx<R> up = r < RS - 1 ? x[r + 1] : Lm[ly + 1][lx];
+      cx<R> z = mk<R>(d[r] * x[r].re, d[r] * x[r].im);
+      z.re += cxm[ly] * lf.re; z.im += cxm[ly] * lf.im;
+      z.re += cxp[ly] * rt.re; z.im += cxp[ly] * rt.im;
+      z.re += cym[ly] * dn.re; z.im += cym[ly] * dn.im;
+      z.re += cyp[ly] * up.re; z.im += cyp[ly] * up.im;
+      y[r] = mk<R>(u[r].re + s * z.re, u[r].im + s * z.im);
+    }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) x[r] = y[r];
+  }
+  // interior of the tile: forcing, snapshot of u (the state before the step) and the new state
+  if (lx < H || lx >= WX - H) return;
+#pragma unroll
+  for (int r = 0; r < RS; ++r) {
+    const int ly = ly0 + r;
+    if (ly < H || ly >= WY - H || !in[r]) continue;
+    const int64_t e = cb + (y0 + ly) * nx + ix;
+    if (snap != nullptr) snap[e] = u[r];
+    cx<R> v = x[r];
+    if (frc != nullptr) {
+      const cx<R> f = frc[e];
+      v.re += phr * f.re - phi * f.im;
+      v.im += phr * f.im + phi * f.re;
+    }
+    uout[e] = v;
+  }
+}
+
 // One Horner pass of G = h Q_j(Z) F over [n_w][k] blocks (see tri_horner_kernel for the coefficients).
 template <typename TF, typename TO, int NC>
 __global__ __launch_bounds__(256) void grid_horner_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int64_t nz,
@@ -160,6 +249,22 @@ int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* 
   }
 #undef RES_GS2
 #undef RES_GS
+  return 0;
+}
+
+int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
+                       double phi, void* snap, hipStream_t st) {
+  constexpr int TX = 56, TY = 32;  // interior of the 64 x 40 window
+  if (g.ncomp != 1 || g.nz != 1 || k < 1 || k > 65535) return -1;
+  const dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)((g.ny + TY - 1) / TY), (unsigned)k);
+  if (fp64)
+    hipLaunchKernelGGL((grid_step2d_kernel<double>), grid, dim3(256), 0, st, coef_of<double>(g, 1), g.nx,
+                       g.ny, (const cx<double>*)uin, (cx<double>*)uout, (const cx<double>*)frc, phr, phi,
+                       (cx<double>*)snap);
+  else
+    hipLaunchKernelGGL((grid_step2d_kernel<float>), grid, dim3(256), 0, st, coef_of<float>(g, 0), g.nx,
+                       g.ny, (const cx<float>*)uin, (cx<float>*)uout, (const cx<float>*)frc, (float)phr, (float)phi,
+                       (cx<float>*)snap);
   return 0;
 }
 
