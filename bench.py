@@ -38,6 +38,11 @@ def parse():
                     choices=["gl_periodic_n2000", "gl_batched_64", "adr2d_1024x512", "adr3d3c_256x128x128"],
                     help="gl_periodic_n2000 (default, the headline line) or gl_batched_64 (64 uneven GL instances, "
                          "mixed precision, reported beside its FP64 form)")
+    ap.add_argument("--plan", default=None,
+                    help="1-D stepper plan: 'tuned' (autotuner, cached per problem; tuning is set-up, not timed), "
+                         "'default' (the library's default plan) or 'cfg,chunk,block,persist'.  Default: 'default' "
+                         "for gl_periodic_n2000 (the plan its profiles were taken with; the tuner lands on it or on "
+                         "one within noise), 'tuned' for gl_batched_64")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -65,15 +70,16 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step1d_gl_periodic_n2000_traff
 STEPPER_SOURCES = ("step1d.hip", "common.h", "kernels.h")
 
 
-def measured_traffic():
+def measured_traffic(plan=None):
     """HBM bytes per stepper launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
-    stepper's sources have changed since those counters were taken (their hash is recorded beside the figure)."""
+    stepper's sources have changed since those counters were taken (their hash is recorded beside the figure) or
+    when the run uses a different stepper plan than the profiled one."""
     import hashlib
     h = hashlib.sha256()
     for f in STEPPER_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_10904_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    value, digest = None, None
+    value, digest, prof_plan = None, None, None
     try:
         with open(TRAFFIC_PROFILE) as fh:
             for line in fh:
@@ -81,9 +87,23 @@ def measured_traffic():
                     value = float(line.split(":", 1)[1])
                 elif line.startswith("source-sha256"):
                     digest = line.rsplit(":", 1)[1].strip()
+                elif line.startswith("plan:"):
+                    prof_plan = [int(x) for x in line.split(":", 1)[1].split(",")]
     except OSError:
         return None
-    return value if digest == h.hexdigest() else None
+    if digest != h.hexdigest() or (plan is not None and list(plan) != prof_plan):
+        return None
+    return value
+
+
+def choose_plan(op, k, how):
+    """Apply the requested stepper plan (see --plan) and return the plan in effect."""
+    from paper_2008_10904_amd import autotune
+    if how == "tuned":
+        return autotune.tuned(op, k)[0]
+    if how == "default":
+        return op.get_plan()
+    return op.set_plan([int(x) for x in how.split(",")])
 
 
 def time_steps(op, f0, grid, run, K, W):
@@ -148,11 +168,10 @@ def bench_batched(args):
     steps_per_run = cfg["periods"] * P
     F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], ntot)
     sweeps_per_step = ntot * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
-    from paper_2008_10904_amd import autotune
     res, plans = {}, {}
     for prec, dtype in (("mixed", torch.complex64), ("fp64", torch.complex128)):
         op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=prec, offsets=off)
-        plans[prec], _ = autotune.tuned(op, cfg["k"])
+        plans[prec] = choose_plan(op, cfg["k"], args.plan)
         grid = op.grid(w0, dw, cfg["n_omega"])
         run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
         f = torch.from_numpy(F).to(dtype).cuda()
@@ -285,6 +304,8 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.plan is None:
+        args.plan = "tuned" if args.workload == "gl_batched_64" else "default"
     if args.workload == "gl_batched_64":
         bench_batched(args)
         return
@@ -303,9 +324,8 @@ def main():
     F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
     sweeps_per_step = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
 
-    from paper_2008_10904_amd import autotune
     op = build_op(cfg, "fp64")
-    plan64, _ = autotune.tuned(op, cfg["k"])  # set-up: the stepper plan (cached after the first run)
+    plan64 = choose_plan(op, cfg["k"], args.plan)  # set-up: the stepper plan
     grid = op.grid(w0, dw, cfg["n_omega"])
     run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
     f64 = torch.from_numpy(F).cuda()
@@ -335,7 +355,7 @@ def main():
                    "time_steps_per_step": 2 * steps_per_run},
         "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
+                     "traffic": measured_traffic(plan64), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
                      "steps_per_launch": steps_per_launch},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "stepper_plan": list(plan64),
@@ -344,7 +364,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_mixed:
         opm = build_op(cfg, "mixed")
-        planm, _ = autotune.tuned(opm, cfg["k"])
+        planm = choose_plan(opm, cfg["k"], args.plan)
         f32 = torch.from_numpy(F).to(torch.complex64).cuda()
         dtm, gainsm, ktm = time_steps(opm, f32, grid, run, args.steps, args.warmup)
         out["mixed"] = {"value": sweeps_per_step / dtm, "ms_per_step": dtm * 1e3, "dtype": "f32 step/GEMM, f64 acc",
