@@ -165,6 +165,16 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);
 
+/* HIP graphs.  resolvent_apply, resolvent_adjoint_apply and resolvent_apply_backward may be recorded into a
+ * caller's graph (stream capture) once an uncaptured call with the same sizes has sized the handle's workspace:
+ * nothing inside them then allocates, copies from the host or synchronises (fills are kernels, not memset
+ * nodes); a call that would need to grow the workspace during capture fails with RES_EINVAL.  The graph reads
+ * and writes the device buffers given at capture time.  resolvent_modes returns host data and cannot be
+ * captured; with resolvent_op_set_graphs(op, 1) it instead records its second iteration once and replays it for
+ * every iteration but the first and the last (results are identical to the eager form).  For callers that
+ * replay launch sequences (batched serving loops, graph-based pipelines); not part of the paper's method. */
+int resolvent_op_set_graphs(resolvent_op* op, int32_t enable);
+
 /* Stepper plan of a RES_OP_TRIDIAG operator (how the time march is laid out on the device; results do not
  * depend on it, bit for bit): plan[0] = kernel configuration (0..15: threads per workgroup, unknowns per
  * thread and forcing prefetch depth), plan[1] = owned unknowns per workgroup (0: each column in one

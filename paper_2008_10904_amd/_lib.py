@@ -48,6 +48,7 @@ SIGNATURES = {
     "resolvent_apply_backward": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                            c_void_p, _dp, c_int32, c_void_p]),
     "resolvent_op_check": (c_int32, [c_void_p, c_void_p]),
+    "resolvent_op_set_graphs": (c_int32, [c_void_p, c_int32]),
     "resolvent_op_get_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_tune": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), _dp, c_void_p]),

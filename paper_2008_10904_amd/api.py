@@ -201,6 +201,10 @@ class ResolventOp:
             d = np.ascontiguousarray(np.asarray(diag, np.complex128)).view(np.float64)
         check(self._lib.resolvent_op_set_diagonal(self._h, _dptr(d), 0, self._stream_ptr()))
 
+    def set_graphs(self, enable=True):
+        """resolvent_modes replays its middle iterations from one captured HIP graph."""
+        check(self._lib.resolvent_op_set_graphs(self._h, 1 if enable else 0))
+
     # ---- stepper plan and autotuner (1-D operators) ------------------------------------------------------------
     def get_plan(self):
         """(configuration, owned unknowns per workgroup, steps between exchanges, persistent) in effect."""

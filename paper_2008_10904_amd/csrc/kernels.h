@@ -107,5 +107,6 @@ int launch_svd(const void* A, int k, int nw, int ninst, void* phi, void* psi, vo
                double* hist, hipStream_t st);
 int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t st);
 int launch_convert(const void* x, int in_fp64, void* y, int out_fp64, int64_t count, double scale, hipStream_t st);
+int launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: a multiple of 4
 
 }  // namespace res

@@ -288,6 +288,12 @@ __global__ __launch_bounds__(256) void convert_kernel(const cx<TI>* __restrict__
   }
 }
 
+// Zero fill of 4-byte words (a kernel, so that it can sit in a captured graph where memset nodes are avoided).
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
 // ------------------------------------------------------------------------------------------------------
 static inline unsigned grid1d(int64_t count) {
   int64_t b = (count + 255) / 256;
@@ -350,6 +356,13 @@ int launch_svd(const void* A, int k, int nw, int ninst, void* phi, void* psi, vo
 int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t st) {
   if (fp64) hipLaunchKernelGGL((finite_kernel<double>), dim3(grid1d(count)), dim3(256), 0, st, (const cx<double>*)x, count, flag);
   else hipLaunchKernelGGL((finite_kernel<float>), dim3(grid1d(count)), dim3(256), 0, st, (const cx<float>*)x, count, flag);
+  return 0;
+}
+
+int launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes % 4 != 0) return -1;
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words > 0) hipLaunchKernelGGL(zero_kernel, dim3(grid1d(words)), dim3(256), 0, st, (uint32_t*)p, words);
   return 0;
 }
 

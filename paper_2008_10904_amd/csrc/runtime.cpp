@@ -120,6 +120,13 @@ struct resolvent_op {
   std::map<int64_t, void*> btab64;        // FP64 phase tables of the mixed-precision operator (reverse mode)
   int* d_flag = nullptr;
   double decay_time = -1;
+  // graph capture: set while the caller's stream (or the library's own capture) records; nothing may then
+  // allocate, copy from the host or synchronise
+  bool capturing = false;
+  bool use_graphs = false;               // resolvent_modes replays its middle iterations from a captured graph
+  hipStream_t cap_stream = nullptr;      // private stream for that capture (default priority)
+  int plan_version = 0;                  // bumped by every stepper plan change
+  int segs_dev_k = -1, segs_dev_version = -1;  // what the device copy of the regions describes
   bool fp64() const { return prec == RES_FP64; }
   size_t wsize() const { return fp64() ? 16 : 8; }  // bytes per complex in working precision
 };
@@ -135,6 +142,9 @@ std::vector<void*>& retired_exchange_areas() {
 int ws_get(resolvent_op* op, const std::string& name, size_t bytes, void** out) {
   DevBuf& b = op->ws[name];
   if (b.bytes < bytes) {
+    if (op->capturing)
+      return fail(RES_EINVAL, "workspace '" + name + "' must grow during graph capture: make one uncaptured call "
+                              "with the same sizes first");
     if (b.p) HIP_TRY(hipFree(b.p));
     b.p = nullptr;
     b.bytes = 0;
@@ -156,7 +166,7 @@ struct TimedLaunch {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   TimedLaunch(resolvent_op* o, int k, hipStream_t s) : op(o), kind(k), st(s) {
-    if (!op->timing) return;
+    if (!op->timing || op->capturing) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       a = b = nullptr;
       return;
@@ -350,6 +360,7 @@ int apply_plan(resolvent_op* op, int cfg, int64_t chunk, int64_t block, int pers
     cfg = c;
   }
   op->segs = regs;
+  ++op->plan_version;
   op->step_cfg = cfg;
   op->step_chunk = (chunk > 0 && chunk < op->N) ? chunk : 0;
   op->step_block = op->step_chunk ? block : 0;
@@ -394,6 +405,7 @@ int phase_table(resolvent_op* op, int64_t P, void** out) {
     *out = it->second;
     return RES_OK;
   }
+  if (op->capturing) return fail(RES_EINVAL, "phase table must be built by an uncaptured call first");
   void* d = nullptr;
   if (op->fp64()) {
     std::vector<cd> t((size_t)P);
@@ -420,6 +432,7 @@ int phase_table64(resolvent_op* op, int64_t P, void** out) {
     *out = it->second;
     return RES_OK;
   }
+  if (op->capturing) return fail(RES_EINVAL, "phase table must be built by an uncaptured call first");
   std::vector<cd> t((size_t)P);
   for (int64_t m = 0; m < P; ++m) t[m] = std::polar(1.0, 2.0 * M_PI * (double)m / (double)P);
   void* d = nullptr;
@@ -576,6 +589,8 @@ int flush_projection(resolvent_op* op, const Plan& pl, int k, int sigma, void* b
 void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStream_t st) {
   static const bool on = env_long("RESOLVENT_TRACE", 0) != 0;
   if (!on || p == nullptr) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
   (void)hipStreamSynchronize(st);
   double s = 0;
   if (fp64) {
@@ -592,7 +607,8 @@ void trace_norm(const char* what, const void* p, int64_t count, int fp64, hipStr
 }
 
 int zero_device(void* p, size_t bytes, hipStream_t st) {
-  HIP_TRY(hipMemsetAsync(p, 0, bytes, st));
+  if (launch_zero(p, bytes, st)) return fail(RES_EINVAL, "zero fill of a size that is not a multiple of 4 bytes");
+  HIP_TRY(hipGetLastError());
   return RES_OK;
 }
 
@@ -629,6 +645,7 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     // the process ends.  Every slot starts empty for each launch.
     const size_t need = (size_t)4 * ncols * op->wsize();  // [2 buffers][2 directions][ncols]
     if (op->xch_bytes < need) {
+      if (op->capturing) return fail(RES_EINVAL, "exchange area must be allocated by an uncaptured call first");
       void* p = nullptr;
       HIP_TRY(hipExtMallocWithFlags(&p, need, hipDeviceMallocUncached));
       if (op->xch) retired_exchange_areas().push_back(op->xch);
@@ -736,14 +753,20 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
   return RES_OK;
 }
 
+// Device copy of the regions of all k columns; uploaded again only when k or the plan changed.
 int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStream_t st) {
-  std::vector<Seg1D>& segs = op->segs_k;  // kept in the handle: the upload is asynchronous
-  segs.clear();
   if (is_grid(op)) {
     *dsegs = nullptr;
     *nseg = 0;
     return RES_OK;
   }
+  if (op->segs_dev_k == k && op->segs_dev_version == op->plan_version) {
+    *nseg = (int64_t)k * (int64_t)op->segs.size();
+    return ws_get(op, "segs", (size_t)*nseg * sizeof(Seg1D), dsegs);
+  }
+  if (op->capturing) return fail(RES_EINVAL, "stepper regions must be uploaded by an uncaptured call first");
+  std::vector<Seg1D>& segs = op->segs_k;  // kept in the handle: the upload is asynchronous
+  segs.clear();
   const int32_t g = (int32_t)op->segs.size();
   for (int c = 0; c < k; ++c)
     for (auto sg : op->segs) {
@@ -755,6 +778,8 @@ int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStre
   RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), dsegs));
   HIP_TRY(hipMemcpyAsync(*dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
   *nseg = (int64_t)segs.size();
+  op->segs_dev_k = k;
+  op->segs_dev_version = op->plan_version;
   return RES_OK;
 }
 
@@ -922,9 +947,21 @@ int run_any(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64
   return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);  // one driver; the march dispatches on the operator kind
 }
 
+// Marks the handle as capturing while the caller's stream records a graph.
+struct CaptureScope {
+  resolvent_op* op;
+  bool prev;
+  CaptureScope(resolvent_op* o, hipStream_t st) : op(o), prev(o->capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive) op->capturing = true;
+  }
+  ~CaptureScope() { op->capturing = prev; }
+};
+
 int apply_common(resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, int k, const void* in, void* out,
                  int sigma, hipStream_t st) {
   if (!op || !in || !out) return fail(RES_EINVAL, "NULL argument");
+  CaptureScope cap(op, st);
   if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
   Plan pl;
   RES_TRY(make_plan(op, g, r, &pl));
@@ -1443,6 +1480,7 @@ void resolvent_op_destroy(resolvent_op* op) {
     if (op->d_tri[s]) (void)hipFree(op->d_tri[s]);
     if (op->d_band[s]) (void)hipFree(op->d_band[s]);
   }
+  if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   if (op->d_off) (void)hipFree(op->d_off);
   if (op->xch) retired_exchange_areas().push_back(op->xch);  // uncached memory is not freed (see march_1d)
   for (void* b : op->gbufs) (void)hipFree(b);
@@ -1508,6 +1546,12 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   if (k < 1 || k > 8) return fail(RES_EINVAL, "k must be in 1..8");
   if (iters < 1) return fail(RES_EINVAL, "iters must be >= 1");
   hipStream_t st = (hipStream_t)stream;
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(RES_EINVAL, "resolvent_modes returns host data and cannot be captured (capture resolvent_apply, or "
+                              "let the library replay its iterations: resolvent_op_set_graphs)");
+  }
   Plan pl;
   RES_TRY(make_plan(op, grid, run, &pl));
   const int nw = pl.nw;
@@ -1525,26 +1569,74 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   RES_TRY(ws_get(op, "modes_gains", gcount * sizeof(double), &dg));
   if (hist) RES_TRY(ws_get(op, "modes_hist", (size_t)iters * gcount * 2 * sizeof(double), &dh));
   launch_convert(f0_hat, op->fp64(), Fh, 1, count, 1.0, st);
-  for (int it = 0; it < iters; ++it) {
-    double* hprev = (hist && it > 0) ? (double*)dh + (size_t)(it - 1) * gcount * 2 : nullptr;
-    double* hcur = hist ? (double*)dh + (size_t)it * gcount * 2 : nullptr;
+  // One iteration on stream s; hprev receives the norm estimate of the previous iteration, hcur the gains.
+  auto iteration = [&](bool last, double* hprev, double* hcur, hipStream_t s) -> int {
     // 1. F = Q(QR(F_hat))
-    RES_TRY(cholqr2(op, nw, k, (double*)Fh, rY, hprev, st));
+    RES_TRY(cholqr2(op, nw, k, (double*)Fh, rY, hprev, s));
     // 2. Y = R_d F
-    RES_TRY(run_any(op, pl, k, Fh, 1, (double*)Y, +1, st));
+    RES_TRY(run_any(op, pl, k, Fh, 1, (double*)Y, +1, s));
     // 3. Y = Q_Y R_Y, R_Y = Phi Sigma Psi^H
-    RES_TRY(cholqr2(op, nw, k, (double*)Y, rY, nullptr, st));
-    launch_svd(rY, k, nw, op->ninst, phi, psi, apsi, (double*)dg, hcur, st);
-    if (it == iters - 1) {
-      if (U) launch_rmul(Y, 1, U, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), phi, st);
-      if (V) launch_rmul(Fh, 1, V, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), psi, st);
+    RES_TRY(cholqr2(op, nw, k, (double*)Y, rY, nullptr, s));
+    launch_svd(rY, k, nw, op->ninst, phi, psi, apsi, (double*)dg, hcur, s);
+    if (last) {
+      if (U) launch_rmul(Y, 1, U, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), phi, s);
+      if (V) launch_rmul(Fh, 1, V, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), psi, s);
     }
     // 4. Z = R_d^H Q_Y
-    RES_TRY(run_any(op, pl, k, Y, 1, (double*)Z, -1, st));
+    RES_TRY(run_any(op, pl, k, Y, 1, (double*)Z, -1, s));
     // 5. F_hat = Z R_Y Psi
-    launch_rmul(Z, 1, Fh, 1, op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), apsi, st);
+    launch_rmul(Z, 1, Fh, 1, op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), apsi, s);
     HIP_TRY(hipGetLastError());
+    return RES_OK;
+  };
+  auto hslot = [&](int it) -> double* { return hist ? (double*)dh + (size_t)it * gcount * 2 : nullptr; };
+  // Graph mode: the first iteration runs eagerly (it sizes every workspace), the middle ones replay one captured
+  // iteration (history slots are fixed scratch rows copied out after each replay), the last runs eagerly (modes).
+  const bool graphs = op->use_graphs && iters >= 3;
+  int it = 0;
+  RES_TRY(iteration(iters == 1, nullptr, hslot(0), st));
+  ++it;
+  if (graphs) {
+    void* hs = nullptr;
+    if (hist) RES_TRY(ws_get(op, "modes_hist_slots", gcount * 4 * sizeof(double), &hs));
+    double* hs_prev = hist ? (double*)hs : nullptr;
+    double* hs_cur = hist ? (double*)hs + gcount * 2 : nullptr;
+    if (!op->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
+    op->capturing = true;
+    int rc = iteration(false, hs_prev, hs_cur, op->cap_stream);
+    op->capturing = false;
+    const hipError_t ec = hipStreamEndCapture(op->cap_stream, &graph);
+    if (rc == RES_OK && ec != hipSuccess) rc = fail(RES_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    if (rc == RES_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+      rc = fail(RES_EHIP, "graph instantiation failed");
+    for (; rc == RES_OK && it < iters - 1; ++it) {
+      // history rows interleave (gain, norm estimate); the replay writes the estimate of it - 1 into hs_prev and
+      // the gains of it into hs_cur, so hs_prev first takes the row of it - 1 to keep its gains
+      if (hist && hipMemcpyAsync(hs_prev, hslot(it - 1), gcount * 2 * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+                      hipSuccess) {
+        rc = fail(RES_EHIP, "history copy");
+        break;
+      }
+      if (hipGraphLaunch(exec, st) != hipSuccess) {
+        rc = fail(RES_EHIP, "graph launch failed");
+        break;
+      }
+      if (hist) {
+        if (hipMemcpyAsync(hslot(it - 1), hs_prev, gcount * 2 * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(hslot(it), hs_cur, gcount * 2 * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+          rc = fail(RES_EHIP, "history copy");
+      }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    RES_TRY(rc);
   }
+  for (; it < iters; ++it) RES_TRY(iteration(it == iters - 1, hslot(it - 1), hslot(it), st));
   if (hist) {
     // norm estimate of the last iteration from the Gram of the final F_hat
     const int nsplit = nsplit_for(max_instance_len(op));
@@ -1572,7 +1664,14 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
   Plan pl;
   RES_TRY(make_plan(op, grid, run, &pl));
   if (!f_grad && !mu_grad) return RES_OK;
+  CaptureScope cap(op, (hipStream_t)stream);
   return backward(op, pl, k, f_hat, g_hat, f_grad, mu_grad, checkpoint_every, (hipStream_t)stream);
+}
+
+int resolvent_op_set_graphs(resolvent_op* op, int32_t enable) {
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  op->use_graphs = enable != 0;
+  return RES_OK;
 }
 
 int resolvent_op_get_plan(const resolvent_op* op, int32_t plan[4]) {
