@@ -277,6 +277,8 @@ def bench_grid(args):
         steps_per_run = P
         value = N * k * cfg["n_omega"] * P / (kt["stepper"][0] / 1e3 / args.steps)
         step_desc = "stepping of one 64-step apply (value: sweeps/s of the stepping alone at 96 frequencies)"
+    kernel_name = ("grid_step2d_kernel (one RK4 step per launch)" if cfg["kind"] == "adr2d"
+                   else "grid_stage3d_kernel x4 (one RK4 step)")
     step_s = kt["stepper"][0] / 1e3 / time_steps_total
     alg_bytes = 3 * csize * N * k  # read u, write u, read one forcing row
     achieved = alg_bytes / step_s
@@ -288,7 +290,7 @@ def bench_grid(args):
         "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["ny"], cfg.get("nz", 1)], "components": ncomp,
                    "k": k, "n_omega": nw, "P": P, "h": cfg["h"], "step": step_desc,
                    "time_steps_per_step": time_steps_total // args.steps},
-        "roofline": {"bound": "hbm", "kernel": "grid_stage_kernel x4 (one RK4 step)", "achieved": achieved / 1e9,
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                      "us_per_time_step": step_s * 1e6, "algorithmic_bytes_per_step": alg_bytes},
         "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},

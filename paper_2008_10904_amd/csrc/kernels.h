@@ -52,9 +52,9 @@ struct GridOpDev {
   const void* d;
   const void* K;
 };
-// One Horner stage of the RK4 step for all k columns (see stencil.hip).
-int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
-                      const void* frc, double phr, double phi, void* snap, hipStream_t st);
+// One Horner stage of a 3-D three-component operator, marching along z (see stencil.hip).
+int launch_grid_stage3d(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
+                        const void* frc, double phr, double phi, void* snap, hipStream_t st);
 // Whole RK4 step of a 2-D one-component operator in one launch (LDS temporal blocking); uout != uin.
 int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
                        double phi, void* snap, hipStream_t st);

@@ -744,10 +744,11 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
       op->cur_state = 1 - op->cur_state;
       continue;
     }
-    launch_grid_stage(g, op->fp64(), k, u, u, v1, 0.25, 0, nullptr, 0, 0, nullptr, st);
-    launch_grid_stage(g, op->fp64(), k, u, v1, v2, 1.0 / 3.0, 0, nullptr, 0, 0, nullptr, st);
-    launch_grid_stage(g, op->fp64(), k, u, v2, v1, 0.5, 0, nullptr, 0, 0, nullptr, st);
-    launch_grid_stage(g, op->fp64(), k, u, v1, nullptr, 1.0, 1, frow, fs.phi.real(), fs.phi.imag(), srow, st);
+    if (launch_grid_stage3d(g, op->fp64(), k, u, u, v1, 0.25, 0, nullptr, 0, 0, nullptr, st) ||
+        launch_grid_stage3d(g, op->fp64(), k, u, v1, v2, 1.0 / 3.0, 0, nullptr, 0, 0, nullptr, st) ||
+        launch_grid_stage3d(g, op->fp64(), k, u, v2, v1, 0.5, 0, nullptr, 0, 0, nullptr, st) ||
+        launch_grid_stage3d(g, op->fp64(), k, u, v1, nullptr, 1.0, 1, frow, fs.phi.real(), fs.phi.imag(), srow, st))
+      return fail(RES_EINVAL, "3-D stage launch");
   }
   HIP_TRY(hipGetLastError());
   return RES_OK;

@@ -10,52 +10,14 @@
 //   v <- u + Z u / 4,  v <- u + Z v / 3,  v <- u + Z v / 2,  u <- u + Z v + sum_j G_j e^{i w_j t_s}
 //
 // which equals P(Z) u_s + forcing of the classical four-stage scheme (the forcing enters through
-// G_j = h Q_j(Z) F_j, built by three Horner passes of the same stencil; see step1d.hip).  One launch per stage:
-// a thread owns one node and all k columns and components there, so the line coefficients are loaded once and
-// reused; x is the fastest index across threads (coalesced rows), y/z neighbours come through the caches.
+// G_j = h Q_j(Z) F_j, built by three Horner passes of the same stencil; see step1d.hip).  2-D one-component
+// operators run the whole step in one launch (grid_step2d_kernel); 3-D three-component operators run one launch
+// per stage, marching along z (grid_stage3d_kernel).
 #include "common.h"
 #include "kernels.h"
 #include "gridz.h"
 
 namespace res {
-
-// One Horner stage for all k columns:  out = u + s * Z vin   (stage 4,3,2: s = 1/4, 1/3, 1/2)
-// or, last stage (s = 1):  u = u + Z vin + phi * frc   (in place; frc may be null), and before that, if snap is
-// given, the snapshot row receives u (the state before this step's update).
-template <typename R, int NC, bool LAST>
-__global__ __launch_bounds__(256) void grid_stage_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny, int64_t nz, int k,
-                                                         cx<R>* u, const cx<R>* __restrict__ vin, cx<R>* vout,
-                                                         R s, const cx<R>* __restrict__ frc, R phr, R phi,
-                                                         cx<R>* __restrict__ snap) {
-  const int64_t nodes = nx * ny * nz;
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= nodes) return;
-  const int64_t ix = p % nx;
-  const int64_t l = p / nx;
-  const int64_t iy = l % ny, iz = l / ny;
-  const int64_t blk = (int64_t)NC * nodes;
-  for (int b = 0; b < k; ++b) {
-    cx<R> zv[NC];
-    apply_z<R, NC>(Cf, vin + b * blk, nodes, nx, ny, nz, ix, iy, iz, p, l, zv);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int64_t e = b * blk + c * nodes + p;
-      const cx<R> uu = u[e];
-      if (LAST) {
-        if (snap != nullptr) snap[e] = uu;
-        cx<R> r = mk<R>(uu.re + zv[c].re, uu.im + zv[c].im);
-        if (frc != nullptr) {
-          const cx<R> f = frc[e];
-          r.re += phr * f.re - phi * f.im;
-          r.im += phr * f.im + phi * f.re;
-        }
-        u[e] = r;
-      } else {
-        vout[e] = mk<R>(uu.re + s * zv[c].re, uu.im + s * zv[c].im);
-      }
-    }
-  }
-}
 
 // Whole RK4 step of the 2-D five-point operator in one launch (temporal blocking).  A workgroup of 4 x 64
 // threads owns a 56 x 32 tile of one column and works on the 64 x 40 window around it (halo 4 = the radius of
@@ -146,6 +108,151 @@ __global__ __launch_bounds__(256) void grid_step2d_kernel(GridCoef<R> Cf, int64_
   }
 }
 
+// One Horner stage of a 3-D three-component operator, marching along z.  A workgroup of 64 x 4 threads owns a
+// 64 x 4 column of nodes in x and y and a chunk of ZC planes of one state column b.  Each thread keeps the three
+// components of vin at planes z-1, z, z+1 of its own (x, y) in registers; plane z is also published to LDS with
+// a one-node ring around the tile (loaded by the edge threads), which supplies the x and y neighbours.  Every
+// value of vin is therefore read once from HBM per stage (plus the ring, mostly from L2), u once and vout
+// written once, against several reads of vin's neighbour planes when every node reads its own stencil.
+//   out = u + s (Z vin)   (stages 1-3),      u <- u + Z vin + phi frc   (LAST, in place; snapshot of u first)
+// Operation order per component as apply_z: diagonal, -x, +x, -y, +y, -z, +z, then the coupling.
+template <typename R, bool LAST, int ZC>
+__global__ __launch_bounds__(256) void grid_stage3d_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny, int64_t nz,
+                                                           cx<R>* u, const cx<R>* __restrict__ vin,
+                                                           cx<R>* __restrict__ vout, R s,
+                                                           const cx<R>* __restrict__ frc, R phr, R phi,
+                                                           cx<R>* __restrict__ snap) {
+  constexpr int TX = 64, TY = 4, NC = 3;
+  __shared__ cx<R> Lp[2][NC][TY + 2][TX + 2];
+  const int tid = threadIdx.x;
+  const int lx = tid & 63, ly = tid >> 6;
+  const int64_t nodes = nx * ny * nz;
+  const int64_t ix = (int64_t)blockIdx.x * TX + lx, iy = (int64_t)blockIdx.y * TY + ly;
+  const int64_t nzc = (nz + ZC - 1) / ZC;
+  const int64_t b = blockIdx.z / nzc, z0 = (blockIdx.z % nzc) * ZC;
+  const int64_t z1 = z0 + ZC < nz ? z0 + ZC : nz;
+  const bool own = ix < nx && iy < ny;
+  const int64_t cb = b * NC * nodes;
+  const int64_t sy = nx, sz = nx * ny;
+  // ring cells of the tile for the x/y neighbours: (ry, rx) in the (TY+2) x (TX+2) window, ry or rx on the edge
+  // (4*66 + ... = 140 cells); thread t < 140 loads ring cell t of every plane.
+  int ring_ry = -1, ring_rx = -1;
+  if (tid < 2 * (TX + 2)) {
+    ring_ry = tid < TX + 2 ? 0 : TY + 1;
+    ring_rx = tid < TX + 2 ? tid : tid - (TX + 2);
+  } else if (tid < 2 * (TX + 2) + 2 * TY) {
+    const int t = tid - 2 * (TX + 2);
+    ring_ry = 1 + (t >> 1);
+    ring_rx = (t & 1) ? TX + 1 : 0;
+  }
+  const int64_t rgx = (int64_t)blockIdx.x * TX + ring_rx - 1, rgy = (int64_t)blockIdx.y * TY + ring_ry - 1;
+  const bool ring_in = ring_ry >= 0 && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
+  auto ld = [&](int64_t z, int c) -> cx<R> {  // vin at this thread's (x, y), plane z, component c (0 outside)
+    return (own && z >= 0 && z < nz) ? vin[cb + c * nodes + z * sz + iy * sy + ix] : mk<R>(R(0), R(0));
+  };
+  // Per-plane operands of this thread's node: line coefficients, diagonal, coupling row block, u (and the
+  // forcing in the last stage).  They are loaded one plane ahead, with vin two planes ahead, so that every global
+  // load of an iteration is in flight while the previous plane is computed.
+  struct PlaneOps {
+    R cxm, cxp, cym, cyp, czm, czp, dd;
+    R K[9];
+    cx<R> uu[NC], ff[NC];
+  };
+  auto load_ops = [&](int64_t z) -> PlaneOps {
+    PlaneOps o;
+    const bool ok = own && z < nz;
+    const int64_t l = ok ? z * ny + iy : 0;
+    const int64_t p = ok ? z * sz + iy * sy + ix : 0;
+    o.cxm = ok ? Cf.cxm[l] : R(0); o.cxp = ok ? Cf.cxp[l] : R(0);
+    o.cym = ok ? Cf.cym[l] : R(0); o.cyp = ok ? Cf.cyp[l] : R(0);
+    o.czm = ok ? Cf.czm[l] : R(0); o.czp = ok ? Cf.czp[l] : R(0);
+    o.dd = ok ? Cf.d[p] : R(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o.K[q] = (ok && Cf.K != nullptr) ? Cf.K[l * 9 + q] : R(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      o.uu[c] = ok ? u[cb + c * nodes + p] : mk<R>(R(0), R(0));
+      o.ff[c] = (LAST && ok && frc != nullptr) ? frc[cb + c * nodes + p] : mk<R>(R(0), R(0));
+    }
+    return o;
+  };
+  cx<R> xm[NC], x0[NC], xp[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    xm[c] = ld(z0 - 1, c);
+    x0[c] = ld(z0, c);
+    xp[c] = ld(z0 + 1, c);
+  }
+  PlaneOps cur = load_ops(z0);
+  for (int64_t z = z0; z < z1; ++z) {
+    cx<R>(*L)[TY + 2][TX + 2] = Lp[z & 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      L[c][ly + 1][lx + 1] = x0[c];
+      if (ring_ry >= 0)
+        L[c][ring_ry][ring_rx] = ring_in ? vin[cb + c * nodes + z * sz + rgy * sy + rgx] : mk<R>(R(0), R(0));
+    }
+    __syncthreads();
+    // next planes' operands, in flight while this plane is computed
+    cx<R> xn[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xn[c] = ld(z + 2, c);
+    const PlaneOps nxt = load_ops(z + 1);
+    if (own) {
+      const int64_t p = z * sz + iy * sy + ix;
+      cx<R> zv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        cx<R> acc = mk<R>(cur.dd * x0[c].re, cur.dd * x0[c].im);
+        const cx<R> w = L[c][ly + 1][lx], e = L[c][ly + 1][lx + 2], sn = L[c][ly][lx + 1], nn = L[c][ly + 2][lx + 1];
+        acc.re += cur.cxm * w.re; acc.im += cur.cxm * w.im;
+        acc.re += cur.cxp * e.re; acc.im += cur.cxp * e.im;
+        acc.re += cur.cym * sn.re; acc.im += cur.cym * sn.im;
+        acc.re += cur.cyp * nn.re; acc.im += cur.cyp * nn.im;
+        acc.re += cur.czm * xm[c].re; acc.im += cur.czm * xm[c].im;
+        acc.re += cur.czp * xp[c].re; acc.im += cur.czp * xp[c].im;
+        zv[c] = acc;
+      }
+      if (Cf.K != nullptr) {
+        cx<R> add[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          add[c] = zv[c];
+#pragma unroll
+          for (int cp = 0; cp < NC; ++cp) {
+            add[c].re += cur.K[c * 3 + cp] * x0[cp].re;
+            add[c].im += cur.K[c * 3 + cp] * x0[cp].im;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) zv[c] = add[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int64_t e = cb + c * nodes + p;
+        const cx<R> uu = cur.uu[c];
+        if (LAST) {
+          if (snap != nullptr) snap[e] = uu;
+          const cx<R> f = cur.ff[c];
+          cx<R> r = mk<R>(uu.re + zv[c].re, uu.im + zv[c].im);
+          r.re += phr * f.re - phi * f.im;
+          r.im += phr * f.im + phi * f.re;
+          u[e] = r;
+        } else {
+          vout[e] = mk<R>(uu.re + s * zv[c].re, uu.im + s * zv[c].im);
+        }
+      }
+    }
+    cur = nxt;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      xm[c] = x0[c];
+      x0[c] = xp[c];
+      xp[c] = xn[c];
+    }
+  }
+}
+
 // One Horner pass of G = h Q_j(Z) F over [n_w][k] blocks (see tri_horner_kernel for the coefficients).
 template <typename TF, typename TO, int NC>
 __global__ __launch_bounds__(256) void grid_horner_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int64_t nz,
@@ -232,39 +339,23 @@ template <typename R> static GridCoef<R> coef_of(const GridOpDev& g, int fp64) {
   return c;
 }
 
-int launch_grid_stage(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
-                      const void* frc, double phr, double phi, void* snap, hipStream_t st) {
-  const int64_t nodes = g.nx * g.ny * g.nz;
-  const dim3 grid((unsigned)((nodes + 255) / 256));
-#define RES_GS(R, NC, L)                                                                                          \
-  hipLaunchKernelGGL((grid_stage_kernel<R, NC, L>), grid, dim3(256), 0, st, coef_of<R>(g, fp64), g.nx, g.ny, g.nz, \
-                     k, (cx<R>*)u, (const cx<R>*)vin, (cx<R>*)vout, (R)s, (const cx<R>*)frc, (R)phr, (R)phi,      \
+int launch_grid_stage3d(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
+                        const void* frc, double phr, double phi, void* snap, hipStream_t st) {
+  constexpr int ZC = 16;  // planes per workgroup: enough workgroups for whole rounds of the chip
+  if (g.ncomp != 3 || k < 1) return -1;
+  const int64_t nzc = (g.nz + ZC - 1) / ZC;
+  if ((int64_t)k * nzc > 65535) return -1;
+  const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)(k * nzc));
+#define RES_G3(R, L)                                                                                              \
+  hipLaunchKernelGGL((grid_stage3d_kernel<R, L, ZC>), grid, dim3(256), 0, st, coef_of<R>(g, fp64), g.nx, g.ny,     \
+                     g.nz, (cx<R>*)u, (const cx<R>*)vin, (cx<R>*)vout, (R)s, (const cx<R>*)frc, (R)phr, (R)phi,    \
                      (cx<R>*)snap)
-#define RES_GS2(R, NC) \
-  if (last) RES_GS(R, NC, true); else RES_GS(R, NC, false)
   if (fp64) {
-    if (g.ncomp == 3) { RES_GS2(double, 3); } else { RES_GS2(double, 1); }
+    if (last) RES_G3(double, true); else RES_G3(double, false);
   } else {
-    if (g.ncomp == 3) { RES_GS2(float, 3); } else { RES_GS2(float, 1); }
+    if (last) RES_G3(float, true); else RES_G3(float, false);
   }
-#undef RES_GS2
-#undef RES_GS
-  return 0;
-}
-
-int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
-                       double phi, void* snap, hipStream_t st) {
-  constexpr int TX = 56, TY = 32;  // interior of the 64 x 40 window
-  if (g.ncomp != 1 || g.nz != 1 || k < 1 || k > 65535) return -1;
-  const dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)((g.ny + TY - 1) / TY), (unsigned)k);
-  if (fp64)
-    hipLaunchKernelGGL((grid_step2d_kernel<double>), grid, dim3(256), 0, st, coef_of<double>(g, 1), g.nx,
-                       g.ny, (const cx<double>*)uin, (cx<double>*)uout, (const cx<double>*)frc, phr, phi,
-                       (cx<double>*)snap);
-  else
-    hipLaunchKernelGGL((grid_step2d_kernel<float>), grid, dim3(256), 0, st, coef_of<float>(g, 0), g.nx,
-                       g.ny, (const cx<float>*)uin, (cx<float>*)uout, (const cx<float>*)frc, (float)phr, (float)phi,
-                       (cx<float>*)snap);
+#undef RES_G3
   return 0;
 }
 
