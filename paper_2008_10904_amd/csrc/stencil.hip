@@ -339,6 +339,22 @@ template <typename R> static GridCoef<R> coef_of(const GridOpDev& g, int fp64) {
   return c;
 }
 
+int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
+                       double phi, void* snap, hipStream_t st) {
+  constexpr int TX = 56, TY = 32;  // interior of the 64 x 40 window
+  if (g.ncomp != 1 || g.nz != 1 || k < 1 || k > 65535) return -1;
+  const dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)((g.ny + TY - 1) / TY), (unsigned)k);
+  if (fp64)
+    hipLaunchKernelGGL((grid_step2d_kernel<double>), grid, dim3(256), 0, st, coef_of<double>(g, 1), g.nx,
+                       g.ny, (const cx<double>*)uin, (cx<double>*)uout, (const cx<double>*)frc, phr, phi,
+                       (cx<double>*)snap);
+  else
+    hipLaunchKernelGGL((grid_step2d_kernel<float>), grid, dim3(256), 0, st, coef_of<float>(g, 0), g.nx,
+                       g.ny, (const cx<float>*)uin, (cx<float>*)uout, (const cx<float>*)frc, (float)phr, (float)phi,
+                       (cx<float>*)snap);
+  return 0;
+}
+
 int launch_grid_stage3d(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
                         const void* frc, double phr, double phi, void* snap, hipStream_t st) {
   constexpr int ZC = 16;  // planes per workgroup: enough workgroups for whole rounds of the chip
