@@ -12,8 +12,9 @@
 //
 // Tiling: one 256-thread workgroup computes a 64 x 64 tile of the (complex) output; each wave owns a 32 x 32
 // quarter = 2 x 2 MFMA tiles, each complex tile being four real MFMAs (re*re - im*im, re*im + im*re).
-// The generated phase operand and the data operand are staged through LDS 16 deep in K.  The projection can
-// split K over gridDim.z, writing FP64 partial tiles that a reduction adds into the FP64 accumulator.
+// The generated phase operand and the data operand are staged through LDS 16 deep in K, fetched into registers
+// one chunk ahead of the matrix-core work.  The projection can split K over gridDim.z, writing FP64 partial tiles
+// that a reduction adds into the FP64 accumulator.
 #include "common.h"
 #include "kernels.h"
 
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   typedef typename Mfma<R>::v4 v4;
   __shared__ R As[2][GBM][GKC + 1];
   __shared__ R Bs[2][GKC][GBN + 1];
-  __shared__ double ph_re[GBM], ph_im[GBM];  // MODE 0: row factors; MODE 1: per-sample factors (GKC used)
+  __shared__ double ph_re[GBM], ph_im[GBM];  // MODE 0: per-row factors e^{i sigma w0 h s}
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -106,59 +107,61 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
       cim[i][j] = v4{0, 0, 0, 0};
     }
 
+  // Operands of one K chunk are fetched into registers one chunk ahead, so that the table gathers and data loads
+  // of chunk c+1 are in flight while chunk c runs on the matrix cores.  A[ar][ak+q] is a table value (conjugated
+  // for the adjoint sign, and for the projection's e^{-i...}); B[kr][nc+q] is data, whose projection rows carry
+  // the per-sample factor conj(e^{i sigma w0 h s_m}) (the projection phase factorises over j and m).
+  const int kr = tid >> 4;
+  const int nc = (tid & 15) * 4;
+  cx<R> ra[4], rb[4];
+  auto fetch = [&](int64_t k0) {
+    int64_t id = idx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kk = k0 + ak + q;
+      cx<R> v = mk<R>(0, 0);
+      if (arow_ok && kk < ke) {
+        v = btab[id];
+        if (a.sigma < 0) v.im = -v.im;
+        if (MODE == 1) v.im = -v.im;
+      }
+      ra[q] = v;
+      id += step;
+      if (id >= P) id -= P;
+    }
+    idx += step16;
+    if (idx >= P) idx -= P;
+    const int64_t kk = k0 + kr;
+    R pr = R(1), pi = R(0);
+    if (MODE == 1 && kk < ke) {
+      double sn, cs;
+      sincos(sig * a.w0h * (double)(a.s0 + kk * a.stride), &sn, &cs);
+      pr = (R)cs;
+      pi = (R)(-sn);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t n = n0 + nc + q;
+      cx<R> v = mk<R>(0, 0);
+      if (kk < ke && n < a.Ncols) {
+        v = B[kk * ldb + n];
+        if (MODE == 1) v = mk<R>(v.re * pr - v.im * pi, v.re * pi + v.im * pr);
+      }
+      rb[q] = v;
+    }
+  };
+
+  if (kb < ke) fetch(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += GKC) {
-    if (MODE == 1) {
-      __syncthreads();  // previous chunk's readers of ph_* are done
-      if (tid < GKC) {
-        const int64_t m = k0 + tid;
-        const int64_t s = a.s0 + m * a.stride;
-        double sn, cs;
-        sincos(sig * a.w0h * (double)s, &sn, &cs);
-        ph_re[tid] = cs;
-        ph_im[tid] = sn;
-      }
-      __syncthreads();
-    }
-    // ---- generate the phase operand tile As[ar][ak..ak+3]
-    {
-      int64_t id = idx;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t kk = k0 + ak + q;
-        cx<R> v = mk<R>(0, 0);
-        if (arow_ok && kk < ke) {
-          v = btab[id];
-          if (a.sigma < 0) v.im = -v.im;
-          if (MODE == 1) {
-            // conj(table * e^{i sigma w0 h s})
-            const R pr = (R)ph_re[ak + q], pi = (R)ph_im[ak + q];
-            const cx<R> w = mk<R>(v.re * pr - v.im * pi, v.re * pi + v.im * pr);
-            v = mk<R>(w.re, -w.im);
-          }
-        }
-        As[0][ar][ak + q] = v.re;
-        As[1][ar][ak + q] = v.im;
-        id += step;
-        if (id >= P) id -= P;
-      }
-      idx += step16;
-      if (idx >= P) idx -= P;
-    }
-    // ---- load the data operand tile Bs[kk][n]: thread -> row tid/16, four consecutive columns
-    {
-      const int kr = tid >> 4;
-      const int nc = (tid & 15) * 4;
-      const int64_t kk = k0 + kr;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t n = n0 + nc + q;
-        cx<R> v = mk<R>(0, 0);
-        if (kk < ke && n < a.Ncols) v = B[kk * ldb + n];
-        Bs[0][kr][nc + q] = v.re;
-        Bs[1][kr][nc + q] = v.im;
-      }
+    for (int q = 0; q < 4; ++q) {
+      As[0][ar][ak + q] = ra[q].re;
+      As[1][ar][ak + q] = ra[q].im;
+      Bs[0][kr][nc + q] = rb[q].re;
+      Bs[1][kr][nc + q] = rb[q].im;
     }
     __syncthreads();
+    if (k0 + GKC < ke) fetch(k0 + GKC);
 #pragma unroll
     for (int k4 = 0; k4 < GKC; k4 += 4) {
       R are[2], aim[2], nai[2], bre[2], bim[2];
@@ -238,7 +241,7 @@ int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st) {
   const int64_t gx = (a.Ncols + GBN - 1) / GBN;
   const int64_t gy = (a.M + GBM - 1) / GBM;
   const int64_t gz = (a.K + a.k_per_split - 1) / a.k_per_split;
-  if (gx > 0x7fffffff || gy > 65535 * 64 || gz > 65535) return -1;
+  if (gx > 0x7fffffff || gy > 65535 || gz > 65535) return -1;
   dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz);
   if (a.mode == 0) {
     if (fp64) hipLaunchKernelGGL((phase_gemm_kernel<double, 0>), grid, dim3(256), 0, st, a);
