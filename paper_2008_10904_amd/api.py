@@ -166,6 +166,24 @@ class ResolventOp:
             ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
         return gains, V, U, hist
 
+    def modes_polished(self, op_fp64, f0_hat, grid, run, iters, want_hist=True):
+        """Mixed-precision block power iteration with an FP64 Rayleigh-Ritz finish.
+
+        The iterations run on this (mixed-precision) handle; then one FP64 run on op_fp64 (the same operator built
+        with precision "fp64") takes the Rayleigh-Ritz values on the final force-mode subspace.  Those gains are
+        stationary at the modes, so their error is second order in the mixed-precision subspace error, while every
+        iteration keeps the mixed-precision speed (the finish costs one FP64 iteration).  Returns (gains, V, U,
+        hist) as modes, with V, U complex128 from the FP64 finish and hist the mixed iterations' history whose last
+        row carries the finished gains."""
+        torch = _torch()
+        if self.precision != "mixed" or op_fp64.precision != "fp64" or op_fp64.n != self.n:
+            raise ValueError("modes_polished needs this handle in mixed precision and op_fp64 in fp64, same size")
+        _, V, _, hist = self.modes(f0_hat, grid, run, iters, want_modes=True, want_hist=want_hist)
+        gains, V2, U2, _ = op_fp64.modes(V.to(torch.complex128).contiguous(), grid, run, 1, want_hist=False)
+        if want_hist:
+            hist[-1, ..., 0] = gains
+        return gains, V2, U2, hist
+
     def diag_size(self):
         """Length of the diagonal that set_diagonal and the reverse mode address: N for a tridiagonal operator,
         nz*ny*nx (one value per node, shared by the components) for a grid operator."""

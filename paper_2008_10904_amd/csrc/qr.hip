@@ -359,6 +359,51 @@ int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t
   return 0;
 }
 
+// Per-(instance, frequency) amplitude weights of the block power iteration: fac = 1/sqrt(sigma_1) from the last
+// gains (1 where a gain is not a positive finite number).
+__global__ void freq_weight_kernel(const double* __restrict__ gains, double* __restrict__ fac, int ninst, int nw,
+                                   int k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst * nw) return;
+  const double g = gains[(int64_t)i * k];
+  fac[i] = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 1.0;
+}
+
+// out[j][c][n] = in[j][c][n] * fac[m(n)][j] (invert: divided by it), m(n) the instance of unknown n; FP64.
+__global__ __launch_bounds__(256) void freq_scale_kernel(const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
+                                                         int64_t N, int k, int nw, const int64_t* __restrict__ off,
+                                                         int ninst, const double* __restrict__ fac, int invert) {
+  const int64_t total = (int64_t)nw * k * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = e % N;
+    const int64_t j = e / ((int64_t)k * N);
+    int lo = 0, hi = ninst - 1;  // instance m with off[m] <= n < off[m+1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= n) lo = mid;
+      else hi = mid - 1;
+    }
+    const double f = fac[(int64_t)lo * nw + j];
+    const double w = invert ? 1.0 / f : f;
+    const cx<double> v = in[e];
+    out[e] = mk<double>(v.re * w, v.im * w);
+  }
+}
+
+int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st) {
+  const int n = ninst * nw;
+  hipLaunchKernelGGL(freq_weight_kernel, dim3((n + 255) / 256), dim3(256), 0, st, gains, fac, ninst, nw, k);
+  return 0;
+}
+
+int launch_freq_scale(const void* in, void* out, int64_t N, int k, int nw, const int64_t* off, int ninst,
+                      const double* fac, int invert, hipStream_t st) {
+  const int64_t count = (int64_t)nw * k * N;
+  hipLaunchKernelGGL(freq_scale_kernel, dim3(grid1d(count)), dim3(256), 0, st, (const cx<double>*)in,
+                     (cx<double>*)out, N, k, nw, off, ninst, fac, invert);
+  return 0;
+}
+
 int launch_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes % 4 != 0) return -1;
   const int64_t words = (int64_t)(bytes / 4);

@@ -1570,12 +1570,30 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   RES_TRY(ws_get(op, "modes_gains", gcount * sizeof(double), &dg));
   if (hist) RES_TRY(ws_get(op, "modes_hist", (size_t)iters * gcount * 2 * sizeof(double), &dh));
   launch_convert(f0_hat, op->fp64(), Fh, 1, count, 1.0, st);
+  // Amplitude weights (iterations after the first): every run marches all frequencies superposed in one state, so
+  // in the working precision the rounding of the large responses lands on the small ones.  The runs therefore
+  // march frequency j with its input scaled by 1/sqrt(sigma_1(j)) from the previous iteration and unscale the
+  // result, which balances the response amplitudes (large gains) against the forcing amplitudes (small gains)
+  // across frequencies -- the frequency normalisation of Sec. 2.2, applied between iterations.  Exact in exact
+  // arithmetic (the runs are linear); the QR and SVD see unscaled blocks.
+  void* fac;
+  RES_TRY(ws_get(op, "modes_fac", (size_t)op->ninst * nw * sizeof(double), &fac));
+  // Weighted run: the input block is scaled in place (restored afterwards when keep_input) and the output unscaled.
+  auto weighted_run = [&](bool weighted, bool keep_input, void* in, double* out, int sigma, hipStream_t s) -> int {
+    if (!weighted) return run_any(op, pl, k, in, 1, out, sigma, s);
+    launch_freq_scale(in, in, op->N, k, nw, op->d_off, op->ninst, (const double*)fac, 0, s);
+    RES_TRY(run_any(op, pl, k, in, 1, out, sigma, s));
+    if (keep_input) launch_freq_scale(in, in, op->N, k, nw, op->d_off, op->ninst, (const double*)fac, 1, s);
+    launch_freq_scale(out, out, op->N, k, nw, op->d_off, op->ninst, (const double*)fac, 1, s);
+    HIP_TRY(hipGetLastError());
+    return RES_OK;
+  };
   // One iteration on stream s; hprev receives the norm estimate of the previous iteration, hcur the gains.
-  auto iteration = [&](bool last, double* hprev, double* hcur, hipStream_t s) -> int {
+  auto iteration = [&](bool last, bool weighted, double* hprev, double* hcur, hipStream_t s) -> int {
     // 1. F = Q(QR(F_hat))
     RES_TRY(cholqr2(op, nw, k, (double*)Fh, rY, hprev, s));
     // 2. Y = R_d F
-    RES_TRY(run_any(op, pl, k, Fh, 1, (double*)Y, +1, s));
+    RES_TRY(weighted_run(weighted, last && V, Fh, (double*)Y, +1, s));  // F_hat is needed again only for V
     // 3. Y = Q_Y R_Y, R_Y = Phi Sigma Psi^H
     RES_TRY(cholqr2(op, nw, k, (double*)Y, rY, nullptr, s));
     launch_svd(rY, k, nw, op->ninst, phi, psi, apsi, (double*)dg, hcur, s);
@@ -1583,8 +1601,9 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
       if (U) launch_rmul(Y, 1, U, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), phi, s);
       if (V) launch_rmul(Fh, 1, V, op->fp64(), op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), psi, s);
     }
-    // 4. Z = R_d^H Q_Y
-    RES_TRY(run_any(op, pl, k, Y, 1, (double*)Z, -1, s));
+    // 4. Z = R_d^H Q_Y (with the weights of the previous iteration, as the direct run)
+    RES_TRY(weighted_run(weighted, false, Y, (double*)Z, -1, s));
+    launch_freq_weights((const double*)dg, (double*)fac, op->ninst, nw, k, s);  // for the next iteration
     // 5. F_hat = Z R_Y Psi
     launch_rmul(Z, 1, Fh, 1, op->N, k, op->d_off, op->ninst, nw, nsplit_for(max_instance_len(op)), apsi, s);
     HIP_TRY(hipGetLastError());
@@ -1595,7 +1614,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   // iteration (history slots are fixed scratch rows copied out after each replay), the last runs eagerly (modes).
   const bool graphs = op->use_graphs && iters >= 3;
   int it = 0;
-  RES_TRY(iteration(iters == 1, nullptr, hslot(0), st));
+  RES_TRY(iteration(iters == 1, false, nullptr, hslot(0), st));
   ++it;
   if (graphs) {
     void* hs = nullptr;
@@ -1607,7 +1626,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
     op->capturing = true;
-    int rc = iteration(false, hs_prev, hs_cur, op->cap_stream);
+    int rc = iteration(false, true, hs_prev, hs_cur, op->cap_stream);
     op->capturing = false;
     const hipError_t ec = hipStreamEndCapture(op->cap_stream, &graph);
     if (rc == RES_OK && ec != hipSuccess) rc = fail(RES_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
@@ -1637,7 +1656,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
     (void)hipGetLastError();
     RES_TRY(rc);
   }
-  for (; it < iters; ++it) RES_TRY(iteration(it == iters - 1, hslot(it - 1), hslot(it), st));
+  for (; it < iters; ++it) RES_TRY(iteration(it == iters - 1, true, hslot(it - 1), hslot(it), st));
   if (hist) {
     // norm estimate of the last iteration from the Gram of the final F_hat
     const int nsplit = nsplit_for(max_instance_len(op));

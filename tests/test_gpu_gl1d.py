@@ -155,6 +155,31 @@ def test_mixed_precision_error_vs_fp64_oracle():
     assert np.abs(g[0] / g_ref - 1).max() < 1e-4
 
 
+def test_mixed_modes_with_fp64_finish():
+    import torch
+    say("case: mixed modes + FP64 Rayleigh-Ritz finish, tiny GL k=3")
+    h, P, nw, k, periods, iters = 0.05, 400, 3, 3, 10, 6
+    dw = 2 * np.pi / (P * h)
+    L, _ = O_ops.gl_operator(N_T, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F0 = forcing(9, nw, k, N_T)
+    a, ad = O_it.stepped_applies(L, h, -0.2, dw, "periodic", periods=periods, stride=100)
+    g_ref, V_ref, _, _ = O_it.block_power_iteration(a, ad, F0, iters)
+    opm = gpu_gl(N_T, 0.2, -0.01, h, precision="mixed")
+    op64 = gpu_gl(N_T, 0.2, -0.01, h, precision="fp64")
+    grid, run = opm.grid(-0.2, dw, nw), opm.run("periodic", periods=periods, stride=100)
+    gm, _, _, _ = opm.modes(gpu_tensor(F0, torch.complex64), grid, run, iters, want_hist=False)
+    g, V, U, H = opm.modes_polished(op64, gpu_tensor(F0, torch.complex64), grid, run, iters)
+    torch.cuda.synchronize()
+    err, err_m = np.abs(g[0] / g_ref - 1).max(), np.abs(gm[0] / g_ref - 1).max()
+    say("  gain err mixed", err_m, "with FP64 finish", err)
+    assert V.dtype == torch.complex128 and U.dtype == torch.complex128
+    assert err < 1e-6 and err <= err_m
+    assert np.array_equal(H[-1, ..., 0], g)
+    assert mode_alignment(to_np(V)[:, :1], V_ref[:, :1]) > 1 - 1e-6
+    with pytest.raises(ValueError):
+        op64.modes_polished(opm, gpu_tensor(F0), grid, run, iters)
+
+
 def test_single_frequency_single_column_edge():
     import torch
     say("case: n_omega=1, k=1, N=5")
