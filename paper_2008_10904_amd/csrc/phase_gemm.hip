@@ -7,14 +7,16 @@
 //
 // sw_j = sigma (w0 + j dw) with dw = 2 pi / (P h).  Phases are index-exact:
 //   e^{i sw_j t_s} = e^{i sigma w0 h s} * btab[(j * (s mod P)) mod P]^sigma,   btab[m] = e^{2 pi i m / P},
-// so no phase is ever accumulated in working precision; the w0 factor is one FP64 sincos per row (synthesis)
-// or per sample (projection).  The table index advances incrementally (no division in the inner loop).
+// so no phase is ever accumulated in working precision; the w0 factor is one FP64 sincos per row (synthesis) or
+// an FP64 rotation per sample, re-evaluated exactly every 64 K chunks (projection).  The table index advances
+// incrementally (no division in the inner loop).
 //
 // Tiling: one 256-thread workgroup computes a 64 x 64 tile of the (complex) output; each wave owns a 32 x 32
 // quarter = 2 x 2 MFMA tiles, each complex tile being four real MFMAs (re*re - im*im, re*im + im*re).
-// The generated phase operand and the data operand are staged through LDS 16 deep in K, fetched into registers
-// one chunk ahead of the matrix-core work.  The projection can split K over gridDim.z, writing FP64 partial tiles
-// that a reduction adds into the FP64 accumulator.
+// The generated phase operand and the data operand are staged through LDS 16 deep in K, loaded into registers
+// one chunk ahead of the matrix-core work.  Workgroups walk the M tiles of one column tile on one XCD.  The
+// projection can split K over gridDim.y, writing FP64 partial tiles that a reduction adds into the FP64
+// accumulator.
 #include "common.h"
 #include "kernels.h"
 
@@ -52,8 +54,16 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t n0 = (int64_t)blockIdx.x * GBN;
-  const int64_t m0 = (int64_t)blockIdx.y * GBM;
+  // Tile order: workgroups are dealt to the eight XCDs in turn (id mod 8), and each XCD has its own L2.  All M
+  // tiles of one column tile go to the same XCD, one after the other, so that its data operand (the column tile's
+  // K rows) is read from HBM once and then hit in that XCD's L2.
+  const int64_t gyt = (a.M + GBM - 1) / GBM;
+  const int64_t slot = (int64_t)(blockIdx.x >> 3);
+  const int64_t mt = slot % gyt;
+  const int64_t nt = (slot / gyt) * 8 + (blockIdx.x & 7);
+  if (nt * GBN >= a.Ncols) return;  // padding of the column tiles to a multiple of 8 (whole workgroup)
+  const int64_t n0 = nt * GBN;
+  const int64_t m0 = mt * GBM;
   const int64_t P = a.P;
   const cx<R>* __restrict__ btab = (const cx<R>*)a.btab;
   const cx<R>* __restrict__ B = (const cx<R>*)a.bmat;
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
   const int64_t ldb = a.ldb > 0 ? a.ldb : a.Ncols;
 
   // K range of this split
-  const int64_t kb = (int64_t)blockIdx.z * a.k_per_split;
+  const int64_t kb = (int64_t)blockIdx.y * a.k_per_split;
   int64_t ke = kb + a.k_per_split;
   if (ke > a.K) ke = a.K;
 
@@ -107,61 +117,81 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
       cim[i][j] = v4{0, 0, 0, 0};
     }
 
-  // Operands of one K chunk are fetched into registers one chunk ahead, so that the table gathers and data loads
-  // of chunk c+1 are in flight while chunk c runs on the matrix cores.  A[ar][ak+q] is a table value (conjugated
-  // for the adjoint sign, and for the projection's e^{-i...}); B[kr][nc+q] is data, whose projection rows carry
-  // the per-sample factor conj(e^{i sigma w0 h s_m}) (the projection phase factorises over j and m).
+  // Operands of one K chunk are loaded into registers one chunk ahead, so that the table gathers and data loads
+  // of chunk c+1 are in flight while chunk c runs on the matrix cores.  The loads are unconditional (addresses
+  // clamped into range) and carry no arithmetic, so nothing waits for them before the next chunk is staged; the
+  // staging step masks the out-of-range entries, conjugates the table values (adjoint sign, and the projection's
+  // e^{-i...}) and multiplies the projection rows by the per-sample factor conj(e^{i sigma w0 h s_m}) (the
+  // projection phase factorises over j and m).  That factor advances by one FP64 complex product per chunk and is
+  // re-evaluated with sincos every 64 chunks, so its drift stays at the FP64 rounding level.
   const int kr = tid >> 4;
   const int nc = (tid & 15) * 4;
+  const bool conj_a = (a.sigma < 0) != (MODE == 1);
   cx<R> ra[4], rb[4];
-  auto fetch = [&](int64_t k0) {
+  auto load = [&](int64_t k0) {
     int64_t id = idx;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t kk = k0 + ak + q;
-      cx<R> v = mk<R>(0, 0);
-      if (arow_ok && kk < ke) {
-        v = btab[id];
-        if (a.sigma < 0) v.im = -v.im;
-        if (MODE == 1) v.im = -v.im;
-      }
-      ra[q] = v;
+      ra[q] = btab[id];
       id += step;
       if (id >= P) id -= P;
     }
     idx += step16;
     if (idx >= P) idx -= P;
-    const int64_t kk = k0 + kr;
+    const int64_t kk = k0 + kr < ke ? k0 + kr : ke - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t n = n0 + nc + q < a.Ncols ? n0 + nc + q : a.Ncols - 1;
+      rb[q] = B[kk * ldb + n];
+    }
+  };
+  double zr = 1.0, zi = 0.0, wr = 1.0, wi = 0.0;  // MODE 1: sample factor of row kr, and its per-chunk step
+  if (MODE == 1) {
+    double sn, cs;
+    sincos(sig * a.w0h * (double)(GKC * a.stride), &sn, &cs);
+    wr = cs;
+    wi = -sn;
+  }
+  auto stage = [&](int64_t k0, int64_t c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = arow_ok && k0 + ak + q < ke;
+      As[0][ar][ak + q] = ok ? ra[q].re : R(0);
+      As[1][ar][ak + q] = ok ? (conj_a ? -ra[q].im : ra[q].im) : R(0);
+    }
+    const bool rok = k0 + kr < ke;
     R pr = R(1), pi = R(0);
-    if (MODE == 1 && kk < ke) {
-      double sn, cs;
-      sincos(sig * a.w0h * (double)(a.s0 + kk * a.stride), &sn, &cs);
-      pr = (R)cs;
-      pi = (R)(-sn);
+    if (MODE == 1) {
+      if ((c & 63) == 0) {
+        double sn, cs;
+        sincos(sig * a.w0h * (double)(a.s0 + (k0 + kr) * a.stride), &sn, &cs);
+        zr = cs;
+        zi = -sn;
+      } else {
+        const double t = zr * wr - zi * wi;
+        zi = zr * wi + zi * wr;
+        zr = t;
+      }
+      pr = (R)zr;
+      pi = (R)zi;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t n = n0 + nc + q;
-      cx<R> v = mk<R>(0, 0);
-      if (kk < ke && n < a.Ncols) {
-        v = B[kk * ldb + n];
-        if (MODE == 1) v = mk<R>(v.re * pr - v.im * pi, v.re * pi + v.im * pr);
-      }
-      rb[q] = v;
+      const bool ok = rok && n0 + nc + q < a.Ncols;
+      cx<R> v = rb[q];
+      if (MODE == 1) v = mk<R>(v.re * pr - v.im * pi, v.re * pi + v.im * pr);
+      Bs[0][kr][nc + q] = ok ? v.re : R(0);
+      Bs[1][kr][nc + q] = ok ? v.im : R(0);
     }
   };
 
-  if (kb < ke) fetch(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += GKC) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[0][ar][ak + q] = ra[q].re;
-      As[1][ar][ak + q] = ra[q].im;
-      Bs[0][kr][nc + q] = rb[q].re;
-      Bs[1][kr][nc + q] = rb[q].im;
-    }
+  if (kb < ke) load(kb);
+  int64_t c = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += GKC, ++c) {
+    stage(k0, c);
     __syncthreads();
-    if (k0 + GKC < ke) fetch(k0 + GKC);
+    load(k0 + GKC);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of this chunk's matrix-core work
 #pragma unroll
     for (int k4 = 0; k4 < GKC; k4 += 4) {
       R are[2], aim[2], nai[2], bre[2], bim[2];
@@ -206,7 +236,7 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
           out[row * a.Ncols + col] = mk<R>((R)(xr * pr - xi * pi), (R)(xr * pi + xi * pr));
         } else if (a.partial != nullptr) {
           cx<double>* part = (cx<double>*)a.partial;
-          part[((int64_t)blockIdx.z * a.M + row) * a.Ncols + col] = mk<double>(xr, xi);
+          part[((int64_t)blockIdx.y * a.M + row) * a.Ncols + col] = mk<double>(xr, xi);
         } else {
           cx<double>* acc = (cx<double>*)a.out;
           cx<double> o = acc[row * a.Ncols + col];
@@ -241,8 +271,9 @@ int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st) {
   const int64_t gx = (a.Ncols + GBN - 1) / GBN;
   const int64_t gy = (a.M + GBM - 1) / GBM;
   const int64_t gz = (a.K + a.k_per_split - 1) / a.k_per_split;
-  if (gx > 0x7fffffff || gy > 65535 || gz > 65535) return -1;
-  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz);
+  const int64_t blocks = (gx + 7) / 8 * 8 * gy;  // column tiles padded to a multiple of 8 (see the tile order)
+  if (blocks > 0x7fffffff || gz > 65535) return -1;
+  dim3 grid((unsigned)blocks, (unsigned)gz);
   if (a.mode == 0) {
     if (fp64) hipLaunchKernelGGL((phase_gemm_kernel<double, 0>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((phase_gemm_kernel<float, 0>), grid, dim3(256), 0, st, a);

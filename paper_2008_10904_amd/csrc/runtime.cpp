@@ -825,6 +825,27 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   RES_TRY(zero_device(acc, (size_t)nw * ncols * sizeof(cd), st));
   op->march_band = op->d_band[s];
 
+  // Snapshot rows (ncols values and one scratch slot each), buffered for the projection GEMM.  Each flush reads
+  // and writes the FP64 accumulator once, so longer flushes amortise that traffic: the default buffer is 8 GiB,
+  // at most a tenth of the free device memory (plus the buffer this handle already holds) and at least 64 rows;
+  // RESOLVENT_SNAP_BUDGET_GB overrides it.  It is taken before the forcing table, whose budget sees what is left.
+  const int64_t snap_ld = ncols + 1;
+  double snap_budget;
+  if (std::getenv("RESOLVENT_SNAP_BUDGET_GB")) {
+    snap_budget = env_double("RESOLVENT_SNAP_BUDGET_GB", 2.0) * 1073741824.0;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const auto held = op->ws.find("snapshots");
+    const double held_b = held != op->ws.end() ? (double)held->second.bytes : 0.0;
+    snap_budget = std::min(8.0 * 1073741824.0, 0.1 * ((double)free_b + held_b));
+    if (op->capturing && held_b > 0) snap_budget = held_b;  // a captured run reuses the buffer it was sized with
+  }
+  int64_t snap_cap = std::max<int64_t>(64, (int64_t)(snap_budget / ((double)snap_ld * ws)));
+  snap_cap = std::min<int64_t>(snap_cap, pl.pcount);
+  void* snap = nullptr;
+  RES_TRY(ws_get(op, "snapshots", (size_t)snap_cap * snap_ld * ws, &snap));
+
   // Forcing rows: the whole first period as one table when it fits in device memory (it is then synthesised
   // once per run and reused by every period), else tiles synthesised as the march goes.  The default budget
   // is the free device memory (plus the table this handle already holds) minus a reserve for the rest of the
@@ -872,13 +893,6 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));
     RES_TRY(ws_get(op, "forcing", (size_t)(tile_rows + 16) * ncols * ws, &frc));  // + prefetch padding rows
   }
-  // snapshot rows: ncols values and one scratch slot
-  const int64_t snap_ld = ncols + 1;
-  const double snap_budget = env_double("RESOLVENT_SNAP_BUDGET_GB", 2.0) * 1073741824.0;
-  int64_t snap_cap = std::max<int64_t>(64, (int64_t)(snap_budget / ((double)snap_ld * ws)));
-  snap_cap = std::min<int64_t>(snap_cap, pl.pcount);
-  void* snap = nullptr;
-  RES_TRY(ws_get(op, "snapshots", (size_t)snap_cap * snap_ld * ws, &snap));
 
   void* dsegs;
   int64_t nseg;
