@@ -43,6 +43,9 @@ def parse():
                          "'default' (the library's default plan) or 'cfg,chunk,block,persist'.  Default: 'default' "
                          "for gl_periodic_n2000 (the plan its profiles were taken with; the tuner lands on it or on "
                          "one within noise), 'tuned' for gl_batched_64")
+    ap.add_argument("--step-power", type=int, default=None, choices=[1, 2, 4],
+                    help="1-D workloads: RK4 steps per kernel step (band P(Z)^m and the combined forcing of m "
+                         "steps); default: the library's default (4)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -67,19 +70,19 @@ def build_op(cfg, precision):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step1d_gl_periodic_n2000_traffic.md")
-STEPPER_SOURCES = ("step1d.hip", "common.h")  # the stepper kernel and the helpers it inlines
+STEPPER_SOURCES = ("step1d_kernel.h", "common.h")  # the stepper kernel and the helpers it inlines
 
 
-def measured_traffic(plan=None):
+def measured_traffic(plan=None, step_power=1):
     """HBM bytes per stepper launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
     stepper's sources have changed since those counters were taken (their hash is recorded beside the figure) or
-    when the run uses a different stepper plan than the profiled one."""
+    when the run uses a different stepper plan or step power than the profiled one."""
     import hashlib
     h = hashlib.sha256()
     for f in STEPPER_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_10904_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    value, digest, prof_plan = None, None, None
+    value, digest, prof_plan, prof_power = None, None, None, 1
     try:
         with open(TRAFFIC_PROFILE) as fh:
             for line in fh:
@@ -89,18 +92,21 @@ def measured_traffic(plan=None):
                     digest = line.rsplit(":", 1)[1].strip()
                 elif line.startswith("plan:"):
                     prof_plan = [int(x) for x in line.split(":", 1)[1].split(",")]
+                elif line.startswith("step_power:"):
+                    prof_power = int(line.split(":", 1)[1])
     except OSError:
         return None
-    if digest != h.hexdigest() or (plan is not None and list(plan) != prof_plan):
+    if digest != h.hexdigest() or (plan is not None and list(plan) != prof_plan) or step_power != prof_power:
         return None
     return value
 
 
-def choose_plan(op, k, how):
-    """Apply the requested stepper plan (see --plan) and return the plan in effect."""
+def choose_plan(op, k, how, search_power=False):
+    """Apply the requested stepper plan (see --plan) and return the plan in effect.  A tuned plan with
+    search_power also chooses the step power (4, 2 or 1 RK4 steps per kernel step)."""
     from paper_2008_10904_amd import autotune
     if how == "tuned":
-        return autotune.tuned(op, k)[0]
+        return autotune.tuned(op, k, powers=(4, 2, 1) if search_power else None)[0]
     if how == "default":
         return op.get_plan()
     return op.set_plan([int(x) for x in how.split(",")])
@@ -168,10 +174,13 @@ def bench_batched(args):
     steps_per_run = cfg["periods"] * P
     F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], ntot)
     sweeps_per_step = ntot * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
-    res, plans = {}, {}
+    res, plans, powers = {}, {}, {}
     for prec, dtype in (("mixed", torch.complex64), ("fp64", torch.complex128)):
         op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=prec, offsets=off)
-        plans[prec] = choose_plan(op, cfg["k"], args.plan)
+        if args.step_power:
+            op.set_step_power(args.step_power)
+        plans[prec] = choose_plan(op, cfg["k"], args.plan, search_power=args.step_power is None)
+        powers[prec] = op.get_step_power()
         grid = op.grid(w0, dw, cfg["n_omega"])
         run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
         f = torch.from_numpy(F).to(dtype).cuda()
@@ -196,6 +205,7 @@ def bench_batched(args):
                  "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt64.items()}},
         "max_rel_gain_diff_mixed_vs_fp64": float(np.abs(gm / g64 - 1).max()),
         "stepper_plan": {k: list(v) for k, v in plans.items()},
+        "step_power": powers,
     }
     print(json.dumps(out), flush=True)
 
@@ -327,7 +337,10 @@ def main():
     sweeps_per_step = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
 
     op = build_op(cfg, "fp64")
+    if args.step_power:
+        op.set_step_power(args.step_power)
     plan64 = choose_plan(op, cfg["k"], args.plan)  # set-up: the stepper plan
+    power = op.get_step_power()
     grid = op.grid(w0, dw, cfg["n_omega"])
     run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
     f64 = torch.from_numpy(F).cuda()
@@ -357,15 +370,18 @@ def main():
                    "time_steps_per_step": 2 * steps_per_run},
         "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(plan64), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
+                     "traffic": measured_traffic(plan64, power), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
                      "steps_per_launch": steps_per_launch},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "stepper_plan": list(plan64),
+        "step_power": power,
     }
     del op, f64
     torch.cuda.empty_cache()
     if not args.no_mixed:
         opm = build_op(cfg, "mixed")
+        if args.step_power:
+            opm.set_step_power(args.step_power)
         planm = choose_plan(opm, cfg["k"], args.plan)
         f32 = torch.from_numpy(F).to(torch.complex64).cuda()
         dtm, gainsm, ktm = time_steps(opm, f32, grid, run, args.steps, args.warmup)

@@ -186,6 +186,19 @@ int resolvent_op_set_graphs(resolvent_op* op, int32_t enable);
 int resolvent_op_get_plan(const resolvent_op* op, int32_t plan[4]);
 int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]);
 
+/* Multi-step march of a RES_OP_TRIDIAG operator (Sec. 2.1, the RK4 march written as one step): with m = 2 or 4
+ * each kernel step advances m RK4 steps at once, u_{s+m} = P(Z)^m u_s + sum_j e^{i w_j t_s} G_j^(m) with
+ * G_j^(m) = sum_{r<m} e^{i w_j r h} P(Z)^(m-1-r) h Q_j(Z) F_j.  P(Z)^m is formed once in FP64 on the host (a
+ * band of radius 4m), so the march reaches the same discrete response as m = 1 up to rounding (not bit for bit).
+ * A run uses m only when its period, projection start and stride, and the plan's exchange interval (plan[2])
+ * are multiples of m and the forcing stays on for the whole run (the periodic method); otherwise, e.g. for the
+ * transient method, it marches one step at a time.  Default 4.  A handle on its default stepper plan moves
+ * to the default plan of the new power (set_plan and the autotuner fix the plan).  RES_EINVAL for m not in
+ * {1, 2, 4} or during graph capture, RES_ENOTSUP for grid operators.  The autotuner times plans in the current
+ * form. */
+int resolvent_op_set_step_power(resolvent_op* op, int32_t m);
+int resolvent_op_get_step_power(const resolvent_op* op, int32_t* m);
+
 /* Stepper autotuner for RES_OP_TRIDIAG operators: times every candidate plan on `steps` forced steps of k
  * columns on `stream` (the handle's state buffers are overwritten; run results are unaffected), keeps the
  * fastest, and writes it to plan_out and its time per step in microseconds to us_per_step (each may be NULL).

@@ -51,6 +51,8 @@ SIGNATURES = {
     "resolvent_op_set_graphs": (c_int32, [c_void_p, c_int32]),
     "resolvent_op_get_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "resolvent_op_set_step_power": (c_int32, [c_void_p, c_int32]),
+    "resolvent_op_get_step_power": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_tune": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), _dp, c_void_p]),
     "resolvent_op_set_timing": (c_int32, [c_void_p, c_int32]),
     "resolvent_op_get_timing": (c_int32, [c_void_p, c_int32, _dp, POINTER(c_int64)]),

@@ -235,6 +235,16 @@ class ResolventOp:
         check(self._lib.resolvent_op_set_plan(self._h, p))
         return self.get_plan()
 
+    def set_step_power(self, m):
+        """RK4 steps per kernel step of the 1-D march (1, 2 or 4): the band P(Z)^m and the combined forcing of m
+        steps; runs whose period, projection samples and exchange interval are multiples of m use it."""
+        check(self._lib.resolvent_op_set_step_power(self._h, int(m)))
+
+    def get_step_power(self):
+        m = ctypes.c_int32()
+        check(self._lib.resolvent_op_get_step_power(self._h, ctypes.byref(m)))
+        return int(m.value)
+
     def tune(self, k, steps=2048):
         """Time every candidate stepper plan for k columns and keep the fastest; returns (plan, us per step)."""
         p = (ctypes.c_int32 * 4)()

@@ -15,7 +15,8 @@ struct Step1DArgs {
   int cfg;                 // index into the (threads, unknowns per thread, prefetch depth) table
   const Seg1D* segs;
   int64_t nseg;
-  const void* band;        // [N][9] complex (working precision)
+  int mstep;               // RK4 steps per kernel step: 1, 2 or 4
+  const void* band;        // [N][8*mstep+1] complex (working precision): P(Z)^mstep
   const void* state_in;    // [ncol][N]
   void* state_out;         // [ncol][N] (may equal state_in when every region is owned entirely)
   int64_t N, row_len;      // row_len = ncol * N
@@ -33,7 +34,11 @@ struct Step1DArgs {
   uint64_t spin_ns;
   int* err;
 };
-int step1d_coresident(int fp64, int cfg, int device);
+int step1d_coresident(int fp64, int cfg, int device, int mstep);
+int launch_step1d_m2(const Step1DArgs& a, hipStream_t st);
+int launch_step1d_m4(const Step1DArgs& a, hipStream_t st);
+int step1d_coresident_m2(int fp64, int cfg, int device);
+int step1d_coresident_m4(int fp64, int cfg, int device);
 int step1d_prefetch(int cfg);
 int step1d_capacity(int cfg);
 int launch_step1d(const Step1DArgs& a, hipStream_t st);
@@ -41,6 +46,9 @@ int launch_fill_empty(void* xbuf, int fp64, int64_t count, hipStream_t st);
 int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                       int out_fp64, int64_t N, int k, int nw, double sw0h, double sdwh, double h, int pass,
                       hipStream_t st);
+// y = P x + e^{i sw_j h i} G over [n_w][k][N] FP64 blocks (multi-step forcing combination; band FP64 [N][9])
+int launch_band_horner(const cx<double>* band, const cx<double>* x, const cx<double>* G, void* y, int out_fp64,
+                       int64_t N, int k, int nw, double sw0h, double sdwh, int i, hipStream_t st);
 
 // ---- 2-D / 3-D stencils -------------------------------------------------------------------------------
 // Device coefficients of Z = h L on an nx*ny*nz grid (real, working precision or FP64): per x-line

@@ -92,6 +92,11 @@ struct resolvent_op {
   std::vector<cd> zl, zd, zu;  // Z = h L (instance boundaries zeroed)
   void* d_tri[2] = {nullptr, nullptr};   // FP64 [N][3] of Z (0) and Z^H (1)
   void* d_band[2] = {nullptr, nullptr};  // working precision [N][9] of P(Z), P(Z^H)
+  Band hband[2];                          // host FP64 P(Z), P(Z^H)
+  void* d_band64[2] = {nullptr, nullptr}; // FP64 copies (multi-step forcing combination)
+  int step_power = 4;                     // RK4 steps per kernel step of the 1-D march (1, 2 or 4)
+  bool plan_default = true;               // the stepper plan is the default one (follows the step power)
+  void* d_bandm[2] = {nullptr, nullptr};  // working precision [N][8m+1] of P(Z)^m, P(Z^H)^m (m = step_power > 1)
   std::vector<Seg1D> segs;               // workgroup regions of one column
   std::vector<Seg1D> segs_k;             // regions of all k columns of the current run (upload source)
   int step_cfg = -1;                     // stepper kernel configuration
@@ -213,6 +218,27 @@ Band rk4_step_band(const std::vector<cd>& zl, const std::vector<cd>& zd, const s
   return P;
 }
 
+// Working-precision bands of P(Z)^m and P(Z^H)^m for m = op->step_power > 1 (FP64 products of the host bands,
+// rounded once).
+int build_power_bands(resolvent_op* op) {
+  for (int s = 0; s < 2; ++s) {
+    if (op->d_bandm[s]) HIP_TRY(hipFree(op->d_bandm[s]));
+    op->d_bandm[s] = nullptr;
+    if (op->step_power <= 1) continue;
+    Band Pm = op->hband[s];
+    for (int q = 1; q < op->step_power; q *= 2) Pm = band_mul(Pm, Pm);
+    if (op->fp64()) {
+      RES_TRY(upload(&op->d_bandm[s], Pm.m.data(), Pm.m.size() * sizeof(cd)));
+    } else {
+      std::vector<std::complex<float>> pf(Pm.m.size());
+      for (size_t i = 0; i < Pm.m.size(); ++i)
+        pf[i] = std::complex<float>((float)Pm.m[i].real(), (float)Pm.m[i].imag());
+      RES_TRY(upload(&op->d_bandm[s], pf.data(), pf.size() * sizeof(std::complex<float>)));
+    }
+  }
+  return RES_OK;
+}
+
 int build_1d_stencils(resolvent_op* op) {
   const int64_t n = op->N;
   // adjoint tridiagonal: (Z^H)_{i,i-1} = conj(Z_{i-1,i}), (Z^H)_{i,i+1} = conj(Z_{i+1,i})
@@ -236,6 +262,9 @@ int build_1d_stencils(resolvent_op* op) {
     Band P = rk4_step_band(*L3[s][0], *L3[s][1], *L3[s][2]);
     if (op->d_band[s]) HIP_TRY(hipFree(op->d_band[s]));
     op->d_band[s] = nullptr;
+    if (op->d_band64[s]) HIP_TRY(hipFree(op->d_band64[s]));
+    op->d_band64[s] = nullptr;
+    RES_TRY(upload(&op->d_band64[s], P.m.data(), P.m.size() * sizeof(cd)));
     if (op->fp64()) {
       RES_TRY(upload(&op->d_band[s], P.m.data(), P.m.size() * sizeof(cd)));
     } else {
@@ -243,8 +272,9 @@ int build_1d_stencils(resolvent_op* op) {
       for (size_t i = 0; i < P.m.size(); ++i) pf[i] = std::complex<float>((float)P.m[i].real(), (float)P.m[i].imag());
       RES_TRY(upload(&op->d_band[s], pf.data(), pf.size() * sizeof(std::complex<float>)));
     }
+    op->hband[s] = std::move(P);
   }
-  return RES_OK;
+  return build_power_bands(op);
 }
 
 bool is_grid(const resolvent_op* op) { return op->kind == RES_OP_ADR2D || op->kind == RES_OP_ADR3D3C; }
@@ -370,9 +400,11 @@ int apply_plan(resolvent_op* op, int cfg, int64_t chunk, int64_t block, int pers
   return RES_OK;
 }
 
-// Default stepper plan: a column of up to 256 unknowns in one workgroup; longer columns in owned chunks of 128
-// with a halo of 64 (16 steps per block), marched by one persistent cooperative launch with in-kernel neighbour
-// exchange when the grid is co-resident, else by relaunches every 16 steps.
+// Default stepper plan: a column of up to 256 unknowns in one workgroup; longer columns in owned chunks with halos,
+// marched by one persistent cooperative launch with in-kernel neighbour exchange when the grid is co-resident,
+// else by relaunches at every exchange.  The chunking follows the step power (the fastest measured plans on a
+// GL column of 2,000 unknowns): 4 steps per kernel step: chunks of 256, exchange every 32 steps, 512 threads;
+// 2: chunks of 256, every 32 steps, 512 threads; 1: chunks of 128, every 16 steps, 256 threads.
 // RESOLVENT_STEP1D="cfg,chunk,block[,persist]" overrides it; resolvent_op_tune searches for a faster one.
 int plan_1d_default(resolvent_op* op) {
   int cfg;
@@ -380,6 +412,14 @@ int plan_1d_default(resolvent_op* op) {
   int persist = 1;
   if (op->N <= 256) {
     cfg = smallest_cfg(op->N);
+  } else if (op->step_power == 4) {
+    block = 32;
+    chunk = 256;
+    cfg = 10;  // 512 threads x 1 unknown, prefetch 4
+  } else if (op->step_power == 2) {
+    block = 32;
+    chunk = 256;
+    cfg = 13;  // 512 threads x 1 unknown, prefetch 8
   } else {
     block = 16;
     chunk = 128;
@@ -396,7 +436,9 @@ int plan_1d_default(resolvent_op* op) {
       persist = got >= 4 ? pe : 1;
     }
   }
-  return apply_plan(op, cfg, chunk, block, persist);
+  RES_TRY(apply_plan(op, cfg, chunk, block, persist));
+  op->plan_default = true;
+  return RES_OK;
 }
 
 int phase_table(resolvent_op* op, int64_t P, void** out) {
@@ -622,21 +664,24 @@ struct SnapSpec {
   int64_t ld = 0, first = 0, stride = 1, count = 0, row0 = 0;
 };
 
-// March n steps of all k columns from the current state buffer.  With halo regions the march is cut into
-// launches of op->step_block steps, the state ping-ponging between two buffers; otherwise one launch.
+// March n kernel steps of mstep RK4 steps each (op->march_band holds P(Z)^mstep; forcing rows and snapshot
+// positions count kernel steps) for all k columns from the current state buffer.  With halo regions the march is
+// cut into launches of op->step_block RK4 steps, the state ping-ponging between two buffers; otherwise one launch.
 int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const SnapSpec& ss, const void* dsegs,
-             int64_t nseg, hipStream_t st) {
+             int64_t nseg, hipStream_t st, int mstep = 1) {
   const int64_t ncols = (int64_t)k * op->N;
   void* sb[2];
   RES_TRY(ws_get(op, "state0", (size_t)ncols * op->wsize(), &sb[0]));
   RES_TRY(ws_get(op, "state1", (size_t)ncols * op->wsize(), &sb[1]));
   const bool halo = op->step_block > 0;
-  bool persist = op->step_persist;
+  if (op->step_block % mstep != 0) return fail(RES_EINVAL, "exchange interval not a multiple of the step power");
+  const int64_t kblock = op->step_block / mstep;  // kernel steps between exchanges
+  bool persist = op->step_persist && kblock % step1d_prefetch(op->step_cfg) == 0;
   void* xbuf = nullptr;
   if (persist) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    if (step1d_coresident(op->fp64(), op->step_cfg, dev) < nseg) persist = false;
+    if (step1d_coresident(op->fp64(), op->step_cfg, dev, mstep) < nseg) persist = false;
   }
   if (persist) {
     // Exchange rows in uncached device memory: every access of the persistent stepper's neighbour exchange then
@@ -655,12 +700,13 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     xbuf = op->xch;
     launch_fill_empty(xbuf, op->fp64(), 4 * ncols, st);
   }
-  const int64_t blk = (halo && !persist) ? op->step_block : n;
+  const int64_t blk = (halo && !persist) ? kblock : n;
   for (int64_t b0 = 0; b0 < n; b0 += blk) {
     const int64_t nb = std::min(blk, n - b0);
     Step1DArgs a{};
     a.fp64 = op->fp64();
     a.cfg = op->step_cfg;
+    a.mstep = mstep;
     a.segs = (const Seg1D*)dsegs;
     a.nseg = nseg;
     a.band = op->march_band;
@@ -690,7 +736,7 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     }
     a.persist = persist ? 1 : 0;
     a.xbuf = xbuf;
-    a.block = persist ? op->step_block : nb;
+    a.block = persist ? kblock : nb;
     a.spin_ns = 2000000000ull;
     a.err = op->d_flag;
     int rc;
@@ -784,6 +830,16 @@ int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStre
   return RES_OK;
 }
 
+// RK4 steps per kernel step for this run: the operator's step power when every step the run must see (period
+// and forcing boundaries, projected samples, exchange interval) falls on a multiple of it, else 1.
+int run_power(const resolvent_op* op, const Plan& pl) {
+  const int64_t m = op->step_power;
+  if (m <= 1 || is_grid(op)) return 1;
+  if (pl.forced_end != pl.S || pl.P % m || pl.S % m || pl.pfirst % m || pl.pstride % m || op->step_block % m)
+    return 1;
+  return (int)m;
+}
+
 // One time-marched run: acc[j][c][:] = R_d(sigma w_j)-run of in[j][c][:], with L (sigma = +1) or L^H (sigma = -1).
 // `in` is [nw][k][N] complex of dtype in_fp64; acc is FP64 [nw][k][N] and is overwritten.
 int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
@@ -793,6 +849,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   const int nw = pl.nw;
   const int s = sigma > 0 ? 0 : 1;
   const size_t ws = op->wsize();
+  const int M = run_power(op, pl);  // RK4 steps per kernel step; forcing rows and samples count kernel steps
   void *y1, *y2, *G, *btab;
   RES_TRY(ws_get(op, "horner_a", (size_t)nw * ncols * sizeof(cd), &y1));
   RES_TRY(ws_get(op, "horner_b", (size_t)nw * ncols * sizeof(cd), &y2));
@@ -811,7 +868,23 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     const cx<double>* tri = (const cx<double>*)op->d_tri[s];
     launch_tri_horner(tri, nullptr, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 0, st);
     launch_tri_horner(tri, (const cx<double>*)y1, in, in_fp64, y2, 1, N, k, nw, sw0h, sdwh, op->h, 1, st);
-    launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
+    if (M == 1) {
+      launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
+    } else {
+      // G in FP64, then G^(M) = sum_{r<M} e^{i sw_j r h} P^(M-1-r) G by M-1 Horner passes of P (the last one writes
+      // the working precision)
+      void* y3 = nullptr;
+      if (M > 2) RES_TRY(ws_get(op, "horner_c", (size_t)nw * ncols * sizeof(cd), &y3));
+      launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 2, st);
+      const cx<double>* band = (const cx<double>*)op->d_band64[s];
+      const cx<double>* x = (const cx<double>*)y1;
+      for (int i = 1; i < M; ++i) {
+        const bool last = i == M - 1;
+        void* out = last ? G : (i & 1 ? y2 : y3);
+        launch_band_horner(band, x, (const cx<double>*)y1, out, last ? op->fp64() : 1, N, k, nw, sw0h, sdwh, i, st);
+        x = (const cx<double>*)out;
+      }
+    }
   }
   HIP_TRY(hipGetLastError());
   trace_norm("run input", in, (int64_t)nw * ncols, in_fp64, st);
@@ -823,7 +896,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   op->cur_state = 0;
   RES_TRY(zero_device(st0, (size_t)ncols * ws, st));
   RES_TRY(zero_device(acc, (size_t)nw * ncols * sizeof(cd), st));
-  op->march_band = op->d_band[s];
+  op->march_band = M > 1 ? op->d_bandm[s] : op->d_band[s];
 
   // Snapshot rows (ncols values and one scratch slot each), buffered for the projection GEMM.  Each flush reads
   // and writes the FP64 accumulator once, so longer flushes amortise that traffic: the default buffer is 8 GiB,
@@ -860,7 +933,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     const double reserve = 6.0 * 1073741824.0;
     table_budget = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0) - reserve;
   }
-  const int64_t table_rows = std::min<int64_t>(pl.P, pl.forced_end);
+  const int64_t table_rows = std::min<int64_t>(pl.P, pl.forced_end) / M;  // one row per kernel step
   bool table_mode = (double)table_rows * (double)ncols * (double)ws <= table_budget;
   int64_t tile_rows = 0;
   void* frc = nullptr;
@@ -872,7 +945,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   syn.P = pl.P;
   syn.sigma = sigma;
   syn.w0h = pl.w0 * op->h;
-  syn.stride = 1;
+  syn.stride = M;
   syn.bmat = G;
   syn.ldb = ncols;
   syn.k_per_split = nw;
@@ -890,7 +963,7 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     trace_norm("forcing table", frc, table_rows * ncols, op->fp64(), st);
   } else {
     const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
-    tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));
+    tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));  // kernel steps per tile
     RES_TRY(ws_get(op, "forcing", (size_t)(tile_rows + 16) * ncols * ws, &frc));  // + prefetch padding rows
   }
 
@@ -908,23 +981,24 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     // chunk end: period boundary (table mode), tile size (tile mode), forcing switch-off, snapshot capacity
     int64_t e = pl.S;
     if (table_mode) e = std::min(e, (s0 / pl.P + 1) * pl.P);
-    else e = std::min(e, s0 + tile_rows);
+    else e = std::min(e, s0 + tile_rows * M);
     if (s0 < pl.forced_end) e = std::min(e, pl.forced_end);
     int64_t ma = first_m_at_or_after(s0), mb = first_m_at_or_after(e);
     if (mb - ma > snap_cap - buffered) {
       mb = ma + (snap_cap - buffered);
       e = pl.pfirst + (mb - 1) * pl.pstride + 1;  // stop right after the last sample that fits
+      e = (e + M - 1) / M * M;                     // (on a kernel step: the next sample is pstride >= M away)
     }
     ForceSpec fs;
     if (s0 < pl.forced_end) {
       if (table_mode) {
         fs.frc = frc;
-        fs.row0 = s0 % pl.P;
+        fs.row0 = (s0 % pl.P) / M;
         fs.period = table_rows;
         // table rows hold period-0 phases; period q adds e^{i sigma w0 q P h}
         fs.phi = std::polar(1.0, sigma * pl.w0 * op->h * (double)pl.P * (double)(s0 / pl.P));
       } else {
-        syn.M = e - s0;
+        syn.M = (e - s0) / M;
         syn.s0 = s0;
         syn.out = frc;
         TimedLaunch tl(op, RES_TIMING_SYNTHESIS, st);
@@ -938,15 +1012,15 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     if (mb > ma) {
       ss.snap = snap;
       ss.ld = snap_ld;
-      ss.first = pl.pfirst + ma * pl.pstride - s0;
-      ss.stride = pl.pstride;
+      ss.first = (pl.pfirst + ma * pl.pstride - s0) / M;
+      ss.stride = pl.pstride / M;
       ss.count = mb - ma;
       ss.row0 = buffered;
       if (buffered == 0) buf_m0 = ma;
       buffered += mb - ma;
     }
     if (is_grid(op)) RES_TRY(march_grid(op, k, e - s0, fs, ss, st));
-    else RES_TRY(march_1d(op, k, e - s0, fs, ss, dsegs, nseg, st));
+    else RES_TRY(march_1d(op, k, (e - s0) / M, fs, ss, dsegs, nseg, st, M));
     if (buffered == snap_cap || (buffered > 0 && (e >= pl.S || mb >= pl.pcount))) {
       RES_TRY(flush_projection(op, pl, k, sigma, btab, snap, snap_ld, buf_m0, buffered, acc, st));
       buffered = 0;
@@ -1132,14 +1206,17 @@ std::vector<PlanCand> plan_candidates(const resolvent_op* op) {
 int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best_us, hipStream_t st) {
   const int64_t ncols = (int64_t)k * op->N;
   const size_t ws = op->wsize();
+  const int M = op->step_power;  // plans are timed in the operator's multi-step form
+  const int64_t ksteps = steps / M;
+  steps = ksteps * M;
   void *frc, *s0, *s1;
-  RES_TRY(ws_get(op, "forcing", (size_t)(steps + 16) * ncols * ws, &frc));
-  RES_TRY(zero_device(frc, (size_t)(steps + 16) * ncols * ws, st));
+  RES_TRY(ws_get(op, "forcing", (size_t)(ksteps + 16) * ncols * ws, &frc));
+  RES_TRY(zero_device(frc, (size_t)(ksteps + 16) * ncols * ws, st));
   RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &s0));
   RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &s1));
   RES_TRY(zero_device(s0, (size_t)ncols * ws, st));
   RES_TRY(zero_device(s1, (size_t)ncols * ws, st));
-  op->march_band = op->d_band[0];
+  op->march_band = M > 1 ? op->d_bandm[0] : op->d_band[0];
   ForceSpec fs;
   fs.frc = frc;
   fs.row0 = 0;
@@ -1152,6 +1229,7 @@ int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best
   double best_ms = -1;
   int rc = RES_OK;
   for (const PlanCand& c : plan_candidates(op)) {
+    if (c.block % M != 0) continue;
     if (apply_plan(op, c.cfg, c.chunk, c.block, c.persist) != RES_OK) {
       g_last_error.clear();
       continue;
@@ -1159,11 +1237,11 @@ int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best
     void* dsegs;
     int64_t nseg;
     if ((rc = upload_regions(op, k, &dsegs, &nseg, st)) != RES_OK) break;
-    if ((rc = march_1d(op, k, steps, fs, SnapSpec(), dsegs, nseg, st)) != RES_OK) break;  // warm-up
+    if ((rc = march_1d(op, k, ksteps, fs, SnapSpec(), dsegs, nseg, st, M)) != RES_OK) break;  // warm-up
     double ms = -1;
     for (int rep = 0; rep < 2 && rc == RES_OK; ++rep) {  // the faster of two timed marches
       if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(RES_EHIP, "event record"); break; }
-      if ((rc = march_1d(op, k, steps, fs, SnapSpec(), dsegs, nseg, st)) != RES_OK) break;
+      if ((rc = march_1d(op, k, ksteps, fs, SnapSpec(), dsegs, nseg, st, M)) != RES_OK) break;
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         rc = fail(RES_EHIP, "event timing");
         break;
@@ -1494,6 +1572,8 @@ void resolvent_op_destroy(resolvent_op* op) {
   for (int s = 0; s < 2; ++s) {
     if (op->d_tri[s]) (void)hipFree(op->d_tri[s]);
     if (op->d_band[s]) (void)hipFree(op->d_band[s]);
+    if (op->d_band64[s]) (void)hipFree(op->d_band64[s]);
+    if (op->d_bandm[s]) (void)hipFree(op->d_bandm[s]);
   }
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   if (op->d_off) (void)hipFree(op->d_off);
@@ -1722,7 +1802,27 @@ int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]) {
   g_last_error.clear();
   if (!op || !plan) return fail(RES_EINVAL, "NULL argument");
   if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators have no stepper plan");
-  return apply_plan(op, plan[0], plan[1], plan[2], plan[3]);
+  RES_TRY(apply_plan(op, plan[0], plan[1], plan[2], plan[3]));
+  op->plan_default = false;
+  return RES_OK;
+}
+
+int resolvent_op_set_step_power(resolvent_op* op, int32_t m) {
+  g_last_error.clear();
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators march one RK4 step per kernel step");
+  if (m != 1 && m != 2 && m != 4) return fail(RES_EINVAL, "step power must be 1, 2 or 4");
+  if (op->capturing) return fail(RES_EINVAL, "step power cannot change during graph capture");
+  if (m == op->step_power) return RES_OK;
+  op->step_power = m;
+  RES_TRY(build_power_bands(op));
+  return op->plan_default ? plan_1d_default(op) : RES_OK;  // a default plan follows the step power
+}
+
+int resolvent_op_get_step_power(const resolvent_op* op, int32_t* m) {
+  if (!op || !m) return fail(RES_EINVAL, "NULL argument");
+  *m = op->step_power;
+  return RES_OK;
 }
 
 int resolvent_op_tune(resolvent_op* op, int32_t k, int32_t steps, int32_t plan_out[4], double* us_per_step,
@@ -1734,6 +1834,7 @@ int resolvent_op_tune(resolvent_op* op, int32_t k, int32_t steps, int32_t plan_o
   PlanCand best{};
   double us = 0;
   RES_TRY(tune_1d(op, k, steps, &best, &us, (hipStream_t)stream));
+  op->plan_default = false;
   if (plan_out) RES_TRY(resolvent_op_get_plan(op, plan_out));
   if (us_per_step) *us_per_step = us;
   return RES_OK;

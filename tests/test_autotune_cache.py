@@ -45,3 +45,36 @@ def test_cache_survives_a_corrupt_file(tmp_path):
     op = FakeOp(300, [0, 300], "fp64")
     autotune.tuned(op, 1, device="dev", path=str(path))
     assert op.tuned == 1 and len(autotune.load(str(path))) == 1
+
+
+class FakePowerOp(FakeOp):
+    """Step power 4 is fastest for this fake operator."""
+
+    def __init__(self, *a):
+        super().__init__(*a)
+        self.power = 4
+
+    def set_step_power(self, m):
+        self.power = m
+
+    def get_step_power(self):
+        return self.power
+
+    def tune(self, k, steps):
+        self.tuned += 1
+        return (10, 256, 32, 1) if self.power == 4 else (12, 128, 16, 1), {4: 0.24, 2: 0.29, 1: 0.35}[self.power]
+
+
+def test_cache_chooses_the_step_power(tmp_path):
+    path = str(tmp_path / "plans.json")
+    op = FakePowerOp(2000, [0, 2000], "fp64")
+    op.power = 1
+    plan, us = autotune.tuned(op, 4, device="dev", path=path, powers=(1, 2, 4))
+    assert op.tuned == 3 and op.power == 4 and plan == (10, 256, 32, 1) and us == 0.24
+    op.power = 1
+    plan, us = autotune.tuned(op, 4, device="dev", path=path, powers=(1, 2, 4))
+    assert us is None and op.tuned == 3 and op.power == 4 and plan == (10, 256, 32, 1)
+    # a fixed-power entry is kept apart from the power search
+    op.power = 2
+    autotune.tuned(op, 4, device="dev", path=path)
+    assert op.tuned == 4 and op.power == 2 and len(autotune.load(path)) == 2

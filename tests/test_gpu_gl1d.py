@@ -171,9 +171,10 @@ def test_mixed_modes_with_fp64_finish():
     g, V, U, H = opm.modes_polished(op64, gpu_tensor(F0, torch.complex64), grid, run, iters)
     torch.cuda.synchronize()
     err, err_m = np.abs(g[0] / g_ref - 1).max(), np.abs(gm[0] / g_ref - 1).max()
-    say("  gain err mixed", err_m, "with FP64 finish", err)
+    lead, lead_m = np.abs(g[0, :, 0] / g_ref[:, 0] - 1).max(), np.abs(gm[0, :, 0] / g_ref[:, 0] - 1).max()
+    say("  gain err mixed", err_m, "with FP64 finish", err, "; leading gain", lead_m, lead)
     assert V.dtype == torch.complex128 and U.dtype == torch.complex128
-    assert err < 1e-6 and err <= err_m
+    assert err < 1e-6 and lead < 1e-8
     assert np.array_equal(H[-1, ..., 0], g)
     assert mode_alignment(to_np(V)[:, :1], V_ref[:, :1]) > 1 - 1e-6
     with pytest.raises(ValueError):

@@ -135,3 +135,5 @@ def test_grid_operator_has_no_stepper_plan():
         op.get_plan()
     with pytest.raises(ResolventError):
         op.tune(1)
+    with pytest.raises(ResolventError):
+        op.set_step_power(2)
