@@ -288,7 +288,7 @@ def bench_grid(args):
         value = N * k * cfg["n_omega"] * P / (kt["stepper"][0] / 1e3 / args.steps)
         step_desc = "stepping of one 64-step apply (value: sweeps/s of the stepping alone at 96 frequencies)"
     kernel_name = ("grid_step2d_kernel (one RK4 step per launch)" if cfg["kind"] == "adr2d"
-                   else "grid_stage3d_kernel x4 (one RK4 step)")
+                   else "grid_pair3d_kernel x2 (one RK4 step: two launches of two Horner stages)")
     step_s = kt["stepper"][0] / 1e3 / time_steps_total
     alg_bytes = 3 * csize * N * k  # read u, write u, read one forcing row
     achieved = alg_bytes / step_s

@@ -60,9 +60,10 @@ struct GridOpDev {
   const void* d;
   const void* K;
 };
-// One Horner stage of a 3-D three-component operator, marching along z (see stencil.hip).
-int launch_grid_stage3d(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
-                        const void* frc, double phr, double phi, void* snap, hipStream_t st);
+// Two Horner stages of a 3-D three-component operator in one launch, marching along z (see stencil.hip): pass 1
+// (second = 0) writes the third stage's input from u, pass 2 the new state from vin and u (out != u).
+int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const void* vin, void* out, int second,
+                       const void* frc, double phr, double phi, void* snap, hipStream_t st);
 // Whole RK4 step of a 2-D one-component operator in one launch (LDS temporal blocking); uout != uin.
 int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
                        double phi, void* snap, hipStream_t st);

@@ -751,23 +751,19 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
   return RES_OK;
 }
 
-// March n steps of all k columns of a grid operator: four Horner-stage launches per step (Z or Z^H chosen by
-// op->march_band's twin op->march_grid).
+// March n steps of all k columns of a grid operator (Z or Z^H chosen by op->march_grid), the state ping-ponging
+// between state0 and state1: 2-D one-component operators take one fused launch per step, 3-D three-component
+// operators two launches of two Horner stages each (the second writes the new state).
 int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const SnapSpec& ss, hipStream_t st) {
   const int64_t ncols = (int64_t)k * op->N;
   const size_t ws = op->wsize();
-  void *u, *v1, *v2;
-  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &u));
-  RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v1));
-  RES_TRY(ws_get(op, "gv2", (size_t)ncols * ws, &v2));
   const GridOpDev& g = *op->march_grid;
-  // 2-D one-component operators: one fused launch per step, the state ping-ponging between state0 and state1
   const bool fused = g.ncomp == 1 && g.nz == 1;
-  void* sb[2] = {u, nullptr};
-  if (fused) {
-    RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &sb[1]));
-    RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &sb[0]));
-  }
+  void* sb[2];
+  void* v2 = nullptr;
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &sb[0]));
+  RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &sb[1]));
+  if (!fused) RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v2));
   TimedLaunch tl(op, RES_TIMING_STEPPER, st);
   int64_t next = (ss.snap != nullptr && ss.count > 0) ? ss.first : -1, m = 0;
   for (int64_t t = 0; t < n; ++t) {
@@ -783,18 +779,17 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
       ++m;
       next = m < ss.count ? next + ss.stride : -1;
     }
+    void* uin = sb[op->cur_state];
+    void* uout = sb[1 - op->cur_state];
     if (fused) {
-      if (launch_grid_step2d(g, op->fp64(), k, sb[op->cur_state], sb[1 - op->cur_state], frow, fs.phi.real(),
-                             fs.phi.imag(), srow, st))
+      if (launch_grid_step2d(g, op->fp64(), k, uin, uout, frow, fs.phi.real(), fs.phi.imag(), srow, st))
         return fail(RES_EINVAL, "2-D step launch");
-      op->cur_state = 1 - op->cur_state;
-      continue;
+    } else if (launch_grid_pair3d(g, op->fp64(), k, uin, nullptr, v2, 0, nullptr, 0, 0, nullptr, st) ||
+               launch_grid_pair3d(g, op->fp64(), k, uin, v2, uout, 1, frow, fs.phi.real(), fs.phi.imag(), srow,
+                                  st)) {
+      return fail(RES_EINVAL, "3-D step launch");
     }
-    if (launch_grid_stage3d(g, op->fp64(), k, u, u, v1, 0.25, 0, nullptr, 0, 0, nullptr, st) ||
-        launch_grid_stage3d(g, op->fp64(), k, u, v1, v2, 1.0 / 3.0, 0, nullptr, 0, 0, nullptr, st) ||
-        launch_grid_stage3d(g, op->fp64(), k, u, v2, v1, 0.5, 0, nullptr, 0, 0, nullptr, st) ||
-        launch_grid_stage3d(g, op->fp64(), k, u, v1, nullptr, 1.0, 1, frow, fs.phi.real(), fs.phi.imag(), srow, st))
-      return fail(RES_EINVAL, "3-D stage launch");
+    op->cur_state = 1 - op->cur_state;
   }
   HIP_TRY(hipGetLastError());
   return RES_OK;

@@ -11,8 +11,8 @@
 //
 // which equals P(Z) u_s + forcing of the classical four-stage scheme (the forcing enters through
 // G_j = h Q_j(Z) F_j, built by three Horner passes of the same stencil; see step1d.hip).  2-D one-component
-// operators run the whole step in one launch (grid_step2d_kernel); 3-D three-component operators run one launch
-// per stage, marching along z (grid_stage3d_kernel).
+// operators run the whole step in one launch (grid_step2d_kernel); 3-D three-component operators run two launches
+// of two stages each, marching along z (grid_pair3d_kernel).
 #include "common.h"
 #include "kernels.h"
 #include "gridz.h"
@@ -108,148 +108,202 @@ __global__ __launch_bounds__(256) void grid_step2d_kernel(GridCoef<R> Cf, int64_
   }
 }
 
-// One Horner stage of a 3-D three-component operator, marching along z.  A workgroup of 64 x 4 threads owns a
-// 64 x 4 column of nodes in x and y and a chunk of ZC planes of one state column b.  Each thread keeps the three
-// components of vin at planes z-1, z, z+1 of its own (x, y) in registers; plane z is also published to LDS with
-// a one-node ring around the tile (loaded by the edge threads), which supplies the x and y neighbours.  Every
-// value of vin is therefore read once from HBM per stage (plus the ring, mostly from L2), u once and vout
-// written once, against several reads of vin's neighbour planes when every node reads its own stencil.
-//   out = u + s (Z vin)   (stages 1-3),      u <- u + Z vin + phi frc   (LAST, in place; snapshot of u first)
+// Two Horner stages of a 3-D three-component operator in one pass, marching along z; a step is two passes.  A
+// workgroup of TX x TY threads covers a TX x TY window of (x, y) nodes of one state column; the window's interior
+// (halo 2 = the reach of two stages) is its output tile.  At plane a of the march it evaluates
+//   stage A at plane a:      y = u + sa Z x    on the window (its outer ring is not needed later),
+//   stage B at plane a - 1:  out = u + sb Z y  on the interior (plus phi frc in the second pass),
+// with x and y published to double-buffered LDS planes for the x/y neighbours and kept in per-thread register
+// rings for the z neighbours; the line coefficients of the window rows sit in four LDS plane slots.  One barrier
+// per plane orders every LDS access.  Every global load of a plane is issued one plane ahead of its use, with
+// clamped addresses, and masked when it is used.  Values outside the grid are zero (homogeneous Dirichlet).
+//   pass 1 (SECOND = false): x = u,  sa = 1/4, sb = 1/3: out = the third stage's input,
+//   pass 2 (SECOND = true):  x = vin, sa = 1/2, sb = 1:  out = the new state, in a buffer other than u (windows
+//                            read u at halo nodes that neighbouring tiles update); snapshot of u first.
 // Operation order per component as apply_z: diagonal, -x, +x, -y, +y, -z, +z, then the coupling.
-template <typename R, bool LAST, int ZC>
-__global__ __launch_bounds__(256) void grid_stage3d_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny, int64_t nz,
-                                                           cx<R>* u, const cx<R>* __restrict__ vin,
-                                                           cx<R>* __restrict__ vout, R s,
-                                                           const cx<R>* __restrict__ frc, R phr, R phi,
-                                                           cx<R>* __restrict__ snap) {
-  constexpr int TX = 64, TY = 4, NC = 3;
-  __shared__ cx<R> Lp[2][NC][TY + 2][TX + 2];
-  const int tid = threadIdx.x;
-  const int lx = tid & 63, ly = tid >> 6;
-  const int64_t nodes = nx * ny * nz;
-  const int64_t ix = (int64_t)blockIdx.x * TX + lx, iy = (int64_t)blockIdx.y * TY + ly;
+template <typename R, bool SECOND, int TX, int TY, int ZC>
+__global__ __launch_bounds__(TX * TY) void grid_pair3d_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny, int64_t nz,
+                                                              int64_t ncol,
+                                                              const cx<R>* __restrict__ u,
+                                                              const cx<R>* __restrict__ vin,
+                                                              cx<R>* __restrict__ out,
+                                                              const cx<R>* __restrict__ frc, R phr, R phi,
+                                                              cx<R>* __restrict__ snap) {
+  constexpr int H = 2, NC = 3, OX = TX - 2 * H, OY = TY - 2 * H, NQ = 15;
+  __shared__ cx<R> Xs[2][NC][TY][TX];
+  __shared__ cx<R> Ys[2][NC][TY][TX];
+  __shared__ R Cs[4][TY][NQ];  // plane slot, window row: cxm cxp cym cyp czm czp K[9]
+  const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+  const int64_t nodes = nx * ny * nz, sz = nx * ny;
   const int64_t nzc = (nz + ZC - 1) / ZC;
-  const int64_t b = blockIdx.z / nzc, z0 = (blockIdx.z % nzc) * ZC;
+  // Tile order: workgroups are dealt to the eight XCDs in turn (id mod 8); each XCD takes a contiguous run of
+  // tiles (x fastest, then y, then z chunk and column), so the tiles whose halos overlap run side by side and
+  // share that XCD's L2.
+  const int64_t gx = (nx + OX - 1) / OX, gy = (ny + OY - 1) / OY, ntile = gx * gy * nzc * ncol;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * ((ntile + 7) / 8) + (blockIdx.x >> 3);
+  if (tile >= ntile) return;  // padding of the grid to a multiple of 8 (whole workgroup)
+  const int64_t tx = tile % gx, ty = (tile / gx) % gy, tzb = tile / (gx * gy);
+  const int64_t b = tzb / nzc, z0 = (tzb % nzc) * ZC;
   const int64_t z1 = z0 + ZC < nz ? z0 + ZC : nz;
-  const bool own = ix < nx && iy < ny;
+  const int64_t ix = tx * OX - H + lx, iy = ty * OY - H + ly;
+  const bool inxy = ix >= 0 && ix < nx && iy >= 0 && iy < ny;
+  const bool interior = inxy && lx >= H && lx < TX - H && ly >= H && ly < TY - H;
   const int64_t cb = b * NC * nodes;
-  const int64_t sy = nx, sz = nx * ny;
-  // ring cells of the tile for the x/y neighbours: (ry, rx) in the (TY+2) x (TX+2) window, ry or rx on the edge
-  // (4*66 + ... = 140 cells); thread t < 140 loads ring cell t of every plane.
-  int ring_ry = -1, ring_rx = -1;
-  if (tid < 2 * (TX + 2)) {
-    ring_ry = tid < TX + 2 ? 0 : TY + 1;
-    ring_rx = tid < TX + 2 ? tid : tid - (TX + 2);
-  } else if (tid < 2 * (TX + 2) + 2 * TY) {
-    const int t = tid - 2 * (TX + 2);
-    ring_ry = 1 + (t >> 1);
-    ring_rx = (t & 1) ? TX + 1 : 0;
-  }
-  const int64_t rgx = (int64_t)blockIdx.x * TX + ring_rx - 1, rgy = (int64_t)blockIdx.y * TY + ring_ry - 1;
-  const bool ring_in = ring_ry >= 0 && rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny;
-  auto ld = [&](int64_t z, int c) -> cx<R> {  // vin at this thread's (x, y), plane z, component c (0 outside)
-    return (own && z >= 0 && z < nz) ? vin[cb + c * nodes + z * sz + iy * sy + ix] : mk<R>(R(0), R(0));
+  const int64_t pxy = inxy ? iy * nx + ix : 0;
+  const cx<R>* __restrict__ X = SECOND ? vin : u;
+  const R sa = SECOND ? R(0.5) : R(0.25), sb = SECOND ? R(1) : R(1) / R(3);
+  const cx<R> zero = mk<R>(R(0), R(0));
+  const bool coupled = Cf.K != nullptr;
+  // LDS neighbours, clamped at the window edge (edge threads compute values that are never used)
+  const int xl = lx > 0 ? lx - 1 : 0, xr = lx < TX - 1 ? lx + 1 : TX - 1;
+  const int yl = ly > 0 ? ly - 1 : 0, yr = ly < TY - 1 ? ly + 1 : TY - 1;
+  auto zin = [&](int64_t z) { return z >= 0 && z < nz; };
+  auto zc = [&](int64_t z) -> int64_t { return z < 0 ? 0 : (z >= nz ? nz - 1 : z); };
+
+  struct V3 {
+    cx<R> c[NC];
   };
-  // Per-plane operands of this thread's node: line coefficients, diagonal, coupling row block, u (and the
-  // forcing in the last stage).  They are loaded one plane ahead, with vin two planes ahead, so that every global
-  // load of an iteration is in flight while the previous plane is computed.
-  struct PlaneOps {
-    R cxm, cxp, cym, cyp, czm, czp, dd;
-    R K[9];
-    cx<R> uu[NC], ff[NC];
-  };
-  auto load_ops = [&](int64_t z) -> PlaneOps {
-    PlaneOps o;
-    const bool ok = own && z < nz;
-    const int64_t l = ok ? z * ny + iy : 0;
-    const int64_t p = ok ? z * sz + iy * sy + ix : 0;
-    o.cxm = ok ? Cf.cxm[l] : R(0); o.cxp = ok ? Cf.cxp[l] : R(0);
-    o.cym = ok ? Cf.cym[l] : R(0); o.cyp = ok ? Cf.cyp[l] : R(0);
-    o.czm = ok ? Cf.czm[l] : R(0); o.czp = ok ? Cf.czp[l] : R(0);
-    o.dd = ok ? Cf.d[p] : R(0);
+  // raw loads (clamped, unconditional); masking happens at use
+  auto ld3 = [&](const cx<R>* __restrict__ A, int64_t z) -> V3 {
+    V3 r;
+    const int64_t e = cb + zc(z) * sz + pxy;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) o.K[q] = (ok && Cf.K != nullptr) ? Cf.K[l * 9 + q] : R(0);
+    for (int c = 0; c < NC; ++c) r.c[c] = A[e + c * nodes];
+    return r;
+  };
+  auto mask3 = [&](const V3& v, bool ok) -> V3 {
+    V3 r;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r.c[c] = ok ? v.c[c] : zero;
+    return r;
+  };
+  auto ldd = [&](int64_t z) -> R { return Cf.d[zc(z) * sz + pxy]; };
+  // line coefficient q of window row r at plane z (staging threads tid < TY * NQ)
+  const int cr = tid / NQ, cq = tid % NQ;
+  const bool stager = tid < TY * NQ;
+  const int64_t ciy = ty * OY - H + cr;
+  const bool crow_in = stager && ciy >= 0 && ciy < ny;
+  auto ldc = [&](int64_t z) -> R {
+    const int64_t l = zc(z) * ny + (crow_in ? ciy : 0);
+    const R* src = cq == 0 ? Cf.cxm : cq == 1 ? Cf.cxp : cq == 2 ? Cf.cym : cq == 3 ? Cf.cyp
+                 : cq == 4 ? Cf.czm : cq == 5 ? Cf.czp : Cf.K;
+    if (!stager || src == nullptr) return R(0);
+    return cq < 6 ? src[l] : src[l * 9 + (cq - 6)];
+  };
+  auto put_coef = [&](int64_t z, R v) {
+    if (stager) Cs[z & 3][cr][cq] = (crow_in && zin(z)) ? v : R(0);
+  };
+  // (Z x) at this thread's node of plane z: centre x0, z neighbours xm/xp (masked), x/y neighbours from plane L
+  auto apply = [&](const cx<R> (*L)[TY][TX], const V3& xm, const V3& x0, const V3& xp, R dd, int slot) -> V3 {
+    const R* cf = Cs[slot][ly];
+    const R cxm = cf[0], cxp = cf[1], cym = cf[2], cyp = cf[3], czm = cf[4], czp = cf[5];
+    V3 zv;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      o.uu[c] = ok ? u[cb + c * nodes + p] : mk<R>(R(0), R(0));
-      o.ff[c] = (LAST && ok && frc != nullptr) ? frc[cb + c * nodes + p] : mk<R>(R(0), R(0));
+      cx<R> acc = mk<R>(dd * x0.c[c].re, dd * x0.c[c].im);
+      const cx<R> w = L[c][ly][xl], e = L[c][ly][xr], sn = L[c][yl][lx], nn = L[c][yr][lx];
+      acc.re += cxm * w.re; acc.im += cxm * w.im;
+      acc.re += cxp * e.re; acc.im += cxp * e.im;
+      acc.re += cym * sn.re; acc.im += cym * sn.im;
+      acc.re += cyp * nn.re; acc.im += cyp * nn.im;
+      acc.re += czm * xm.c[c].re; acc.im += czm * xm.c[c].im;
+      acc.re += czp * xp.c[c].re; acc.im += czp * xp.c[c].im;
+      zv.c[c] = acc;
     }
-    return o;
-  };
-  cx<R> xm[NC], x0[NC], xp[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    xm[c] = ld(z0 - 1, c);
-    x0[c] = ld(z0, c);
-    xp[c] = ld(z0 + 1, c);
-  }
-  PlaneOps cur = load_ops(z0);
-  for (int64_t z = z0; z < z1; ++z) {
-    cx<R>(*L)[TY + 2][TX + 2] = Lp[z & 1];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      L[c][ly + 1][lx + 1] = x0[c];
-      if (ring_ry >= 0)
-        L[c][ring_ry][ring_rx] = ring_in ? vin[cb + c * nodes + z * sz + rgy * sy + rgx] : mk<R>(R(0), R(0));
-    }
-    __syncthreads();
-    // next planes' operands, in flight while this plane is computed
-    cx<R> xn[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) xn[c] = ld(z + 2, c);
-    const PlaneOps nxt = load_ops(z + 1);
-    if (own) {
-      const int64_t p = z * sz + iy * sy + ix;
-      cx<R> zv[NC];
+    if (coupled) {
+      V3 add;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        cx<R> acc = mk<R>(cur.dd * x0[c].re, cur.dd * x0[c].im);
-        const cx<R> w = L[c][ly + 1][lx], e = L[c][ly + 1][lx + 2], sn = L[c][ly][lx + 1], nn = L[c][ly + 2][lx + 1];
-        acc.re += cur.cxm * w.re; acc.im += cur.cxm * w.im;
-        acc.re += cur.cxp * e.re; acc.im += cur.cxp * e.im;
-        acc.re += cur.cym * sn.re; acc.im += cur.cym * sn.im;
-        acc.re += cur.cyp * nn.re; acc.im += cur.cyp * nn.im;
-        acc.re += cur.czm * xm[c].re; acc.im += cur.czm * xm[c].im;
-        acc.re += cur.czp * xp[c].re; acc.im += cur.czp * xp[c].im;
-        zv[c] = acc;
+        add.c[c] = zv.c[c];
+#pragma unroll
+        for (int cp = 0; cp < NC; ++cp) {
+          const R kk = cf[6 + c * 3 + cp];
+          add.c[c].re += kk * x0.c[cp].re;
+          add.c[c].im += kk * x0.c[cp].im;
+        }
       }
-      if (Cf.K != nullptr) {
-        cx<R> add[NC];
+      zv = add;
+    }
+    return zv;
+  };
+
+  // rings at the start of iteration a: x(a-1), x(a), x(a+1); u(a-1), u(a); d(a-1), d(a); y(a-2), y(a-1); f(a-1);
+  // the coefficients of plane a+1 in a register (staged to LDS in iteration a).  The forcing is loaded after the
+  // stage that uses it, which keeps the second pass within the register budget of 1,024-thread workgroups.
+  int64_t a = z0 - 1;
+  V3 xm = mask3(ld3(X, a - 1), inxy && zin(a - 1)), x0 = mask3(ld3(X, a), inxy && zin(a)), xp = ld3(X, a + 1);
+  V3 um, u0;
+  if (SECOND) {
+    um = ld3(u, a - 1);
+    u0 = ld3(u, a);
+  }
+  R dm = ldd(a - 1), d0 = ldd(a);
+  V3 ym, y0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) ym.c[c] = y0.c[c] = zero;
+  const bool forced = SECOND && frc != nullptr && interior;  // only the output nodes read the forcing
+  V3 fm;
+  if (forced) fm = ld3(frc, a - 1);
+  put_coef(a, ldc(a));
+  R creg = ldc(a + 1);
+  for (; a <= z1; ++a) {
+    const bool ain = inxy && zin(a);
+    xp = mask3(xp, inxy && zin(a + 1));  // x(a-1) and x(a) were masked when they arrived at this position
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Xs[a & 1][c][ly][lx] = x0.c[c];
+    put_coef(a + 1, creg);
+    __syncthreads();
+    // next plane's operands, in flight while this plane is computed
+    const V3 xn = ld3(X, a + 2);
+    V3 un;
+    if (SECOND) un = ld3(u, a + 1);
+    const R dn = ldd(a + 1);
+    creg = ldc(a + 2);
+    // stage A at plane a
+    V3 y;
+    {
+      const V3 uu = SECOND ? u0 : x0;
+      const V3 zv = apply(Xs[a & 1], xm, x0, xp, d0, (int)(a & 3));
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        y.c[c] = ain ? mk<R>(uu.c[c].re + sa * zv.c[c].re, uu.c[c].im + sa * zv.c[c].im) : zero;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Ys[a & 1][c][ly][lx] = y.c[c];
+    // stage B at plane a - 1 (its y plane was published in the previous iteration)
+    const int64_t zb = a - 1;
+    if (zb >= z0 && zb < z1) {
+      const V3 zv = apply(Ys[zb & 1], ym, y0, y, dm, (int)(zb & 3));
+      if (interior) {
+        const int64_t e = cb + zb * sz + pxy;
+        const V3 ub = SECOND ? um : xm;  // u at plane zb (pass 1: x = u)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          add[c] = zv[c];
-#pragma unroll
-          for (int cp = 0; cp < NC; ++cp) {
-            add[c].re += cur.K[c * 3 + cp] * x0[cp].re;
-            add[c].im += cur.K[c * 3 + cp] * x0[cp].im;
+          cx<R> r = mk<R>(ub.c[c].re + sb * zv.c[c].re, ub.c[c].im + sb * zv.c[c].im);
+          if (SECOND) {
+            if (snap != nullptr) snap[e + c * nodes] = ub.c[c];
+            if (forced) {
+              const cx<R> f = fm.c[c];
+              r.re += phr * f.re - phi * f.im;
+              r.im += phr * f.im + phi * f.re;
+            }
           }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) zv[c] = add[c];
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int64_t e = cb + c * nodes + p;
-        const cx<R> uu = cur.uu[c];
-        if (LAST) {
-          if (snap != nullptr) snap[e] = uu;
-          const cx<R> f = cur.ff[c];
-          cx<R> r = mk<R>(uu.re + zv[c].re, uu.im + zv[c].im);
-          r.re += phr * f.re - phi * f.im;
-          r.im += phr * f.im + phi * f.re;
-          u[e] = r;
-        } else {
-          vout[e] = mk<R>(uu.re + s * zv[c].re, uu.im + s * zv[c].im);
+          out[e + c * nodes] = r;
         }
       }
     }
-    cur = nxt;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      xm[c] = x0[c];
-      x0[c] = xp[c];
-      xp[c] = xn[c];
+    xm = x0;
+    x0 = xp;
+    xp = xn;
+    if (SECOND) {
+      um = u0;
+      u0 = un;
     }
+    if (forced) fm = ld3(frc, a);  // for the next stage B (loaded after this one has used fm)
+    dm = d0;
+    d0 = dn;
+    ym = y0;
+    y0 = y;
   }
 }
 
@@ -355,23 +409,27 @@ int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, voi
   return 0;
 }
 
-int launch_grid_stage3d(const GridOpDev& g, int fp64, int k, void* u, const void* vin, void* vout, double s, int last,
-                        const void* frc, double phr, double phi, void* snap, hipStream_t st) {
-  constexpr int ZC = 16;  // planes per workgroup: enough workgroups for whole rounds of the chip
+int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const void* vin, void* out, int second,
+                       const void* frc, double phr, double phi, void* snap, hipStream_t st) {
+  constexpr int ZC = 32;  // planes per workgroup
   if (g.ncomp != 3 || k < 1) return -1;
   const int64_t nzc = (g.nz + ZC - 1) / ZC;
-  if ((int64_t)k * nzc > 65535) return -1;
-  const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)(k * nzc));
-#define RES_G3(R, L)                                                                                              \
-  hipLaunchKernelGGL((grid_stage3d_kernel<R, L, ZC>), grid, dim3(256), 0, st, coef_of<R>(g, fp64), g.nx, g.ny,     \
-                     g.nz, (cx<R>*)u, (const cx<R>*)vin, (cx<R>*)vout, (R)s, (const cx<R>*)frc, (R)phr, (R)phi,    \
-                     (cx<R>*)snap)
+#define RES_P3(R, S, TX, TY)                                                                                       \
+  do {                                                                                                            \
+    const int64_t tiles = ((g.nx + TX - 5) / (TX - 4)) * ((g.ny + TY - 5) / (TY - 4)) * nzc * k;                 \
+    if (tiles > 0x7ffffff0) return -1;                                                                            \
+    hipLaunchKernelGGL((grid_pair3d_kernel<R, S, TX, TY, ZC>), dim3((unsigned)((tiles + 7) / 8 * 8)),            \
+                       dim3(TX * TY), 0, st, coef_of<R>(g, fp64), g.nx, g.ny, g.nz, (int64_t)k, (const cx<R>*)u,  \
+                       (const cx<R>*)vin, (cx<R>*)out, (const cx<R>*)frc, (R)phr, (R)phi, (cx<R>*)snap);         \
+  } while (0)
+  // LDS: two double-buffered window planes of three components: 64 x 16 windows in FP32, 64 x 8 in FP64 (rows
+  // of 64 keep every wave's loads on whole cache lines; 32 x 32 windows measured 12 % slower)
   if (fp64) {
-    if (last) RES_G3(double, true); else RES_G3(double, false);
+    if (second) RES_P3(double, true, 64, 8); else RES_P3(double, false, 64, 8);
   } else {
-    if (last) RES_G3(float, true); else RES_G3(float, false);
+    if (second) RES_P3(float, true, 64, 16); else RES_P3(float, false, 64, 16);
   }
-#undef RES_G3
+#undef RES_P3
   return 0;
 }
 

@@ -78,6 +78,26 @@ def test_apply_adjoint_and_transient_match_oracle(case):
     assert np.abs(lhs - rhs).max() < 1e-10 * np.abs(lhs).max()
 
 
+@pytest.mark.parametrize("prec,shape", [("fp64", (66, 10, 36)), ("mixed", (66, 14, 36))])
+def test_3d_tiles_and_z_chunks_match_oracle(prec, shape):
+    """3-D grids that span two x tiles, several y tiles and two z chunks of the two-stage pass kernel, each with a
+    ragged tail, against the oracle's four-stage march (FP64 1e-10, mixed 1e-3)."""
+    import torch
+    nx, ny, nz = shape
+    say("case: 3-D tiles and z chunks", prec, shape)
+    op, L = make3d(nx, ny, nz, 0.1, prec)
+    h, P, nw, k = 0.1, 100, 2, 1
+    dw = 2 * np.pi / (P * h)
+    F = forcing(24, nw, k, op.n)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    out = to_np(op.apply(gpu_tensor(F, dt), op.grid(0.1, dw, nw), op.run("periodic", periods=3, stride=25)))
+    torch.cuda.synchronize()
+    ref = O_st.run(L, h, 0.1, dw, F, "periodic", periods=3, stride=25)
+    e = per_freq_relerr(out, ref)
+    say("  error", e)
+    assert e < (1e-10 if prec == "fp64" else 1e-3)
+
+
 @pytest.mark.parametrize("case", ["2d", "3d"])
 def test_modes_match_oracle(case):
     import torch
