@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import dense, gradient, iteration, operators, stepping
+from oracle import dense, gradient, iteration, krylov, operators, stepping
 
 # A small, stable GL problem on [-15, 15] (32 nodes) shared by several pins.
 N_T, XL_T, XR_T = 32, -15.0, 15.0
@@ -286,6 +286,55 @@ def test_stepped_iteration_matches_dense_iteration():
     g1 = iteration.block_power_iteration(a1, d1, F0, 3)[0]
     g2 = iteration.block_power_iteration(a2, d2, F0, 3)[0]
     assert np.allclose(g1, g2, rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------------------------
+# Arnoldi (Krylov-subspace) pins.
+# ---------------------------------------------------------------------------------------------
+def test_arnoldi_on_the_whole_space_is_the_svd():
+    # Appendix A: once the orthonormal forcings span the whole space, H = F^H R^H R F is R^H R in that basis, so
+    # its eigenvalues are the squared singular values of R_d and F psi are its right singular vectors.
+    L, _ = tiny_gl(n=8)
+    om = np.array([-0.4, 0.25])
+    apply, adj = iteration.dense_rk4_applies(L, H_T, om)
+    g, V, U, hist = krylov.block_arnoldi(apply, adj, forcing(31, 2, 2, 8), 4)
+    for j, w in enumerate(om):
+        Rd = dense.resolvent_rk4(L, w, H_T)
+        s, Us, Vs = dense.gains_and_modes(Rd, 2)
+        assert np.allclose(g[j], s, rtol=1e-11)
+        for i in range(2):
+            assert abs(abs(np.vdot(Vs[:, i], V[j, i])) - 1) < 1e-10
+            assert abs(abs(np.vdot(Us[:, i], U[j, i])) - 1) < 1e-10
+    assert np.allclose(hist[-1], g, rtol=1e-14)
+
+
+def test_arnoldi_first_block_is_the_rayleigh_quotient():
+    # One block: H = F^H R^H R F for the orthonormalised start, whose top eigenvalue is sigma(R F)^2 -- the gain
+    # of one power iteration from the same start.
+    L, _ = tiny_gl()
+    om = np.array([0.1, 0.7])
+    apply, adj = iteration.dense_rk4_applies(L, H_T, om)
+    F0 = forcing(32, 2, 2, N_T)
+    g = krylov.block_arnoldi(apply, adj, F0, 1)[0]
+    for j in range(2):
+        F = iteration.qr_positive(F0[j].T)[0]
+        s = np.linalg.svd(dense.resolvent_rk4(L, om[j], H_T) @ F, compute_uv=False)
+        assert np.allclose(g[j], s, rtol=1e-12)
+
+
+def test_arnoldi_converges_faster_than_the_power_iteration():
+    # Appendix A: with small gain separation the Krylov estimate of the suboptimal gain is far ahead of the power
+    # iteration after the same number of runs; both approach the SVD from below (Ritz values).
+    L, _ = tiny_gl()
+    om = np.array([0.2])
+    apply, adj = iteration.dense_rk4_applies(L, H_T, om)
+    s = dense.gains_and_modes(dense.resolvent_rk4(L, om[0], H_T), 2)[0]
+    F0 = forcing(33, 1, 2, N_T)
+    gk = krylov.block_arnoldi(apply, adj, F0, 6)[0][0]
+    gp = iteration.block_power_iteration(apply, adj, F0, 6)[0][0]
+    ek, ep = np.abs(gk / s - 1), np.abs(gp / s - 1)
+    assert np.all(gk <= s * (1 + 1e-12))
+    assert ek[1] < 0.1 * ep[1] and ek[0] <= ep[0] * (1 + 1e-9)
 
 
 # ---------------------------------------------------------------------------------------------
