@@ -155,6 +155,23 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
                     int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
                     void* stream);
 
+/* Block Arnoldi (Krylov-subspace) estimates (Appendix A, eqs. RRFi, arDec, freqOrt and the mode estimates that
+ * follow them), `blocks` direct and `blocks` adjoint runs: the forcing blocks are B_0 = Q(QR(f0_hat)) and
+ * B_{i+1} = Q(QR(part of R_d^H R_d B_i orthogonal to B_0 .. B_i)) (classical Gram-Schmidt, two passes, per
+ * frequency and instance, FP64); H = B^H R_d^H R_d B (from the upper block triangle of the Gram-Schmidt
+ * coefficients, mirrored) gives gains = sqrt(eigenvalues of H), V = B psi, U = R_d B psi / gain.  Converges to
+ * suboptimal gains much faster than resolvent_modes when the gains are close (the paper's recommendation for
+ * suboptimal modes with the periodic method).
+ * f0_hat: device [n_omega][k][N] start block (working precision, as resolvent_modes).
+ * gains:  host double [ninst][n_omega][k], the k largest estimates per frequency, descending.
+ * V, U:   device [n_omega][k][N] force and response modes (each up to a unit-modulus factor), or NULL.
+ * hist:   host double [blocks][ninst][n_omega][k] or NULL: the estimates after each block.
+ * Synchronises `stream`.  k <= 8, blocks * k <= 40 and at most the unknowns of every instance; RES_EINVAL
+ * otherwise. */
+int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                     int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                     void* stream);
+
 /* Gradient of a real objective J(u_hat) of u_hat = resolvent_apply(f_hat) through the time-stepped run
  * (discrete adjoint of the RK4 march, recomputing the forward trajectory from checkpoints taken every
  * `checkpoint_every` steps).  g_hat = dJ/du_hat (device, same layout/dtype as u_hat, with the convention

@@ -45,6 +45,8 @@ SIGNATURES = {
                                           c_void_p]),
     "resolvent_modes": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_int32, c_void_p, _dp,
                                   c_void_p, c_void_p, _dp, c_void_p]),
+    "resolvent_krylov": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_int32, c_void_p, _dp,
+                                   c_void_p, c_void_p, _dp, c_void_p]),
     "resolvent_apply_backward": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                            c_void_p, _dp, c_int32, c_void_p]),
     "resolvent_op_check": (c_int32, [c_void_p, c_void_p]),

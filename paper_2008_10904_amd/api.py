@@ -166,6 +166,22 @@ class ResolventOp:
             ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
         return gains, V, U, hist
 
+    def krylov(self, f0_hat, grid, run, blocks, want_modes=True, want_hist=True):
+        """Block Arnoldi estimates from `blocks` blocks of k forcings (k = f0_hat.shape[1]); returns (gains
+        [ninst, nw, k], V, U, hist [blocks, ninst, nw, k]) like modes."""
+        torch = _torch()
+        nw, k = grid.n_omega, f0_hat.shape[1]
+        self._check_io(f0_hat, nw, k)
+        gains = np.zeros((self.ninst, nw, k))
+        hist = np.zeros((blocks, self.ninst, nw, k)) if want_hist else None
+        V = torch.empty_like(f0_hat) if want_modes else None
+        U = torch.empty_like(f0_hat) if want_modes else None
+        check(self._lib.resolvent_krylov(
+            self._h, ctypes.byref(grid), ctypes.byref(run), k, int(blocks), ctypes.c_void_p(f0_hat.data_ptr()),
+            _dptr(gains), ctypes.c_void_p(V.data_ptr()) if V is not None else None,
+            ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
+        return gains, V, U, hist
+
     def modes_polished(self, op_fp64, f0_hat, grid, run, iters, want_hist=True):
         """Mixed-precision block power iteration with an FP64 Rayleigh-Ritz finish.
 

@@ -85,6 +85,18 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
 
+// ---- block Arnoldi (krylov.hip) ---------------------------------------------------------------------------
+int launch_xgram(const void* basis, int64_t bstride, int nb, const void* W, int64_t N, int k, const int64_t* off,
+                 int ninst, int nw, int nsplit, void* part, hipStream_t st);
+int launch_xgram_reduce(const void* part, int nsplit, int k, int nb, int nw, int ninst, void* C, void* H, int hld,
+                        int col0, hipStream_t st);
+int launch_combine(void* out, int out_fp64, int subtract, const void* X, int64_t xstride, int nb, int64_t N, int k,
+                   int kout, const int64_t* off, int ninst, int nw, int nsplit, const void* M, int mld,
+                   const double* s, hipStream_t st);
+int launch_heig(const void* H, int hld, int n, int k, int nw, int ninst, double* gains, void* psi, int pld,
+                hipStream_t st);
+int launch_recip_gains(const double* gains, double* inv, int ninst, int nw, int k, hipStream_t st);
+
 // ---- phase GEMMs --------------------------------------------------------------------------------------
 struct PhaseGemmArgs {
   int mode;                // 0 synthesis, 1 projection

@@ -1763,6 +1763,105 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   return resolvent_op_check(op, stream);
 }
 
+// Block Arnoldi (Appendix A): basis blocks B_0 = Q(QR(f0)), B_{i+1} = Q(QR(W_i - sum_b B_b C_b)) with
+// W_i = R_d^H R_d B_i and the coefficients C_b = B_b^H W_i taken twice (classical Gram-Schmidt, two passes).  The
+// first-pass coefficients fill the upper block triangle of H = B^H R_d^H R_d B; the estimates come from the
+// eigen-decomposition of its Hermitian completion: gains sqrt(lambda), V = B psi, U = R_d B psi / gain.
+int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                     int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                     void* stream) {
+  g_last_error.clear();
+  if (!op || !f0_hat || !gains) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1 || k > 8) return fail(RES_EINVAL, "k must be in 1..8");
+  if (blocks < 1 || blocks * k > 40) return fail(RES_EINVAL, "blocks must be >= 1 with blocks * k <= 40");
+  for (int i = 0; i < op->ninst; ++i)
+    if (op->off[i + 1] - op->off[i] < (int64_t)blocks * k)
+      return fail(RES_EINVAL, "blocks * k exceeds the unknowns of an instance");
+  hipStream_t st = (hipStream_t)stream;
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(RES_EINVAL, "resolvent_krylov returns host data and cannot be captured");
+  }
+  Plan pl;
+  RES_TRY(make_plan(op, grid, run, &pl));
+  const int nw = pl.nw, ninst = op->ninst;
+  const int64_t N = op->N;
+  const int64_t bsz = (int64_t)nw * k * N;  // complex values per block
+  const int nmax = blocks * k;
+  const int nsplit = nsplit_for(max_instance_len(op));
+  const int km = gram_km(k);
+  const size_t gcount = (size_t)ninst * nw * k;
+  void *B, *Yb, *H, *C, *part, *psi, *dg, *dh = nullptr, *rq, *one;
+  RES_TRY(ws_get(op, "kry_basis", (size_t)(blocks + 1) * bsz * sizeof(cd), &B));
+  RES_TRY(ws_get(op, "kry_y", (size_t)blocks * bsz * sizeof(cd), &Yb));
+  RES_TRY(ws_get(op, "kry_h", (size_t)nw * ninst * nmax * nmax * sizeof(cd), &H));
+  RES_TRY(ws_get(op, "kry_c", (size_t)nw * ninst * nmax * k * sizeof(cd), &C));
+  RES_TRY(ws_get(op, "kry_part", (size_t)blocks * nw * ninst * nsplit * km * km * sizeof(cd), &part));
+  RES_TRY(ws_get(op, "kry_psi", (size_t)nw * ninst * nmax * k * sizeof(cd), &psi));
+  RES_TRY(ws_get(op, "kry_gains", gcount * sizeof(double), &dg));
+  RES_TRY(ws_get(op, "kry_one", gcount * sizeof(double), &one));
+  RES_TRY(ws_get(op, "kry_rq", (size_t)nw * ninst * 64 * sizeof(cd), &rq));
+  if (hist) RES_TRY(ws_get(op, "kry_hist", (size_t)blocks * gcount * sizeof(double), &dh));
+  auto blk = [&](void* base, int i) { return (double*)base + (size_t)2 * i * bsz; };
+  RES_TRY(zero_device(H, (size_t)nw * ninst * nmax * nmax * sizeof(cd), st));
+  {
+    std::vector<double> ones(gcount, 1.0);
+    HIP_TRY(hipMemcpyAsync(one, ones.data(), gcount * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the host vector goes out of scope
+  }
+  launch_convert(f0_hat, op->fp64(), blk(B, 0), 1, bsz, 1.0, st);
+  RES_TRY(cholqr2(op, nw, k, blk(B, 0), rq, nullptr, st));
+  for (int i = 0; i < blocks; ++i) {
+    double* W = blk(B, i + 1);  // the next block is built in place (the spare slot after the last one)
+    RES_TRY(run_any(op, pl, k, blk(B, i), 1, blk(Yb, i), +1, st));
+    RES_TRY(run_any(op, pl, k, blk(Yb, i), 1, W, -1, st));
+    {
+      TimedLaunch tl(op, RES_TIMING_QR, st);
+      // first pass: coefficients of every basis block, recorded as column block i of H
+      if (launch_xgram(B, bsz, i + 1, W, N, k, op->d_off, ninst, nw, nsplit, part, st))
+        return fail(RES_EINVAL, "Krylov Gram launch");
+      launch_xgram_reduce(part, nsplit, k, i + 1, nw, ninst, C, H, nmax, i * k, st);
+      if (hist && launch_heig(H, nmax, (i + 1) * k, k, nw, ninst, (double*)dh + (size_t)i * gcount, nullptr, 0, st))
+        return fail(RES_EINVAL, "Krylov eigen-decomposition launch");
+      if (i + 1 < blocks) {
+        for (int pass = 0; pass < 2; ++pass) {
+          if (pass == 1) {
+            launch_xgram(B, bsz, i + 1, W, N, k, op->d_off, ninst, nw, nsplit, part, st);
+            launch_xgram_reduce(part, nsplit, k, i + 1, nw, ninst, C, nullptr, 0, 0, st);
+          }
+          if (launch_combine(W, 1, 1, B, bsz, i + 1, N, k, k, op->d_off, ninst, nw, nsplit, C, (i + 1) * k,
+                             nullptr, st))
+            return fail(RES_EINVAL, "Krylov update launch");
+        }
+      }
+      HIP_TRY(hipGetLastError());
+    }
+    if (i + 1 < blocks) RES_TRY(cholqr2(op, nw, k, W, rq, nullptr, st));
+  }
+  {
+    TimedLaunch tl(op, RES_TIMING_QR, st);
+    if (launch_heig(H, nmax, nmax, k, nw, ninst, (double*)dg, psi, nmax, st))
+      return fail(RES_EINVAL, "Krylov eigen-decomposition launch");
+    if (V && launch_combine(V, op->fp64(), 0, B, bsz, blocks, N, k, k, op->d_off, ninst, nw, nsplit, psi, nmax,
+                            (const double*)one, st))
+      return fail(RES_EINVAL, "Krylov mode launch");
+    if (U) {
+      // U = R_d B psi / gain: the same combination of the stored responses, scaled by the reciprocal gains
+      void* inv;
+      RES_TRY(ws_get(op, "kry_inv", gcount * sizeof(double), &inv));
+      launch_recip_gains((const double*)dg, (double*)inv, ninst, nw, k, st);
+      if (launch_combine(U, op->fp64(), 0, Yb, bsz, blocks, N, k, k, op->d_off, ninst, nw, nsplit, psi, nmax,
+                         (const double*)inv, st))
+        return fail(RES_EINVAL, "Krylov mode launch");
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  if (hist) HIP_TRY(hipMemcpyAsync(hist, dh, (size_t)blocks * gcount * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(gains, dg, gcount * sizeof(double), hipMemcpyDeviceToHost, st));
+  return resolvent_op_check(op, stream);
+}
+
 int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream) {
