@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--step-power", type=int, default=None, choices=[1, 2, 4],
                     help="1-D workloads: RK4 steps per kernel step (band P(Z)^m and the combined forcing of m "
                          "steps); default: the library's default (4)")
+    ap.add_argument("--algorithm", default="power", choices=["power", "krylov"],
+                    help="gl_periodic_n2000: 'power' (block power iteration, the headline line) or 'krylov' (block "
+                         "Arnoldi with --krylov-blocks blocks of k forcings; one step = one call)")
+    ap.add_argument("--krylov-blocks", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -308,6 +312,88 @@ def bench_grid(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_krylov(args):
+    """gl_periodic_n2000 with the block Arnoldi estimates: one step is one resolvent_krylov call of
+    --krylov-blocks blocks of k = 4 forcings (that many direct and adjoint runs), FP64 and mixed.  The power
+    iteration's gains after the same number of runs are reported beside it, with both compared on their
+    largest suboptimal-gain change over the last block (a convergence indicator)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.operators import snap_grid
+
+    cfg = W.GL_PERIODIC
+    nb = args.krylov_blocks
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+    steps_per_run = cfg["periods"] * P
+    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
+    sweeps = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run * nb
+    res = {}
+    for prec, dtype in (("fp64", torch.complex128), ("mixed", torch.complex64)):
+        op = build_op(cfg, prec)
+        if args.step_power:
+            op.set_step_power(args.step_power)
+        grid = op.grid(w0, dw, cfg["n_omega"])
+        run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+        f = torch.from_numpy(F).to(dtype).cuda()
+        for _ in range(args.warmup):
+            op.krylov(f, grid, run, nb, want_modes=False, want_hist=False)
+        torch.cuda.synchronize()
+        op.set_timing(True)
+        for kind in range(4):
+            op.timing(kind)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g, _, _, hist = op.krylov(f, grid, run, nb, want_modes=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        kt = {name: op.timing(kind)[0] / args.steps for name, kind in (("stepper", L.RES_TIMING_STEPPER),
+                                                                       ("synthesis", L.RES_TIMING_SYNTHESIS),
+                                                                       ("projection", L.RES_TIMING_PROJECTION),
+                                                                       ("arnoldi_and_qr", L.RES_TIMING_QR))}
+        op.set_timing(False)
+        gp, _, _, hp = op.modes(f, grid, run, nb, want_modes=False)
+        torch.cuda.synchronize()
+        if prec == "mixed":
+            op64 = build_op(cfg, "fp64")
+            if args.step_power:
+                op64.set_step_power(args.step_power)
+            g_fin = op.krylov_polished(op64, f, grid, run, nb)[0]
+            torch.cuda.synchronize()
+            del op64
+        else:
+            g_fin = None
+        res[prec] = dict(value=sweeps / dt, ms_per_step=dt * 1e3, kernel_ms_per_step=kt, gains=g, power_gains=gp,
+                         finished_gains=g_fin,
+                         krylov_last_change=float(np.abs(hist[-1] / hist[-2] - 1).max()) if nb > 1 else None,
+                         power_last_change=float(np.abs(hp[-1, ..., 0] / hp[-2, ..., 0] - 1).max()) if nb > 1 else None)
+        del op, f
+        torch.cuda.empty_cache()
+    r64, rm = res["fp64"], res["mixed"]
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)", "value": r64["value"], "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": cfg["N"], "k": cfg["k"], "n_omega": cfg["n_omega"], "P": P,
+                   "h": cfg["h"], "method": "periodic", "periods": cfg["periods"], "stride": cfg["stride"],
+                   "step": "one block Arnoldi call of %d blocks" % nb, "time_steps_per_step": 2 * steps_per_run * nb},
+        "kernel_ms_per_step": r64["kernel_ms_per_step"],
+        "krylov_vs_power_same_runs": {
+            "max_rel_gain_diff": float(np.abs(r64["gains"] / r64["power_gains"] - 1).max()),
+            "krylov_last_block_change": r64["krylov_last_change"],
+            "power_last_iteration_change": r64["power_last_change"]},
+        "mixed": {"value": rm["value"], "ms_per_step": rm["ms_per_step"], "kernel_ms_per_step": rm["kernel_ms_per_step"],
+                  "max_rel_gain_diff_vs_fp64": float(np.abs(rm["gains"] / r64["gains"] - 1).max()),
+                  "with_fp64_finish": {
+                      "max_rel_gain_diff_vs_fp64": float(np.abs(rm["finished_gains"] / r64["gains"] - 1).max()),
+                      "leading_gain": float(np.abs(rm["finished_gains"][..., 0] / r64["gains"][..., 0] - 1).max())},
+                  "leading_gain_diff_vs_fp64": float(np.abs(rm["gains"][..., 0] / r64["gains"][..., 0] - 1).max())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -318,6 +404,12 @@ def main():
         return
     if args.plan is None:
         args.plan = "tuned" if args.workload == "gl_batched_64" else "default"
+    if args.algorithm == "krylov":
+        if args.workload != "gl_periodic_n2000":
+            print("--algorithm krylov measures gl_periodic_n2000", file=sys.stderr)
+            sys.exit(2)
+        bench_krylov(args)
+        return
     if args.workload == "gl_batched_64":
         bench_batched(args)
         return

@@ -182,6 +182,16 @@ class ResolventOp:
             ctypes.c_void_p(U.data_ptr()) if U is not None else None, _dptr(hist), self._stream_ptr()))
         return gains, V, U, hist
 
+    def krylov_polished(self, op_fp64, f0_hat, grid, run, blocks):
+        """Mixed-precision block Arnoldi with an FP64 Rayleigh-Ritz finish on its k leading Ritz vectors (one FP64
+        direct and adjoint run on op_fp64, as modes_polished).  Returns (gains, V, U) with V, U complex128."""
+        torch = _torch()
+        if self.precision != "mixed" or op_fp64.precision != "fp64" or op_fp64.n != self.n:
+            raise ValueError("krylov_polished needs this handle in mixed precision and op_fp64 in fp64, same size")
+        _, V, _, _ = self.krylov(f0_hat, grid, run, blocks, want_modes=True, want_hist=False)
+        gains, V2, U2, _ = op_fp64.modes(V.to(torch.complex128).contiguous(), grid, run, 1, want_hist=False)
+        return gains, V2, U2
+
     def modes_polished(self, op_fp64, f0_hat, grid, run, iters, want_hist=True):
         """Mixed-precision block power iteration with an FP64 Rayleigh-Ritz finish.
 

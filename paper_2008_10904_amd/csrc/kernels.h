@@ -131,7 +131,8 @@ int launch_convert(const void* x, int in_fp64, void* y, int out_fp64, int64_t co
 int launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: a multiple of 4
 // Amplitude weights of the block power iteration (fac[ninst][nw] = 1/sqrt(leading gain)) and their application
 // to FP64 blocks [nw][k][N] (invert: divide).
-int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st);
+int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st,
+                        double power = 0.5);
 int launch_freq_scale(const void* in, void* out, int64_t N, int k, int nw, const int64_t* off, int ninst,
                       const double* fac, int invert, hipStream_t st);
 

@@ -359,14 +359,14 @@ int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t
   return 0;
 }
 
-// Per-(instance, frequency) amplitude weights of the block power iteration: fac = 1/sqrt(sigma_1) from the last
-// gains (1 where a gain is not a positive finite number).
+// Per-(instance, frequency) amplitude weights: fac = sigma_1^(-power) from the leading gain estimates (1 where a
+// gain is not a positive finite number).
 __global__ void freq_weight_kernel(const double* __restrict__ gains, double* __restrict__ fac, int ninst, int nw,
-                                   int k) {
+                                   int k, double power) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ninst * nw) return;
   const double g = gains[(int64_t)i * k];
-  fac[i] = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 1.0;
+  fac[i] = (g > 0.0 && isfinite(g)) ? pow(g, -power) : 1.0;
 }
 
 // out[j][c][n] = in[j][c][n] * fac[m(n)][j] (invert: divided by it), m(n) the instance of unknown n; FP64.
@@ -390,9 +390,9 @@ __global__ __launch_bounds__(256) void freq_scale_kernel(const cx<double>* __res
   }
 }
 
-int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st) {
+int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st, double power) {
   const int n = ninst * nw;
-  hipLaunchKernelGGL(freq_weight_kernel, dim3((n + 255) / 256), dim3(256), 0, st, gains, fac, ninst, nw, k);
+  hipLaunchKernelGGL(freq_weight_kernel, dim3((n + 255) / 256), dim3(256), 0, st, gains, fac, ninst, nw, k, power);
   return 0;
 }
 

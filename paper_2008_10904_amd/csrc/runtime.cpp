@@ -1802,8 +1802,26 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
   RES_TRY(ws_get(op, "kry_gains", gcount * sizeof(double), &dg));
   RES_TRY(ws_get(op, "kry_one", gcount * sizeof(double), &one));
   RES_TRY(ws_get(op, "kry_rq", (size_t)nw * ninst * 64 * sizeof(cd), &rq));
-  if (hist) RES_TRY(ws_get(op, "kry_hist", (size_t)blocks * gcount * sizeof(double), &dh));
+  RES_TRY(ws_get(op, "kry_hist", (size_t)blocks * gcount * sizeof(double), &dh));
+  // Mixed precision: amplitude weights from the second block on, as in resolvent_modes.  Every run superposes all
+  // frequencies in one FP32 state, so the direct run takes B_i scaled by sigma_1^{-1/2} and the adjoint run takes
+  // R B_i (amplitude sigma) scaled by sigma_1^{-3/2} (sigma_1 from the previous block's estimates), and their
+  // outputs are unscaled.  FP64 runs are not weighted: the later basis blocks come from strongly cancelling
+  // differences, which would turn the rescaling's rounding into differences of 1e-9 in the estimates.
+  const bool weigh = !op->fp64();
+  void *fd, *fa, *tmp;
+  RES_TRY(ws_get(op, "kry_fd", (size_t)ninst * nw * sizeof(double), &fd));
+  RES_TRY(ws_get(op, "kry_fa", (size_t)ninst * nw * sizeof(double), &fa));
+  RES_TRY(ws_get(op, "kry_tmp", (size_t)bsz * sizeof(cd), &tmp));
   auto blk = [&](void* base, int i) { return (double*)base + (size_t)2 * i * bsz; };
+  auto weighted = [&](bool w, const void* fac, double* in, double* out, int sigma) -> int {
+    if (!w) return run_any(op, pl, k, in, 1, out, sigma, st);
+    launch_freq_scale(in, tmp, N, k, nw, op->d_off, ninst, (const double*)fac, 0, st);
+    RES_TRY(run_any(op, pl, k, tmp, 1, out, sigma, st));
+    launch_freq_scale(out, out, N, k, nw, op->d_off, ninst, (const double*)fac, 1, st);
+    HIP_TRY(hipGetLastError());
+    return RES_OK;
+  };
   RES_TRY(zero_device(H, (size_t)nw * ninst * nmax * nmax * sizeof(cd), st));
   {
     std::vector<double> ones(gcount, 1.0);
@@ -1814,16 +1832,19 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
   RES_TRY(cholqr2(op, nw, k, blk(B, 0), rq, nullptr, st));
   for (int i = 0; i < blocks; ++i) {
     double* W = blk(B, i + 1);  // the next block is built in place (the spare slot after the last one)
-    RES_TRY(run_any(op, pl, k, blk(B, i), 1, blk(Yb, i), +1, st));
-    RES_TRY(run_any(op, pl, k, blk(Yb, i), 1, W, -1, st));
+    RES_TRY(weighted(weigh && i > 0, fd, blk(B, i), blk(Yb, i), +1));
+    RES_TRY(weighted(weigh && i > 0, fa, blk(Yb, i), W, -1));
     {
       TimedLaunch tl(op, RES_TIMING_QR, st);
       // first pass: coefficients of every basis block, recorded as column block i of H
       if (launch_xgram(B, bsz, i + 1, W, N, k, op->d_off, ninst, nw, nsplit, part, st))
         return fail(RES_EINVAL, "Krylov Gram launch");
       launch_xgram_reduce(part, nsplit, k, i + 1, nw, ninst, C, H, nmax, i * k, st);
-      if (hist && launch_heig(H, nmax, (i + 1) * k, k, nw, ninst, (double*)dh + (size_t)i * gcount, nullptr, 0, st))
+      double* est = (double*)dh + (size_t)i * gcount;  // estimates after this block (history, weights)
+      if (launch_heig(H, nmax, (i + 1) * k, k, nw, ninst, est, nullptr, 0, st))
         return fail(RES_EINVAL, "Krylov eigen-decomposition launch");
+      launch_freq_weights(est, (double*)fd, ninst, nw, k, st, 0.5);
+      launch_freq_weights(est, (double*)fa, ninst, nw, k, st, 1.5);
       if (i + 1 < blocks) {
         for (int pass = 0; pass < 2; ++pass) {
           if (pass == 1) {

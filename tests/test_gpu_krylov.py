@@ -118,3 +118,22 @@ def test_krylov_mixed_precision_and_errors():
         with pytest.raises(ResolventError) as e:
             op.krylov(gpu_tensor(forcing(48, nw, kk, n), torch.complex64), grid, run, bb, want_modes=False)
         assert e.value.code == L_.RES_EINVAL
+
+
+def test_krylov_mixed_with_fp64_finish():
+    import torch
+    say("case: krylov mixed + FP64 Rayleigh-Ritz finish")
+    n, nw, k, blocks, w0 = 32, 3, 2, 4, -0.2
+    dw = 2 * np.pi / (P * H)
+    L, _ = O_ops.gl_operator(n, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F0 = forcing(49, nw, k, n)
+    a, ad = O_it.stepped_applies(L, H, w0, dw, "periodic", periods=PERIODS, stride=STRIDE)
+    g_ref = O_kr.block_arnoldi(a, ad, F0, blocks)[0]
+    opm, op64 = gl_op(n, 0.2, -0.01, "mixed"), gl_op(n, 0.2, -0.01, "fp64")
+    grid, run = opm.grid(w0, dw, nw), opm.run("periodic", periods=PERIODS, stride=STRIDE)
+    g, V, U = opm.krylov_polished(op64, gpu_tensor(F0, torch.complex64), grid, run, blocks)
+    torch.cuda.synchronize()
+    lead = np.abs(g[0, :, 0] / g_ref[:, 0] - 1).max()
+    say("  leading gain err", lead, "all", np.abs(g[0] / g_ref - 1).max())
+    assert V.dtype == torch.complex128 and U.dtype == torch.complex128
+    assert lead < 1e-8 and np.abs(g[0] / g_ref - 1).max() < 1e-5
