@@ -265,6 +265,19 @@ def bench_grid(args):
         time_steps_total = 2 * steps_per_run * args.steps
         value = N * k * nw * 2 * steps_per_run / dt
         step_desc = "one block-power iteration"
+        # forward plus reverse mode (the C4 gradient path): one apply and one apply_backward with the forcing and
+        # mu gradients, checkpoints every ~sqrt(steps), timed outside the iteration above
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = op.apply(f, grid, run)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = (u / u.abs().clamp_min(1e-30)).contiguous()  # dJ/du_hat of J = sum |u_hat| (leading-mode objective)
+        op.apply_backward(f, g, grid, run)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        autograd = {"forward_s": t1 - t0, "backward_s": t2 - t1,
+                    "note": "one apply and one apply_backward (forcing and mu gradients) of the full workload"}
     else:
         nw, P = 8, 64
         dw = 2 * np.pi / (P * cfg["h"])
@@ -309,6 +322,8 @@ def bench_grid(args):
                      "us_per_time_step": step_s * 1e6, "algorithmic_bytes_per_step": alg_bytes},
         "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
     }
+    if cfg["kind"] == "adr2d":
+        out["autograd"] = autograd
     print(json.dumps(out), flush=True)
 
 

@@ -1365,7 +1365,22 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   }
   HIP_TRY(hipGetLastError());
 
-  // 2. reverse sweep over the segments
+  // 2. reverse sweep over the segments.  The segment's forward recomputation keeps the three stage inputs of every
+  // step but its last when they fit in a quarter of the free device memory, so the reverse steps do not march them
+  // again (the values are the same: the stages of a step depend only on its state and forcing).
+  void* stg = nullptr;
+  {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const auto held = op->ws.find("bw_stages");
+    const double avail = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0);
+    const size_t need = (size_t)3 * C * rowb;
+    if ((double)need <= 0.25 * avail && ws_get(op, "bw_stages", need, &stg) != RES_OK) {
+      g_last_error.clear();
+      stg = nullptr;
+    }
+  }
+  auto srow = [&](int64_t r, int i) { return row(stg, 3 * r + i); };
   RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C), len = sb - sa;
@@ -1375,10 +1390,13 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     for (int64_t s = sa; s + 1 < sb; ++s) {
       const int64_t r = s - sa;
       void* us = row(seg, r);
-      launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, acc, frc(s, r, 0), h, st);
-      launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y2, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 4, us, row(seg, r + 1), y2, nullptr, acc, frc(s, r, 2), h, st);
+      void* a2 = stg ? srow(r, 0) : y2;
+      void* a3 = stg ? srow(r, 1) : y3;
+      void* a4 = stg ? srow(r, 2) : y2;
+      launch_fwd_stage(fwd, k, 1, us, nullptr, us, a2, acc, frc(s, r, 0), h, st);
+      launch_fwd_stage(fwd, k, 2, us, nullptr, a2, a3, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 3, us, nullptr, a3, a4, acc, frc(s, r, 1), h, st);
+      launch_fwd_stage(fwd, k, 4, us, row(seg, r + 1), a4, nullptr, acc, frc(s, r, 2), h, st);
     }
     // projection seeds of the sampled steps in [sa, sb)
     const int64_t ma = first_m_at_or_after(sa), mb = first_m_at_or_after(sb);
@@ -1390,18 +1408,25 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     for (int64_t s = sb - 1; s >= sa; --s) {
       const int64_t r = s - sa;
       void* us = row(seg, r);
-      launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st);
-      launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st);
+      const void *s2 = y2, *s3 = y3, *s4 = y4;  // stage inputs of step s
+      if (stg && s + 1 < sb) {
+        s2 = srow(r, 0);
+        s3 = srow(r, 1);
+        s4 = srow(r, 2);
+      } else {
+        launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st);
+        launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);
+        launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st);
+      }
       const void* lp = row(lrows, r);
       const void* seed = nullptr;
       if (s >= pl.pfirst && (s - pl.pfirst) % pl.pstride == 0) {
         const int64_t m = (s - pl.pfirst) / pl.pstride;
         if (m < pl.pcount) seed = row(inj, m - ma);
       }
-      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, y4, ka, ub, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 3, lp, nullptr, ka, y3, kb, ub, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 2, lp, nullptr, kb, y2, ka, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, ub, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ka, ub, mu_grad, nullptr, h, st);
       launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lrows, r - 1) : carry, ka, us, nullptr, ub, mu_grad, seed, h, st);
     }
     HIP_TRY(hipGetLastError());
