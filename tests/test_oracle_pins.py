@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import dense, gradient, iteration, krylov, operators, stepping
+from oracle import dense, gradient, iteration, krylov, operators, stepping, weights
 
 # A small, stable GL problem on [-15, 15] (32 nodes) shared by several pins.
 N_T, XL_T, XR_T = 32, -15.0, 15.0
@@ -335,6 +335,53 @@ def test_arnoldi_converges_faster_than_the_power_iteration():
     ek, ep = np.abs(gk / s - 1), np.abs(gp / s - 1)
     assert np.all(gk <= s * (1 + 1e-12))
     assert ek[1] < 0.1 * ep[1] and ek[0] <= ep[0] * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------------------------------------
+# B, C and metric pins.
+# ---------------------------------------------------------------------------------------------
+def _weights(n, seed):
+    g = np.random.default_rng(seed)
+    b = np.where(np.arange(n) < 3 * n // 4, 1.0, 0.0) * (0.5 + g.random(n))  # a force mask with amplitudes
+    c = np.where(np.arange(n) >= n // 4, 1.0, 0.0)                            # an observation window
+    wf = 0.2 + g.random(n)                                                    # quadrature-like weights
+    wy = 0.2 + g.random(n)
+    return b, c, wf, wy
+
+
+def test_weighted_adjoint_identity():
+    # Sec. 2.1: <R_y f, y>_{W_y} = <f, R_y^dagger y>_{W_f} with R_y^dagger = W_f^{-1} B^H R^H C^H W_y.
+    L, _ = tiny_gl()
+    om = np.array([-0.2, 0.4])
+    a, ad = iteration.dense_rk4_applies(L, H_T, om)
+    b, c, wf, wy = _weights(N_T, 50)
+    ay, ady = weights.observed_applies(a, ad, b, c, wf, wy)
+    F, Y = forcing(51, 2, 1, N_T), forcing(52, 2, 1, N_T)
+    lhs = np.sum(np.conj(ay(F)) * wy * Y, axis=-1)
+    rhs = np.sum(np.conj(F) * wf * ady(Y), axis=-1)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=0)
+
+
+def test_weighted_gains_are_the_generalised_singular_values():
+    # max ||C R B f||_{W_y} / ||f||_{W_f}: the generalised eigenproblem (R_y^H W_y R_y) v = s^2 W_f v, solved densely,
+    # against the SVD of the Euclidean R~ and against the block iteration with R~'s applies.
+    import scipy.linalg as sla
+    L, _ = tiny_gl()
+    om = np.array([0.0, 0.6])
+    a, ad = iteration.dense_rk4_applies(L, H_T, om)
+    b, c, wf, wy = _weights(N_T, 53)
+    ae, ade = weights.euclidean_applies(a, ad, b, c, wf, wy)
+    g, V, U, _ = iteration.block_power_iteration(ae, ade, forcing(54, 2, 2, N_T), 80)
+    Vw, Uw = weights.modes_from_euclidean(V, U, wf, wy)
+    for j, w in enumerate(om):
+        Ry = np.diag(c) @ dense.resolvent_rk4(L, w, H_T) @ np.diag(b)
+        lam, vec = sla.eigh(Ry.conj().T @ np.diag(wy) @ Ry, np.diag(wf))
+        s = np.sqrt(np.maximum(lam[::-1][:2], 0))
+        assert np.allclose(g[j], s, rtol=1e-10)
+        v1 = vec[:, -1]
+        # W_f-normalised leading force mode, up to a phase; its W_y gain is s_1
+        assert abs(abs(np.vdot(v1, wf * Vw[j, 0])) / np.sqrt(np.vdot(v1, wf * v1).real) - 1) < 1e-8
+        assert abs(np.sqrt(np.sum(wy * np.abs(Ry @ Vw[j, 0]) ** 2)) / s[0] - 1) < 1e-10
 
 
 # ---------------------------------------------------------------------------------------------
