@@ -203,6 +203,21 @@ int resolvent_op_set_graphs(resolvent_op* op, int32_t enable);
 int resolvent_op_get_plan(const resolvent_op* op, int32_t plan[4]);
 int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]);
 
+/* Input and output matrices and metrics of the resolvent problem (Sec. 2.1, eqs. systemFreqDomain, adsystem and
+ * the discrete adjoints after them), diagonal: B = diag(b), C = diag(c) (force and observation masks or weights),
+ * W_f = diag(wf), W_y = diag(wy) (force and observation metrics, e.g. non-uniform-grid quadrature).  Host arrays of
+ * the operator's N unknowns (all instances, grid layout for grid operators), each NULL for the identity; all NULL
+ * restores B = C = W = I.  Afterwards
+ *   resolvent_apply returns y = C R_d B f, resolvent_adjoint_apply returns R_y^dagger y = W_f^{-1} B^H R_d^H C^H W_y y
+ *   (the adjoint of R_y = C R_d B in these metrics; W_u of the state cancels),
+ *   resolvent_modes and resolvent_krylov maximise ||C R_d B f||_{W_y} / ||f||_{W_f}: they iterate on the Euclidean
+ *   R~ = W_y^{1/2} C R_d B W_f^{-1/2}, take f0_hat in the problem's coordinates and return W_f-orthonormal force
+ *   modes V and response modes U = C R_d B V / sigma.
+ * The reverse mode (resolvent_apply_backward) returns RES_ENOTSUP while weights are set.  RES_EINVAL for
+ * non-finite b or c, wf or wy not finite and positive, or during graph capture. */
+int resolvent_op_set_weights(resolvent_op* op, const double* b, const double* c, const double* wf,
+                             const double* wy);
+
 /* Multi-step march of a RES_OP_TRIDIAG operator (Sec. 2.1, the RK4 march written as one step): with m = 2 or 4
  * each kernel step advances m RK4 steps at once, u_{s+m} = P(Z)^m u_s + sum_j e^{i w_j t_s} G_j^(m) with
  * G_j^(m) = sum_{r<m} e^{i w_j r h} P(Z)^(m-1-r) h Q_j(Z) F_j.  P(Z)^m is formed once in FP64 on the host (a

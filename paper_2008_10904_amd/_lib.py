@@ -54,6 +54,7 @@ SIGNATURES = {
     "resolvent_op_get_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_step_power": (c_int32, [c_void_p, c_int32]),
+    "resolvent_op_set_weights": (c_int32, [c_void_p, _dp, _dp, _dp, _dp]),
     "resolvent_op_get_step_power": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_tune": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), _dp, c_void_p]),
     "resolvent_op_set_timing": (c_int32, [c_void_p, c_int32]),

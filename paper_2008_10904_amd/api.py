@@ -188,6 +188,8 @@ class ResolventOp:
         torch = _torch()
         if self.precision != "mixed" or op_fp64.precision != "fp64" or op_fp64.n != self.n:
             raise ValueError("krylov_polished needs this handle in mixed precision and op_fp64 in fp64, same size")
+        if getattr(self, "weights", None) is not None:
+            op_fp64.set_weights(*self.weights)
         _, V, _, _ = self.krylov(f0_hat, grid, run, blocks, want_modes=True, want_hist=False)
         gains, V2, U2, _ = op_fp64.modes(V.to(torch.complex128).contiguous(), grid, run, 1, want_hist=False)
         return gains, V2, U2
@@ -204,6 +206,8 @@ class ResolventOp:
         torch = _torch()
         if self.precision != "mixed" or op_fp64.precision != "fp64" or op_fp64.n != self.n:
             raise ValueError("modes_polished needs this handle in mixed precision and op_fp64 in fp64, same size")
+        if getattr(self, "weights", None) is not None:
+            op_fp64.set_weights(*self.weights)
         _, V, _, hist = self.modes(f0_hat, grid, run, iters, want_modes=True, want_hist=want_hist)
         gains, V2, U2, _ = op_fp64.modes(V.to(torch.complex128).contiguous(), grid, run, 1, want_hist=False)
         if want_hist:
@@ -260,6 +264,18 @@ class ResolventOp:
         p = (ctypes.c_int32 * 4)(*[int(x) for x in plan])
         check(self._lib.resolvent_op_set_plan(self._h, p))
         return self.get_plan()
+
+    def set_weights(self, b=None, c=None, wf=None, wy=None):
+        """Diagonal B, C and metrics W_f, W_y (real arrays of the N unknowns, None = identity): apply returns
+        C R B f, adjoint_apply W_f^-1 B^H R^H C^H W_y y, and modes / krylov maximise ||C R B f||_Wy / ||f||_Wf."""
+        arrs = []
+        for a in (b, c, wf, wy):
+            arrs.append(None if a is None else np.ascontiguousarray(np.asarray(a, np.float64).ravel()))
+        for a in arrs:
+            if a is not None and a.shape != (self.n,):
+                raise ValueError("weights must have the operator's %d unknowns" % self.n)
+        check(self._lib.resolvent_op_set_weights(self._h, *[_dptr(a) for a in arrs]))
+        self.weights = None if all(a is None for a in arrs) else tuple(arrs)
 
     def set_step_power(self, m):
         """RK4 steps per kernel step of the 1-D march (1, 2 or 4): the band P(Z)^m and the combined forcing of m

@@ -128,6 +128,9 @@ int launch_svd(const void* A, int k, int nw, int ninst, void* phi, void* psi, vo
                double* hist, hipStream_t st);
 int launch_finite(const void* x, int fp64, int64_t count, int* flag, hipStream_t st);
 int launch_convert(const void* x, int in_fp64, void* y, int out_fp64, int64_t count, double scale, hipStream_t st);
+// out[b][n] = in[b][n] * s[n] over `blocks` blocks of N values (in place allowed when the types match).
+int launch_node_scale(const void* in, int in_fp64, void* out, int out_fp64, const double* s, int64_t blocks,
+                      int64_t N, hipStream_t st);
 int launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: a multiple of 4
 // Amplitude weights of the block power iteration (fac[ninst][nw] = 1/sqrt(leading gain)) and their application
 // to FP64 blocks [nw][k][N] (invert: divide).

@@ -404,6 +404,30 @@ int launch_freq_scale(const void* in, void* out, int64_t N, int k, int nw, const
   return 0;
 }
 
+// out[b][n] = in[b][n] * s[n] for `blocks` consecutive blocks of N values (diagonal B, C and metric scalings).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void node_scale_kernel(const cx<TI>* in, cx<TO>* out, const double* __restrict__ s,
+                                                         int64_t count, int64_t N) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+    const double w = s[e % N];
+    const cx<TI> v = in[e];
+    out[e] = mk<TO>((TO)(w * (double)v.re), (TO)(w * (double)v.im));
+  }
+}
+
+int launch_node_scale(const void* in, int in_fp64, void* out, int out_fp64, const double* s, int64_t blocks,
+                      int64_t N, hipStream_t st) {
+  const int64_t count = blocks * N;
+#define RES_NS(TI, TO) hipLaunchKernelGGL((node_scale_kernel<TI, TO>), dim3(grid1d(count)), dim3(256), 0, st, \
+                                          (const cx<TI>*)in, (cx<TO>*)out, s, count, N)
+  if (in_fp64 && out_fp64) RES_NS(double, double);
+  else if (in_fp64) RES_NS(double, float);
+  else if (out_fp64) RES_NS(float, double);
+  else RES_NS(float, float);
+#undef RES_NS
+  return 0;
+}
+
 int launch_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes % 4 != 0) return -1;
   const int64_t words = (int64_t)(bytes / 4);

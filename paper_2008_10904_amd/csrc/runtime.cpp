@@ -132,6 +132,10 @@ struct resolvent_op {
   hipStream_t cap_stream = nullptr;      // private stream for that capture (default priority)
   int plan_version = 0;                  // bumped by every stepper plan change
   int segs_dev_k = -1, segs_dev_version = -1;  // what the device copy of the regions describes
+  // diagonal B, C and metrics W_f, W_y (resolvent_op_set_weights): rows of d_wsc, each [N] FP64
+  bool weighted = false;
+  void* d_wsc = nullptr;
+  int scale_role = 0;                    // 0: apply/adjoint_apply (y = C R B f), 1: gains and modes (Euclidean R~)
   bool fp64() const { return prec == RES_FP64; }
   size_t wsize() const { return fp64() ? 16 : 8; }  // bytes per complex in working precision
 };
@@ -1026,10 +1030,41 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   return RES_OK;
 }
 
+// Rows of the diagonal scalings (resolvent_op_set_weights): input and output scales of a run by role and
+// direction, and the mode transforms.
+enum { kWscB = 0, kWscC, kWscCWy, kWscBInvWf, kWscBInvSqrtWf, kWscCSqrtWy, kWscInvSqrtWf, kWscInvSqrtWy, kWscSqrtWf,
+       kWscRows };
+
 int run_any(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
             hipStream_t st) {
-  return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);  // one driver; the march dispatches on the operator kind
+  if (!op->weighted) return run_1d(op, pl, k, in, in_fp64, acc, sigma, st);  // the march dispatches on the kind
+  // y = C R B f and R_y^dagger y = W_f^{-1} B R^H C W_y y (apply role); R~ = W_y^{1/2} C R B W_f^{-1/2} and R~^H
+  // (gains and modes)
+  int rin, rout;
+  if (op->scale_role == 0) {
+    rin = sigma > 0 ? kWscB : kWscCWy;
+    rout = sigma > 0 ? kWscC : kWscBInvWf;
+  } else {
+    rin = sigma > 0 ? kWscBInvSqrtWf : kWscCSqrtWy;
+    rout = sigma > 0 ? kWscCSqrtWy : kWscBInvSqrtWf;
+  }
+  const double* w = (const double*)op->d_wsc;
+  const int64_t blocks = (int64_t)pl.nw * k;
+  void* tmp;
+  RES_TRY(ws_get(op, "wsc_in", (size_t)blocks * op->N * sizeof(cd), &tmp));
+  launch_node_scale(in, in_fp64, tmp, 1, w + (size_t)rin * op->N, blocks, op->N, st);
+  RES_TRY(run_1d(op, pl, k, tmp, 1, acc, sigma, st));
+  launch_node_scale(acc, 1, acc, 1, w + (size_t)rout * op->N, blocks, op->N, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
 }
+
+// Gains and modes of the Euclidean R~ while in scope (no-op without weights).
+struct ModesRole {
+  resolvent_op* op;
+  ModesRole(resolvent_op* o) : op(o) { op->scale_role = 1; }
+  ~ModesRole() { op->scale_role = 0; }
+};
 
 // Marks the handle as capturing while the caller's stream records a graph.
 struct CaptureScope {
@@ -1460,6 +1495,17 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   return RES_OK;
 }
 
+// Force and response modes of the Euclidean R~ back to the problem's metrics: V <- W_f^{-1/2} V, U <- W_y^{-1/2} U
+// (outputs in working precision, in place).
+int modes_to_problem(resolvent_op* op, int nw, int k, void* V, void* U, hipStream_t st) {
+  const double* w = (const double*)op->d_wsc;
+  const int fp = op->fp64();
+  if (V) launch_node_scale(V, fp, V, fp, w + (size_t)kWscInvSqrtWf * op->N, (int64_t)nw * k, op->N, st);
+  if (U) launch_node_scale(U, fp, U, fp, w + (size_t)kWscInvSqrtWy * op->N, (int64_t)nw * k, op->N, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 }  // namespace
 
 // =====================================================================================================
@@ -1595,6 +1641,7 @@ void resolvent_op_destroy(resolvent_op* op) {
     if (op->d_band64[s]) (void)hipFree(op->d_band64[s]);
     if (op->d_bandm[s]) (void)hipFree(op->d_bandm[s]);
   }
+  if (op->d_wsc) (void)hipFree(op->d_wsc);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   if (op->d_off) (void)hipFree(op->d_off);
   if (op->xch) retired_exchange_areas().push_back(op->xch);  // uncached memory is not freed (see march_1d)
@@ -1683,7 +1730,10 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   const size_t gcount = (size_t)op->ninst * nw * k;
   RES_TRY(ws_get(op, "modes_gains", gcount * sizeof(double), &dg));
   if (hist) RES_TRY(ws_get(op, "modes_hist", (size_t)iters * gcount * 2 * sizeof(double), &dh));
+  ModesRole role(op);
   launch_convert(f0_hat, op->fp64(), Fh, 1, count, 1.0, st);
+  if (op->weighted)  // start forcings in the problem's coordinates: to the Euclidean R~'s (times W_f^{1/2})
+    launch_node_scale(Fh, 1, Fh, 1, (const double*)op->d_wsc + (size_t)kWscSqrtWf * op->N, (int64_t)nw * k, op->N, st);
   // Amplitude weights (iterations after the first): every run marches all frequencies superposed in one state, so
   // in the working precision the rounding of the large responses lands on the small ones.  The runs therefore
   // march frequency j with its input scaled by 1/sqrt(sigma_1(j)) from the previous iteration and unscale the
@@ -1784,6 +1834,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
                 (double*)dh + (size_t)(iters - 1) * gcount * 2, op->d_flag, st);
     HIP_TRY(hipMemcpyAsync(hist, dh, (size_t)iters * gcount * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   }
+  if (op->weighted) RES_TRY(modes_to_problem(op, nw, k, V, U, st));
   HIP_TRY(hipMemcpyAsync(gains, dg, gcount * sizeof(double), hipMemcpyDeviceToHost, st));
   return resolvent_op_check(op, stream);
 }
@@ -1853,7 +1904,11 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
     HIP_TRY(hipMemcpyAsync(one, ones.data(), gcount * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));  // the host vector goes out of scope
   }
+  ModesRole role(op);
   launch_convert(f0_hat, op->fp64(), blk(B, 0), 1, bsz, 1.0, st);
+  if (op->weighted)  // start forcings in the problem's coordinates: to the Euclidean R~'s (times W_f^{1/2})
+    launch_node_scale(blk(B, 0), 1, blk(B, 0), 1, (const double*)op->d_wsc + (size_t)kWscSqrtWf * N, (int64_t)nw * k, N,
+                      st);
   RES_TRY(cholqr2(op, nw, k, blk(B, 0), rq, nullptr, st));
   for (int i = 0; i < blocks; ++i) {
     double* W = blk(B, i + 1);  // the next block is built in place (the spare slot after the last one)
@@ -1904,6 +1959,7 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
     HIP_TRY(hipGetLastError());
   }
   if (hist) HIP_TRY(hipMemcpyAsync(hist, dh, (size_t)blocks * gcount * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (op->weighted) RES_TRY(modes_to_problem(op, nw, k, V, U, st));
   HIP_TRY(hipMemcpyAsync(gains, dg, gcount * sizeof(double), hipMemcpyDeviceToHost, st));
   return resolvent_op_check(op, stream);
 }
@@ -1915,6 +1971,7 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
   if (!op || !f_hat || !g_hat) return fail(RES_EINVAL, "NULL argument");
   if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
   if (checkpoint_every < 0) return fail(RES_EINVAL, "checkpoint_every must be >= 0");
+  if (op->weighted) return fail(RES_ENOTSUP, "the reverse mode does not take B, C or metric weights");
   Plan pl;
   RES_TRY(make_plan(op, grid, run, &pl));
   if (!f_grad && !mu_grad) return RES_OK;
@@ -1944,6 +2001,38 @@ int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]) {
   if (is_grid(op)) return fail(RES_ENOTSUP, "grid operators have no stepper plan");
   RES_TRY(apply_plan(op, plan[0], plan[1], plan[2], plan[3]));
   op->plan_default = false;
+  return RES_OK;
+}
+
+int resolvent_op_set_weights(resolvent_op* op, const double* b, const double* c, const double* wf,
+                             const double* wy) {
+  g_last_error.clear();
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  if (op->capturing) return fail(RES_EINVAL, "weights cannot change during graph capture");
+  const int64_t n = op->N;
+  if (!b && !c && !wf && !wy) {
+    op->weighted = false;
+    return RES_OK;
+  }
+  std::vector<double> h((size_t)kWscRows * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double bi = b ? b[i] : 1.0, ci = c ? c[i] : 1.0, fi = wf ? wf[i] : 1.0, yi = wy ? wy[i] : 1.0;
+    if (!std::isfinite(bi) || !std::isfinite(ci) || !(fi > 0) || !(yi > 0) || !std::isfinite(fi) ||
+        !std::isfinite(yi))
+      return fail(RES_EINVAL, "weights: b and c must be finite, wf and wy finite and positive");
+    h[(size_t)kWscB * n + i] = bi;
+    h[(size_t)kWscC * n + i] = ci;
+    h[(size_t)kWscCWy * n + i] = ci * yi;
+    h[(size_t)kWscBInvWf * n + i] = bi / fi;
+    h[(size_t)kWscBInvSqrtWf * n + i] = bi / std::sqrt(fi);
+    h[(size_t)kWscCSqrtWy * n + i] = ci * std::sqrt(yi);
+    h[(size_t)kWscInvSqrtWf * n + i] = 1.0 / std::sqrt(fi);
+    h[(size_t)kWscInvSqrtWy * n + i] = 1.0 / std::sqrt(yi);
+    h[(size_t)kWscSqrtWf * n + i] = std::sqrt(fi);
+  }
+  if (!op->d_wsc) HIP_TRY(hipMalloc(&op->d_wsc, h.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(op->d_wsc, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  op->weighted = true;
   return RES_OK;
 }
 

@@ -1,0 +1,126 @@
+"""GPU parity of diagonal B, C and metrics W_f, W_y (resolvent_op_set_weights) against the oracle's definitions on
+the same seeded inputs: observed applies y = C R B f and R_y^dagger y to 1e-10 per vector, the weighted adjoint
+identity on the GPU results, and gains of the power iteration and of the block Arnoldi (the Euclidean
+R~ = W_y^{1/2} C R B W_f^{-1/2}) to 1e-8 with W_f-orthonormal force modes."""
+import numpy as np
+import pytest
+
+from _helpers import gpu_tensor, mode_alignment, per_freq_relerr, say
+from oracle import iteration as O_it
+from oracle import krylov as O_kr
+from oracle import operators as O_ops
+from oracle import stepping as O_st
+from oracle import weights as O_w
+
+pytestmark = pytest.mark.gpu
+
+XL_T, XR_T = -15.0, 15.0
+N, H, P, PERIODS, STRIDE = 32, 0.05, 400, 10, 100
+
+
+def forcing(seed, nw, k, n):
+    g = np.random.default_rng(seed)
+    return g.standard_normal((nw, k, n)) + 1j * g.standard_normal((nw, k, n))
+
+
+def to_np(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def weights(seed):
+    g = np.random.default_rng(seed)
+    b = np.where(np.arange(N) < 3 * N // 4, 1.0, 0.0) * (0.5 + g.random(N))
+    c = np.where(np.arange(N) >= N // 4, 1.0, 0.0)
+    return b, c, 0.2 + g.random(N), 0.2 + g.random(N)
+
+
+def setup(precision="fp64"):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    lo, d, up = gl_coefficients(N, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    op = ResolventOp.tridiagonal(lo, d, up, H, precision=precision)
+    L, _ = O_ops.gl_operator(N, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    return op, L
+
+
+def test_weighted_applies_match_oracle():
+    import torch
+    say("case: weighted apply / adjoint apply")
+    op, L = setup()
+    b, c, wf, wy = weights(60)
+    op.set_weights(b, c, wf, wy)
+    nw, w0 = 3, -0.2
+    dw = 2 * np.pi / (P * H)
+    F, Y = forcing(61, nw, 2, N), forcing(62, nw, 2, N)
+    grid, run = op.grid(w0, dw, nw), op.run("periodic", periods=PERIODS, stride=STRIDE)
+    y = to_np(op.apply(gpu_tensor(F), grid, run))
+    z = to_np(op.adjoint_apply(gpu_tensor(Y), grid, run))
+    torch.cuda.synchronize()
+    a = lambda X: O_st.run(L, H, w0, dw, X, "periodic", periods=PERIODS, stride=STRIDE)
+    ad = lambda X: O_st.run(L, H, w0, dw, X, "periodic", periods=PERIODS, stride=STRIDE, adjoint=True)
+    ay, ady = O_w.observed_applies(a, ad, b, c, wf, wy)
+    e = (per_freq_relerr(y, ay(F)), per_freq_relerr(z, ady(Y)))
+    say("  errors", e)
+    assert max(e) < 1e-10
+    lhs = np.sum(np.conj(y) * wy * Y, axis=-1)
+    rhs = np.sum(np.conj(F) * wf * z, axis=-1)
+    assert np.abs(lhs - rhs).max() < 1e-10 * np.abs(lhs).max()
+    # clearing the weights restores the plain operator
+    op.set_weights()
+    y0 = to_np(op.apply(gpu_tensor(F), grid, run))
+    torch.cuda.synchronize()
+    assert per_freq_relerr(y0, a(F)) < 1e-10
+
+
+@pytest.mark.parametrize("algorithm", ["power", "krylov"])
+def test_weighted_gains_and_modes_match_oracle(algorithm):
+    import torch
+    say("case: weighted gains,", algorithm)
+    op, L = setup()
+    b, c, wf, wy = weights(63)
+    op.set_weights(b, c, wf, wy)
+    nw, k, w0 = 3, 2, 0.1
+    dw = 2 * np.pi / (P * H)
+    F0 = forcing(64, nw, k, N)
+    grid, run = op.grid(w0, dw, nw), op.run("periodic", periods=PERIODS, stride=STRIDE)
+    a, ad = O_it.stepped_applies(L, H, w0, dw, "periodic", periods=PERIODS, stride=STRIDE)
+    ae, ade = O_w.euclidean_applies(a, ad, b, c, wf, wy)
+    F0e = F0 * np.sqrt(wf)  # the library takes the start in the problem's coordinates
+    if algorithm == "power":
+        g_ref, V_ref, U_ref, _ = O_it.block_power_iteration(ae, ade, F0e, 4)
+        g, V, U, _ = op.modes(gpu_tensor(F0), grid, run, 4)
+    else:
+        g_ref, V_ref, U_ref, _ = O_kr.block_arnoldi(ae, ade, F0e, 4)
+        g, V, U, _ = op.krylov(gpu_tensor(F0), grid, run, 4)
+    torch.cuda.synchronize()
+    V_ref, U_ref = O_w.modes_from_euclidean(V_ref, U_ref, wf, wy)
+    say("  gains err", np.abs(g[0] / g_ref - 1).max())
+    assert np.abs(g[0] / g_ref - 1).max() < 1e-8
+    assert mode_alignment(to_np(V)[:, :1], V_ref[:, :1]) > 1 - 1e-8
+    assert mode_alignment(to_np(U)[:, :1], U_ref[:, :1]) > 1 - 1e-8
+    # force modes are W_f-orthonormal
+    Vn = to_np(V)
+    assert np.abs(np.sum(wf * np.abs(Vn[:, 0]) ** 2, axis=-1) - 1).max() < 1e-10
+
+
+def test_weights_errors_and_reverse_mode_refusal():
+    import torch
+    from paper_2008_10904_amd import ResolventError
+    from paper_2008_10904_amd import _lib as L_
+    say("case: weights errors")
+    op, _ = setup()
+    b, c, wf, wy = weights(65)
+    with pytest.raises(ResolventError) as e:
+        op.set_weights(b, c, -wf, wy)
+    assert e.value.code == L_.RES_EINVAL
+    with pytest.raises(ResolventError) as e:
+        op.set_weights(np.full(N, np.nan), c, wf, wy)
+    assert e.value.code == L_.RES_EINVAL
+    op.set_weights(b, c, wf, wy)
+    dw = 2 * np.pi / (P * H)
+    F = gpu_tensor(forcing(66, 2, 1, N))
+    grid, run = op.grid(0.0, dw, 2), op.run("periodic", periods=2, stride=STRIDE)
+    with pytest.raises(ResolventError) as e:
+        op.apply_backward(F, F, grid, run)
+    assert e.value.code == L_.RES_ENOTSUP
+    torch.cuda.synchronize()
