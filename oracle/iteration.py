@@ -68,6 +68,28 @@ def block_power_iteration(apply, adjoint_apply, F0, iters):
     return gains, V, U, hist
 
 
+def globally_scaled_power_iteration(apply, adjoint_apply, F0, iters):
+    """The power iteration without frequency normalisation, the unregularised scheme of Sec. 3: w = R^H R f is
+    handed back as the next forcing with one common scale for all frequencies, as a hand-off of the adjoint run's
+    time signal does (the scale only keeps the largest frequency's norm at 1).  One column per frequency
+    (F0 of shape (n_w, 1, N)).  Returns (gains (iters, n_w), amplitudes (iters, n_w)): the estimate
+    ||R f_j|| / ||f_j|| and the norm ||f_j|| of the forcing each iteration starts from."""
+    nw, k, N = F0.shape
+    if k != 1:
+        raise ValueError("one column per frequency")
+    F = np.array(F0, dtype=complex)
+    F /= np.linalg.norm(F, axis=2).max()
+    gains = np.zeros((iters, nw))
+    amps = np.zeros((iters, nw))
+    for n in range(iters):
+        amps[n] = np.linalg.norm(F[:, 0], axis=1)
+        Y = apply(F)
+        gains[n] = np.linalg.norm(Y[:, 0], axis=1) / amps[n]
+        W = adjoint_apply(Y)
+        F = W / np.linalg.norm(W, axis=2).max()
+    return gains, amps
+
+
 def dense_rk4_applies(L, h, omegas):
     """(apply, adjoint_apply) with the exact RK4 transfer matrices R_d(w_j) (see ``dense.resolvent_rk4``)."""
     from .dense import resolvent_rk4

@@ -8,6 +8,8 @@ interior nodes and homogeneous Dirichlet values just outside it.
 * ``gl_operator``      -- linearised Ginzburg-Landau  L = -nu d/dx + gamma d2/dx2 + mu(x)
                           (complex nu, gamma; the model family of Sec. 3 in the form with complex
                           coefficients used by the 1-D workloads).
+* ``paper_gl_operator`` -- the paper's own real Ginzburg-Landau model of Sec. 3 (U = 6, gamma = 1,
+                          mu(x) = beta mu_c (1 - x/20) on (0, 40)).
 * ``adr2d_operator``   -- 2-D advection-diffusion-reaction  L q = -U(y) q_x + Re^-1 lap q + (mu - s) q.
 * ``adr3d3c_operator`` -- 3-D three-component advection-diffusion with shear coupling
                           L (u,v,w) = (-U u_x - v U_y - w U_z, -U v_x, -U w_x) + Re^-1 lap + (mu - s).
@@ -67,6 +69,15 @@ def gl_batched_operator(instances, nu=GL_NU, gamma=GL_GAMMA, xl=-50.0, xr=50.0):
     """Block-diagonal L of independent GL instances, ``instances`` = list of (n, mu0, mu2)."""
     blocks = [gl_operator(n, mu0, mu2, nu, gamma, xl, xr)[0] for (n, mu0, mu2) in instances]
     return sp.block_diag(blocks, format="csr").astype(np.complex128)
+
+
+def paper_gl_operator(n, beta=0.1, U=6.0, gamma=1.0, length=40.0):
+    """The Ginzburg-Landau model of Sec. 3 (eq. GL_timeDomain): A = U d/dx - mu(x) - gamma d2/dx2 on (0, length)
+    with u = 0 at both ends, mu(x) = beta mu_c (1 - x/20) and mu_c = U^2 Re(gamma) / |gamma|^2.  All
+    coefficients are real.  Returns (L = -A as CSR complex128, x)."""
+    x, _ = uniform_interior_grid(n, 0.0, length)
+    mu_c = U * U * np.real(gamma) / abs(gamma) ** 2
+    return gl_operator(n, nu=U, gamma=gamma, xl=0.0, xr=length, mu=beta * mu_c * (1.0 - x / 20.0))
 
 
 # ----------------------------------------------------------------------------------------------

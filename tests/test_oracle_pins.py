@@ -469,3 +469,80 @@ def test_stepped_mu_gradient_of_diagonal_operator_matches_closed_form():
         dr = (q.deriv()(z) * (b - p(z)) + q(z) * p.deriv()(z)) / (b - p(z)) ** 2
         ref += np.real(np.sum(np.conj(G[j]) * h * dr * F[j], axis=0))
     assert np.abs(fd - ref).max() < 1e-7 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------------------------
+# The paper's own Ginzburg-Landau model (Sec. 3) and its normalisation ablation.
+# ---------------------------------------------------------------------------------------------
+def test_paper_gl_operator_matches_pde_on_smooth_function():
+    # U = 6, gamma = 1, mu_c = U^2 Re(gamma)/|gamma|^2 = 36, beta = 0.1 on (0, 40): L g must approach
+    # -6 g' + g'' + 3.6 (1 - x/20) g at second order in dx (g and g' vanish at both ends).
+    errs = []
+    for n in (200, 400):
+        L, x = operators.paper_gl_operator(n)
+        a = np.pi / 40.0
+        g = np.sin(a * x) ** 2
+        gp = a * np.sin(2 * a * x)
+        gpp = 2 * a * a * np.cos(2 * a * x)
+        exact = -6.0 * gp + gpp + 3.6 * (1.0 - x / 20.0) * g
+        errs.append(np.abs(L @ g - exact).max())
+    assert errs[0] < 1e-2 and 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_paper_gl_without_growth_has_the_real_toeplitz_spectrum():
+    # beta = 0: Dirichlet tridiagonal Toeplitz with sub 1/dx^2 + 3/dx, super 1/dx^2 - 3/dx and diagonal -2/dx^2.
+    # For dx < 1/3 the product of the off-diagonals is positive, so the spectrum
+    # -2/dx^2 + 2 sqrt((1/dx^2)^2 - 9/dx^2) cos(m pi/(n+1)) is real.  A short domain keeps the matrix only mildly
+    # non-normal (the off-diagonal ratio to the power n/2 is 2e5), so LAPACK's eigenvalues are accurate.
+    n = 30
+    L, x = operators.paper_gl_operator(n, beta=0.0, length=4.0)
+    dx = x[1] - x[0]
+    m = np.arange(1, n + 1)
+    ref = -2 / dx ** 2 + 2 * np.sqrt(1 / dx ** 4 - 9 / dx ** 2) * np.cos(m * np.pi / (n + 1))
+    got = np.linalg.eigvals(L.toarray())
+    assert np.abs(got.imag).max() < 1e-8 * np.abs(ref).max()
+    assert np.abs(np.sort(got.real) - np.sort(ref)).max() < 1e-8 * np.abs(ref).max()
+    assert np.abs(L.toarray().imag).max() == 0.0
+
+
+def test_globally_scaled_iteration_on_scalar_systems_closed_form():
+    # N = 1: R f = r_j f, so each estimate is |r_j| and under one common scale the amplitudes grow like |r_j|^{2n}:
+    # a_n(j) / a_n(0) = (|r_j| / |r_0|)^{2n} a_0(j) / a_0(0), with the largest kept at 1.
+    lam = -0.7 + 0.3j
+    om = np.array([0.0, 0.5, 2.0, 6.0])
+    r = 1.0 / (1j * om - lam)
+    apply = lambda F: F * r[:, None, None]
+    adj = lambda G: G * np.conj(r)[:, None, None]
+    g, amps = iteration.globally_scaled_power_iteration(apply, adj, forcing(70, 4, 1, 1), 6)
+    assert np.allclose(g, np.abs(r)[None, :], rtol=1e-13)
+    n = np.arange(6)[:, None]
+    ref = (np.abs(r)[None, :] / np.abs(r[0])) ** (2 * n) * (amps[0] / amps[0, 0])[None, :]
+    assert np.allclose(amps / amps[:, :1], ref, rtol=1e-12)
+    assert np.allclose(amps.max(axis=1), 1.0, rtol=1e-14)
+
+
+def test_unnormalised_iteration_saturates_on_the_paper_gl():
+    # Sec. 3: without per-frequency normalisation all frequencies share one time signal.  Once the ratio of the
+    # largest to the smallest spectral amplitude nears the inverse FP64 rounding unit, the small components drown
+    # in the rounding of the large ones: the ratio stops growing and the high-frequency estimates drift to the
+    # largest gain.  The same scheme on separate per-frequency transfer matrices keeps growing and converging, and
+    # the normalised iteration on the same shared march converges.
+    n = 200
+    L, _ = operators.paper_gl_operator(n)
+    dw, P = 5.0, 128  # frequencies 0, 5, 10, 15
+    h = 2 * np.pi / (P * dw)
+    om = dw * np.arange(4)
+    F0 = forcing(71, 4, 1, n)
+    a, ad = iteration.stepped_applies(L, h, 0.0, dw, "periodic", periods=12, stride=8)
+    da, dad = iteration.dense_rk4_applies(L, h, om)
+    gs, ams = iteration.globally_scaled_power_iteration(a, ad, F0, 7)
+    gd, amd = iteration.globally_scaled_power_iteration(da, dad, F0, 7)
+    exact = np.array([dense.gains_and_modes(dense.resolvent_rk4(L, w, h), 1)[0][0] for w in om])
+    cs, cd = ams.max(1) / ams.min(1), amd.max(1) / amd.min(1)
+    assert np.allclose(gs[:2], gd[:2], rtol=1e-6)            # amplitude ratio below 1e6: no loss yet
+    assert cd[-1] > 1e30 and cs.max() < 1e16                  # the shared march saturates
+    assert np.all(np.abs(gs[4:, 3] / exact[0] - 1) < 0.05)    # omega = 15 reads the largest gain
+    # normalised on the shared march: the same estimates as the unnormalised scheme on separate frequencies
+    hn = iteration.block_power_iteration(a, ad, F0, 7)[3]
+    assert np.allclose(hn[:, :, 0, 0], gd, rtol=1e-8)
+    assert np.abs(gd[-1, :3] / exact[:3] - 1).max() < 1e-3
