@@ -35,9 +35,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="gl_periodic_n2000",
-                    choices=["gl_periodic_n2000", "gl_batched_64", "adr2d_1024x512", "adr3d3c_256x128x128"],
-                    help="gl_periodic_n2000 (default, the headline line) or gl_batched_64 (64 uneven GL instances, "
-                         "mixed precision, reported beside its FP64 form)")
+                    choices=["gl_periodic_n2000", "gl_batched_64", "adr2d_1024x512", "adr3d3c_256x128x128",
+                             "gl_paper_n200"],
+                    help="gl_periodic_n2000 (default, the headline line), gl_batched_64 (64 uneven GL instances, "
+                         "mixed precision, reported beside its FP64 form), the 2-D and 3-D grid operators, or "
+                         "gl_paper_n200 (the paper's own real GL model of Sec. 3, with its power vs Arnoldi study)")
     ap.add_argument("--plan", default=None,
                     help="1-D stepper plan: 'tuned' (autotuner, cached per problem; tuning is set-up, not timed), "
                          "'default' (the library's default plan) or 'cfg,chunk,block,persist'.  Default: 'default' "
@@ -143,7 +145,10 @@ def cpu_baseline(cfg, w0, dw, F, seconds):
     """The oracle's explicit RK4 march of the same operator and forcing, timed for a bounded sample of steps."""
     import numpy as np
     from oracle import operators as O_ops
-    L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
+    if cfg["kind"] == "gl_paper":
+        L, _ = O_ops.paper_gl_operator(cfg["N"], cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    else:
+        L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
     om = w0 + dw * np.arange(cfg["n_omega"])
     from oracle.stepping import march
     march(L, cfg["h"], om, F, 3, lambda s: True, lambda s: False, 1.0)  # warm caches and BLAS threads
@@ -156,8 +161,8 @@ def cpu_baseline(cfg, w0, dw, F, seconds):
     sweeps = cfg["N"] * cfg["k"] * cfg["n_omega"] * n / dt
     threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or str(os.cpu_count())
     return dict(value=sweeps, unit="resolvent sweeps/s", cores=int(threads), kind="oracle",
-                sample="%d forced RK4 steps of the N=2000, k=4, 256-frequency periodic run (FP64 NumPy/SciPy), "
-                       "%.1f s" % (n, dt))
+                sample="%d forced RK4 steps of the N=%d, k=%d, %d-frequency periodic run (FP64 NumPy/SciPy), "
+                       "%.1f s" % (n, cfg["N"], cfg["k"], cfg["n_omega"], dt))
 
 
 def bench_batched(args):
@@ -409,6 +414,69 @@ def bench_krylov(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper(args):
+    """gl_paper_n200, the paper's own Ginzburg-Landau study (Sec. 3): N = 200, k = 1, 77 frequencies from 0 to 15,
+    periodic method with 2 periods of P = 3200 steps, FP64.  One step is one block-power iteration.  Beside it, the
+    paper's comparison after the same 15 direct and adjoint runs: one resolvent_modes call of 15 iterations and one
+    resolvent_krylov call of 15 blocks, with their omega = 15 gains and the change over their last run."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import paper_gl_coefficients
+
+    cfg = W.GL_PAPER
+    N, k, nw, P = cfg["N"], cfg["k"], cfg["n_omega"], cfg["P"]
+    steps_per_run = cfg["periods"] * P
+    F = W.random_forcing(cfg["seed"] + 1, nw, k, N)
+    sweeps_per_step = N * k * nw * 2 * steps_per_run
+    lo, d, up = paper_gl_coefficients(N, cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision="fp64")
+    if args.step_power:
+        op.set_step_power(args.step_power)
+    plan = choose_plan(op, k, args.plan)
+    grid = op.grid(cfg["w0"], cfg["dw"], nw)
+    run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+    f = torch.from_numpy(F).cuda()
+    dt, _, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
+    stepper_ms, stepper_n = kt["stepper"]
+    avg_launch_s = stepper_ms / 1e3 / max(stepper_n, 1)
+    steps_per_launch = 2 * steps_per_run * args.steps / max(stepper_n, 1)
+    achieved = STEP_FLOP_PER_UNKNOWN * N * k * steps_per_launch / avg_launch_s / 1e12
+    peak = FP64_VECTOR_PEAK / 1e12
+    n = cfg["iters"]
+    study = {"runs": n}
+    for name, call in (("power", lambda: op.modes(f, grid, run, n, want_modes=False)),
+                       ("arnoldi", lambda: op.krylov(f, grid, run, n, want_modes=False))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, _, _, hist = call()
+        torch.cuda.synchronize()
+        h15 = hist[..., 0] if name == "power" else hist
+        study[name] = {"seconds": time.perf_counter() - t0, "gain_omega0": float(g[0, 0, 0]),
+                       "gain_omega15": float(g[0, -1, 0]),
+                       "last_run_change_omega15": float(abs(h15[-1, 0, -1, 0] / h15[-2, 0, -1, 0] - 1))}
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)", "value": sweeps_per_step / dt, "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": N, "k": k, "n_omega": nw, "omega0": cfg["w0"], "domega": cfg["dw"],
+                   "P": P, "h": cfg["h"], "method": "periodic", "periods": cfg["periods"], "stride": cfg["stride"],
+                   "U": cfg["U"], "gamma": cfg["gamma"], "beta": cfg["beta"], "step": "one block-power iteration",
+                   "time_steps_per_step": 2 * steps_per_run},
+        "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n, "steps_per_launch": steps_per_launch},
+        "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
+        "stepper_plan": list(plan), "step_power": op.get_step_power(),
+        "power_vs_arnoldi_same_runs": study,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, cfg["w0"], cfg["dw"], F, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -427,6 +495,9 @@ def main():
         return
     if args.workload == "gl_batched_64":
         bench_batched(args)
+        return
+    if args.workload == "gl_paper_n200":
+        bench_paper(args)
         return
     if args.workload in ("adr2d_1024x512", "adr3d3c_256x128x128"):
         bench_grid(args)

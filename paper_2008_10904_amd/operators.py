@@ -5,7 +5,8 @@ These are the library's own builders (host NumPy, set-up only); they produce the
 
 * linearised Ginzburg-Landau  L = -nu d/dx + gamma d2/dx2 + mu(x),  mu(x) = (mu0 - c_mu^2) + mu2 x^2 / 2,
   second-order central differences on N interior nodes of [xl, xr] with u = 0 at both ends;
-* the same for a batch of independent instances placed back to back.
+* the same for a batch of independent instances placed back to back;
+* the paper's own real Ginzburg-Landau model of Sec. 3 (U = 6, gamma = 1, mu(x) = beta mu_c (1 - x/20) on (0, 40)).
 """
 import numpy as np
 
@@ -47,6 +48,14 @@ def gl_batched_coefficients(instances, nu=GL_NU, gamma=GL_GAMMA, xl=-50.0, xr=50
     offsets = np.zeros(len(instances) + 1, dtype=np.int64)
     offsets[1:] = np.cumsum([n for (n, _, _) in instances])
     return lower, diag, upper, offsets
+
+
+def paper_gl_coefficients(n, beta=0.1, U=6.0, gamma=1.0, length=40.0):
+    """Three-point coefficients of the Sec. 3 model L = -U d/dx + gamma d2/dx2 + mu(x), u(0) = u(length) = 0, with
+    mu(x) = beta mu_c (1 - x/20) and mu_c = U^2 Re(gamma)/|gamma|^2 (real coefficients, stored as complex)."""
+    x, _ = gl_nodes(n, 0.0, length)
+    mu_c = U * U * np.real(gamma) / abs(gamma) ** 2
+    return gl_coefficients(n, nu=U, gamma=gamma, xl=0.0, xr=length, mu=beta * mu_c * (1.0 - x / 20.0))
 
 
 def snap_grid(wmin, wmax, n_omega, h, stride=1):

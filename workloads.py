@@ -16,6 +16,10 @@ Workloads (the paper publishes no data set; every input is synthetic):
                     ``tests/golden/gl_batched_instances.json`` (see the script beside it).
 * ``ADR2D``         2-D advection-diffusion-reaction, 1024 x 512, complex64 state, U(y) = tanh(y), Re = 200,
                     128 frequencies in [0, 2], k = 2, transient method with a 300-time-unit tail.
+* ``GL_PAPER``      the paper's own real Ginzburg-Landau model (Sec. 3): U = 6, gamma = 1, beta = 0.1 on (0, 40),
+                    N = 200, 77 frequencies 0, 15/76, ..., 15 (the band of the paper's study), P = 3200 so that
+                    h = 2 pi 76 / (15 * 3200) = 0.00995 (the paper's step is 0.01), periodic method with 2 periods
+                    (the transient decays like exp(-4.8 t), 1e-66 after one period), k = 1.
 * ``ADR3D``         3-D three-component advection-diffusion with shear coupling, 256 x 128 x 128, FP32 state,
                     96 frequencies in [0, pi/2], k = 3, periodic method, checkpoints every 64 steps.
 
@@ -55,6 +59,10 @@ ADR2D = dict(name="adr2d_1024x512", kind="adr2d", nx=1024, ny=512, Re=200.0, h=0
              wmin=0.0, wmax=2.0, n_omega=128, method="transient", tail=15000, stride=1, periods=1,
              k=2, iters=10, precision="mixed", mu_base=-0.1, mu_amp=0.08, mu_xc=10.0, mu_w2=4.0,
              nu_s=1.0, seed=SEED_BASE + 3)
+
+GL_PAPER = dict(name="gl_paper_n200", kind="gl_paper", N=200, U=6.0, gamma=1.0, beta=0.1, length=40.0,
+                w0=0.0, dw=15.0 / 76, n_omega=77, P=3200, h=2 * math.pi * 76 / (15.0 * 3200), method="periodic",
+                periods=2, stride=32, tail=0, k=1, iters=15, precision="fp64", seed=SEED_BASE + 5)
 
 ADR3D = dict(name="adr3d3c_256x128x128", kind="adr3d3c", nx=256, ny=128, nz=128, Re=200.0, h=0.1,
              wmin=0.0, wmax=math.pi / 2, n_omega=96, method="periodic", periods=3, stride=1, tail=0,
