@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import dense, gradient, iteration, krylov, operators, stepping, weights
+from oracle import dense, gradient, iteration, krylov, operators, stepping, trm, weights
 
 # A small, stable GL problem on [-15, 15] (32 nodes) shared by several pins.
 N_T, XL_T, XR_T = 32, -15.0, 15.0
@@ -546,3 +546,126 @@ def test_unnormalised_iteration_saturates_on_the_paper_gl():
     hn = iteration.block_power_iteration(a, ad, F0, 7)[3]
     assert np.allclose(hn[:, :, 0, 0], gd, rtol=1e-8)
     assert np.abs(gd[-1, :3] / exact[:3] - 1).max() < 1e-3
+
+
+# ---------------------------------------------------------------------------------------------
+# Time-domain hand-off (Sec. 2.2, App. B, App. C).
+# ---------------------------------------------------------------------------------------------
+def test_interpolation_reproduces_polynomials():
+    # C0 is exact for lines, C1 (second-order derivatives) for quadratics and C2 (five-point derivatives) for
+    # quartics, away from the end samples where the one-sided rules apply.
+    n = 14
+    x = np.arange(n, dtype=float)
+    xq = np.linspace(0.0, n - 1.0, 157)
+    for scheme, deg, lo, hi in ((0, 1, 0, n - 1), (1, 2, 1, n - 2), (2, 4, 2, n - 3)):
+        c = np.random.default_rng(72 + scheme).standard_normal(deg + 1)
+        S = np.polyval(c, x)[:, None]
+        inner = (xq >= lo) & (xq <= hi)
+        got = trm.interpolate(S, xq[inner], scheme)[:, 0]
+        assert np.abs(got - np.polyval(c, xq[inner])).max() < 1e-10 * np.abs(S).max()
+        if scheme > 0:  # one degree more is not reproduced
+            c2 = np.append(c, 0.0) + np.eye(deg + 2)[0]
+            S2 = np.polyval(c2, x)[:, None]
+            assert np.abs(trm.interpolate(S2, xq[inner], scheme)[:, 0] - np.polyval(c2, xq[inner])).max() > 1e-6
+
+
+def test_interpolation_errors_per_points_per_cycle():
+    # App. C: errors of order 1e-2 need about 4.5 points per cycle (with C2); the error falls at second, third and
+    # fifth order in the sample spacing for C0, C1 and C2.
+    def err(ppc, scheme):
+        n = int(40 * ppc) + 1
+        s = np.exp(2j * np.pi * np.arange(n) / ppc)[:, None]
+        xq = np.linspace(10, n - 11, 1500)
+        return np.abs(trm.interpolate(s, xq, scheme)[:, 0] - np.exp(2j * np.pi * xq / ppc)).max()
+    assert 5e-3 < err(4.5, 2) < 5e-2
+    for scheme, order in ((0, 2), (1, 3), (2, 5)):
+        rate = err(9.0, scheme) / err(18.0, scheme)
+        assert abs(np.log2(rate) - order) < 0.35
+
+
+def test_interpolation_first_spurious_peak():
+    # App. C: a sinusoid sampled with p points per cycle and interpolated shows its first spurious spectral peak
+    # at p - 1 times its frequency (the image of the sampling frequency).
+    p, cycles, fine = 4, 64, 16
+    n = p * cycles + 1
+    s = np.cos(2 * np.pi * np.arange(n) / p)[:, None]
+    xq = np.arange((n - 1) * fine) / fine
+    spec = np.abs(np.fft.rfft(trm.interpolate(s, xq, 2)[:, 0]))
+    spec[cycles] = 0.0  # the signal itself
+    assert np.argmax(spec) == (p - 1) * cycles
+
+
+def test_signal_march_converges_to_the_scalar_closed_forms():
+    # du/dt = lam u + e^{iwt} from rest: u = (e^{iwt} - e^{lam t}) / (iw - lam); the adjoint -dz/dt = conj(lam) z
+    # + e^{iwt}, z(T) = 0: z = (e^{(conj(lam) + iw) T - conj(lam) t} - e^{iwt}) / (conj(lam) + iw).  With C2
+    # stage forcing the error falls at third order: the first-order one-sided derivative at the end samples (App. C)
+    # costs one order against RK4's fourth when the forcing does not vanish there.
+    lam, w, Tend = -0.8 + 1.3j, 2.0, 4.0
+    L1 = sp.csr_matrix(np.array([[lam]]))
+    errs = []
+    for h in (0.04, 0.02):
+        every = 2
+        n = int(round(Tend / (every * h))) + 1
+        t = every * h * np.arange(n)
+        F = np.exp(1j * w * t)[:, None, None]
+        u = trm.march_signal(L1, h, F, every, 2)[:, 0, 0]
+        z = trm.march_signal(L1, h, F, every, 2, adjoint=True)[:, 0, 0]
+        lb = np.conj(lam)
+        u_ex = (np.exp(1j * w * t) - np.exp(lam * t)) / (1j * w - lam)
+        z_ex = (np.exp((lb + 1j * w) * Tend - lb * t) - np.exp(1j * w * t)) / (lb + 1j * w)
+        errs.append((np.abs(u - u_ex).max(), np.abs(z - z_ex).max()))
+    for a, b in zip(errs[0], errs[1]):
+        assert a < 1e-4 and 6.5 < a / b < 9.5
+
+
+def test_fir_design_of_a_flat_response_is_a_delta():
+    # A unit response sampled on a whole period inverts to a unit impulse at the centre, where the Hamming window
+    # is one: the filter is the identity.
+    b = trm.fir_design(40, np.array([-1.0, 1.0]), np.array([1.0, 1.0]))
+    ref = np.zeros(41)
+    ref[20] = 1.0
+    assert np.abs(b - ref).max() < 1e-13
+
+
+def test_fir_design_is_linear_phase_and_follows_the_response():
+    # App. B: a response symmetric in frequency gives real, symmetric taps (linear phase, delay n/2); with the
+    # delay removed the filter approximates the desired amplitudes where they vary slowly on its resolution.
+    order = 200
+    nu = np.linspace(-1, 1, 41)
+    D = np.exp(-(nu / 0.3) ** 2)
+    b = trm.fir_design(order, nu, D)
+    assert np.abs(b.imag).max() < 1e-14 and np.abs(b - b[::-1]).max() < 1e-14
+    nq = np.linspace(-0.8, 0.8, 33)
+    assert np.abs(trm.fir_response(b, nq) - np.interp(nq, nu, D)).max() < 1e-2
+
+
+def test_fir_apply_multiplies_an_exponential_by_the_response():
+    # y_t = sum_m b_m x_{t+n/2-m}: away from the ends, x_t = e^{i pi nu t} leaves as H(nu) x_t exactly.
+    b = trm.fir_design(30, np.array([-1.0, -0.2, 0.4, 1.0]), np.array([0.1, 1.0, 0.3, 0.0]))
+    T, nu = 200, 0.37
+    x = np.exp(1j * np.pi * nu * np.arange(T))[:, None, None] * np.array([1.0, 2.0 - 1.0j])[None, :, None]
+    y = trm.fir_apply(b, x)
+    H = trm.fir_response(b, nu)[0]
+    assert np.abs(y[15:T - 15] - H * x[15:T - 15]).max() < 1e-13
+
+
+def test_trm_power_iteration_with_flattening_on_the_paper_gl():
+    # Sec. 2.2, Sec. 3: with the flattening filter the spectral amplitudes stay within a small ratio and the gains
+    # at omega = 0, 5, 10, 15 converge to the continuous resolvent's; without it the ratio grows with the squared
+    # gain ratio (1e6) per iteration until the window's leakage floor, five orders of magnitude above.
+    n_x = 200
+    L, _ = operators.paper_gl_operator(n_x)
+    h, every, n = 0.01, 4, 1501
+    dt = every * h
+    om = np.linspace(-15, 15, 61)
+    sel = [30, 40, 50, 60]
+    ex = np.array([dense.gains_and_modes(dense.resolvent(L, w), 1)[0][0] for w in om[sel]])
+    F0 = forcing(73, n, 1, n_x)
+    kw = dict(order=600, pad=int(12 / dt), ramp=int(6 / dt), margin=3.0, passes=2)
+    g, amps, _ = trm.trm_power_iteration(L, h, every, 2, F0, om, 6, **kw)
+    ratio = amps.max(1) / amps.min(1)
+    assert ratio[1:].max() < 20
+    err = np.abs(g[-1, sel] / ex - 1)
+    assert err[:3].max() < 1e-3 and err[3] < 2e-2  # omega = 15: sigma_2 / sigma_1 = 0.8, slow power convergence
+    _, amps_u, _ = trm.trm_power_iteration(L, h, every, 2, F0, om, 3, flatten=False, **kw)
+    assert (amps_u.max(1) / amps_u.min(1))[-1] > 1e5
