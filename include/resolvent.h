@@ -246,6 +246,61 @@ enum { RES_TIMING_STEPPER = 0, RES_TIMING_SYNTHESIS = 1, RES_TIMING_PROJECTION =
 int resolvent_op_set_timing(resolvent_op* op, int32_t enable);
 int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, int64_t* launches);
 
+/* ---- Transient-response method with time-domain hand-off (Sec. 2.2, App. B, App. C) ----------------------------
+ * A signal is a series of samples [n_samples][k][N] (caller-owned device memory, complex128 for RES_FP64 handles,
+ * complex64 for RES_MIXED ones, interleaved): sample i is the signal at t_i = i * every * h.
+ *
+ * resolvent_signal_run: the run of a RES_OP_TRIDIAG operator forced by a sampled signal, from rest (Sec. 2.2,
+ * eqs. system and adsystem with B = C = I).  adjoint = 0: du/dt = L u + f(t), u(0) = 0; y receives u(t_i).
+ * adjoint = 1: -dz/dt = L^H z + f(t) backward in time from z(T) = 0, T = (n_samples - 1) every h; y receives
+ * z(t_i).  Classical RK4 with step h; each stage is forced by the signal at its own time, interpolated between
+ * samples (App. C) by scheme 0 (C0, linear), 1 (C1, cubic Hermite on second-order central derivatives, first-order
+ * one-sided at the end samples) or 2 (C2, quintic Hermite on five-point first and second derivatives;
+ * second-order at the samples next to the ends, first-order first derivative and zero second derivative at the end
+ * samples).  f and y must not alias.  RES_ENOTSUP for grid operators and while weights are set; RES_EINVAL for
+ * k < 1, n_samples < 2, every < 1 or an unknown scheme.  Asynchronous on `stream`.
+ *
+ * resolvent_fir_design: a linear-phase FIR filter of even order n (n + 1 taps, App. B) approximating a desired
+ * amplitude response given at npts breakpoints nu (non-decreasing in [-1, 1]: frequency over the Nyquist
+ * frequency pi / dt, negative frequencies included; linear between breakpoints, the end values beyond them) with
+ * gains >= 0: the response sampled on M = 2 max(512, 2^ceil(log2 n)) uniform frequencies nu_q = -1 + 2q/M,
+ * transformed back with an n/2-sample delay and multiplied by a Hamming window,
+ *     b_m = (0.54 - 0.46 cos(2 pi m / n)) (1/M) sum_q D(nu_q) e^{i pi nu_q (m - n/2)}.
+ * A response symmetric in nu gives real taps.  Host only: taps receives n + 1 complex128 (2 (n + 1) doubles,
+ * caller-owned host memory).  RES_EINVAL for an odd order, order < 2 or beyond the limit of resolvent_fir_apply,
+ * or malformed breakpoints.
+ *
+ * resolvent_fir_apply: y[t][c] = sum_{m=0}^{n} b[m] x[t + n/2 - m][c] for t < n_t, c < ncols (x = 0 outside
+ * [0, n_t)): the filter with its delay removed, so a complex exponential of frequency nu leaves multiplied by
+ * H(nu) = sum_m b_m e^{-i pi nu (m - n/2)}.  taps: device complex128 [order + 1]; x, y: device [n_t][ncols],
+ * complex128 if fp64 else complex64, not aliased.  Order even, 0 <= order <= 4094.  Asynchronous on `stream`.
+ *
+ * resolvent_trm_modes: the power iteration with time-domain hand-off (Sec. 2.2 and App. A).  Starting from the
+ * sampled forcing f0 (tapered: zero on the first and last `pad` samples, raised-cosine ramps of `ramp` samples,
+ * one between; then normalised), each of `iters` iterations
+ *   1. runs the direct signal run of the forcing F and the adjoint signal run forced by its response Y, giving W;
+ *   2. transforms F, Y and W at the n_omega analysis frequencies omegas (host array, any values with
+ *      |w| every h <= pi): X(w) = dt sum_i x_i e^{-i w t_i}, dt = every h, and writes
+ *      gains[it][j] = ||Y(w_j)|| / ||F(w_j)|| and (if amps is not NULL) amps[it][j] = ||F(w_j)||, norms over all
+ *      k N values of the frequency;
+ *   3. flattens W (App. B): `passes` passes of the FIR filter of order `order` designed for
+ *      (1/||W(w_j)||)^(1/passes) at the analysis frequencies (largest 1), falling linearly to zero `margin`
+ *      rad per time unit outside them and zero beyond (passes = 0: no filter);
+ *   4. hands the result back, tapered and normalised, as the next F.
+ * f_out (device, may be NULL) receives the last F.  The flattening response spans the square of the gain range,
+ * more than one windowed filter realises when gains differ by 1e3 (passes = 2 realises 1e6).  Synchronises
+ * `stream` every iteration and cannot be captured.  Errors as resolvent_signal_run, and RES_EINVAL for
+ * n_omega < 1, iters < 1, a bad order, a taper that leaves no sample at one or frequencies beyond Nyquist. */
+int resolvent_signal_run(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
+                         int32_t adjoint, const void* f, void* y, void* stream);
+int resolvent_fir_design(int32_t order, int32_t npts, const double* nu, const double* gain, double* taps);
+int resolvent_fir_apply(int32_t fp64, int64_t n_t, int64_t ncols, int32_t order, const double* taps, const void* x,
+                        void* y, void* stream);
+int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
+                        const void* f0, int32_t n_omega, const double* omegas, int32_t iters, int32_t order,
+                        int32_t passes, int64_t pad, int64_t ramp, double margin, double* gains, double* amps,
+                        void* f_out, void* stream);
+
 /* Synchronise `stream` and report RES_ENONFINITE if any result produced since the last check held NaN/Inf. */
 int resolvent_op_check(resolvent_op* op, void* stream);
 

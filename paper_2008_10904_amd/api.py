@@ -306,3 +306,74 @@ class ResolventOp:
 
     def check(self):
         check(self._lib.resolvent_op_check(self._h, self._stream_ptr()))
+
+    # ---- transient-response method with time-domain hand-off ----------------------------------------------------
+    _SCHEMES = {"C0": 0, "C1": 1, "C2": 2}
+
+    def _check_series(self, x):
+        torch = _torch()
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.cdtype and x.is_contiguous()):
+            raise TypeError("expected a contiguous %s CUDA tensor" % self.cdtype)
+        if x.dim() != 3 or x.shape[2] != self.n:
+            raise ValueError("expected shape (n_samples, k, N) with N = %d, got %s" % (self.n, tuple(x.shape)))
+
+    def signal_run(self, f, every, scheme="C2", adjoint=False, out=None):
+        """State samples [n, k, N] of the run forced by the samples f [n, k, N] (sample i at t = i every h), from
+        rest; adjoint=True runs -dz/dt = L^H z + f backward from z(T) = 0.  scheme: "C0", "C1" or "C2"."""
+        torch = _torch()
+        self._check_series(f)
+        if out is None:
+            out = torch.empty_like(f)
+        check(self._lib.resolvent_signal_run(self._h, int(f.shape[1]), int(f.shape[0]), int(every),
+                                             self._SCHEMES[scheme], 1 if adjoint else 0, ctypes.c_void_p(f.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), self._stream_ptr()))
+        return out
+
+    def trm_modes(self, f0, omegas, iters, every, scheme="C2", order=600, passes=2, pad=0, ramp=0, margin=0.0,
+                  want_forcing=False):
+        """Power iteration with time-domain hand-off and FIR flattening (resolvent_trm_modes).  Returns (gains
+        [iters, n_omega], amplitudes [iters, n_omega], last forcing [n, k, N] or None)."""
+        torch = _torch()
+        self._check_series(f0)
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+        gains = np.zeros((int(iters), len(om)))
+        amps = np.zeros((int(iters), len(om)))
+        fo = torch.empty_like(f0) if want_forcing else None
+        check(self._lib.resolvent_trm_modes(
+            self._h, int(f0.shape[1]), int(f0.shape[0]), int(every), self._SCHEMES[scheme],
+            ctypes.c_void_p(f0.data_ptr()), len(om), _dptr(om), int(iters), int(order), int(passes), int(pad),
+            int(ramp), float(margin), _dptr(gains), _dptr(amps),
+            ctypes.c_void_p(fo.data_ptr()) if fo is not None else None, self._stream_ptr()))
+        return gains, amps, fo
+
+
+def fir_design(order, nu, gain):
+    """Taps (complex128, order + 1) of the linear-phase FIR filter for the amplitudes `gain` at breakpoints `nu`
+    (frequency over Nyquist, non-decreasing in [-1, 1]); host computation in the library."""
+    lib = _lib.load()
+    nu = np.ascontiguousarray(np.asarray(nu, dtype=np.float64))
+    gain = np.ascontiguousarray(np.asarray(gain, dtype=np.float64))
+    if nu.shape != gain.shape:
+        raise ValueError("nu and gain must have the same length")
+    taps = np.zeros(int(order) + 1, dtype=np.complex128)
+    out = taps.view(np.float64)
+    check(lib.resolvent_fir_design(int(order), len(nu), _dptr(nu), _dptr(gain), _dptr(out)))
+    return taps
+
+
+def fir_apply(taps, x, out=None):
+    """Delay-compensated FIR filtering along the first axis of the CUDA tensor x [n_t, ...] (complex128 or
+    complex64) with complex taps (order + 1, even order)."""
+    torch = _torch()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.is_contiguous()
+            and x.dtype in (torch.complex128, torch.complex64)):
+        raise TypeError("expected a contiguous complex CUDA tensor")
+    t = torch.as_tensor(np.asarray(taps, dtype=np.complex128)).to(x.device).contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    ncols = int(x.numel() // x.shape[0])
+    check(_lib.load().resolvent_fir_apply(1 if x.dtype == torch.complex128 else 0, int(x.shape[0]), ncols,
+                                          int(t.numel()) - 1, ctypes.c_void_p(t.data_ptr()),
+                                          ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return out

@@ -132,6 +132,26 @@ int launch_convert(const void* x, int in_fp64, void* y, int out_fp64, int64_t co
 int launch_node_scale(const void* in, int in_fp64, void* out, int out_fp64, const double* s, int64_t blocks,
                       int64_t N, hipStream_t st);
 int launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: a multiple of 4
+
+// ---- transient-response method with time-domain hand-off (trm.hip) ------------------------------------------
+// Stage-forcing pre-filter of a run forced by a sampled signal S [n][ncols] (working precision, sample i at step
+// i*every, read reversed if rev): pass 0 and 1 write FP64 xout, pass 2 the forcing rows g (working precision) of
+// steps s0 .. s0 + rows - 1.  scheme: 0 linear, 1 cubic Hermite, 2 quintic Hermite.
+int launch_signal_prefilter(const void* S, int64_t n, int every, int scheme, int rev, const cx<double>* tri,
+                            const void* xin, void* xout, void* g, int fp64, int64_t s0, int64_t rows, int64_t N,
+                            int64_t ncols, double h, int pass, hipStream_t st);
+int launch_copy_rows(const void* src, int64_t src_ld, void* dst, int64_t row0, int dir, int64_t rows, int64_t ncols,
+                     int fp64, hipStream_t st);
+int fir_max_order();
+// y = delay-compensated FIR of x along time (taps FP64 complex [order+1] on the device), times the taper of
+// `pad`/`ramp` samples (pad < 0: none).  Returns -1 for an order beyond fir_max_order().
+int launch_fir(const cx<double>* taps, int order, const void* x, void* y, int64_t Tn, int64_t ncols, int64_t pad,
+               int64_t ramp, int fp64, hipStream_t st);
+int launch_series_dft(const void* x, int fp64, int64_t Tn, int64_t ncols, const double* omegas, int nw, double dt,
+                      void* out, hipStream_t st);
+int launch_row_norms(const void* X, int64_t nrows, int64_t ncols, double* norms, hipStream_t st);
+int normalise_parts();
+int launch_normalise(void* x, int fp64, int64_t count, double* part, double* scale, hipStream_t st);
 // Amplitude weights of the block power iteration (fac[ninst][nw] = 1/sqrt(leading gain)) and their application
 // to FP64 blocks [nw][k][N] (invert: divide).
 int launch_freq_weights(const double* gains, double* fac, int ninst, int nw, int k, hipStream_t st,

@@ -1,0 +1,192 @@
+"""GPU parity of the transient-response method with time-domain hand-off (Sec. 2.2, App. B, App. C) against the
+CPU oracle on the same seeded inputs:
+
+* resolvent_signal_run: direct and adjoint runs forced by a sampled signal, for the C0, C1 and C2 interpolation
+  schemes, in FP64 (1e-10 per sample vector) and mixed precision (1e-3), on a complex GL operator; batched
+  instances; forcing rows in many small tiles; multi-workgroup stepper plans;
+* resolvent_fir_apply: FP64 (1e-12) and mixed (1e-5), ragged column blocks, an order longer than the series, the
+  identity filter;
+* resolvent_trm_modes: the power iteration with FIR flattening on the paper's GL model, gains per iteration and the
+  last forcing against the oracle's trm_power_iteration (1e-8 FP64; mixed 5e-3 on gains, 2e-2 on the spectral
+  amplitudes of the FP32 samples), and without the filter;
+* argument errors.
+"""
+import numpy as np
+import pytest
+
+from _helpers import gpu_tensor, say
+from oracle import operators as O_ops
+from oracle import trm as O_trm
+
+pytestmark = pytest.mark.gpu
+
+XL_T, XR_T = -15.0, 15.0
+SCHEMES = {"C0": 0, "C1": 1, "C2": 2}
+
+
+def series(seed, n, k, N):
+    g = np.random.default_rng(seed)
+    return g.standard_normal((n, k, N)) + 1j * g.standard_normal((n, k, N))
+
+
+def to_np(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def per_sample_relerr(A, B):
+    """max over samples and columns of ||A[i, c] - B[i, c]|| / max_i ||B[i, c]||."""
+    d = np.linalg.norm(A - B, axis=-1)
+    s = np.linalg.norm(B, axis=-1).max(axis=0)
+    return float((d / np.maximum(s, 1e-300)[None, :]).max())
+
+
+def gl_op(n, h, precision="fp64"):
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    lo, d, up = gl_coefficients(n, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    return ResolventOp.tridiagonal(lo, d, up, h, precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("scheme", ["C0", "C1", "C2"])
+def test_signal_run_matches_oracle(scheme, precision):
+    import torch
+    say("case: signal run", scheme, precision, "GL N = 37, k = 2, 41 samples every 3 steps")
+    n_x, h, every, n = 37, 0.05, 3, 41
+    L, _ = O_ops.gl_operator(n_x, 0.2, -0.01, xl=XL_T, xr=XR_T)
+    F = series(80, n, 2, n_x)
+    op = gl_op(n_x, h, precision)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    tol = 1e-10 if precision == "fp64" else 1e-3
+    for adjoint in (False, True):
+        y = to_np(op.signal_run(gpu_tensor(F, dt), every, scheme, adjoint=adjoint))
+        torch.cuda.synchronize()
+        ref = O_trm.march_signal(L, h, F, every, SCHEMES[scheme], adjoint=adjoint)
+        e = per_sample_relerr(y, ref)
+        say("  adjoint" if adjoint else "  direct", e)
+        assert e < tol
+        assert np.abs(y[-1 if adjoint else 0]).max() == 0.0  # the run starts from rest
+
+
+def test_signal_run_batched_tiles_and_plans(monkeypatch):
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_batched_coefficients
+    inst = [(50, 0.2, -0.01), (37, 0.15, -0.02), (33, 0.12, -0.012)]
+    h, every, n = 0.05, 2, 30
+    lo, d, up, off = gl_batched_coefficients(inst, xl=XL_T, xr=XR_T)
+    F = series(81, n, 2, int(off[-1]))
+    refs = {}
+    for m, (nn, mu0, mu2) in enumerate(inst):
+        L, _ = O_ops.gl_operator(nn, mu0, mu2, xl=XL_T, xr=XR_T)
+        sl = slice(int(off[m]), int(off[m + 1]))
+        refs[m] = (O_trm.march_signal(L, h, F[:, :, sl], every, 2),
+                   O_trm.march_signal(L, h, F[:, :, sl], every, 2, adjoint=True))
+    # one-interval forcing tiles (a 1 KiB budget), default plan; then halo plans (relaunch and persistent)
+    for plan, budget in ((None, "0.000001"), ("1,40,4,0", None), ("13,64,16", None)):
+        say("case: batched signal run, plan", plan, "tile budget", budget)
+        if plan:
+            monkeypatch.setenv("RESOLVENT_STEP1D", plan)
+        else:
+            monkeypatch.delenv("RESOLVENT_STEP1D", raising=False)
+        if budget:
+            monkeypatch.setenv("RESOLVENT_TILE_BUDGET_GB", budget)
+        else:
+            monkeypatch.delenv("RESOLVENT_TILE_BUDGET_GB", raising=False)
+        op = ResolventOp.tridiagonal(lo, d, up, h, offsets=off)
+        y = to_np(op.signal_run(gpu_tensor(F), every, "C2"))
+        z = to_np(op.signal_run(gpu_tensor(F), every, "C2", adjoint=True))
+        torch.cuda.synchronize()
+        for m in range(len(inst)):
+            sl = slice(int(off[m]), int(off[m + 1]))
+            e = (per_sample_relerr(y[:, :, sl], refs[m][0]), per_sample_relerr(z[:, :, sl], refs[m][1]))
+            say("  instance", m, e)
+            assert max(e) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fir_apply_matches_oracle(precision):
+    import torch
+    from paper_2008_10904_amd.api import fir_apply, fir_design
+    say("case: FIR apply", precision)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for T, cols, order in ((300, 70, 64), (300, 70, 400), (129, 3, 0), (1000, 130, 600)):
+        X = series(82 + order, T, 1, cols)
+        if order == 0:
+            b = np.array([0.5 - 0.25j])
+        else:
+            b = fir_design(order, [-1.0, -0.3, 0.1, 0.6, 1.0], [0.0, 1.0, 0.2, 1.0, 0.0])
+        y = to_np(fir_apply(b, gpu_tensor(X, dt)))
+        torch.cuda.synchronize()
+        ref = O_trm.fir_apply(b, X)
+        e = np.abs(y - ref).max() / np.abs(ref).max()
+        say("  T = %d, cols = %d, order = %d:" % (T, cols, order), e)
+        assert e < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trm_modes_match_oracle(precision):
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import paper_gl_coefficients
+    say("case: TRM power iteration with flattening,", precision, "paper GL N = 200, 751 samples")
+    n_x, h, every, n = 200, 0.01, 4, 751
+    dtau = every * h
+    om = np.linspace(-15, 15, 31)
+    kw = dict(order=300, passes=2, pad=int(6 / dtau), ramp=int(3 / dtau), margin=3.0)
+    F0 = series(84, n, 1, n_x)
+    L, _ = O_ops.paper_gl_operator(n_x)
+    g_ref, a_ref, f_ref = O_trm.trm_power_iteration(L, h, every, 2, F0, om, 3, **kw)
+    lo, d, up = paper_gl_coefficients(n_x)
+    op = ResolventOp.tridiagonal(lo, d, up, h, precision=precision)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    g, a, f = op.trm_modes(gpu_tensor(F0, dt), om, 3, every, "C2", want_forcing=True, **kw)
+    torch.cuda.synchronize()
+    eg, ea = np.abs(g / g_ref - 1).max(), np.abs(a / a_ref - 1).max()
+    ef = per_sample_relerr(to_np(f), f_ref)
+    say("  gains", eg, "amplitudes", ea, "last forcing", ef)
+    # Mixed precision keeps the samples in FP32.  The adjoint output spans the squared gain range (1e6 here), so its
+    # smallest spectral components carry FP32 rounding of the largest, about 1e-2 relative; the flattening then
+    # lifts them.  The gains (ratios of run outputs) stay within a few 1e-3.
+    tol = 1e-8 if precision == "fp64" else 5e-3
+    assert eg < tol and max(ea, ef) < (1e-8 if precision == "fp64" else 2e-2)
+    # without the filter (passes = 0) the forcing is the tapered adjoint output
+    g0, _, _ = op.trm_modes(gpu_tensor(F0, dt), om, 2, every, "C2", order=0, passes=0, pad=kw["pad"],
+                            ramp=kw["ramp"])
+    g0_ref = O_trm.trm_power_iteration(L, h, every, 2, F0, om, 2, flatten=False, **kw)[0]
+    torch.cuda.synchronize()
+    say("  unfiltered gains", np.abs(g0 / g0_ref - 1).max())
+    assert np.abs(g0 / g0_ref - 1).max() < (1e-8 if precision == "fp64" else 2e-2)
+
+
+def test_trm_errors():
+    import torch
+    from paper_2008_10904_amd import ResolventError, ResolventOp
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.api import fir_apply
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    say("case: TRM argument errors")
+    op = gl_op(20, 0.05)
+    F = gpu_tensor(series(85, 10, 1, 20))
+    for kw in (dict(every=0), dict(every=2, scheme="C3")):
+        with pytest.raises((ResolventError, KeyError)):
+            op.signal_run(F, **kw)
+    with pytest.raises(ResolventError) as e:
+        op.signal_run(F, 2, out=F)
+    assert e.value.code == L.RES_EINVAL
+    with pytest.raises(ResolventError) as e:
+        op.trm_modes(F, [0.0, 1.0], 1, 2, pad=3, ramp=2)  # the taper leaves no sample at one
+    assert e.value.code == L.RES_EINVAL
+    with pytest.raises(ResolventError) as e:
+        op.trm_modes(F, [0.0, 1000.0], 1, 2)  # beyond Nyquist
+    assert e.value.code == L.RES_EINVAL
+    with pytest.raises(ResolventError) as e:
+        fir_apply(np.ones(4), F)  # odd order
+    assert e.value.code == L.RES_EINVAL
+    c = adr2d_coefficients(16, 8)
+    gop = ResolventOp.grid_operator("adr2d", 16, 8, 1, c, 0.02, precision="mixed")
+    with pytest.raises(ResolventError) as e:
+        gop.signal_run(gpu_tensor(series(86, 4, 1, 128), torch.complex64), 2)
+    assert e.value.code == L.RES_ENOTSUP
+    torch.cuda.synchronize()
