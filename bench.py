@@ -48,9 +48,11 @@ def parse():
     ap.add_argument("--step-power", type=int, default=None, choices=[1, 2, 4],
                     help="1-D workloads: RK4 steps per kernel step (band P(Z)^m and the combined forcing of m "
                          "steps); default: the library's default (4)")
-    ap.add_argument("--algorithm", default="power", choices=["power", "krylov"],
+    ap.add_argument("--algorithm", default="power", choices=["power", "krylov", "trm"],
                     help="gl_periodic_n2000: 'power' (block power iteration, the headline line) or 'krylov' (block "
-                         "Arnoldi with --krylov-blocks blocks of k forcings; one step = one call)")
+                         "Arnoldi with --krylov-blocks blocks of k forcings; one step = one call); gl_paper_n200: "
+                         "'trm' (transient-response method with time-domain hand-off and FIR flattening; one step = "
+                         "one iteration)")
     ap.add_argument("--krylov-blocks", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
@@ -477,6 +479,115 @@ def bench_paper(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_trm(args):
+    """gl_paper_trm_n200: the transient-response method with time-domain hand-off on the paper's GL model at its
+    own settings (h = 0.01 sampled every step, FIR order 3000 in two passes, 61 analysis frequencies in [-15, 15],
+    6001 samples).  One step is one iteration: the direct and adjoint signal runs (6000 RK4 steps each), the
+    spectra of F, Y and W, the filter design (host) and the two filter passes.  The roofline object is that of the
+    kernel with the larger share of the device time, the FIR filter or the stepper, timed with HIP events on the
+    stream it runs on."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.api import fir_apply, fir_design
+    from paper_2008_10904_amd.operators import paper_gl_coefficients
+
+    cfg = W.GL_PAPER_TRM
+    N, k, n, every = cfg["N"], cfg["k"], cfg["n_samples"], cfg["every"]
+    om = np.linspace(-cfg["wmax"], cfg["wmax"], cfg["n_omega"])
+    steps_per_run = (n - 1) * every
+    sweeps_per_step = N * k * cfg["n_omega"] * 2 * steps_per_run
+    lo, d, up = paper_gl_coefficients(N, cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision="fp64")
+    F0 = W.random_forcing(cfg["seed"], n, k, N)
+    f0 = torch.from_numpy(F0).cuda()
+    kw = dict(order=cfg["order"], passes=cfg["passes"], pad=cfg["pad"], ramp=cfg["ramp"], margin=cfg["margin"])
+    for _ in range(args.warmup):
+        op.trm_modes(f0, om, 1, every, cfg["scheme"], **kw)
+    torch.cuda.synchronize()
+    op.set_timing(True)
+    for kind in range(4):
+        op.timing(kind)
+    iters = max(args.steps, 2)
+    t0 = time.perf_counter()
+    gains, amps, _ = op.trm_modes(f0, om, iters, every, cfg["scheme"], **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
+                                                   ("prefilter", L.RES_TIMING_SYNTHESIS),
+                                                   ("spectra", L.RES_TIMING_PROJECTION),
+                                                   ("fir_and_normalise", L.RES_TIMING_QR))}
+    op.set_timing(False)
+    # the FIR kernel alone at the same shape, on torch's current stream (the stream fir_apply launches on)
+    b = fir_design(cfg["order"], [-1.0, -0.2, 0.0, 0.2, 1.0], [0.0, 0.0, 1.0, 0.0, 0.0])
+    y = fir_apply(b, f0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 5
+    ev[0].record()
+    for _ in range(reps):
+        fir_apply(b, f0, out=y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    fir_s = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+    fir_flop = 8.0 * (cfg["order"] + 1) * n * k * N  # complex multiply-adds of the taps per output
+    st_ms, st_n = kt["stepper"]
+    peak = FP64_VECTOR_PEAK / 1e12
+    fir_share = cfg["passes"] * fir_s * 1e3 * (iters - 1)
+    if fir_share >= st_ms:
+        roof = {"bound": "alu", "kernel": "fir_kernel (delay-compensated FIR, FP64, order %d)" % cfg["order"],
+                "achieved": fir_flop / fir_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                "frac": fir_flop / fir_s / 1e12 / peak, "traffic": None, "avg_launch_ms": fir_s * 1e3}
+    else:
+        avg = st_ms / 1e3 / max(st_n, 1)
+        spl = 2 * steps_per_run * iters / max(st_n, 1)
+        ach = STEP_FLOP_PER_UNKNOWN * N * k * spl / avg / 1e12
+        roof = {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "avg_launch_ms": avg * 1e3,
+                "launches": st_n, "steps_per_launch": spl}
+    sel = [int(np.argmin(np.abs(om - w))) for w in (0.0, 5.0, 10.0, 15.0)]
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)", "value": sweeps_per_step / dt, "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": iters, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": N, "k": k, "n_omega": cfg["n_omega"], "band": [-cfg["wmax"], cfg["wmax"]],
+                   "h": cfg["h"], "samples": n, "every": every, "fir_order": cfg["order"], "fir_passes": cfg["passes"],
+                   "interpolation": cfg["scheme"], "method": "transient, time-domain hand-off",
+                   "step": "one TRM iteration", "time_steps_per_step": 2 * steps_per_run},
+        "roofline": roof,
+        "kernel_ms_per_step": {kk: v[0] / iters for kk, v in kt.items()},
+        "fir_kernel_ms": fir_s * 1e3,
+        "gains_last_iteration": {"omega": [float(om[j]) for j in sel], "gain": [float(gains[-1, j]) for j in sel]},
+        "amplitude_ratio_per_iteration": [float(a.max() / a.min()) for a in amps],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_trm(cfg, F0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_trm(cfg, F0, seconds):
+    """The oracle's signal run (RK4 with C2 stage forcing) of the same operator, timed on growing prefixes of the
+    forcing until about `seconds` have passed; rate in the same unit as the GPU line."""
+    from oracle import operators as O_ops
+    from oracle import trm as O_trm
+    L, _ = O_ops.paper_gl_operator(cfg["N"], cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    scheme = {"C0": 0, "C1": 1, "C2": 2}[cfg["scheme"]]
+    O_trm.march_signal(L, cfg["h"], F0[:3], cfg["every"], scheme)  # warm up
+    steps, t, m = 0, time.perf_counter(), 101
+    while time.perf_counter() - t < seconds:
+        O_trm.march_signal(L, cfg["h"], F0[:m], cfg["every"], scheme)
+        steps += (m - 1) * cfg["every"]
+    dt = time.perf_counter() - t
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or str(os.cpu_count())
+    return dict(value=cfg["N"] * cfg["k"] * cfg["n_omega"] * steps / dt, unit="resolvent sweeps/s",
+                cores=int(threads), kind="oracle",
+                sample="%d RK4 steps of the oracle's signal run (C2 stage forcing, N=%d, k=%d; the spectra at %d "
+                       "frequencies counted as in the GPU line), %.1f s" % (steps, cfg["N"], cfg["k"],
+                                                                          cfg["n_omega"], dt))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -487,6 +598,12 @@ def main():
         return
     if args.plan is None:
         args.plan = "tuned" if args.workload == "gl_batched_64" else "default"
+    if args.algorithm == "trm":
+        if args.workload != "gl_paper_n200":
+            print("--algorithm trm measures gl_paper_n200", file=sys.stderr)
+            sys.exit(2)
+        bench_trm(args)
+        return
     if args.algorithm == "krylov":
         if args.workload != "gl_periodic_n2000":
             print("--algorithm krylov measures gl_periodic_n2000", file=sys.stderr)

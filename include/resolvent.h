@@ -273,7 +273,7 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  * resolvent_fir_apply: y[t][c] = sum_{m=0}^{n} b[m] x[t + n/2 - m][c] for t < n_t, c < ncols (x = 0 outside
  * [0, n_t)): the filter with its delay removed, so a complex exponential of frequency nu leaves multiplied by
  * H(nu) = sum_m b_m e^{-i pi nu (m - n/2)}.  taps: device complex128 [order + 1]; x, y: device [n_t][ncols],
- * complex128 if fp64 else complex64, not aliased.  Order even, 0 <= order <= 4094.  Asynchronous on `stream`.
+ * complex128 if fp64 else complex64, not aliased.  Order even, 0 <= order <= 4080.  Asynchronous on `stream`.
  *
  * resolvent_trm_modes: the power iteration with time-domain hand-off (Sec. 2.2 and App. A).  Starting from the
  * sampled forcing f0 (tapered: zero on the first and last `pad` samples, raised-cosine ramps of `ramp` samples,

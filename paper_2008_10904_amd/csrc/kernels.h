@@ -147,8 +147,12 @@ int fir_max_order();
 // `pad`/`ramp` samples (pad < 0: none).  Returns -1 for an order beyond fir_max_order().
 int launch_fir(const cx<double>* taps, int order, const void* x, void* y, int64_t Tn, int64_t ncols, int64_t pad,
                int64_t ramp, int fp64, hipStream_t st);
+// out [nw][ncols] FP64 = dt sum_i x_i e^{-i w_j t_i}; part: series_dft_part_elems(...) FP64 complex scratch.
+int64_t series_dft_part_elems(int64_t Tn, int64_t ncols, int nw);
 int launch_series_dft(const void* x, int fp64, int64_t Tn, int64_t ncols, const double* omegas, int nw, double dt,
-                      void* out, hipStream_t st);
+                      void* part, void* out, hipStream_t st);
+// FIR taps [order + 1] (FP64 complex) from the response sampled at M frequencies and the table E[p] = e^{2 pi i p/M}.
+int launch_fir_taps(const double* D, const void* E, int64_t M, int order, void* taps, hipStream_t st);
 int launch_row_norms(const void* X, int64_t nrows, int64_t ncols, double* norms, hipStream_t st);
 int normalise_parts();
 int launch_normalise(void* x, int fp64, int64_t count, double* part, double* scale, hipStream_t st);

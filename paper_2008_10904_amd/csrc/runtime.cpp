@@ -1580,7 +1580,8 @@ int signal_args(const resolvent_op* op, int k, int64_t n, int every, int scheme)
 // outside them), is sampled on M uniform frequencies nu_q = -1 + 2q/M and transformed back with an n/2-sample
 // delay:  b_m = w_m (1/M) sum_q D(nu_q) e^{i pi nu_q (m - n/2)},  w_m = 0.54 - 0.46 cos(2 pi m / n).
 // M = 2 max(512, 2^ceil(log2 n)).  The phases are index-exact: e^{i pi nu_q r} = (-1)^r e^{2 pi i q r / M}.
-int fir_design_host(int order, int npts, const double* nu, const double* gain, std::vector<cd>* taps) {
+// The desired response sampled on the design grid (and M); shared by the host design and the device one.
+int fir_response_samples(int order, int npts, const double* nu, const double* gain, std::vector<double>* Dout) {
   if (order < 2 || order % 2 || order > fir_max_order())
     return fail(RES_EINVAL, "FIR order must be even, >= 2 and <= " + std::to_string(fir_max_order()));
   if (npts < 2 || !nu || !gain) return fail(RES_EINVAL, "need at least two breakpoints");
@@ -1592,7 +1593,8 @@ int fir_design_host(int order, int npts, const double* nu, const double* gain, s
   int64_t p2 = 1;
   while (p2 < order) p2 <<= 1;
   const int64_t M = 2 * std::max<int64_t>(512, p2);
-  std::vector<double> D((size_t)M);
+  std::vector<double>& D = *Dout;
+  D.assign((size_t)M, 0.0);
   for (int64_t q = 0; q < M; ++q) {
     const double x = -1.0 + 2.0 * (double)q / (double)M;
     double v;
@@ -1608,8 +1610,20 @@ int fir_design_host(int order, int npts, const double* nu, const double* gain, s
     }
     D[q] = v;
   }
+  return RES_OK;
+}
+
+std::vector<cd> unit_circle(int64_t M) {
   std::vector<cd> E((size_t)M);
   for (int64_t p = 0; p < M; ++p) E[p] = std::polar(1.0, 2.0 * M_PI * (double)p / (double)M);
+  return E;
+}
+
+int fir_design_host(int order, int npts, const double* nu, const double* gain, std::vector<cd>* taps) {
+  std::vector<double> D;
+  RES_TRY(fir_response_samples(order, npts, nu, gain, &D));
+  const int64_t M = (int64_t)D.size();
+  const std::vector<cd> E = unit_circle(M);
   taps->assign((size_t)order + 1, cd(0, 0));
   for (int m = 0; m <= order; ++m) {
     const int64_t r = m - order / 2;
@@ -1660,7 +1674,7 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
   const int64_t ncols = (int64_t)k * op->N, count = n * ncols;
   const size_t ws = op->wsize();
   const double dt = (double)every * op->h;
-  void *F, *Y, *W, *Tm, *hat, *nrm, *taps, *omd, *part;
+  void *F, *Y, *W, *Tm, *hat, *nrm, *taps, *omd, *part, *dpart, *dD = nullptr, *dE = nullptr;
   RES_TRY(ws_get(op, "trm_F", (size_t)count * ws, &F));
   RES_TRY(ws_get(op, "trm_Y", (size_t)count * ws, &Y));
   RES_TRY(ws_get(op, "trm_W", (size_t)count * ws, &W));
@@ -1670,9 +1684,20 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
   RES_TRY(ws_get(op, "trm_taps", (size_t)(std::max(order, 0) + 1) * sizeof(cd), &taps));
   RES_TRY(ws_get(op, "trm_omegas", (size_t)nw * sizeof(double), &omd));
   RES_TRY(ws_get(op, "trm_part", (size_t)(normalise_parts() + 1) * sizeof(double), &part));
+  RES_TRY(ws_get(op, "trm_dft_part", (size_t)series_dft_part_elems(n, ncols, nw) * sizeof(cd), &dpart));
+  std::vector<cd> Etab;
+  std::vector<double> Dq;
+  if (passes > 0) {  // the design grid: the response samples (host, per iteration) and the unit circle (once)
+    int64_t p2 = 1;
+    while (p2 < order) p2 <<= 1;
+    const int64_t M = 2 * std::max<int64_t>(512, p2);
+    RES_TRY(ws_get(op, "trm_design_D", (size_t)M * sizeof(double), &dD));
+    RES_TRY(ws_get(op, "trm_design_E", (size_t)M * sizeof(cd), &dE));
+    Etab = unit_circle(M);
+    HIP_TRY(hipMemcpyAsync(dE, Etab.data(), Etab.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+  }
   double* scale = (double*)part + normalise_parts();
   std::vector<double> om(omegas, omegas + nw), hn((size_t)3 * nw), bnu, bgain;
-  std::vector<cd> b;
   const cd one(1.0, 0.0);
   HIP_TRY(hipMemcpyAsync(omd, om.data(), (size_t)nw * sizeof(double), hipMemcpyHostToDevice, st));
   // F = taper(f0) / ||taper(f0)||: the identity filter with the taper
@@ -1687,7 +1712,8 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
     {
       TimedLaunch tl(op, RES_TIMING_PROJECTION, st);
       for (int q = 0; q < 3; ++q) {
-        launch_series_dft(ser[q], op->fp64(), n, ncols, (const double*)omd, nw, dt, hat, st);
+        if (launch_series_dft(ser[q], op->fp64(), n, ncols, (const double*)omd, nw, dt, dpart, hat, st))
+          return fail(RES_EINVAL, "series too long for the transform's chunk grid");
         launch_row_norms(hat, nw, ncols, (double*)nrm + (size_t)q * nw, st);
       }
     }
@@ -1698,17 +1724,23 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
       if (amps) amps[(size_t)it * nw + j] = hn[j];
     }
     if (it + 1 == iters && !f_out) break;
+    if (passes == 0) {
+      HIP_TRY(hipMemcpyAsync(taps, &one, sizeof(cd), hipMemcpyHostToDevice, st));
+    } else {
+      std::vector<double> wn(hn.begin() + 2 * nw, hn.end());
+      RES_TRY(flattening_breakpoints(om, wn, dt, margin, passes, &bnu, &bgain));
+      RES_TRY(fir_response_samples(order, (int)bnu.size(), bnu.data(), bgain.data(), &Dq));
+      HIP_TRY(hipMemcpyAsync(dD, Dq.data(), Dq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      TimedLaunch tl(op, RES_TIMING_QR, st);
+      if (launch_fir_taps((const double*)dD, dE, (int64_t)Dq.size(), order, taps, st))
+        return fail(RES_EINVAL, "FIR design launch");
+    }
     {
       TimedLaunch tl(op, RES_TIMING_QR, st);
       if (passes == 0) {
-        HIP_TRY(hipMemcpyAsync(taps, &one, sizeof(cd), hipMemcpyHostToDevice, st));
         if (launch_fir((const cx<double>*)taps, 0, W, F, n, ncols, pad, ramp, op->fp64(), st))
           return fail(RES_EINVAL, "taper launch");
       } else {
-        std::vector<double> wn(hn.begin() + 2 * nw, hn.end());
-        RES_TRY(flattening_breakpoints(om, wn, dt, margin, passes, &bnu, &bgain));
-        RES_TRY(fir_design_host(order, (int)bnu.size(), bnu.data(), bgain.data(), &b));
-        HIP_TRY(hipMemcpyAsync(taps, b.data(), b.size() * sizeof(cd), hipMemcpyHostToDevice, st));
         const void* src = W;
         for (int p = 0; p < passes; ++p) {
           const bool last = p + 1 == passes;

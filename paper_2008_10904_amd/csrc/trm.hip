@@ -181,10 +181,12 @@ int launch_copy_rows(const void* src, int64_t src_ld, void* dst, int64_t row0, i
 // FIR filtering along time with the n/2-sample delay removed (App. B):
 //     y[t][c] = wt(t) * sum_{m=0}^{n} b[m] x[t + n/2 - m][c],   x = 0 outside [0, T),
 // with the optional taper wt (zero on the first and last `pad` samples, raised-cosine ramps of `ramp` samples, one
-// between; pad < 0: no taper).  The taps sit in LDS (every lane of a wave reads the same tap: a broadcast); each
-// lane owns one column and kFirRT consecutive output times, so each loaded sample serves kFirRT outputs.  FP64
-// accumulation in both precisions.
-constexpr int kFirRT = 8;
+// between; pad < 0: no taper).  Each lane owns one column and kFirRT consecutive output times t0 .. t0 + kFirRT - 1
+// and walks the taps: for tap m it needs x[t0 + j + n/2 - m], j < kFirRT, a window that slides down by one sample
+// per tap.  The window lives in registers as a ring (slot (j - u) mod kFirRT at step u of an unrolled group of
+// kFirRT taps), so each tap costs one new sample load, one broadcast read of the tap from LDS (zero-padded to a
+// whole group) and kFirRT complex multiply-adds.  FP64 accumulation in both precisions.
+constexpr int kFirRT = 16;
 
 __device__ __forceinline__ double taper_at(int64_t t, int64_t T, int64_t pad, int64_t ramp) {
   if (pad < 0) return 1.0;
@@ -195,32 +197,39 @@ __device__ __forceinline__ double taper_at(int64_t t, int64_t T, int64_t pad, in
 }
 
 template <typename T>
+__device__ __forceinline__ cx<double> load_or_zero(const cx<T>* __restrict__ x, int64_t q, int64_t Tn, int64_t ncols,
+                                                   int64_t c, bool live) {
+  return (live && q >= 0 && q < Tn) ? ccast<double>(x[q * ncols + c]) : mk<double>(0.0, 0.0);
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void fir_kernel(const cx<double>* __restrict__ taps, int order,
                                                   const cx<T>* __restrict__ x, cx<T>* __restrict__ y, int64_t Tn,
                                                   int64_t ncols, int64_t pad, int64_t ramp) {
   extern __shared__ cx<double> sb[];
-  for (int m = threadIdx.x; m <= order; m += blockDim.x) sb[m] = taps[m];
+  const int ntap = (order + kFirRT) / kFirRT * kFirRT;  // order + 1 rounded up to whole groups
+  for (int m = threadIdx.x; m < ntap; m += blockDim.x) sb[m] = m <= order ? taps[m] : mk<double>(0.0, 0.0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   const int64_t t0 = ((int64_t)blockIdx.y * (blockDim.x >> 6) + wave) * kFirRT;
   if (t0 >= Tn) return;
   const bool live = c < ncols;
-  const int half = order / 2;
-  cx<double> acc[kFirRT];
+  const int64_t base = t0 + order / 2;  // x index of output j at tap m: base + j - m
+  cx<double> acc[kFirRT], ring[kFirRT];
 #pragma unroll
-  for (int j = 0; j < kFirRT; ++j) acc[j] = mk<double>(0.0, 0.0);
-  // input rows q = t0 + j + half - m for m in [0, order], j in [0, kFirRT)
-  int64_t qlo = t0 + half - order, qhi = t0 + kFirRT - 1 + half;
-  if (qlo < 0) qlo = 0;
-  if (qhi > Tn - 1) qhi = Tn - 1;
-  for (int64_t q = qlo; q <= qhi; ++q) {
-    const cx<double> xv = live ? ccast<double>(x[q * ncols + c]) : mk<double>(0.0, 0.0);
-    const int64_t mb = t0 + half - q;  // tap index for j = 0
+  for (int j = 0; j < kFirRT; ++j) {
+    acc[j] = mk<double>(0.0, 0.0);
+    ring[j] = load_or_zero(x, base + j, Tn, ncols, c, live);
+  }
+  for (int m0 = 0; m0 < ntap; m0 += kFirRT) {
 #pragma unroll
-    for (int j = 0; j < kFirRT; ++j) {
-      const int64_t m = mb + j;
-      if (m >= 0 && m <= order) acc[j] = cfma(sb[m], xv, acc[j]);
+    for (int u = 0; u < kFirRT; ++u) {
+      const cx<double> b = sb[m0 + u];
+#pragma unroll
+      for (int j = 0; j < kFirRT; ++j) acc[j] = cfma(b, ring[(j - u + kFirRT) % kFirRT], acc[j]);
+      // the slot of offset j - u = kFirRT - 1 - u is not needed again: it takes the sample of offset -(u + 1)
+      ring[(kFirRT - 1 - u) % kFirRT] = load_or_zero(x, base - (m0 + u) - 1, Tn, ncols, c, live);
     }
   }
   if (!live) return;
@@ -234,13 +243,13 @@ __global__ __launch_bounds__(256) void fir_kernel(const cx<double>* __restrict__
   }
 }
 
-int fir_max_order() { return 65536 / (int)sizeof(cx<double>) - 2; }
+int fir_max_order() { return 65536 / (int)sizeof(cx<double>) - kFirRT; }
 
 int launch_fir(const cx<double>* taps, int order, const void* x, void* y, int64_t Tn, int64_t ncols, int64_t pad,
                int64_t ramp, int fp64, hipStream_t st) {
   if (order < 0 || order > fir_max_order() || Tn < 1 || ncols < 1) return -1;
   const dim3 grid((unsigned)((ncols + 63) / 64), (unsigned)((Tn + 4 * kFirRT - 1) / (4 * kFirRT)));
-  const size_t lds = (size_t)(order + 1) * sizeof(cx<double>);
+  const size_t lds = (size_t)((order + kFirRT) / kFirRT * kFirRT) * sizeof(cx<double>);
   if (fp64)
     hipLaunchKernelGGL((fir_kernel<double>), grid, dim3(256), lds, st, taps, order, (const cx<double>*)x,
                        (cx<double>*)y, Tn, ncols, pad, ramp);
@@ -250,45 +259,106 @@ int launch_fir(const cx<double>* taps, int order, const void* x, void* y, int64_
   return 0;
 }
 
-// Fourier transform of a series at arbitrary frequencies: out[j][c] = dt sum_i x[i][c] e^{-i w_j i dt} (FP64).
-// The phase advances by a complex rotation per sample and is recomputed exactly every 64 samples.
+// Fourier transform of a series at arbitrary frequencies, out[j][c] = dt sum_i x[i][c] e^{-i w_j i dt} (FP64), in
+// two deterministic stages: workgroup row blockIdx.y sums its chunk of kDftChunk samples into part[chunk][j][c]
+// (the phase advances by a complex rotation per sample and is recomputed exactly every 64 samples), then the
+// chunks are added in order.
+constexpr int kDftChunk = 256;
+
 template <typename T>
 __global__ __launch_bounds__(256) void series_dft_kernel(const cx<T>* __restrict__ x, int64_t Tn, int64_t ncols,
                                                          const double* __restrict__ omegas, int nw, double dt,
-                                                         cx<double>* __restrict__ out) {
+                                                         cx<double>* __restrict__ part) {
   const int64_t total = (int64_t)nw * ncols;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t j = e / ncols, c = e - j * ncols;
+  const int64_t i0 = (int64_t)blockIdx.y * kDftChunk;
+  const int64_t i1 = i0 + kDftChunk < Tn ? i0 + kDftChunk : Tn;
+  const double w = omegas[j];
+  double sr, cr;
+  sincos(-w * dt, &sr, &cr);
+  const cx<double> rot = mk<double>(cr, sr);
+  cx<double> acc = mk<double>(0.0, 0.0), ph = mk<double>(1.0, 0.0);
+  for (int64_t i = i0; i < i1; ++i) {
+    if (((i - i0) & 63) == 0) {
+      double s, co;
+      sincos(-w * dt * (double)i, &s, &co);
+      ph = mk<double>(co, s);
+    }
+    acc = cfma(ph, ccast<double>(x[i * ncols + c]), acc);
+    ph = cmul(ph, rot);
+  }
+  part[(int64_t)blockIdx.y * total + e] = mk<double>(dt * acc.re, dt * acc.im);
+}
+
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const cx<double>* __restrict__ part, int64_t total,
+                                                         int nchunk, cx<double>* __restrict__ out) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / ncols, c = e - j * ncols;
-    const double w = omegas[j];
-    double sr, cr;
-    sincos(-w * dt, &sr, &cr);
-    const cx<double> rot = mk<double>(cr, sr);
-    cx<double> acc = mk<double>(0.0, 0.0), ph = mk<double>(1.0, 0.0);
-    for (int64_t i = 0; i < Tn; ++i) {
-      if ((i & 63) == 0) {
-        double s, co;
-        sincos(-w * dt * (double)i, &s, &co);
-        ph = mk<double>(co, s);
-      }
-      acc = cfma(ph, ccast<double>(x[i * ncols + c]), acc);
-      ph = cmul(ph, rot);
-    }
-    out[e] = mk<double>(dt * acc.re, dt * acc.im);
+    cx<double> s = mk<double>(0.0, 0.0);
+    for (int q = 0; q < nchunk; ++q) s = cadd(s, part[(int64_t)q * total + e]);
+    out[e] = s;
   }
 }
 
+int64_t series_dft_part_elems(int64_t Tn, int64_t ncols, int nw) {
+  return ((Tn + kDftChunk - 1) / kDftChunk) * (int64_t)nw * ncols;
+}
+
+// part: series_dft_part_elems(Tn, ncols, nw) FP64 complex values of scratch.
 int launch_series_dft(const void* x, int fp64, int64_t Tn, int64_t ncols, const double* omegas, int nw, double dt,
-                      void* out, hipStream_t st) {
-  int64_t blocks = ((int64_t)nw * ncols + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) return 0;
+                      void* part, void* out, hipStream_t st) {
+  const int64_t total = (int64_t)nw * ncols;
+  const int64_t nchunk = (Tn + kDftChunk - 1) / kDftChunk;
+  if (total < 1 || Tn < 1 || nchunk > 65535) return -1;
+  const dim3 grid((unsigned)((total + 255) / 256), (unsigned)nchunk);
   if (fp64)
-    hipLaunchKernelGGL((series_dft_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st, (const cx<double>*)x,
-                       Tn, ncols, omegas, nw, dt, (cx<double>*)out);
+    hipLaunchKernelGGL((series_dft_kernel<double>), grid, dim3(256), 0, st, (const cx<double>*)x, Tn, ncols, omegas,
+                       nw, dt, (cx<double>*)part);
   else
-    hipLaunchKernelGGL((series_dft_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st, (const cx<float>*)x,
-                       Tn, ncols, omegas, nw, dt, (cx<double>*)out);
+    hipLaunchKernelGGL((series_dft_kernel<float>), grid, dim3(256), 0, st, (const cx<float>*)x, Tn, ncols, omegas,
+                       nw, dt, (cx<double>*)part);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (const cx<double>*)part, total,
+                     (int)nchunk, (cx<double>*)out);
+  return 0;
+}
+
+// Taps of the frequency-sampling FIR design (App. B) from the sampled response D[q] at nu_q = -1 + 2q/M:
+//     taps[m] = w_m (1/M) sum_q D[q] e^{i pi nu_q (m - n/2)},  e^{i pi nu_q r} = (-1)^r E[(q r) mod M],
+// E[p] = e^{2 pi i p / M} (a table), w_m the Hamming window.  One workgroup per tap; lanes stride over q and the
+// partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void fir_taps_kernel(const double* __restrict__ D, const cx<double>* __restrict__ E,
+                                                       int64_t M, int order, cx<double>* __restrict__ taps) {
+  __shared__ cx<double> red[256];
+  const int m = blockIdx.x;
+  const int64_t r = (int64_t)m - order / 2;
+  const int64_t rm = ((r % M) + M) % M;
+  cx<double> acc = mk<double>(0.0, 0.0);
+  for (int64_t q = threadIdx.x; q < M; q += blockDim.x) {
+    const cx<double> e = E[(q * rm) % M];
+    acc = mk<double>(fma(D[q], e.re, acc.re), fma(D[q], e.im, acc.im));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cx<double> t = red[0];
+    if (r & 1) t = mk<double>(-t.re, -t.im);
+    const double wm = (0.54 - 0.46 * cos(2.0 * M_PI * (double)m / (double)order)) / (double)M;
+    taps[m] = mk<double>(wm * t.re, wm * t.im);
+  }
+}
+
+int launch_fir_taps(const double* D, const void* E, int64_t M, int order, void* taps, hipStream_t st) {
+  if (order < 2 || M < 1) return -1;
+  hipLaunchKernelGGL(fir_taps_kernel, dim3((unsigned)(order + 1)), dim3(256), 0, st, D, (const cx<double>*)E, M, order,
+                     (cx<double>*)taps);
   return 0;
 }
 

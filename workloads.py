@@ -20,6 +20,11 @@ Workloads (the paper publishes no data set; every input is synthetic):
                     N = 200, 77 frequencies 0, 15/76, ..., 15 (the band of the paper's study), P = 3200 so that
                     h = 2 pi 76 / (15 * 3200) = 0.00995 (the paper's step is 0.01), periodic method with 2 periods
                     (the transient decays like exp(-4.8 t), 1e-66 after one period), k = 1.
+* ``GL_PAPER_TRM``  the same model with the transient-response method and time-domain hand-off at the paper's
+                    settings (Sec. 3, App. B): h = 0.01 sampled every step, 6001 samples (60 time units; forcing
+                    tapered to zero on the first and last 12 with 6-unit ramps), FIR flattening filters of order 3000
+                    (resolution about 0.2 rad per time unit) applied in two passes, 61 analysis frequencies in
+                    [-15, 15], C2 interpolation, k = 1.
 * ``ADR3D``         3-D three-component advection-diffusion with shear coupling, 256 x 128 x 128, FP32 state,
                     96 frequencies in [0, pi/2], k = 3, periodic method, checkpoints every 64 steps.
 
@@ -63,6 +68,10 @@ ADR2D = dict(name="adr2d_1024x512", kind="adr2d", nx=1024, ny=512, Re=200.0, h=0
 GL_PAPER = dict(name="gl_paper_n200", kind="gl_paper", N=200, U=6.0, gamma=1.0, beta=0.1, length=40.0,
                 w0=0.0, dw=15.0 / 76, n_omega=77, P=3200, h=2 * math.pi * 76 / (15.0 * 3200), method="periodic",
                 periods=2, stride=32, tail=0, k=1, iters=15, precision="fp64", seed=SEED_BASE + 5)
+
+GL_PAPER_TRM = dict(name="gl_paper_trm_n200", kind="gl_paper", N=200, U=6.0, gamma=1.0, beta=0.1, length=40.0,
+                    h=0.01, every=1, n_samples=6001, wmax=15.0, n_omega=61, order=3000, passes=2, pad=1200, ramp=600,
+                    margin=3.0, scheme="C2", k=1, iters=8, precision="fp64", seed=SEED_BASE + 6)
 
 ADR3D = dict(name="adr3d3c_256x128x128", kind="adr3d3c", nx=256, ny=128, nz=128, Re=200.0, h=0.1,
              wmin=0.0, wmax=math.pi / 2, n_omega=96, method="periodic", periods=3, stride=1, tail=0,
