@@ -287,7 +287,9 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  *      (1/||W(w_j)||)^(1/passes) at the analysis frequencies (largest 1), falling linearly to zero `margin`
  *      rad per time unit outside them and zero beyond (passes = 0: no filter);
  *   4. hands the result back, tapered and normalised, as the next F.
- * f_out (device, may be NULL) receives the last F.  The flattening response spans the square of the gain range,
+ * f_out (device, may be NULL) receives the last F; V and U (device [n_omega][k][N] in the handle's I/O type, each
+ * may be NULL) receive the force and response modes of the last iteration, F(w_j) / ||F(w_j)|| and
+ * Y(w_j) / ||Y(w_j)|| (for k = 1 the leading modes at any analysis frequency).  The flattening response spans the square of the gain range,
  * more than one windowed filter realises when gains differ by 1e3 (passes = 2 realises 1e6).  Synchronises
  * `stream` every iteration and cannot be captured.  Errors as resolvent_signal_run, and RES_EINVAL for
  * n_omega < 1, iters < 1, a bad order, a taper that leaves no sample at one or frequencies beyond Nyquist. */
@@ -299,7 +301,7 @@ int resolvent_fir_apply(int32_t fp64, int64_t n_t, int64_t ncols, int32_t order,
 int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
                         const void* f0, int32_t n_omega, const double* omegas, int32_t iters, int32_t order,
                         int32_t passes, int64_t pad, int64_t ramp, double margin, double* gains, double* amps,
-                        void* f_out, void* stream);
+                        void* f_out, void* V, void* U, void* stream);
 
 /* Synchronise `stream` and report RES_ENONFINITE if any result produced since the last check held NaN/Inf. */
 int resolvent_op_check(resolvent_op* op, void* stream);

@@ -192,9 +192,12 @@ def flattening_breakpoints(omegas, Wh_norm, dt, margin):
     return x, y
 
 
-def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp, margin, passes=1, flatten=True):
+def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp, margin, passes=1, flatten=True,
+                        want_modes=False):
     """Returns (gains (iters, n_w): ||Y(w_j)|| / ||F(w_j)|| of each iteration's forcing, amplitudes (iters, n_w):
-    ||F(w_j)|| of each iteration's forcing, F the last forcing series).  F0 (n, k, N) is tapered first."""
+    ||F(w_j)|| of each iteration's forcing, F the last forcing series), and with want_modes also the force and
+    response modes of the last iteration at the analysis frequencies, V = F(w_j) / ||F(w_j)|| and
+    U = Y(w_j) / ||Y(w_j)|| (n_w, k, N).  F0 (n, k, N) is tapered first."""
     n = F0.shape[0]
     dt = every * h
     win = taper(n, pad, ramp)[:, None, None]
@@ -205,11 +208,13 @@ def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp
     for it in range(iters):
         Y = march_signal(L, h, F, every, scheme)
         W = march_signal(L, h, Y, every, scheme, adjoint=True)
-        Fh = np.linalg.norm(dft(F, omegas, dt).reshape(len(omegas), -1), axis=1)
-        Yh = np.linalg.norm(dft(Y, omegas, dt).reshape(len(omegas), -1), axis=1)
+        Fs, Ys = dft(F, omegas, dt), dft(Y, omegas, dt)
+        Fh = np.linalg.norm(Fs.reshape(len(omegas), -1), axis=1)
+        Yh = np.linalg.norm(Ys.reshape(len(omegas), -1), axis=1)
         Wh = np.linalg.norm(dft(W, omegas, dt).reshape(len(omegas), -1), axis=1)
         gains[it] = Yh / Fh
         amps[it] = Fh
+        V, U = Fs / Fh[:, None, None], Ys / Yh[:, None, None]
         if flatten:
             nu, D = flattening_breakpoints(omegas, Wh, dt, margin)
             b = fir_design(order, nu, D ** (1.0 / passes))
@@ -217,4 +222,6 @@ def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp
                 W = fir_apply(b, W)
         F = win * W
         F = F / np.linalg.norm(F)
+    if want_modes:
+        return gains, amps, F, V, U
     return gains, amps, F

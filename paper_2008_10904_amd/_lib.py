@@ -64,7 +64,8 @@ SIGNATURES = {
     "resolvent_fir_design": (c_int32, [c_int32, c_int32, _dp, _dp, _dp]),
     "resolvent_fir_apply": (c_int32, [c_int32, c_int64, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "resolvent_trm_modes": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_int32, c_void_p, c_int32, _dp, c_int32,
-                                      c_int32, c_int32, c_int64, c_int64, c_double, _dp, _dp, c_void_p, c_void_p]),
+                                      c_int32, c_int32, c_int64, c_int64, c_double, _dp, _dp, c_void_p, c_void_p,
+                                      c_void_p, c_void_p]),
     "resolvent_strerror": (ctypes.c_char_p, [c_int32]),
     "resolvent_last_error": (ctypes.c_char_p, []),
 }

@@ -330,20 +330,27 @@ class ResolventOp:
         return out
 
     def trm_modes(self, f0, omegas, iters, every, scheme="C2", order=600, passes=2, pad=0, ramp=0, margin=0.0,
-                  want_forcing=False):
+                  want_forcing=False, want_modes=False):
         """Power iteration with time-domain hand-off and FIR flattening (resolvent_trm_modes).  Returns (gains
-        [iters, n_omega], amplitudes [iters, n_omega], last forcing [n, k, N] or None)."""
+        [iters, n_omega], amplitudes [iters, n_omega], last forcing [n, k, N] or None), and with want_modes also
+        the force and response modes of the last iteration, V and U [n_omega, k, N]."""
         torch = _torch()
         self._check_series(f0)
         om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
         gains = np.zeros((int(iters), len(om)))
         amps = np.zeros((int(iters), len(om)))
         fo = torch.empty_like(f0) if want_forcing else None
+        V = torch.empty((len(om), f0.shape[1], self.n), dtype=self.cdtype, device=f0.device) if want_modes else None
+        U = torch.empty_like(V) if want_modes else None
         check(self._lib.resolvent_trm_modes(
             self._h, int(f0.shape[1]), int(f0.shape[0]), int(every), self._SCHEMES[scheme],
             ctypes.c_void_p(f0.data_ptr()), len(om), _dptr(om), int(iters), int(order), int(passes), int(pad),
             int(ramp), float(margin), _dptr(gains), _dptr(amps),
-            ctypes.c_void_p(fo.data_ptr()) if fo is not None else None, self._stream_ptr()))
+            ctypes.c_void_p(fo.data_ptr()) if fo is not None else None,
+            ctypes.c_void_p(V.data_ptr()) if V is not None else None,
+            ctypes.c_void_p(U.data_ptr()) if U is not None else None, self._stream_ptr()))
+        if want_modes:
+            return gains, amps, fo, V, U
         return gains, amps, fo
 
 

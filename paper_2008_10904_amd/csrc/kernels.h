@@ -154,6 +154,9 @@ int launch_series_dft(const void* x, int fp64, int64_t Tn, int64_t ncols, const 
 // FIR taps [order + 1] (FP64 complex) from the response sampled at M frequencies and the table E[p] = e^{2 pi i p/M}.
 int launch_fir_taps(const double* D, const void* E, int64_t M, int order, void* taps, hipStream_t st);
 int launch_row_norms(const void* X, int64_t nrows, int64_t ncols, double* norms, hipStream_t st);
+// out[j][c] = X[j][c] / norms[j], X FP64 [nrows][ncols], out working precision.
+int launch_scale_rows(const void* X, const double* norms, int64_t nrows, int64_t ncols, void* out, int out_fp64,
+                      hipStream_t st);
 int normalise_parts();
 int launch_normalise(void* x, int fp64, int64_t count, double* part, double* scale, hipStream_t st);
 // Amplitude weights of the block power iteration (fac[ninst][nw] = 1/sqrt(leading gain)) and their application

@@ -1670,7 +1670,7 @@ int flattening_breakpoints(const std::vector<double>& om, const std::vector<doub
 // passes = 0 hands W back unfiltered.
 int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const void* f0, int nw, const double* omegas,
               int iters, int order, int passes, int64_t pad, int64_t ramp, double margin, double* gains,
-              double* amps, void* f_out, hipStream_t st) {
+              double* amps, void* f_out, void* V, void* U, hipStream_t st) {
   const int64_t ncols = (int64_t)k * op->N, count = n * ncols;
   const size_t ws = op->wsize();
   const double dt = (double)every * op->h;
@@ -1722,6 +1722,15 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
     for (int j = 0; j < nw; ++j) {
       gains[(size_t)it * nw + j] = hn[(size_t)nw + j] / hn[j];
       if (amps) amps[(size_t)it * nw + j] = hn[j];
+    }
+    if (it + 1 == iters) {  // modes of the last iteration: the spectra of F and Y normalised per frequency
+      void* mo[2] = {V, U};
+      for (int q = 0; q < 2; ++q) {
+        if (!mo[q]) continue;
+        if (launch_series_dft(ser[q], op->fp64(), n, ncols, (const double*)omd, nw, dt, dpart, hat, st))
+          return fail(RES_EINVAL, "series too long for the transform's chunk grid");
+        launch_scale_rows(hat, (const double*)nrm + (size_t)q * nw, nw, ncols, mo[q], op->fp64(), st);
+      }
     }
     if (it + 1 == iters && !f_out) break;
     if (passes == 0) {
@@ -2272,7 +2281,7 @@ int resolvent_fir_apply(int32_t fp64, int64_t n_t, int64_t ncols, int32_t order,
 int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
                         const void* f0, int32_t n_omega, const double* omegas, int32_t iters, int32_t order,
                         int32_t passes, int64_t pad, int64_t ramp, double margin, double* gains, double* amps,
-                        void* f_out, void* stream) {
+                        void* f_out, void* V, void* U, void* stream) {
   g_last_error.clear();
   if (!op || !f0 || !omegas || !gains) return fail(RES_EINVAL, "NULL argument");
   RES_TRY(signal_args(op, k, n_samples, every, scheme));
@@ -2291,7 +2300,7 @@ int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t 
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
     return fail(RES_EINVAL, "resolvent_trm_modes synchronises its stream and cannot be captured");
   return trm_modes(op, k, n_samples, every, scheme, f0, n_omega, omegas, iters, order, passes, pad, ramp, margin,
-                   gains, amps, f_out, st);
+                   gains, amps, f_out, V, U, st);
 }
 
 int resolvent_op_set_graphs(resolvent_op* op, int32_t enable) {

@@ -362,6 +362,33 @@ int launch_fir_taps(const double* D, const void* E, int64_t M, int order, void* 
   return 0;
 }
 
+// out[j][c] = X[j][c] / norms[j] (X FP64 [nw][ncols], out in the working precision; a zero norm gives zeros).
+template <typename TO>
+__global__ __launch_bounds__(256) void scale_rows_kernel(const cx<double>* __restrict__ X, const double* __restrict__ norms,
+                                                         int64_t nrows, int64_t ncols, cx<TO>* __restrict__ out) {
+  const int64_t total = nrows * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double nv = norms[e / ncols];
+    const double s = nv > 0.0 ? 1.0 / nv : 0.0;
+    out[e] = ccast<TO>(mk<double>(s * X[e].re, s * X[e].im));
+  }
+}
+
+int launch_scale_rows(const void* X, const double* norms, int64_t nrows, int64_t ncols, void* out, int out_fp64,
+                      hipStream_t st) {
+  int64_t blocks = (nrows * ncols + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return 0;
+  if (out_fp64)
+    hipLaunchKernelGGL((scale_rows_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st, (const cx<double>*)X,
+                       norms, nrows, ncols, (cx<double>*)out);
+  else
+    hipLaunchKernelGGL((scale_rows_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st, (const cx<double>*)X,
+                       norms, nrows, ncols, (cx<float>*)out);
+  return 0;
+}
+
 // norms[j] = sqrt(sum_c |X[j][c]|^2) for X FP64 [nw][ncols]: one workgroup per row.
 __global__ __launch_bounds__(256) void row_norms_kernel(const cx<double>* __restrict__ X, int64_t ncols,
                                                         double* __restrict__ norms) {

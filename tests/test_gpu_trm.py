@@ -7,8 +7,9 @@ CPU oracle on the same seeded inputs:
 * resolvent_fir_apply: FP64 (1e-12) and mixed (1e-5), ragged column blocks, an order longer than the series, the
   identity filter;
 * resolvent_trm_modes: the power iteration with FIR flattening on the paper's GL model, gains per iteration and the
-  last forcing against the oracle's trm_power_iteration (1e-8 FP64; mixed 5e-3 on gains, 2e-2 on the spectral
-  amplitudes of the FP32 samples), and without the filter;
+  last forcing and the modes at the analysis frequencies against the oracle's trm_power_iteration (1e-8 FP64;
+  mixed 5e-3 on gains, 2e-2 on the spectral amplitudes of the FP32 samples, 5e-2 on mode entries), and without
+  the filter;
 * argument errors.
 """
 import numpy as np
@@ -137,15 +138,17 @@ def test_trm_modes_match_oracle(precision):
     kw = dict(order=300, passes=2, pad=int(6 / dtau), ramp=int(3 / dtau), margin=3.0)
     F0 = series(84, n, 1, n_x)
     L, _ = O_ops.paper_gl_operator(n_x)
-    g_ref, a_ref, f_ref = O_trm.trm_power_iteration(L, h, every, 2, F0, om, 3, **kw)
+    g_ref, a_ref, f_ref, V_ref, U_ref = O_trm.trm_power_iteration(L, h, every, 2, F0, om, 3, want_modes=True, **kw)
     lo, d, up = paper_gl_coefficients(n_x)
     op = ResolventOp.tridiagonal(lo, d, up, h, precision=precision)
     dt = torch.complex128 if precision == "fp64" else torch.complex64
-    g, a, f = op.trm_modes(gpu_tensor(F0, dt), om, 3, every, "C2", want_forcing=True, **kw)
+    g, a, f, V, U = op.trm_modes(gpu_tensor(F0, dt), om, 3, every, "C2", want_forcing=True, want_modes=True, **kw)
     torch.cuda.synchronize()
     eg, ea = np.abs(g / g_ref - 1).max(), np.abs(a / a_ref - 1).max()
     ef = per_sample_relerr(to_np(f), f_ref)
-    say("  gains", eg, "amplitudes", ea, "last forcing", ef)
+    ev = max(np.abs(to_np(V) - V_ref).max(), np.abs(to_np(U) - U_ref).max())
+    say("  gains", eg, "amplitudes", ea, "last forcing", ef, "modes", ev)
+    assert ev < (1e-8 if precision == "fp64" else 5e-2)  # mixed: the smallest-gain force modes are FP32-limited
     # Mixed precision keeps the samples in FP32.  The adjoint output spans the squared gain range (1e6 here), so its
     # smallest spectral components carry FP32 rounding of the largest, about 1e-2 relative; the flattening then
     # lifts them.  The gains (ratios of run outputs) stay within a few 1e-3.

@@ -651,7 +651,7 @@ def test_fir_apply_multiplies_an_exponential_by_the_response():
 
 def test_trm_power_iteration_with_flattening_on_the_paper_gl():
     # Sec. 2.2, Sec. 3: with the flattening filter the spectral amplitudes stay within a small ratio and the gains
-    # at omega = 0, 5, 10, 15 converge to the continuous resolvent's; without it the ratio grows with the squared
+    # at omega = 0, 5, 10, 15 (and the modes) converge to the continuous resolvent's; without it the ratio grows with the squared
     # gain ratio (1e6) per iteration until the window's leakage floor, five orders of magnitude above.
     n_x = 200
     L, _ = operators.paper_gl_operator(n_x)
@@ -662,10 +662,13 @@ def test_trm_power_iteration_with_flattening_on_the_paper_gl():
     ex = np.array([dense.gains_and_modes(dense.resolvent(L, w), 1)[0][0] for w in om[sel]])
     F0 = forcing(73, n, 1, n_x)
     kw = dict(order=600, pad=int(12 / dt), ramp=int(6 / dt), margin=3.0, passes=2)
-    g, amps, _ = trm.trm_power_iteration(L, h, every, 2, F0, om, 6, **kw)
+    g, amps, _, V, U = trm.trm_power_iteration(L, h, every, 2, F0, om, 6, want_modes=True, **kw)
     ratio = amps.max(1) / amps.min(1)
     assert ratio[1:].max() < 20
     err = np.abs(g[-1, sel] / ex - 1)
     assert err[:3].max() < 1e-3 and err[3] < 2e-2  # omega = 15: sigma_2 / sigma_1 = 0.8, slow power convergence
+    for j in sel[:3]:  # the modes at omega = 0, 5, 10 are those of the continuous resolvent's SVD
+        _, Us, Vs = dense.gains_and_modes(dense.resolvent(L, om[j]), 1)
+        assert abs(np.vdot(Vs[:, 0], V[j, 0])) > 1 - 1e-3 and abs(np.vdot(Us[:, 0], U[j, 0])) > 1 - 1e-3
     _, amps_u, _ = trm.trm_power_iteration(L, h, every, 2, F0, om, 3, flatten=False, **kw)
     assert (amps_u.max(1) / amps_u.min(1))[-1] > 1e5
