@@ -54,6 +54,10 @@ def parse():
                          "'trm' (transient-response method with time-domain hand-off and FIR flattening; one step = "
                          "one iteration)")
     ap.add_argument("--krylov-blocks", type=int, default=10)
+    ap.add_argument("--trm-every", type=int, default=1,
+                    help="--algorithm trm: RK4 steps between samples (1: the paper's every-step sampling); the window, "
+                         "taper and FIR resolution stay the same (order 3000 / every), and the march takes four "
+                         "steps per kernel step when every is a multiple of four")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -495,7 +499,14 @@ def bench_trm(args):
     from paper_2008_10904_amd.api import fir_apply, fir_design
     from paper_2008_10904_amd.operators import paper_gl_coefficients
 
-    cfg = W.GL_PAPER_TRM
+    cfg = dict(W.GL_PAPER_TRM)
+    e = max(1, args.trm_every)
+    if e != cfg["every"]:  # same window, taper and filter resolution with samples e steps apart
+        if (cfg["n_samples"] - 1) % e or cfg["order"] % (2 * e) or cfg["pad"] % e or cfg["ramp"] % e:
+            print("--trm-every must divide 6000, 1500, 1200 and 600", file=sys.stderr)
+            sys.exit(2)
+        cfg.update(every=e, n_samples=(cfg["n_samples"] - 1) // e + 1, order=cfg["order"] // e, pad=cfg["pad"] // e,
+                   ramp=cfg["ramp"] // e, name=cfg["name"] + "_every%d" % e)
     N, k, n, every = cfg["N"], cfg["k"], cfg["n_samples"], cfg["every"]
     om = np.linspace(-cfg["wmax"], cfg["wmax"], cfg["n_omega"])
     steps_per_run = (n - 1) * every
@@ -558,6 +569,7 @@ def bench_trm(args):
                    "step": "one TRM iteration", "time_steps_per_step": 2 * steps_per_run},
         "roofline": roof,
         "kernel_ms_per_step": {kk: v[0] / iters for kk, v in kt.items()},
+        "step_power": op.get_step_power(),
         "fir_kernel_ms": fir_s * 1e3,
         "gains_last_iteration": {"omega": [float(om[j]) for j in sel], "gain": [float(gains[-1, j]) for j in sel]},
         "amplitude_ratio_per_iteration": [float(a.max() / a.min()) for a in amps],

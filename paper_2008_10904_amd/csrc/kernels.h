@@ -138,8 +138,11 @@ int launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: a multiple of
 // i*every, read reversed if rev): pass 0 and 1 write FP64 xout, pass 2 the forcing rows g (working precision) of
 // steps s0 .. s0 + rows - 1.  scheme: 0 linear, 1 cubic Hermite, 2 quintic Hermite.
 int launch_signal_prefilter(const void* S, int64_t n, int every, int scheme, int rev, const cx<double>* tri,
-                            const void* xin, void* xout, void* g, int fp64, int64_t s0, int64_t rows, int64_t N,
-                            int64_t ncols, double h, int pass, hipStream_t st);
+                            const void* xin, void* xout, void* g, int fp64, int g_fp64, int64_t s0, int64_t rows,
+                            int64_t N, int64_t ncols, double h, int pass, hipStream_t st);
+// Horner pass i (1 <= i < M) of the combined forcing of M steps over per-step FP64 rows g: out = P xin + g_{RM+i}.
+int launch_row_horner(const cx<double>* band, const void* xin, int64_t xstride, const void* g, int M, int i,
+                      void* out, int out_fp64, int64_t rows, int64_t N, int64_t ncols, hipStream_t st);
 int launch_copy_rows(const void* src, int64_t src_ld, void* dst, int64_t row0, int dir, int64_t rows, int64_t ncols,
                      int fp64, hipStream_t st);
 int fir_max_order();

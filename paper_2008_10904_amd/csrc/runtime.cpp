@@ -1511,14 +1511,18 @@ int modes_to_problem(resolvent_op* op, int nw, int k, void* V, void* U, hipStrea
 // March from rest forced by the sampled signal `in` ([n][k][N], working precision; sample i at step i * every),
 // writing the state at the sample times to `out` (same layout).  adjoint = 0: du/dt = L u + f.  adjoint = 1:
 // -dz/dt = L^H z + g backward in time from z(T) = 0, T = (n - 1) every h, which is the forward march of L^H in
-// reversed time (the samples are read and written in reversed order).  One RK4 step per kernel step; the forcing
-// rows come from the stage-forcing pre-filter, in tiles of whole sample intervals.
+// reversed time (the samples are read and written in reversed order).  The forcing rows come from the stage-forcing
+// pre-filter, in tiles of whole sample intervals.  When the samples are a multiple of the operator's step power m
+// apart (and the plan's exchange interval allows it), the march takes m RK4 steps per kernel step with the band
+// P(Z)^m, its forcing rows combined from the per-step rows by m - 1 Horner passes of P(Z); else one step at a time.
 int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int adjoint, const void* in, void* out,
                hipStream_t st) {
   const int64_t N = op->N, ncols = (int64_t)k * N;
   const size_t ws = op->wsize();
   const int s = adjoint ? 1 : 0;
   const int64_t S = (n - 1) * (int64_t)every;
+  const int M = (op->step_power > 1 && every % op->step_power == 0 && op->step_block % op->step_power == 0)
+                    ? op->step_power : 1;
   const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
   const double per_step = (double)ncols * (2.0 * sizeof(cd) + (double)ws) + (double)(ncols + 1) * ws / every;
   int64_t tile = (int64_t)(tile_budget / per_step) / every * every;
@@ -1527,25 +1531,43 @@ int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int ad
   void *x2, *x1, *frc, *snap, *st0;
   RES_TRY(ws_get(op, "sig_x2", (size_t)tile * ncols * sizeof(cd), &x2));
   RES_TRY(ws_get(op, "sig_x1", (size_t)tile * ncols * sizeof(cd), &x1));
-  RES_TRY(ws_get(op, "forcing", (size_t)(tile + 16) * ncols * ws, &frc));  // + the stepper's prefetch rows
+  RES_TRY(ws_get(op, "forcing", (size_t)(tile / M + 16) * ncols * ws, &frc));  // + the stepper's prefetch rows
   RES_TRY(ws_get(op, "sig_snap", (size_t)(tile / every) * (ncols + 1) * ws, &snap));
   RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
   RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &st0));
   RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
   op->cur_state = 0;
   RES_TRY(zero_device(st0, (size_t)ncols * ws, st));
-  op->march_band = op->d_band[s];
+  op->march_band = M > 1 ? op->d_bandm[s] : op->d_band[s];
   void* dsegs;
   int64_t nseg;
   RES_TRY(upload_regions(op, k, &dsegs, &nseg, st));
   const cx<double>* tri = (const cx<double>*)op->d_tri[s];
+  const cx<double>* band64 = (const cx<double>*)op->d_band64[s];
   for (int64_t s0 = 0; s0 < S; s0 += tile) {
     const int64_t rows = std::min(tile, S - s0);
     {
       TimedLaunch tl(op, RES_TIMING_SYNTHESIS, st);
+      // passes 0 and 1 write x2 and x1; pass 2 writes the per-step rows: the forcing table itself for M = 1, else
+      // FP64 rows into x2 (free again), combined below into one row per kernel step
       for (int pass = 0; pass < 3; ++pass)
-        launch_signal_prefilter(in, n, every, scheme, adjoint, tri, pass == 1 ? x2 : x1, pass == 0 ? x2 : x1, frc,
-                                op->fp64(), s0, rows, N, ncols, op->h, pass, st);
+        launch_signal_prefilter(in, n, every, scheme, adjoint, tri, pass == 1 ? x2 : x1, pass == 0 ? x2 : x1,
+                                M > 1 ? x2 : frc, op->fp64(), M > 1 ? 1 : op->fp64(), s0, rows, N, ncols, op->h,
+                                pass, st);
+      if (M > 1) {
+        const int64_t krows = rows / M;
+        cx<double>* ya = (cx<double>*)x1;            // x1 holds rows >= 2 * krows FP64 rows: two Horner buffers
+        cx<double>* yb = ya + (size_t)krows * ncols;
+        const void* prev = x2;
+        int64_t pstride = M;
+        for (int i = 1; i < M; ++i) {
+          const bool last = i == M - 1;
+          void* out = last ? frc : (void*)((i & 1) ? ya : yb);
+          launch_row_horner(band64, prev, pstride, x2, M, i, out, last ? op->fp64() : 1, krows, N, ncols, st);
+          prev = out;
+          pstride = 1;
+        }
+      }
     }
     ForceSpec fs;
     fs.frc = frc;
@@ -1553,9 +1575,9 @@ int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int ad
     ss.snap = snap;
     ss.ld = ncols + 1;
     ss.first = 0;
-    ss.stride = every;
+    ss.stride = every / M;
     ss.count = rows / every;
-    RES_TRY(march_1d(op, k, rows, fs, ss, dsegs, nseg, st, 1));
+    RES_TRY(march_1d(op, k, rows / M, fs, ss, dsegs, nseg, st, M));
     const int64_t i0 = s0 / every;  // sample index of the tile's first snapshot (the state before its first step)
     launch_copy_rows(snap, ncols + 1, out, adjoint ? n - 1 - i0 : i0, adjoint ? -1 : 1, rows / every, ncols,
                      op->fp64(), st);

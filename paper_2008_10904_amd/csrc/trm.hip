@@ -135,19 +135,58 @@ __global__ __launch_bounds__(256) void signal_prefilter_kernel(const cx<TS>* __r
 }
 
 int launch_signal_prefilter(const void* S, int64_t n, int every, int scheme, int rev, const cx<double>* tri,
-                            const void* xin, void* xout, void* g, int fp64, int64_t s0, int64_t rows, int64_t N,
-                            int64_t ncols, double h, int pass, hipStream_t st) {
+                            const void* xin, void* xout, void* g, int fp64, int g_fp64, int64_t s0, int64_t rows,
+                            int64_t N, int64_t ncols, double h, int pass, hipStream_t st) {
   int64_t blocks = (rows * ncols + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) return 0;
-  if (fp64)
-    hipLaunchKernelGGL((signal_prefilter_kernel<double, double>), dim3((unsigned)blocks), dim3(256), 0, st,
-                       (const cx<double>*)S, n, every, scheme, rev, tri, (const cx<double>*)xin, (cx<double>*)xout,
-                       (cx<double>*)g, s0, rows, N, ncols, h, pass);
+#define RES_SP(TS, TO)                                                                                           \
+  hipLaunchKernelGGL((signal_prefilter_kernel<TS, TO>), dim3((unsigned)blocks), dim3(256), 0, st,                \
+                     (const cx<TS>*)S, n, every, scheme, rev, tri, (const cx<double>*)xin, (cx<double>*)xout,     \
+                     (cx<TO>*)g, s0, rows, N, ncols, h, pass)
+  if (fp64) RES_SP(double, double);
+  else if (g_fp64) RES_SP(float, double);
+  else RES_SP(float, float);
+#undef RES_SP
+  return 0;
+}
+
+// One pass of the combined forcing of M steps (the multi-step march of a signal run): with the per-step rows g_s
+// (FP64) and the band of P(Z) (FP64 [N][9], zero across instance boundaries), kernel step R needs
+//     g^(M)_R = sum_{r<M} P^{M-1-r} g_{RM + r},
+// built by Horner passes y_0 = g_{RM}, y_i = P y_{i-1} + g_{RM+i}.  Pass i reads y_{i-1} from rows R * xstride of
+// xin (xstride = M with xin = g for i = 1, else 1) and writes y_i to out (working precision on the last pass).
+template <typename TO>
+__global__ __launch_bounds__(256) void row_horner_kernel(const cx<double>* __restrict__ band,
+                                                         const cx<double>* __restrict__ xin, int64_t xstride,
+                                                         const cx<double>* __restrict__ g, int M, int i,
+                                                         cx<TO>* __restrict__ out, int64_t rows, int64_t N,
+                                                         int64_t ncols) {
+  const int64_t total = rows * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t R = e / ncols, c = e - R * ncols;
+    const int64_t n = c % N;
+    const cx<double>* xr = xin + R * xstride * ncols;
+    cx<double> acc = g[(R * M + i) * ncols + c];
+#pragma unroll
+    for (int d = -kBandRadius; d <= kBandRadius; ++d)
+      if (n + d >= 0 && n + d < N) acc = cfma(band[n * kBandWidth + d + kBandRadius], xr[c + d], acc);
+    out[e] = ccast<TO>(acc);
+  }
+}
+
+int launch_row_horner(const cx<double>* band, const void* xin, int64_t xstride, const void* g, int M, int i,
+                      void* out, int out_fp64, int64_t rows, int64_t N, int64_t ncols, hipStream_t st) {
+  int64_t blocks = (rows * ncols + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return 0;
+  if (out_fp64)
+    hipLaunchKernelGGL((row_horner_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st, band,
+                       (const cx<double>*)xin, xstride, (const cx<double>*)g, M, i, (cx<double>*)out, rows, N, ncols);
   else
-    hipLaunchKernelGGL((signal_prefilter_kernel<float, float>), dim3((unsigned)blocks), dim3(256), 0, st,
-                       (const cx<float>*)S, n, every, scheme, rev, tri, (const cx<double>*)xin, (cx<double>*)xout,
-                       (cx<float>*)g, s0, rows, N, ncols, h, pass);
+    hipLaunchKernelGGL((row_horner_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st, band,
+                       (const cx<double>*)xin, xstride, (const cx<double>*)g, M, i, (cx<float>*)out, rows, N, ncols);
   return 0;
 }
 

@@ -3,7 +3,8 @@ CPU oracle on the same seeded inputs:
 
 * resolvent_signal_run: direct and adjoint runs forced by a sampled signal, for the C0, C1 and C2 interpolation
   schemes, in FP64 (1e-10 per sample vector) and mixed precision (1e-3), on a complex GL operator; batched
-  instances; forcing rows in many small tiles; multi-workgroup stepper plans;
+  instances; forcing rows in many small tiles; multi-workgroup stepper plans; the multi-step march (1, 2 or 4 RK4
+  steps per kernel step) when the samples allow it;
 * resolvent_fir_apply: FP64 (1e-12) and mixed (1e-5), ragged column blocks, an order longer than the series, the
   identity filter;
 * resolvent_trm_modes: the power iteration with FIR flattening on the paper's GL model, gains per iteration and the
@@ -67,6 +68,44 @@ def test_signal_run_matches_oracle(scheme, precision):
         say("  adjoint" if adjoint else "  direct", e)
         assert e < tol
         assert np.abs(y[-1 if adjoint else 0]).max() == 0.0  # the run starts from rest
+
+
+@pytest.mark.parametrize("power", [1, 2, 4])
+def test_signal_run_multistep_matches_oracle(power, monkeypatch):
+    """Samples a multiple of the step power apart: the march takes `power` RK4 steps per kernel step (the band P^m
+    and forcing rows combined by Horner passes); otherwise it falls back to single steps.  Same results as the
+    oracle's single-step march, also under halo plans (relaunch and persistent) and one-interval tiles."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_batched_coefficients
+    inst = [(50, 0.2, -0.01), (37, 0.15, -0.02), (33, 0.12, -0.012)]
+    h = 0.05
+    lo, d, up, off = gl_batched_coefficients(inst, xl=XL_T, xr=XR_T)
+    for every, n in ((4, 26), (8, 13), (6, 17)):
+        F = series(90 + every, n, 2, int(off[-1]))
+        refs = []
+        for m, (nn, mu0, mu2) in enumerate(inst):
+            L, _ = O_ops.gl_operator(nn, mu0, mu2, xl=XL_T, xr=XR_T)
+            sl = slice(int(off[m]), int(off[m + 1]))
+            refs.append((O_trm.march_signal(L, h, F[:, :, sl], every, 2),
+                         O_trm.march_signal(L, h, F[:, :, sl], every, 2, adjoint=True)))
+        for plan, budget in ((None, None), (None, "0.000001"), ("1,40,4,0", None), ("13,64,16", None)):
+            say("case: signal run, step power", power, "every", every, "plan", plan, "tile budget", budget)
+            for name, val in (("RESOLVENT_STEP1D", plan), ("RESOLVENT_TILE_BUDGET_GB", budget)):
+                if val:
+                    monkeypatch.setenv(name, val)
+                else:
+                    monkeypatch.delenv(name, raising=False)
+            op = ResolventOp.tridiagonal(lo, d, up, h, offsets=off)
+            op.set_step_power(power)
+            y = to_np(op.signal_run(gpu_tensor(F), every, "C2"))
+            z = to_np(op.signal_run(gpu_tensor(F), every, "C2", adjoint=True))
+            torch.cuda.synchronize()
+            for m in range(len(inst)):
+                sl = slice(int(off[m]), int(off[m + 1]))
+                e = (per_sample_relerr(y[:, :, sl], refs[m][0]), per_sample_relerr(z[:, :, sl], refs[m][1]))
+                assert max(e) < 1e-10, (m, e)
+            say("  ok")
 
 
 def test_signal_run_batched_tiles_and_plans(monkeypatch):
