@@ -136,6 +136,10 @@ struct resolvent_op {
   bool weighted = false;
   void* d_wsc = nullptr;
   int scale_role = 0;                    // 0: apply/adjoint_apply (y = C R B f), 1: gains and modes (Euclidean R~)
+  // host sources of the TRM driver's asynchronous uploads, kept in the handle so that they outlive the copies
+  std::vector<double> trm_om, trm_D;
+  std::vector<cd> trm_E;
+  cd trm_one = cd(1.0, 0.0);
   bool fp64() const { return prec == RES_FP64; }
   size_t wsize() const { return fp64() ? 16 : 8; }  // bytes per complex in working precision
 };
@@ -1707,8 +1711,8 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
   RES_TRY(ws_get(op, "trm_omegas", (size_t)nw * sizeof(double), &omd));
   RES_TRY(ws_get(op, "trm_part", (size_t)(normalise_parts() + 1) * sizeof(double), &part));
   RES_TRY(ws_get(op, "trm_dft_part", (size_t)series_dft_part_elems(n, ncols, nw) * sizeof(cd), &dpart));
-  std::vector<cd> Etab;
-  std::vector<double> Dq;
+  std::vector<cd>& Etab = op->trm_E;
+  std::vector<double>& Dq = op->trm_D;
   if (passes > 0) {  // the design grid: the response samples (host, per iteration) and the unit circle (once)
     int64_t p2 = 1;
     while (p2 < order) p2 <<= 1;
@@ -1719,8 +1723,10 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
     HIP_TRY(hipMemcpyAsync(dE, Etab.data(), Etab.size() * sizeof(cd), hipMemcpyHostToDevice, st));
   }
   double* scale = (double*)part + normalise_parts();
-  std::vector<double> om(omegas, omegas + nw), hn((size_t)3 * nw), bnu, bgain;
-  const cd one(1.0, 0.0);
+  op->trm_om.assign(omegas, omegas + nw);
+  const std::vector<double>& om = op->trm_om;
+  std::vector<double> hn((size_t)3 * nw), bnu, bgain;
+  const cd& one = op->trm_one;
   HIP_TRY(hipMemcpyAsync(omd, om.data(), (size_t)nw * sizeof(double), hipMemcpyHostToDevice, st));
   // F = taper(f0) / ||taper(f0)||: the identity filter with the taper
   HIP_TRY(hipMemcpyAsync(taps, &one, sizeof(cd), hipMemcpyHostToDevice, st));

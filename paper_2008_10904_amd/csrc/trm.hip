@@ -224,8 +224,10 @@ int launch_copy_rows(const void* src, int64_t src_ld, void* dst, int64_t row0, i
 // and walks the taps: for tap m it needs x[t0 + j + n/2 - m], j < kFirRT, a window that slides down by one sample
 // per tap.  The window lives in registers as a ring (slot (j - u) mod kFirRT at step u of an unrolled group of
 // kFirRT taps), so each tap costs one new sample load, one broadcast read of the tap from LDS (zero-padded to a
-// whole group) and kFirRT complex multiply-adds.  FP64 accumulation in both precisions.
-constexpr int kFirRT = 16;
+// whole group) and kFirRT complex multiply-adds.  FP64 accumulation in both precisions.  Two instantiations:
+// kFirRT = 16 (one load per 64 FMAs), and 8 for grids that would otherwise give the chip fewer than two waves per
+// SIMD.
+constexpr int kFirRT = 16, kFirRTSmall = 8;
 
 __device__ __forceinline__ double taper_at(int64_t t, int64_t T, int64_t pad, int64_t ramp) {
   if (pad < 0) return 1.0;
@@ -241,39 +243,39 @@ __device__ __forceinline__ cx<double> load_or_zero(const cx<T>* __restrict__ x, 
   return (live && q >= 0 && q < Tn) ? ccast<double>(x[q * ncols + c]) : mk<double>(0.0, 0.0);
 }
 
-template <typename T>
+template <typename T, int RT>
 __global__ __launch_bounds__(256) void fir_kernel(const cx<double>* __restrict__ taps, int order,
                                                   const cx<T>* __restrict__ x, cx<T>* __restrict__ y, int64_t Tn,
                                                   int64_t ncols, int64_t pad, int64_t ramp) {
   extern __shared__ cx<double> sb[];
-  const int ntap = (order + kFirRT) / kFirRT * kFirRT;  // order + 1 rounded up to whole groups
+  const int ntap = (order + RT) / RT * RT;  // order + 1 rounded up to whole groups
   for (int m = threadIdx.x; m < ntap; m += blockDim.x) sb[m] = m <= order ? taps[m] : mk<double>(0.0, 0.0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t t0 = ((int64_t)blockIdx.y * (blockDim.x >> 6) + wave) * kFirRT;
+  const int64_t t0 = ((int64_t)blockIdx.y * (blockDim.x >> 6) + wave) * RT;
   if (t0 >= Tn) return;
   const bool live = c < ncols;
   const int64_t base = t0 + order / 2;  // x index of output j at tap m: base + j - m
-  cx<double> acc[kFirRT], ring[kFirRT];
+  cx<double> acc[RT], ring[RT];
 #pragma unroll
-  for (int j = 0; j < kFirRT; ++j) {
+  for (int j = 0; j < RT; ++j) {
     acc[j] = mk<double>(0.0, 0.0);
     ring[j] = load_or_zero(x, base + j, Tn, ncols, c, live);
   }
-  for (int m0 = 0; m0 < ntap; m0 += kFirRT) {
+  for (int m0 = 0; m0 < ntap; m0 += RT) {
 #pragma unroll
-    for (int u = 0; u < kFirRT; ++u) {
+    for (int u = 0; u < RT; ++u) {
       const cx<double> b = sb[m0 + u];
 #pragma unroll
-      for (int j = 0; j < kFirRT; ++j) acc[j] = cfma(b, ring[(j - u + kFirRT) % kFirRT], acc[j]);
-      // the slot of offset j - u = kFirRT - 1 - u is not needed again: it takes the sample of offset -(u + 1)
-      ring[(kFirRT - 1 - u) % kFirRT] = load_or_zero(x, base - (m0 + u) - 1, Tn, ncols, c, live);
+      for (int j = 0; j < RT; ++j) acc[j] = cfma(b, ring[(j - u + RT) % RT], acc[j]);
+      // the slot of offset j - u = RT - 1 - u is not needed again: it takes the sample of offset -(u + 1)
+      ring[(RT - 1 - u) % RT] = load_or_zero(x, base - (m0 + u) - 1, Tn, ncols, c, live);
     }
   }
   if (!live) return;
 #pragma unroll
-  for (int j = 0; j < kFirRT; ++j) {
+  for (int j = 0; j < RT; ++j) {
     const int64_t t = t0 + j;
     if (t < Tn) {
       const double w = taper_at(t, Tn, pad, ramp);
@@ -287,14 +289,22 @@ int fir_max_order() { return 65536 / (int)sizeof(cx<double>) - kFirRT; }
 int launch_fir(const cx<double>* taps, int order, const void* x, void* y, int64_t Tn, int64_t ncols, int64_t pad,
                int64_t ramp, int fp64, hipStream_t st) {
   if (order < 0 || order > fir_max_order() || Tn < 1 || ncols < 1) return -1;
-  const dim3 grid((unsigned)((ncols + 63) / 64), (unsigned)((Tn + 4 * kFirRT - 1) / (4 * kFirRT)));
-  const size_t lds = (size_t)((order + kFirRT) / kFirRT * kFirRT) * sizeof(cx<double>);
-  if (fp64)
-    hipLaunchKernelGGL((fir_kernel<double>), grid, dim3(256), lds, st, taps, order, (const cx<double>*)x,
-                       (cx<double>*)y, Tn, ncols, pad, ramp);
-  else
-    hipLaunchKernelGGL((fir_kernel<float>), grid, dim3(256), lds, st, taps, order, (const cx<float>*)x,
-                       (cx<float>*)y, Tn, ncols, pad, ramp);
+  const int64_t cblocks = (ncols + 63) / 64;
+  const bool small = cblocks * ((Tn + kFirRT - 1) / kFirRT) < 2 * 1024;  // waves at 16 outputs per lane
+  const int rt = small ? kFirRTSmall : kFirRT;
+  const dim3 grid((unsigned)cblocks, (unsigned)((Tn + 4 * rt - 1) / (4 * rt)));
+  const size_t lds = (size_t)((order + rt) / rt * rt) * sizeof(cx<double>);
+#define RES_FIR(T, R)                                                                                           \
+  hipLaunchKernelGGL((fir_kernel<T, R>), grid, dim3(256), lds, st, taps, order, (const cx<T>*)x, (cx<T>*)y, Tn,  \
+                     ncols, pad, ramp)
+  if (fp64) {
+    if (small) RES_FIR(double, kFirRTSmall);
+    else RES_FIR(double, kFirRT);
+  } else {
+    if (small) RES_FIR(float, kFirRTSmall);
+    else RES_FIR(float, kFirRT);
+  }
+#undef RES_FIR
   return 0;
 }
 
