@@ -165,6 +165,28 @@ def test_fir_apply_matches_oracle(precision):
         assert e < tol
 
 
+def test_fir_apply_at_the_largest_order():
+    """The largest order (its padded taps fill 64 KiB of LDS) on a series shorter than the filter, and one order
+    beyond it refused."""
+    import torch
+    from paper_2008_10904_amd import ResolventError
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.api import fir_apply, fir_design
+    say("case: FIR apply at order 4080")
+    b = fir_design(4080, [-1.0, -0.1, 0.0, 0.1, 1.0], [0.0, 0.0, 1.0, 0.0, 0.0])
+    for T, cols in ((900, 5), (5000, 70)):
+        X = series(87, T, 1, cols)
+        y = to_np(fir_apply(b, gpu_tensor(X)))
+        torch.cuda.synchronize()
+        ref = O_trm.fir_apply(b, X)
+        e = np.abs(y - ref).max() / np.abs(ref).max()
+        say("  T = %d, cols = %d:" % (T, cols), e)
+        assert e < 1e-12
+    with pytest.raises(ResolventError) as err:
+        fir_apply(np.ones(4083), gpu_tensor(series(88, 10, 1, 3)))  # order 4082: even, beyond the limit
+    assert err.value.code == L.RES_EINVAL
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_trm_modes_match_oracle(precision):
     import torch
