@@ -250,14 +250,15 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  * A signal is a series of samples [n_samples][k][N] (caller-owned device memory, complex128 for RES_FP64 handles,
  * complex64 for RES_MIXED ones, interleaved): sample i is the signal at t_i = i * every * h.
  *
- * resolvent_signal_run: the run of a RES_OP_TRIDIAG operator forced by a sampled signal, from rest (Sec. 2.2,
+ * resolvent_signal_run: the run of an operator (three-point or grid) forced by a sampled signal, from rest (Sec. 2.2,
  * eqs. system and adsystem with B = C = I).  adjoint = 0: du/dt = L u + f(t), u(0) = 0; y receives u(t_i).
  * adjoint = 1: -dz/dt = L^H z + f(t) backward in time from z(T) = 0, T = (n_samples - 1) every h; y receives
  * z(t_i).  Classical RK4 with step h; each stage is forced by the signal at its own time, interpolated between
  * samples (App. C) by scheme 0 (C0, linear), 1 (C1, cubic Hermite on second-order central derivatives, first-order
  * one-sided at the end samples) or 2 (C2, quintic Hermite on five-point first and second derivatives;
  * second-order at the samples next to the ends, first-order first derivative and zero second derivative at the end
- * samples).  f and y must not alias.  RES_ENOTSUP for grid operators and while weights are set; RES_EINVAL for
+ * samples).  Three-point operators take m RK4 steps per kernel step (resolvent_op_set_step_power) when every is a
+ * multiple of m; grid operators one.  f and y must not alias.  RES_ENOTSUP while weights are set; RES_EINVAL for
  * k < 1, n_samples < 2, every < 1 or an unknown scheme.  Asynchronous on `stream`.
  *
  * resolvent_fir_design: a linear-phase FIR filter of even order n (n + 1 taps, App. B) approximating a desired

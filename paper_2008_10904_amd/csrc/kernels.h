@@ -145,6 +145,12 @@ int launch_row_horner(const cx<double>* band, const void* xin, int64_t xstride, 
                       void* out, int out_fp64, int64_t rows, int64_t N, int64_t ncols, hipStream_t st);
 int launch_copy_rows(const void* src, int64_t src_ld, void* dst, int64_t row0, int dir, int64_t rows, int64_t ncols,
                      int fp64, hipStream_t st);
+// Grid operators: the signal at the half steps of a tile (FP64 [nhalf][ncols]), and one pre-filter pass over `rows`
+// steps with the FP64 coefficient set g64 (passes 0, 1 write FP64 xout; pass 2 the rows g, working precision).
+int launch_signal_half_rows(const void* S, int64_t n, int every, int scheme, int rev, int fp64, void* H, int64_t s0,
+                            int64_t nhalf, int64_t ncols, hipStream_t st);
+int launch_grid_signal_pass(const GridOpDev& g64, const void* H, const void* xin, void* xout, void* g, int out_fp64,
+                            int k, int64_t rows, double h, int pass, hipStream_t st);
 int fir_max_order();
 // y = delay-compensated FIR of x along time (taps FP64 complex [order+1] on the device), times the taper of
 // `pad`/`ramp` samples (pad < 0: none).  Returns -1 for an order beyond fir_max_order().

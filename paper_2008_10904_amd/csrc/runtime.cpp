@@ -1519,8 +1519,65 @@ int modes_to_problem(resolvent_op* op, int nw, int k, void* V, void* U, hipStrea
 // pre-filter, in tiles of whole sample intervals.  When the samples are a multiple of the operator's step power m
 // apart (and the plan's exchange interval allows it), the march takes m RK4 steps per kernel step with the band
 // P(Z)^m, its forcing rows combined from the per-step rows by m - 1 Horner passes of P(Z); else one step at a time.
+// The same for a grid operator: the signal at the half steps of each tile first (FP64), then the three pre-filter
+// passes with the grid stencil, then the grid march (one RK4 step per launch or launch pair).
+int signal_run_grid(resolvent_op* op, int k, int64_t n, int every, int scheme, int adjoint, const void* in,
+                    void* out, hipStream_t st) {
+  const int64_t ncols = (int64_t)k * op->N;
+  const size_t ws = op->wsize();
+  const int s = adjoint ? 1 : 0;
+  const int64_t S = (n - 1) * (int64_t)every;
+  const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
+  const double per_step = (double)ncols * (4.0 * sizeof(cd) + (double)ws) + (double)(ncols + 1) * ws / every;
+  int64_t tile = std::min<int64_t>((int64_t)(tile_budget / per_step), 4096) / every * every;
+  if (tile < every) tile = every;
+  if (tile > S) tile = S;
+  if (tile > 65535) return fail(RES_EINVAL, "sample interval too long for the grid pre-filter");
+  void *H, *x2, *x1, *frc, *snap, *st0;
+  RES_TRY(ws_get(op, "sig_half", (size_t)(2 * tile + 1) * ncols * sizeof(cd), &H));
+  RES_TRY(ws_get(op, "sig_x2", (size_t)tile * ncols * sizeof(cd), &x2));
+  RES_TRY(ws_get(op, "sig_x1", (size_t)tile * ncols * sizeof(cd), &x1));
+  RES_TRY(ws_get(op, "forcing", (size_t)tile * ncols * ws, &frc));
+  RES_TRY(ws_get(op, "sig_snap", (size_t)(tile / every) * (ncols + 1) * ws, &snap));
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
+  RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &st0));
+  RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &st0));
+  op->cur_state = 0;
+  RES_TRY(zero_device(st0, (size_t)ncols * ws, st));
+  op->march_grid = &op->gw[s];
+  for (int64_t s0 = 0; s0 < S; s0 += tile) {
+    const int64_t rows = std::min(tile, S - s0);
+    {
+      TimedLaunch tl(op, RES_TIMING_SYNTHESIS, st);
+      launch_signal_half_rows(in, n, every, scheme, adjoint, op->fp64(), H, s0, 2 * rows + 1, ncols, st);
+      for (int pass = 0; pass < 3; ++pass)
+        if (launch_grid_signal_pass(op->g64[s], H, pass == 1 ? x2 : x1, pass == 0 ? x2 : x1, frc,
+                                    pass == 2 ? op->fp64() : 1, k, rows, op->h, pass, st))
+          return fail(RES_EINVAL, "grid pre-filter launch");
+    }
+    ForceSpec fs;
+    fs.frc = frc;
+    SnapSpec ss;
+    ss.snap = snap;
+    ss.ld = ncols + 1;
+    ss.first = 0;
+    ss.stride = every;
+    ss.count = rows / every;
+    RES_TRY(march_grid(op, k, rows, fs, ss, st));
+    const int64_t i0 = s0 / every;
+    launch_copy_rows(snap, ncols + 1, out, adjoint ? n - 1 - i0 : i0, adjoint ? -1 : 1, rows / every, ncols,
+                     op->fp64(), st);
+  }
+  void* cur;
+  RES_TRY(ws_get(op, op->cur_state ? "state1" : "state0", (size_t)ncols * ws, &cur));
+  launch_copy_rows(cur, ncols, out, adjoint ? 0 : n - 1, 1, 1, ncols, op->fp64(), st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int adjoint, const void* in, void* out,
                hipStream_t st) {
+  if (is_grid(op)) return signal_run_grid(op, k, n, every, scheme, adjoint, in, out, st);
   const int64_t N = op->N, ncols = (int64_t)k * N;
   const size_t ws = op->wsize();
   const int s = adjoint ? 1 : 0;
@@ -1594,7 +1651,6 @@ int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int ad
 }
 
 int signal_args(const resolvent_op* op, int k, int64_t n, int every, int scheme) {
-  if (is_grid(op)) return fail(RES_ENOTSUP, "runs forced by a sampled signal are built for 1-D operators");
   if (op->weighted) return fail(RES_ENOTSUP, "runs forced by a sampled signal do not apply B, C or metrics");
   if (k < 1 || n < 2 || every < 1) return fail(RES_EINVAL, "need k >= 1, at least two samples and every >= 1");
   if (scheme < 0 || scheme > 2) return fail(RES_EINVAL, "interpolation scheme must be 0 (C0), 1 (C1) or 2 (C2)");

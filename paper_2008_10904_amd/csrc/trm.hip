@@ -4,6 +4,7 @@
 // t_i = i * every * h.  The run forced by it is the ordinary 1-D stepper fed with one forcing row per RK4 step;
 // the rows come from the stage-forcing pre-filter below, which interpolates the samples at the stage times.
 #include "common.h"
+#include "gridz.h"
 #include "kernels.h"
 
 namespace res {
@@ -187,6 +188,95 @@ int launch_row_horner(const cx<double>* band, const void* xin, int64_t xstride, 
   else
     hipLaunchKernelGGL((row_horner_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st, band,
                        (const cx<double>*)xin, xstride, (const cx<double>*)g, M, i, (cx<float>*)out, rows, N, ncols);
+  return 0;
+}
+
+// ---- grid operators ------------------------------------------------------------------------------------------
+// The signal at the half steps of a tile, H[q][c] = f((2 s0 + q) h / 2) for q < nhalf (FP64).
+template <typename TS>
+__global__ __launch_bounds__(256) void signal_half_rows_kernel(const cx<TS>* __restrict__ S, int64_t n, int every,
+                                                               int scheme, int rev, cx<double>* __restrict__ H,
+                                                               int64_t s0, int64_t nhalf, int64_t ncols) {
+  const int64_t total = nhalf * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e / ncols, c = e - q * ncols;
+    H[e] = signal_at(S, n, ncols, c, 2 * s0 + q, every, scheme, rev);
+  }
+}
+
+int launch_signal_half_rows(const void* S, int64_t n, int every, int scheme, int rev, int fp64, void* H, int64_t s0,
+                            int64_t nhalf, int64_t ncols, hipStream_t st) {
+  int64_t blocks = (nhalf * ncols + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return 0;
+  if (fp64)
+    hipLaunchKernelGGL((signal_half_rows_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const cx<double>*)S, n, every, scheme, rev, (cx<double>*)H, s0, nhalf, ncols);
+  else
+    hipLaunchKernelGGL((signal_half_rows_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const cx<float>*)S, n, every, scheme, rev, (cx<double>*)H, s0, nhalf, ncols);
+  return 0;
+}
+
+// One pass of the stage-forcing pre-filter (the same three passes as signal_prefilter_kernel) for a grid operator:
+// f_a, f_b, f_c of row r are the half-step rows 2r, 2r + 1, 2r + 2 of H, and Z is the grid stencil (FP64
+// coefficients).  Workgroup (x, y, z) = (node block, column, row).
+template <typename TO, int NC>
+__global__ __launch_bounds__(256) void grid_signal_pass_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int64_t nz,
+                                                               const cx<double>* __restrict__ H,
+                                                               const cx<double>* __restrict__ xin,
+                                                               cx<double>* __restrict__ xout, cx<TO>* __restrict__ g,
+                                                               int k, double h, int pass) {
+  const int64_t nodes = nx * ny * nz;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= nodes) return;
+  const int64_t ix = p % nx, l = p / nx, iy = l % ny, iz = l / ny;
+  const int64_t blk = (int64_t)NC * nodes, ncols = (int64_t)k * blk;
+  const int64_t b = blockIdx.y, r = blockIdx.z;
+  const cx<double>* fa = H + (2 * r) * ncols + b * blk;
+  const cx<double>* fb = fa + ncols;
+  const cx<double>* x = pass == 0 ? fa : xin + r * ncols + b * blk;
+  cx<double> zx[NC];
+  apply_z<double, NC>(Cf, x, nodes, nx, ny, nz, ix, iy, iz, p, l, zx);
+  const int64_t base = r * ncols + b * blk + p;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const cx<double> a = fa[c * nodes + p], bb = fb[c * nodes + p];
+    if (pass == 0) {
+      xout[base + c * nodes] = mk<double>(0.5 * (a.re + bb.re) + 0.25 * zx[c].re, 0.5 * (a.im + bb.im) + 0.25 * zx[c].im);
+    } else if (pass == 1) {
+      xout[base + c * nodes] = mk<double>(a.re + 2.0 * bb.re + zx[c].re, a.im + 2.0 * bb.im + zx[c].im);
+    } else {
+      const cx<double> fc = fb[ncols + c * nodes + p];
+      const double cc = h / 6.0;
+      g[base + c * nodes] = ccast<TO>(mk<double>(cc * (a.re + 4.0 * bb.re + fc.re + zx[c].re),
+                                                 cc * (a.im + 4.0 * bb.im + fc.im + zx[c].im)));
+    }
+  }
+}
+
+// rows <= 65535 and k <= 65535 (grid dimensions).
+int launch_grid_signal_pass(const GridOpDev& g64, const void* H, const void* xin, void* xout, void* g, int out_fp64,
+                            int k, int64_t rows, double h, int pass, hipStream_t st) {
+  if (rows < 1 || rows > 65535 || k < 1 || k > 65535) return -1;
+  const int64_t nodes = g64.nx * g64.ny * g64.nz;
+  GridCoef<double> c;
+  c.cxm = (const double*)g64.cxm; c.cxp = (const double*)g64.cxp; c.cym = (const double*)g64.cym;
+  c.cyp = (const double*)g64.cyp; c.czm = (const double*)g64.czm; c.czp = (const double*)g64.czp;
+  c.d = (const double*)g64.d; c.K = (const double*)g64.K;
+  const dim3 grid((unsigned)((nodes + 255) / 256), (unsigned)k, (unsigned)rows);
+#define RES_GS(TO, NC)                                                                                          \
+  hipLaunchKernelGGL((grid_signal_pass_kernel<TO, NC>), grid, dim3(256), 0, st, c, g64.nx, g64.ny, g64.nz,       \
+                     (const cx<double>*)H, (const cx<double>*)xin, (cx<double>*)xout, (cx<TO>*)g, k, h, pass)
+  if (g64.ncomp == 3) {
+    if (out_fp64) RES_GS(double, 3);
+    else RES_GS(float, 3);
+  } else {
+    if (out_fp64) RES_GS(double, 1);
+    else RES_GS(float, 1);
+  }
+#undef RES_GS
   return 0;
 }
 

@@ -4,7 +4,7 @@ CPU oracle on the same seeded inputs:
 * resolvent_signal_run: direct and adjoint runs forced by a sampled signal, for the C0, C1 and C2 interpolation
   schemes, in FP64 (1e-10 per sample vector) and mixed precision (1e-3), on a complex GL operator; batched
   instances; forcing rows in many small tiles; multi-workgroup stepper plans; the multi-step march (1, 2 or 4 RK4
-  steps per kernel step) when the samples allow it;
+  steps per kernel step) when the samples allow it; the 2-D and 3-D grid operators;
 * resolvent_fir_apply: FP64 (1e-12) and mixed (1e-5), ragged column blocks, an order longer than the series, the
   identity filter;
 * resolvent_trm_modes: the power iteration with FIR flattening on the paper's GL model, gains per iteration and the
@@ -106,6 +106,71 @@ def test_signal_run_multistep_matches_oracle(power, monkeypatch):
                 e = (per_sample_relerr(y[:, :, sl], refs[m][0]), per_sample_relerr(z[:, :, sl], refs[m][1]))
                 assert max(e) < 1e-10, (m, e)
             say("  ok")
+
+
+WAKE = dict(amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+
+
+@pytest.mark.parametrize("case", ["2d-fp64", "2d-mixed", "3d-fp64", "3d-mixed"])
+def test_signal_run_grid_matches_oracle(case, monkeypatch):
+    """Signal runs of the 2-D five-point and 3-D three-component operators (one RK4 step per launch or launch
+    pair), whole-run tiles and one-interval tiles, against the oracle's march_signal on the same sparse L."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients, adr3d3c_coefficients
+    kind, precision = case.split("-")
+    h, every, n = 0.1, 2, 21
+    if kind == "2d":
+        nx, ny, nz, k = 24, 16, 1, 2
+        f = O_ops.adr2d_fields(nx, ny)
+        mu = O_ops.adr2d_mu_default(f["X"], f["Y"], base=-0.3, amp=0.08)
+        op = ResolventOp.grid_operator("adr2d", nx, ny, 1, adr2d_coefficients(nx, ny, mu=mu), h, precision=precision)
+        L, _ = O_ops.adr2d_operator(nx, ny, mu=mu)
+    else:
+        nx, ny, nz, k = 12, 8, 6, 1
+        mu = np.full((nz, ny, nx), -0.2)
+        op = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, adr3d3c_coefficients(nx, ny, nz, WAKE, mu=mu), h,
+                                       precision=precision)
+        L, _ = O_ops.adr3d3c_operator(nx, ny, nz, WAKE, mu=mu)
+    F = series(95, n, k, op.n)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    tol = 1e-10 if precision == "fp64" else 1e-3
+    refs = (O_trm.march_signal(L, h, F, every, 2), O_trm.march_signal(L, h, F, every, 2, adjoint=True))
+    for budget in (None, "0.000001"):
+        say("case: grid signal run", case, "tile budget", budget)
+        if budget:
+            monkeypatch.setenv("RESOLVENT_TILE_BUDGET_GB", budget)
+        else:
+            monkeypatch.delenv("RESOLVENT_TILE_BUDGET_GB", raising=False)
+        for adjoint, ref in zip((False, True), refs):
+            y = to_np(op.signal_run(gpu_tensor(F, dt), every, "C2", adjoint=adjoint))
+            torch.cuda.synchronize()
+            e = per_sample_relerr(y, ref)
+            say("  adjoint" if adjoint else "  direct", e)
+            assert e < tol
+
+
+def test_trm_modes_on_a_grid_operator():
+    """The TRM iteration with FIR flattening on the 2-D operator against the oracle's trm_power_iteration."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    say("case: TRM iteration on a 2-D grid operator 24 x 16")
+    nx, ny, h, every, n = 24, 16, 0.1, 2, 301
+    f = O_ops.adr2d_fields(nx, ny)
+    mu = O_ops.adr2d_mu_default(f["X"], f["Y"], base=-0.3, amp=0.08)
+    op = ResolventOp.grid_operator("adr2d", nx, ny, 1, adr2d_coefficients(nx, ny, mu=mu), h)
+    L, _ = O_ops.adr2d_operator(nx, ny, mu=mu)
+    om = np.linspace(-2.0, 2.0, 17)
+    kw = dict(order=60, passes=2, pad=25, ramp=15, margin=0.5)
+    F0 = series(96, n, 1, op.n)
+    g_ref, a_ref, _, V_ref, U_ref = O_trm.trm_power_iteration(L, h, every, 2, F0, om, 3, want_modes=True, **kw)
+    g, a, _, V, U = op.trm_modes(gpu_tensor(F0), om, 3, every, "C2", want_modes=True, **kw)
+    torch.cuda.synchronize()
+    e = (np.abs(g / g_ref - 1).max(), np.abs(a / a_ref - 1).max(),
+         max(np.abs(to_np(V) - V_ref).max(), np.abs(to_np(U) - U_ref).max()))
+    say("  gains, amplitudes, modes", e)
+    assert max(e) < 1e-8
 
 
 def test_signal_run_batched_tiles_and_plans(monkeypatch):
@@ -229,7 +294,6 @@ def test_trm_errors():
     from paper_2008_10904_amd import ResolventError, ResolventOp
     from paper_2008_10904_amd import _lib as L
     from paper_2008_10904_amd.api import fir_apply
-    from paper_2008_10904_amd.operators import adr2d_coefficients
     say("case: TRM argument errors")
     op = gl_op(20, 0.05)
     F = gpu_tensor(series(85, 10, 1, 20))
@@ -248,9 +312,8 @@ def test_trm_errors():
     with pytest.raises(ResolventError) as e:
         fir_apply(np.ones(4), F)  # odd order
     assert e.value.code == L.RES_EINVAL
-    c = adr2d_coefficients(16, 8)
-    gop = ResolventOp.grid_operator("adr2d", 16, 8, 1, c, 0.02, precision="mixed")
+    op.set_weights(np.ones(20), np.ones(20), np.ones(20), np.ones(20))
     with pytest.raises(ResolventError) as e:
-        gop.signal_run(gpu_tensor(series(86, 4, 1, 128), torch.complex64), 2)
+        op.signal_run(F, 2)
     assert e.value.code == L.RES_ENOTSUP
     torch.cuda.synchronize()
