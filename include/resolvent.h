@@ -258,8 +258,10 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  * one-sided at the end samples) or 2 (C2, quintic Hermite on five-point first and second derivatives;
  * second-order at the samples next to the ends, first-order first derivative and zero second derivative at the end
  * samples).  Three-point operators take m RK4 steps per kernel step (resolvent_op_set_step_power) when every is a
- * multiple of m; grid operators one.  f and y must not alias.  RES_ENOTSUP while weights are set; RES_EINVAL for
- * k < 1, n_samples < 2, every < 1 or an unknown scheme.  Asynchronous on `stream`.
+ * multiple of m; grid operators one.  With B, C and metrics set (resolvent_op_set_weights) the run returns C u for
+ * the forcing B f, and the adjoint run W_f^{-1} B^H z for the forcing C^H W_y f, as resolvent_apply and
+ * resolvent_adjoint_apply do.  f and y must not alias.  RES_EINVAL for k < 1, n_samples < 2, every < 1 or an
+ * unknown scheme.  Asynchronous on `stream`.
  *
  * resolvent_fir_design: a linear-phase FIR filter of even order n (n + 1 taps, App. B) approximating a desired
  * amplitude response given at npts breakpoints nu (non-decreasing in [-1, 1]: frequency over the Nyquist
@@ -288,6 +290,9 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  *      (1/||W(w_j)||)^(1/passes) at the analysis frequencies (largest 1), falling linearly to zero `margin`
  *      rad per time unit outside them and zero beyond (passes = 0: no filter);
  *   4. hands the result back, tapered and normalised, as the next F.
+ * With B, C and metrics set the iteration runs on the Euclidean R~ = W_y^{1/2} C R B W_f^{-1/2} as resolvent_modes
+ * does: f0 is taken in the problem's coordinates (times W_f^{1/2} before the taper), F, Y, W and the gains are those
+ * of R~, and the modes come back as W_f^{-1/2} V~ and W_y^{-1/2} U~.
  * f_out (device, may be NULL) receives the last F; V and U (device [n_omega][k][N] in the handle's I/O type, each
  * may be NULL) receive the force and response modes of the last iteration, F(w_j) / ||F(w_j)|| and
  * Y(w_j) / ||Y(w_j)|| (for k = 1 the leading modes at any analysis frequency).  The flattening response spans the square of the gain range,

@@ -193,11 +193,12 @@ def flattening_breakpoints(omegas, Wh_norm, dt, margin):
 
 
 def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp, margin, passes=1, flatten=True,
-                        want_modes=False):
+                        want_modes=False, runs=None):
     """Returns (gains (iters, n_w): ||Y(w_j)|| / ||F(w_j)|| of each iteration's forcing, amplitudes (iters, n_w):
     ||F(w_j)|| of each iteration's forcing, F the last forcing series), and with want_modes also the force and
     response modes of the last iteration at the analysis frequencies, V = F(w_j) / ||F(w_j)|| and
-    U = Y(w_j) / ||Y(w_j)|| (n_w, k, N).  F0 (n, k, N) is tapered first."""
+    U = Y(w_j) / ||Y(w_j)|| (n_w, k, N).  F0 (n, k, N) is tapered first.  `runs` = (direct, adjoint) maps of
+    sample series replace the signal runs of L (e.g. with input and output matrices wrapped around them)."""
     n = F0.shape[0]
     dt = every * h
     win = taper(n, pad, ramp)[:, None, None]
@@ -205,9 +206,12 @@ def trm_power_iteration(L, h, every, scheme, F0, omegas, iters, order, pad, ramp
     F = F / np.linalg.norm(F)
     gains = np.zeros((iters, len(omegas)))
     amps = np.zeros((iters, len(omegas)))
+    if runs is None:
+        runs = (lambda X: march_signal(L, h, X, every, scheme),
+                lambda X: march_signal(L, h, X, every, scheme, adjoint=True))
     for it in range(iters):
-        Y = march_signal(L, h, F, every, scheme)
-        W = march_signal(L, h, Y, every, scheme, adjoint=True)
+        Y = runs[0](F)
+        W = runs[1](Y)
         Fs, Ys = dft(F, omegas, dt), dft(Y, omegas, dt)
         Fh = np.linalg.norm(Fs.reshape(len(omegas), -1), axis=1)
         Yh = np.linalg.norm(Ys.reshape(len(omegas), -1), axis=1)

@@ -1650,8 +1650,32 @@ int signal_run(resolvent_op* op, int k, int64_t n, int every, int scheme, int ad
   return RES_OK;
 }
 
+// A signal run with the diagonal B, C and metrics around it (the node scalings of run_any, by role and direction):
+// observed runs C R B f and W_f^{-1} B R^H C W_y y, or the Euclidean R~ and R~^H of the gains and modes.
+int signal_run_any(resolvent_op* op, int k, int64_t n, int every, int scheme, int adjoint, const void* in, void* out,
+                   hipStream_t st) {
+  if (!op->weighted) return signal_run(op, k, n, every, scheme, adjoint, in, out, st);
+  int rin, rout;
+  if (op->scale_role == 0) {
+    rin = adjoint ? kWscCWy : kWscB;
+    rout = adjoint ? kWscBInvWf : kWscC;
+  } else {
+    rin = adjoint ? kWscCSqrtWy : kWscBInvSqrtWf;
+    rout = adjoint ? kWscBInvSqrtWf : kWscCSqrtWy;
+  }
+  const double* w = (const double*)op->d_wsc;
+  const int64_t blocks = n * k;
+  const int fp = op->fp64();
+  void* tmp;
+  RES_TRY(ws_get(op, "sig_wsc_in", (size_t)blocks * op->N * op->wsize(), &tmp));
+  launch_node_scale(in, fp, tmp, fp, w + (size_t)rin * op->N, blocks, op->N, st);
+  RES_TRY(signal_run(op, k, n, every, scheme, adjoint, tmp, out, st));
+  launch_node_scale(out, fp, out, fp, w + (size_t)rout * op->N, blocks, op->N, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
 int signal_args(const resolvent_op* op, int k, int64_t n, int every, int scheme) {
-  if (op->weighted) return fail(RES_ENOTSUP, "runs forced by a sampled signal do not apply B, C or metrics");
   if (k < 1 || n < 2 || every < 1) return fail(RES_EINVAL, "need k >= 1, at least two samples and every >= 1");
   if (scheme < 0 || scheme > 2) return fail(RES_EINVAL, "interpolation scheme must be 0 (C0), 1 (C1) or 2 (C2)");
   return RES_OK;
@@ -1784,14 +1808,19 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
   std::vector<double> hn((size_t)3 * nw), bnu, bgain;
   const cd& one = op->trm_one;
   HIP_TRY(hipMemcpyAsync(omd, om.data(), (size_t)nw * sizeof(double), hipMemcpyHostToDevice, st));
-  // F = taper(f0) / ||taper(f0)||: the identity filter with the taper
+  // F = taper(f0) / ||taper(f0)||: the identity filter with the taper (with metrics, of W_f^{1/2} f0: the iteration
+  // runs on the Euclidean R~)
+  ModesRole role(op);
   HIP_TRY(hipMemcpyAsync(taps, &one, sizeof(cd), hipMemcpyHostToDevice, st));
   if (launch_fir((const cx<double>*)taps, 0, f0, F, n, ncols, pad, ramp, op->fp64(), st))
     return fail(RES_EINVAL, "taper launch");
+  if (op->weighted)
+    launch_node_scale(F, op->fp64(), F, op->fp64(), (const double*)op->d_wsc + (size_t)kWscSqrtWf * op->N, n * k,
+                      op->N, st);
   launch_normalise(F, op->fp64(), count, (double*)part, scale, st);
   for (int it = 0; it < iters; ++it) {
-    RES_TRY(signal_run(op, k, n, every, scheme, 0, F, Y, st));
-    RES_TRY(signal_run(op, k, n, every, scheme, 1, Y, W, st));
+    RES_TRY(signal_run_any(op, k, n, every, scheme, 0, F, Y, st));
+    RES_TRY(signal_run_any(op, k, n, every, scheme, 1, Y, W, st));
     const void* ser[3] = {F, Y, W};
     {
       TimedLaunch tl(op, RES_TIMING_PROJECTION, st);
@@ -1815,6 +1844,7 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
           return fail(RES_EINVAL, "series too long for the transform's chunk grid");
         launch_scale_rows(hat, (const double*)nrm + (size_t)q * nw, nw, ncols, mo[q], op->fp64(), st);
       }
+      if (op->weighted) RES_TRY(modes_to_problem(op, nw, k, V, U, st));  // W_f^{-1/2} V~, W_y^{-1/2} U~
     }
     if (it + 1 == iters && !f_out) break;
     if (passes == 0) {
@@ -2333,7 +2363,7 @@ int resolvent_signal_run(resolvent_op* op, int32_t k, int64_t n_samples, int32_t
   RES_TRY(signal_args(op, k, n_samples, every, scheme));
   hipStream_t st = (hipStream_t)stream;
   CaptureScope cap(op, st);
-  RES_TRY(signal_run(op, k, n_samples, every, scheme, adjoint ? 1 : 0, f, y, st));
+  RES_TRY(signal_run_any(op, k, n_samples, every, scheme, adjoint ? 1 : 0, f, y, st));
   launch_finite(y, op->fp64(), n_samples * k * op->N, op->d_flag, st);
   HIP_TRY(hipGetLastError());
   return RES_OK;
