@@ -213,7 +213,8 @@ int resolvent_op_set_plan(resolvent_op* op, const int32_t plan[4]);
  *   resolvent_modes and resolvent_krylov maximise ||C R_d B f||_{W_y} / ||f||_{W_f}: they iterate on the Euclidean
  *   R~ = W_y^{1/2} C R_d B W_f^{-1/2}, take f0_hat in the problem's coordinates and return W_f-orthonormal force
  *   modes V and response modes U = C R_d B V / sigma.
- * The reverse mode (resolvent_apply_backward) returns RES_ENOTSUP while weights are set.  RES_EINVAL for
+ * The reverse mode (resolvent_apply_backward) differentiates y = C R_d B f: the forcing gradient is
+ * B R_d^H C g and the mu gradient that of R_d at the input B f with the cotangent C g.  RES_EINVAL for
  * non-finite b or c, wf or wy not finite and positive, or during graph capture. */
 int resolvent_op_set_weights(resolvent_op* op, const double* b, const double* c, const double* wf,
                              const double* wy);

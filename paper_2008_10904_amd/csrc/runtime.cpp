@@ -2347,12 +2347,26 @@ int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const
   if (!op || !f_hat || !g_hat) return fail(RES_EINVAL, "NULL argument");
   if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
   if (checkpoint_every < 0) return fail(RES_EINVAL, "checkpoint_every must be >= 0");
-  if (op->weighted) return fail(RES_ENOTSUP, "the reverse mode does not take B, C or metric weights");
   Plan pl;
   RES_TRY(make_plan(op, grid, run, &pl));
   if (!f_grad && !mu_grad) return RES_OK;
-  CaptureScope cap(op, (hipStream_t)stream);
-  return backward(op, pl, k, f_hat, g_hat, f_grad, mu_grad, checkpoint_every, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  CaptureScope cap(op, st);
+  if (!op->weighted) return backward(op, pl, k, f_hat, g_hat, f_grad, mu_grad, checkpoint_every, st);
+  // y = C R B f with real diagonal B, C: the reverse mode of R at the input B f with the cotangent C g; the forcing
+  // gradient is B R^H C g (the metrics do not enter a Euclidean vector-Jacobian product)
+  const double* w = (const double*)op->d_wsc;
+  const int64_t blocks = (int64_t)pl.nw * k;
+  const int fp = op->fp64();
+  void *fb, *gc;
+  RES_TRY(ws_get(op, "bw_wsc_f", (size_t)blocks * op->N * op->wsize(), &fb));
+  RES_TRY(ws_get(op, "bw_wsc_g", (size_t)blocks * op->N * op->wsize(), &gc));
+  launch_node_scale(f_hat, fp, fb, fp, w + (size_t)kWscB * op->N, blocks, op->N, st);
+  launch_node_scale(g_hat, fp, gc, fp, w + (size_t)kWscC * op->N, blocks, op->N, st);
+  RES_TRY(backward(op, pl, k, fb, gc, f_grad, mu_grad, checkpoint_every, st));
+  if (f_grad) launch_node_scale(f_grad, fp, f_grad, fp, w + (size_t)kWscB * op->N, blocks, op->N, st);
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
 }
 
 int resolvent_signal_run(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,

@@ -1,7 +1,7 @@
 """GPU parity of diagonal B, C and metrics W_f, W_y (resolvent_op_set_weights) against the oracle's definitions on
 the same seeded inputs: observed applies y = C R B f and R_y^dagger y to 1e-10 per vector, the weighted adjoint
-identity on the GPU results, and gains of the power iteration and of the block Arnoldi (the Euclidean
-R~ = W_y^{1/2} C R B W_f^{-1/2}) to 1e-8 with W_f-orthonormal force modes."""
+identity on the GPU results, gains of the power iteration and of the block Arnoldi (the Euclidean
+R~ = W_y^{1/2} C R B W_f^{-1/2}) to 1e-8 with W_f-orthonormal force modes, and the reverse mode of C R B f."""
 import numpy as np
 import pytest
 
@@ -103,7 +103,30 @@ def test_weighted_gains_and_modes_match_oracle(algorithm):
     assert np.abs(np.sum(wf * np.abs(Vn[:, 0]) ** 2, axis=-1) - 1).max() < 1e-10
 
 
-def test_weights_errors_and_reverse_mode_refusal():
+def test_weighted_reverse_mode_matches_oracle():
+    """Reverse mode of y = C R B f: forcing gradient B R^H C g and the mu gradient at input B f, cotangent C g."""
+    import torch
+    from oracle import gradient as O_grad
+    say("case: weighted reverse mode")
+    op, L = setup()
+    b, c, wf, wy = weights(67)
+    op.set_weights(b, c, wf, wy)
+    nw, w0 = 3, -0.2
+    dw = 2 * np.pi / (P * H)
+    F, G = forcing(68, nw, 2, N), forcing(69, nw, 2, N)
+    grid, run = op.grid(w0, dw, nw), op.run("periodic", periods=2, stride=STRIDE)
+    fg, mg = op.apply_backward(gpu_tensor(F), gpu_tensor(G), grid, run, checkpoint_every=40)
+    torch.cuda.synchronize()
+    fg, mg = to_np(fg), mg.cpu().numpy()
+    ref_f = b * O_grad.stepped_vjp(L, H, w0, dw, c * G, "periodic", periods=2, stride=STRIDE)
+    ref_mu = O_grad.stepped_mu_gradient(L, np.zeros(N), H, w0, dw, b * F, c * G, "periodic", periods=2,
+                                        stride=STRIDE)
+    e = (np.abs(fg - ref_f).max() / np.abs(ref_f).max(), np.abs(mg - ref_mu).max() / np.abs(ref_mu).max())
+    say("  f_grad err %.3e  mu_grad err %.3e" % e)
+    assert e[0] < 1e-10 and e[1] < 1e-6
+
+
+def test_weights_errors():
     import torch
     from paper_2008_10904_amd import ResolventError
     from paper_2008_10904_amd import _lib as L_
@@ -116,11 +139,4 @@ def test_weights_errors_and_reverse_mode_refusal():
     with pytest.raises(ResolventError) as e:
         op.set_weights(np.full(N, np.nan), c, wf, wy)
     assert e.value.code == L_.RES_EINVAL
-    op.set_weights(b, c, wf, wy)
-    dw = 2 * np.pi / (P * H)
-    F = gpu_tensor(forcing(66, 2, 1, N))
-    grid, run = op.grid(0.0, dw, 2), op.run("periodic", periods=2, stride=STRIDE)
-    with pytest.raises(ResolventError) as e:
-        op.apply_backward(F, F, grid, run)
-    assert e.value.code == L_.RES_ENOTSUP
     torch.cuda.synchronize()
