@@ -20,6 +20,11 @@ paper by eye rather than to be fast:
                     gain/mode estimates of Appendix A.
 * ``gradient``   -- gain sensitivity to the reaction field mu: the closed form from the SVD and
                     finite differences of the discrete gain.
+* ``krylov``     -- block Arnoldi estimates on the steady-state response (Appendix A).
+* ``weights``    -- diagonal input and output matrices B, C and metrics W_f, W_y (Sec. 2.1).
+* ``trm``        -- the transient-response method with time-domain hand-off: runs forced by sampled signals
+                    interpolated between samples (App. C), FIR flattening filters (App. B) and the power
+                    iteration that hands the adjoint output back in time (Sec. 2.2).
 
 Parity pins for every function are in ``tests/test_oracle_*.py``.  Functions without such a pin say
 "parity unpinned" in their docstring (there are none at present).
