@@ -150,6 +150,135 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
   return 0;
 }
 
+// The four forward stages of one step in one launch, for a 2-D one-component grid operator: a 64 x 16 tile of the
+// state with a halo of four sites (the reach of four stencil applications) sits in LDS; stage m computes the
+// padded-tile sites [m, P - m) from the previous stage's values, so the last stage covers the tile.  Writes the
+// stage inputs y2, y3, y4 and the new state uout on the tile (each may be null; uout null: the three stages only).
+// The arithmetic per site and stage is that of fwd_stage_kernel (same operand order); out-of-domain sites hold
+// zero.  uout must not alias u (neighbouring tiles read u's halo).
+//
+// Each of the 1,024 threads owns one tile site (its RK4 accumulator stays in a register) and at most one site of
+// the halo ring of the current stage (516 sites at most).  The stage values live in one LDS buffer updated in
+// place: every thread computes its sites from the buffer, then all write after a barrier.  With the state tile,
+// 55 KB of LDS: two workgroups per CU.
+constexpr int kFsTX = 64, kFsTY = 16, kFsH = 4, kFsPX = kFsTX + 2 * kFsH, kFsPY = kFsTY + 2 * kFsH;
+
+// Ring site i (< ring count) of stage m: the region [m, P - m) minus the tile, as a top band, a bottom band and the
+// left and right bands of the tile rows.
+__device__ __forceinline__ void ring_site(int m, int i, int* py, int* px) {
+  const int band = kFsH - m, wx = kFsPX - 2 * m, ntop = band * wx;
+  if (i < ntop) {
+    *py = m + i / wx;
+    *px = m + i % wx;
+  } else if (i < 2 * ntop) {
+    const int j = i - ntop;
+    *py = kFsH + kFsTY + j / wx;
+    *px = m + j % wx;
+  } else {
+    const int j = i - 2 * ntop, row = j / (2 * band), c = j % (2 * band);
+    *py = kFsH + row;
+    *px = c < band ? m + c : kFsH + kFsTX + (c - band);
+  }
+}
+
+__global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny,
+                                                          const cx<double>* __restrict__ u, cx<double>* uout,
+                                                          cx<double>* y2o, cx<double>* y3o, cx<double>* y4o,
+                                                          const cx<double>* __restrict__ fa,
+                                                          const cx<double>* __restrict__ fb,
+                                                          const cx<double>* __restrict__ fc, double h) {
+  __shared__ cx<double> U[kFsPY][kFsPX], Y[kFsPY][kFsPX];
+  const int64_t nodes = nx * ny;
+  const int64_t col = blockIdx.z;
+  const int64_t gx0 = (int64_t)blockIdx.x * kFsTX - kFsH, gy0 = (int64_t)blockIdx.y * kFsTY - kFsH;
+  const cx<double> zero = mk<double>(0.0, 0.0);
+  for (int i = threadIdx.x; i < kFsPX * kFsPY; i += blockDim.x) {
+    const int py = i / kFsPX, px = i - py * kFsPX;
+    const int64_t gx = gx0 + px, gy = gy0 + py;
+    const cx<double> v = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[col * nodes + gy * nx + gx] : zero;
+    U[py][px] = v;
+    Y[py][px] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int tpy = kFsH + t / kFsTX, tpx = kFsH + t % kFsTX;  // the thread's tile site
+  cx<double> acc = zero;
+  // K = Z x + h f at padded site (py, px) of the LDS buffer x (apply_z order: diagonal, x-, x+, y-, y+)
+  auto stage_k = [&](cx<double>(*X)[kFsPX], const cx<double>* f, int py, int px, int64_t gx, int64_t gy) {
+    const int64_t p = gy * nx + gx;
+    const double dd = Cf.d[p], cxm = Cf.cxm[gy], cxp = Cf.cxp[gy], cym = Cf.cym[gy], cyp = Cf.cyp[gy];
+    const cx<double> sv = X[py][px];
+    cx<double> K = mk<double>(dd * sv.re, dd * sv.im);
+    if (gx > 0) { const cx<double> q = X[py][px - 1]; K.re += cxm * q.re; K.im += cxm * q.im; }
+    if (gx + 1 < nx) { const cx<double> q = X[py][px + 1]; K.re += cxp * q.re; K.im += cxp * q.im; }
+    if (gy > 0) { const cx<double> q = X[py - 1][px]; K.re += cym * q.re; K.im += cym * q.im; }
+    if (gy + 1 < ny) { const cx<double> q = X[py + 1][px]; K.re += cyp * q.re; K.im += cyp * q.im; }
+    if (f != nullptr) {
+      const cx<double> fv = f[col * nodes + p];
+      K.re += h * fv.re;
+      K.im += h * fv.im;
+    }
+    return K;
+  };
+  const int mlast = uout != nullptr ? 4 : 3;
+  for (int m = 1; m <= mlast; ++m) {
+    const cx<double>* f = m == 1 ? fa : (m == 4 ? fc : fb);
+    cx<double>* go = m == 1 ? y2o : (m == 2 ? y3o : (m == 3 ? y4o : uout));
+    const double w = m == 3 ? 1.0 : 0.5;
+    // the tile site
+    const int64_t gx = gx0 + tpx, gy = gy0 + tpy;
+    const bool tin = gx < nx && gy < ny;  // tile sites are never left of or above the domain
+    cx<double> tv = zero;
+    if (tin) {
+      const cx<double> K = stage_k(Y, f, tpy, tpx, gx, gy);
+      const cx<double> uu = U[tpy][tpx];
+      if (m < 4) {
+        tv = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
+        acc = m == 1 ? K : mk<double>(acc.re + 2.0 * K.re, acc.im + 2.0 * K.im);
+      } else {
+        tv = mk<double>(uu.re + (acc.re + K.re) / 6.0, uu.im + (acc.im + K.im) / 6.0);
+      }
+    }
+    // one ring site (stages 1..3)
+    const int band = kFsH - m;
+    const int nring = 2 * band * (kFsPX - 2 * m) + 2 * band * kFsTY;
+    int rpy = 0, rpx = 0;
+    const bool has_ring = m < 4 && t < nring;
+    cx<double> rv = zero;
+    if (has_ring) {
+      ring_site(m, t, &rpy, &rpx);
+      const int64_t rgx = gx0 + rpx, rgy = gy0 + rpy;
+      if (rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny) {
+        const cx<double> K = stage_k(Y, f, rpy, rpx, rgx, rgy);
+        const cx<double> uu = U[rpy][rpx];
+        rv = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
+      }
+    }
+    __syncthreads();  // every read of the stage's operand is done
+    if (m < 4) {
+      Y[tpy][tpx] = tv;
+      if (has_ring) Y[rpy][rpx] = rv;
+    }
+    if (tin && go != nullptr) go[col * nodes + gy * nx + gx] = tv;
+    __syncthreads();
+  }
+}
+
+int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st) {
+  if (op.kind != 1 || op.ncomp != 1 || op.g.nz != 1 || k < 1 || k > 65535 || (uout != nullptr && uout == u))
+    return -1;
+  GridCoef<double> c;
+  c.cxm = (const double*)op.g.cxm; c.cxp = (const double*)op.g.cxp; c.cym = (const double*)op.g.cym;
+  c.cyp = (const double*)op.g.cyp; c.czm = (const double*)op.g.czm; c.czp = (const double*)op.g.czp;
+  c.d = (const double*)op.g.d; c.K = (const double*)op.g.K;
+  const dim3 grid((unsigned)((op.g.nx + kFsTX - 1) / kFsTX), (unsigned)((op.g.ny + kFsTY - 1) / kFsTY), (unsigned)k);
+  hipLaunchKernelGGL(fwd_step2d_kernel, grid, dim3(1024), 0, st, c, op.g.nx, op.g.ny, (const cx<double>*)u,
+                     (cx<double>*)uout, (cx<double>*)y2, (cx<double>*)y3, (cx<double>*)y4, (const cx<double>*)fa,
+                     (const cx<double>*)fb, (const cx<double>*)fc, h);
+  return 0;
+}
+
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st) {
   const dim3 grid((unsigned)((opH.nsite + 255) / 256));

@@ -82,6 +82,10 @@ struct AdjOpDev {
 };
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
                      void* acc, const void* f, double h, hipStream_t st);
+// The four forward stages of one step in one launch for a 2-D one-component grid operator (stage inputs y2, y3, y4
+// and uout may each be null; uout must not alias u).  Returns -1 for other operators.
+int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
 

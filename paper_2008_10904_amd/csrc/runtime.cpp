@@ -1387,15 +1387,31 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
   };
 
+  // 2-D one-component grids take the four forward stages of a step in one LDS-tiled launch (launch_fwd_step2d);
+  // other operators one launch per stage.  The fused step cannot update the state in place, so the checkpoint
+  // march ping-pongs between u and a second row.
+  const bool fused = fwd.kind == 1 && fwd.ncomp == 1 && fwd.g.nz == 1;
+  void* u2 = nullptr;
+  if (fused) RES_TRY(ws_get(op, "bw_u2", rowb, &u2));
+
   // 1. forward march with checkpoints
   RES_TRY(zero_device(u, rowb, st));
+  void* ucur = u;
   for (int64_t c = 0; c < ncp; ++c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C);
-    HIP_TRY(hipMemcpyAsync(row(cps, c), u, rowb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(row(cps, c), ucur, rowb, hipMemcpyDeviceToDevice, st));
     if (c == ncp - 1) break;  // the state after the last step is not needed
     RES_TRY(synth_segment(sa, sb));
     for (int64_t s = sa; s < sb; ++s) {
       const int64_t r = s - sa;
+      if (fused) {
+        void* unext = ucur == u ? u2 : u;
+        if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, frc(s, r, 0), frc(s, r, 1),
+                              frc(s, r, 2), h, st))
+          return fail(RES_EINVAL, "fused forward step launch");
+        ucur = unext;
+        continue;
+      }
       launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, frc(s, r, 0), h, st);
       launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, frc(s, r, 1), h, st);
       launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, frc(s, r, 1), h, st);
@@ -1432,6 +1448,12 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       void* a2 = stg ? srow(r, 0) : y2;
       void* a3 = stg ? srow(r, 1) : y3;
       void* a4 = stg ? srow(r, 2) : y2;
+      if (fused) {
+        if (launch_fwd_step2d(fwd, k, us, row(seg, r + 1), stg ? a2 : nullptr, stg ? a3 : nullptr,
+                              stg ? a4 : nullptr, frc(s, r, 0), frc(s, r, 1), frc(s, r, 2), h, st))
+          return fail(RES_EINVAL, "fused forward step launch");
+        continue;
+      }
       launch_fwd_stage(fwd, k, 1, us, nullptr, us, a2, acc, frc(s, r, 0), h, st);
       launch_fwd_stage(fwd, k, 2, us, nullptr, a2, a3, acc, frc(s, r, 1), h, st);
       launch_fwd_stage(fwd, k, 3, us, nullptr, a3, a4, acc, frc(s, r, 1), h, st);
@@ -1452,6 +1474,9 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         s2 = srow(r, 0);
         s3 = srow(r, 1);
         s4 = srow(r, 2);
+      } else if (fused) {
+        if (launch_fwd_step2d(fwd, k, us, nullptr, y2, y3, y4, frc(s, r, 0), frc(s, r, 1), nullptr, h, st))
+          return fail(RES_EINVAL, "fused forward step launch");
       } else {
         launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st);
         launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);

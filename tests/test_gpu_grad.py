@@ -150,6 +150,36 @@ def test_grid_backward_matches_oracle(case):
             assert abs(mg @ d - fd) < 1e-6 * np.abs(mg).sum() * np.abs(d).max()
 
 
+def test_grid_backward_spans_several_tiles():
+    """The fused 2-D forward step of the reverse mode works on 64 x 16 tiles with halos taken from neighbouring
+    tiles: a 150 x 40 grid (three ragged tiles in each direction).  The forcing gradient is checked by the exact
+    duality <A^H G, d> = <G, A d> of the discrete run against the oracle's forward run, the mu gradient along random
+    directions against central differences of the oracle's objective."""
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    say("case: grid 2d backward on 150 x 40 (several fused-step tiles), transient, checkpoint_every 7")
+    nx, ny, h, P, nw, k, w0 = 150, 40, 0.1, 40, 3, 2, 0.1
+    dw = 2 * np.pi / (P * h)
+    run = dict(tail=30)
+    f = O_ops.adr2d_fields(nx, ny)
+    mu = O_ops.adr2d_mu_default(f["X"], f["Y"], base=-0.3, amp=0.08)
+    op = ResolventOp.grid_operator("adr2d", nx, ny, 1, adr2d_coefficients(nx, ny, mu=mu), h)
+    L0 = O_ops.adr2d_operator(nx, ny, mu=mu)[0]
+    F, G = forcing(51, nw, k, op.n), forcing(52, nw, k, op.n)
+    fg, mg = backward(op, F, G, op.grid(w0, dw, nw), op.run("transient", **run), 7)
+    rng = np.random.default_rng(53)
+    D = rng.standard_normal((nw, k, op.n)) + 1j * rng.standard_normal((nw, k, op.n))
+    AD = O_st.run(L0, h, w0, dw, D, "transient", **run)
+    lhs, rhs = np.vdot(fg, D), np.vdot(G, AD)
+    say("  duality: <A^H G, d> %s  <G, A d> %s" % (lhs, rhs))
+    assert abs(lhs - rhs) < 1e-10 * abs(rhs)
+    for _ in range(2):
+        d = rng.standard_normal(nx * ny)
+        fd = O_grad.stepped_mu_directional(L0, np.zeros(nx * ny), d, h, w0, dw, F, G, "transient", **run)
+        say("  directional: gpu %.12e fd %.12e" % (float(mg @ d), fd))
+        assert abs(mg @ d - fd) < 1e-6 * np.abs(mg).sum() * np.abs(d).max()
+
+
 def test_autograd_gain_objective_matches_oracle():
     # J = sum_j c_j ||u_j||, u = R(mu) V through the torch.autograd function; gradients against the oracle's
     # (forcing: A^H applied to dJ/du; mu: directional central differences of the same J).
