@@ -264,6 +264,121 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
   }
 }
 
+// The four reverse stages of one step in one launch, for a 2-D one-component grid operator (the recursion of the
+// header comment, with opH's coefficients of Z^H): a 64 x 16 tile of lambda' with a halo of four sites in LDS;
+// step s = 1..4 (stage m = 5 - s) applies Z^H on the padded sites [s, P - s), from lambda'/6 (s = 1) or the
+// previous Kb (updated in place in one LDS buffer, as in fwd_step2d_kernel); the running sum lambda' + sum yb and
+// the mu contributions h Re(conj(Kb_m) y_m) stay in registers on the tile.  All k columns run in one workgroup, so
+// a node's mu is summed over columns and stages and added once.  lam_out must not alias lam.
+__global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int k,
+                                                          const cx<double>* __restrict__ lam, cx<double>* lam_out,
+                                                          const cx<double>* __restrict__ y2,
+                                                          const cx<double>* __restrict__ y3,
+                                                          const cx<double>* __restrict__ y4,
+                                                          const cx<double>* __restrict__ u, double* mu,
+                                                          const cx<double>* __restrict__ inj, double h) {
+  __shared__ cx<double> L[kFsPY][kFsPX], KB[kFsPY][kFsPX];
+  const int64_t nodes = nx * ny;
+  const int64_t gx0 = (int64_t)blockIdx.x * kFsTX - kFsH, gy0 = (int64_t)blockIdx.y * kFsTY - kFsH;
+  const cx<double> zero = mk<double>(0.0, 0.0);
+  const int t = threadIdx.x;
+  const int tpy = kFsH + t / kFsTX, tpx = kFsH + t % kFsTX;
+  const int64_t tgx = gx0 + tpx, tgy = gy0 + tpy;
+  const bool tin = tgx < nx && tgy < ny;  // tile sites are never left of or above the domain
+  const int64_t tp = tgy * nx + tgx;
+  // (Z^H x)(site) from an LDS buffer (apply_z order: diagonal, x-, x+, y-, y+)
+  auto zh = [&](cx<double>(*X)[kFsPX], int py, int px, int64_t gx, int64_t gy) {
+    const int64_t p = gy * nx + gx;
+    const double dd = Cf.d[p], cxm = Cf.cxm[gy], cxp = Cf.cxp[gy], cym = Cf.cym[gy], cyp = Cf.cyp[gy];
+    const cx<double> sv = X[py][px];
+    cx<double> z = mk<double>(dd * sv.re, dd * sv.im);
+    if (gx > 0) { const cx<double> q = X[py][px - 1]; z.re += cxm * q.re; z.im += cxm * q.im; }
+    if (gx + 1 < nx) { const cx<double> q = X[py][px + 1]; z.re += cxp * q.re; z.im += cxp * q.im; }
+    if (gy > 0) { const cx<double> q = X[py - 1][px]; z.re += cym * q.re; z.im += cym * q.im; }
+    if (gy + 1 < ny) { const cx<double> q = X[py + 1][px]; z.re += cyp * q.re; z.im += cyp * q.im; }
+    return z;
+  };
+  // Kb_{m-1} at a site from y_bar_m = z and lambda' (step s = 5 - m; s = 4 produces lambda instead)
+  auto next_kb = [&](int s, cx<double> lp, cx<double> z) {
+    const double wl = s == 1 ? 1.0 / 3.0 : (s == 2 ? 1.0 / 3.0 : 1.0 / 6.0);
+    const double wz = s == 1 ? 1.0 : 0.5;
+    return mk<double>(wl * lp.re + wz * z.re, wl * lp.im + wz * z.im);
+  };
+  double musum = 0.0;
+  for (int b = 0; b < k; ++b) {
+    const int64_t cb = (int64_t)b * nodes;
+    for (int i = t; i < kFsPX * kFsPY; i += blockDim.x) {
+      const int py = i / kFsPX, px = i - py * kFsPX;
+      const int64_t gx = gx0 + px, gy = gy0 + py;
+      L[py][px] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? lam[cb + gy * nx + gx] : zero;
+    }
+    __syncthreads();
+    cx<double> ub = zero;
+    for (int s = 1; s <= 4; ++s) {
+      cx<double>(*X)[kFsPX] = s == 1 ? L : KB;
+      const double xs = s == 1 ? 1.0 / 6.0 : 1.0;  // Kb_4 = lambda'/6
+      const cx<double>* ys = s == 1 ? y4 : (s == 2 ? y3 : (s == 3 ? y2 : u));
+      cx<double> tv = zero;
+      if (tin) {
+        const cx<double> lp = L[tpy][tpx];
+        cx<double> z = zh(X, tpy, tpx, tgx, tgy);
+        z = mk<double>(xs * z.re, xs * z.im);
+        const cx<double> kx = X[tpy][tpx];
+        const cx<double> kb = mk<double>(xs * kx.re, xs * kx.im);  // Kb_m at the tile site
+        if (mu != nullptr) {
+          const cx<double> yy = ys[cb + tp];
+          musum += kb.re * yy.re + kb.im * yy.im;
+        }
+        if (s == 1) ub = mk<double>(lp.re + z.re, lp.im + z.im);
+        else ub = mk<double>(ub.re + z.re, ub.im + z.im);
+        tv = s < 4 ? next_kb(s, lp, z) : ub;
+      }
+      const int band = kFsH - s;
+      const int nring = s < 4 ? 2 * band * (kFsPX - 2 * s) + 2 * band * kFsTY : 0;
+      int rpy = 0, rpx = 0;
+      const bool has_ring = t < nring;
+      cx<double> rv = zero;
+      if (has_ring) {
+        ring_site(s, t, &rpy, &rpx);
+        const int64_t rgx = gx0 + rpx, rgy = gy0 + rpy;
+        if (rgx >= 0 && rgx < nx && rgy >= 0 && rgy < ny) {
+          cx<double> z = zh(X, rpy, rpx, rgx, rgy);
+          z = mk<double>(xs * z.re, xs * z.im);
+          rv = next_kb(s, L[rpy][rpx], z);
+        }
+      }
+      __syncthreads();  // every read of the step's operand is done
+      if (s < 4) {
+        KB[tpy][tpx] = tv;
+        if (has_ring) KB[rpy][rpx] = rv;
+      } else if (tin) {
+        cx<double> l = tv;
+        if (inj != nullptr) {
+          l.re += inj[cb + tp].re;
+          l.im += inj[cb + tp].im;
+        }
+        lam_out[cb + tp] = l;
+      }
+      __syncthreads();
+    }
+  }
+  if (mu != nullptr && tin) mu[tp] += h * musum;
+}
+
+int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
+                      const void* y4, const void* u, double* mu, const void* inj, double h, hipStream_t st) {
+  if (opH.kind != 1 || opH.ncomp != 1 || opH.g.nz != 1 || k < 1 || lam_out == lam) return -1;
+  GridCoef<double> c;
+  c.cxm = (const double*)opH.g.cxm; c.cxp = (const double*)opH.g.cxp; c.cym = (const double*)opH.g.cym;
+  c.cyp = (const double*)opH.g.cyp; c.czm = (const double*)opH.g.czm; c.czp = (const double*)opH.g.czp;
+  c.d = (const double*)opH.g.d; c.K = (const double*)opH.g.K;
+  const dim3 grid((unsigned)((opH.g.nx + kFsTX - 1) / kFsTX), (unsigned)((opH.g.ny + kFsTY - 1) / kFsTY));
+  hipLaunchKernelGGL(rev_step2d_kernel, grid, dim3(1024), 0, st, c, opH.g.nx, opH.g.ny, k, (const cx<double>*)lam,
+                     (cx<double>*)lam_out, (const cx<double>*)y2, (const cx<double>*)y3, (const cx<double>*)y4,
+                     (const cx<double>*)u, mu, (const cx<double>*)inj, h);
+  return 0;
+}
+
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
                       const void* fa, const void* fb, const void* fc, double h, hipStream_t st) {
   if (op.kind != 1 || op.ncomp != 1 || op.g.nz != 1 || k < 1 || k > 65535 || (uout != nullptr && uout == u))

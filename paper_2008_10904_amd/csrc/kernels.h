@@ -86,6 +86,10 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
 // and uout may each be null; uout must not alias u).  Returns -1 for other operators.
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
                       const void* fa, const void* fb, const void* fc, double h, hipStream_t st);
+// The four reverse stages of one step in one launch for a 2-D one-component grid operator (all k columns in one
+// workgroup; lam_out must not alias lam).  Returns -1 for other operators.
+int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
+                      const void* y4, const void* u, double* mu, const void* inj, double h, hipStream_t st);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
 

@@ -1488,6 +1488,11 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         const int64_t m = (s - pl.pfirst) / pl.pstride;
         if (m < pl.pcount) seed = row(inj, m - ma);
       }
+      if (fused) {
+        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lrows, r - 1) : carry, s2, s3, s4, us, mu_grad, seed, h, st))
+          return fail(RES_EINVAL, "fused reverse step launch");
+        continue;
+      }
       launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, ub, mu_grad, nullptr, h, st);
       launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, ub, mu_grad, nullptr, h, st);
       launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ka, ub, mu_grad, nullptr, h, st);
