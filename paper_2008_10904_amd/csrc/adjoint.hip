@@ -268,16 +268,18 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
 // header comment, with opH's coefficients of Z^H): a 64 x 16 tile of lambda' with a halo of four sites in LDS;
 // step s = 1..4 (stage m = 5 - s) applies Z^H on the padded sites [s, P - s), from lambda'/6 (s = 1) or the
 // previous Kb (updated in place in one LDS buffer, as in fwd_step2d_kernel); the running sum lambda' + sum yb and
-// the mu contributions h Re(conj(Kb_m) y_m) stay in registers on the tile.  All k columns run in one workgroup, so
-// a node's mu is summed over columns and stages and added once.  lam_out must not alias lam.
-__global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int k,
+// the mu contributions h Re(conj(Kb_m) y_m) stay in registers on the tile.  One workgroup per tile and column; a
+// node's mu contributions of the step are summed over the stages and added to the column's own partial row
+// mu_cols[column][node] (summed over the columns once at the end, without atomics).  lam_out must not alias lam.
+__global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny,
                                                           const cx<double>* __restrict__ lam, cx<double>* lam_out,
                                                           const cx<double>* __restrict__ y2,
                                                           const cx<double>* __restrict__ y3,
                                                           const cx<double>* __restrict__ y4,
-                                                          const cx<double>* __restrict__ u, double* mu,
+                                                          const cx<double>* __restrict__ u, double* mu_cols,
                                                           const cx<double>* __restrict__ inj, double h) {
   __shared__ cx<double> L[kFsPY][kFsPX], KB[kFsPY][kFsPX];
+  double* mu = mu_cols != nullptr ? mu_cols + (int64_t)blockIdx.z * nx * ny : nullptr;
   const int64_t nodes = nx * ny;
   const int64_t gx0 = (int64_t)blockIdx.x * kFsTX - kFsH, gy0 = (int64_t)blockIdx.y * kFsTY - kFsH;
   const cx<double> zero = mk<double>(0.0, 0.0);
@@ -305,8 +307,8 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
     return mk<double>(wl * lp.re + wz * z.re, wl * lp.im + wz * z.im);
   };
   double musum = 0.0;
-  for (int b = 0; b < k; ++b) {
-    const int64_t cb = (int64_t)b * nodes;
+  {
+    const int64_t cb = (int64_t)blockIdx.z * nodes;
     for (int i = t; i < kFsPX * kFsPY; i += blockDim.x) {
       const int py = i / kFsPX, px = i - py * kFsPX;
       const int64_t gx = gx0 + px, gy = gy0 + py;
@@ -366,16 +368,35 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
 }
 
 int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
-                      const void* y4, const void* u, double* mu, const void* inj, double h, hipStream_t st) {
-  if (opH.kind != 1 || opH.ncomp != 1 || opH.g.nz != 1 || k < 1 || lam_out == lam) return -1;
+                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st) {
+  if (opH.kind != 1 || opH.ncomp != 1 || opH.g.nz != 1 || k < 1 || k > 65535 || lam_out == lam) return -1;
   GridCoef<double> c;
   c.cxm = (const double*)opH.g.cxm; c.cxp = (const double*)opH.g.cxp; c.cym = (const double*)opH.g.cym;
   c.cyp = (const double*)opH.g.cyp; c.czm = (const double*)opH.g.czm; c.czp = (const double*)opH.g.czp;
   c.d = (const double*)opH.g.d; c.K = (const double*)opH.g.K;
-  const dim3 grid((unsigned)((opH.g.nx + kFsTX - 1) / kFsTX), (unsigned)((opH.g.ny + kFsTY - 1) / kFsTY));
-  hipLaunchKernelGGL(rev_step2d_kernel, grid, dim3(1024), 0, st, c, opH.g.nx, opH.g.ny, k, (const cx<double>*)lam,
+  const dim3 grid((unsigned)((opH.g.nx + kFsTX - 1) / kFsTX), (unsigned)((opH.g.ny + kFsTY - 1) / kFsTY),
+                  (unsigned)k);
+  hipLaunchKernelGGL(rev_step2d_kernel, grid, dim3(1024), 0, st, c, opH.g.nx, opH.g.ny, (const cx<double>*)lam,
                      (cx<double>*)lam_out, (const cx<double>*)y2, (const cx<double>*)y3, (const cx<double>*)y4,
-                     (const cx<double>*)u, mu, (const cx<double>*)inj, h);
+                     (const cx<double>*)u, mu_cols, (const cx<double>*)inj, h);
+  return 0;
+}
+
+// mu[p] += sum_b cols[b][p] (b < k, in order).
+__global__ __launch_bounds__(256) void sum_columns_kernel(const double* __restrict__ cols, int k, int64_t n,
+                                                          double* __restrict__ mu) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < k; ++b) s += cols[(int64_t)b * n + p];
+    mu[p] += s;
+  }
+}
+
+int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return 0;
+  hipLaunchKernelGGL(sum_columns_kernel, dim3((unsigned)blocks), dim3(256), 0, st, cols, k, n, mu);
   return 0;
 }
 

@@ -86,10 +86,13 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
 // and uout may each be null; uout must not alias u).  Returns -1 for other operators.
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
                       const void* fa, const void* fb, const void* fc, double h, hipStream_t st);
-// The four reverse stages of one step in one launch for a 2-D one-component grid operator (all k columns in one
-// workgroup; lam_out must not alias lam).  Returns -1 for other operators.
+// The four reverse stages of one step in one launch for a 2-D one-component grid operator (one workgroup per tile
+// and column; the mu contributions go to the per-column rows mu_cols [k][nodes]; lam_out must not alias lam).
+// Returns -1 for other operators.
 int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
-                      const void* y4, const void* u, double* mu, const void* inj, double h, hipStream_t st);
+                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st);
+// mu[p] += sum over the k rows of cols [k][n].
+int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStream_t st);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
 

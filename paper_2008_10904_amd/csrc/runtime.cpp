@@ -1392,7 +1392,14 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   // march ping-pongs between u and a second row.
   const bool fused = fwd.kind == 1 && fwd.ncomp == 1 && fwd.g.nz == 1;
   void* u2 = nullptr;
+  double* mu_cols = nullptr;  // per-column mu rows of the fused reverse steps, summed at the end
   if (fused) RES_TRY(ws_get(op, "bw_u2", rowb, &u2));
+  if (fused && mu_grad) {
+    void* p;
+    RES_TRY(ws_get(op, "bw_mu_cols", (size_t)k * nsite * sizeof(double), &p));
+    mu_cols = (double*)p;
+    RES_TRY(zero_device(mu_cols, (size_t)k * nsite * sizeof(double), st));
+  }
 
   // 1. forward march with checkpoints
   RES_TRY(zero_device(u, rowb, st));
@@ -1489,7 +1496,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         if (m < pl.pcount) seed = row(inj, m - ma);
       }
       if (fused) {
-        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lrows, r - 1) : carry, s2, s3, s4, us, mu_grad, seed, h, st))
+        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lrows, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st))
           return fail(RES_EINVAL, "fused reverse step launch");
         continue;
       }
@@ -1505,6 +1512,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       RES_TRY(project_rows(op, 1, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, sa, 1, nf, 1.0,
                            (double*)facc, st));
   }
+  if (mu_cols) launch_sum_columns(mu_cols, k, nsite, mu_grad, st);
   // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j
   if (f_grad) {
     void *ya, *yb;
