@@ -297,14 +297,14 @@ def bench_grid(args):
         del F
         grid = op.grid(cfg["wmin"], dw, nw)
         run = op.run("transient", tail=0)
-        out = op.apply(f, grid, run)
+        out_u = op.apply(f, grid, run)
         torch.cuda.synchronize()
         op.set_timing(True)
         for kind in range(4):
             op.timing(kind)
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            op.apply(f, grid, run, out=out)
+            op.apply(f, grid, run, out=out_u)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
@@ -335,7 +335,50 @@ def bench_grid(args):
     }
     if cfg["kind"] == "adr2d":
         out["autograd"] = autograd
+    else:
+        del f, out_u
+        op = None
+        torch.cuda.empty_cache()
+        out["autograd"] = grad3d_half(cfg)
     print(json.dumps(out), flush=True)
+
+
+def grad3d_half(cfg):
+    """Forward plus reverse mode of the 3-D workload's gradient pattern: one apply of the periodic method (all
+    periods, 96 frequencies, k = 3) and one apply_backward with forcing and mu gradients, checkpoints every 64
+    steps.  The reverse mode keeps FP64 rows (forcing, seed and gradient blocks, 64-step segments, checkpoints),
+    which at the full grid need more memory than one GPU holds, so this runs the same operator on the grid
+    halved in each direction (128 x 64 x 64, one eighth of the state)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd.operators import snap_grid
+
+    half = dict(cfg, nx=cfg["nx"] // 2, ny=cfg["ny"] // 2, nz=cfg["nz"] // 2)
+    op = grid_op(half, cfg["precision"])
+    N = 3 * half["nx"] * half["ny"] * half["nz"]
+    nw, k = cfg["n_omega"], cfg["k"]
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], nw, cfg["h"], cfg["stride"])
+    f = torch.from_numpy(W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)).cuda()
+    grid = op.grid(w0, dw, nw)
+    run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = op.apply(f, grid, run)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = (u / u.abs().clamp_min(1e-30)).contiguous()  # dJ/du_hat of J = sum |u_hat|
+    del u
+    fg, mg = op.apply_backward(f, g, grid, run, checkpoint_every=cfg["checkpoint_every"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = bool(torch.isfinite(fg).all().item()) and bool(np.isfinite(mg.cpu().numpy()).all())
+    return {"grid": [half["nx"], half["ny"], half["nz"]], "n_omega": nw, "k": k, "P": P,
+            "time_steps": cfg["periods"] * P, "checkpoint_every": cfg["checkpoint_every"],
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "finite": ok,
+            "note": "one apply and one apply_backward (forcing and mu gradients), periodic method, on the grid "
+                    "halved in each direction"}
 
 
 def bench_krylov(args):

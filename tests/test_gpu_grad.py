@@ -150,6 +150,28 @@ def test_grid_backward_matches_oracle(case):
             assert abs(mg @ d - fd) < 1e-6 * np.abs(mg).sum() * np.abs(d).max()
 
 
+def test_grid3d_periodic_backward_checkpoint_64():
+    """The 3-D gradient pattern of the periodic method: three periods of 50 steps with a checkpoint every 64 steps
+    (three segments, the last one ragged).  Forcing gradient against the oracle's stepped VJP, mu gradient along
+    random directions against central differences of the oracle's objective."""
+    say("case: grid 3d backward, periodic (3 periods, stride 5), checkpoint_every 64")
+    h, P, nw, k, w0 = 0.1, 50, 3, 2, 0.1
+    dw = 2 * np.pi / (P * h)
+    run = dict(periods=3, stride=5)
+    op, L0, ncomp, nodes = grid_case("3d", h)
+    F, G = forcing(54, nw, k, op.n), forcing(55, nw, k, op.n)
+    fg, mg = backward(op, F, G, op.grid(w0, dw, nw), op.run("periodic", **run), 64)
+    ref_f = O_grad.stepped_vjp(L0, h, w0, dw, G, "periodic", **run)
+    say("  f_grad err %.3e" % maxrel(fg, ref_f))
+    assert maxrel(fg, ref_f) < 1e-10
+    rng = np.random.default_rng(56)
+    for _ in range(2):
+        d = rng.standard_normal(nodes)
+        fd = O_grad.stepped_mu_directional(L0, np.zeros(nodes), d, h, w0, dw, F, G, "periodic", ncomp=ncomp, **run)
+        say("  directional: gpu %.12e fd %.12e" % (float(mg @ d), fd))
+        assert abs(mg @ d - fd) < 1e-6 * np.abs(mg).sum() * np.abs(d).max()
+
+
 def test_grid_backward_spans_several_tiles():
     """The fused 2-D forward step of the reverse mode works on 64 x 16 tiles with halos taken from neighbouring
     tiles: a 150 x 40 grid (three ragged tiles in each direction).  The forcing gradient is checked by the exact
