@@ -1373,11 +1373,25 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(phase_table64(op, pl.P, &btab));
   if (mu_grad) RES_TRY(zero_device(mu_grad, (size_t)nsite * sizeof(double), st));
   auto row = [&](void* base, int64_t r) { return (void*)((char*)base + (size_t)r * rowb); };
-  // raw forcing of steps [sa, sb): half-step samples 2 sa .. 2 sb
-  auto synth_segment = [&](int64_t sa, int64_t sb) -> int {
+  // raw forcing of steps [sa, sb): half-step samples 2 sa .. 2 sb.  The GEMM works on 64-row tiles, so the
+  // 2 C + 1 samples of a whole segment would take a third tile for a single row.  A sample shared with the segment
+  // synthesised just before is copied instead: shared < 0, the first sample is the last one (row 2 C) of the
+  // previous segment in time (forward order); shared > 0, the last sample is the first one (row 0) of the next
+  // segment in time (reverse order).
+  auto synth_segment = [&](int64_t sa, int64_t sb, int shared) -> int {
     if (sa >= pl.forced_end) return RES_OK;
-    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa, 1, 2 * (sb - sa) + 1,
-                      frow, st);
+    const int64_t len = sb - sa;
+    int64_t r0 = 0, n = 2 * len + 1;
+    if (shared < 0) {
+      HIP_TRY(hipMemcpyAsync(row(frow, 0), row(frow, 2 * C), rowb, hipMemcpyDeviceToDevice, st));
+      r0 = 1;
+      --n;
+    } else if (shared > 0) {
+      HIP_TRY(hipMemcpyAsync(row(frow, 2 * len), row(frow, 0), rowb, hipMemcpyDeviceToDevice, st));
+      --n;
+    }
+    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa + r0, 1, n, row(frow, r0),
+                      st);
   };
   auto frc = [&](int64_t s, int64_t r, int half) -> const void* {
     return s < pl.forced_end ? row(frow, 2 * r + half) : nullptr;
@@ -1408,7 +1422,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     const int64_t sa = c * C, sb = std::min(S, sa + C);
     HIP_TRY(hipMemcpyAsync(row(cps, c), ucur, rowb, hipMemcpyDeviceToDevice, st));
     if (c == ncp - 1) break;  // the state after the last step is not needed
-    RES_TRY(synth_segment(sa, sb));
+    RES_TRY(synth_segment(sa, sb, c > 0 ? -1 : 0));  // segments before the last one are C steps long
     for (int64_t s = sa; s < sb; ++s) {
       const int64_t r = s - sa;
       if (fused) {
@@ -1446,7 +1460,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C), len = sb - sa;
-    RES_TRY(synth_segment(sa, sb));
+    RES_TRY(synth_segment(sa, sb, c + 1 < ncp && sb < pl.forced_end ? 1 : 0));
     // states u_sa .. u_{sb-1}
     HIP_TRY(hipMemcpyAsync(row(seg, 0), row(cps, c), rowb, hipMemcpyDeviceToDevice, st));
     for (int64_t s = sa; s + 1 < sb; ++s) {
