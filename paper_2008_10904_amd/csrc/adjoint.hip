@@ -41,8 +41,10 @@ __device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __re
   }
 }
 
-// Forward stage m (1..4):  K = Z yin + h f;  m=1: yout = u + K/2, acc = K;  m=2: yout = u + K/2, acc += 2K;
-// m=3: yout = u + K, acc += 2K;  m=4: uout = u + (acc + K)/6 (uout may equal u).  acc may be null when only the
+// Forward stage m (1..4):  K_m = Z yin + h f;  m=1: yout = u + K_1/2;  m=2: yout = u + K_2/2, acc = K_1 + 2 K_2;
+// m=3: yout = u + K_3;  m=4: uout = u + (acc + 2 K_3 + K_4)/6 (uout may equal u).  The earlier stage increments
+// are recovered from the stage values, K_1 = 2 (y_2 - u) at m = 2 (yin = y_2) and K_3 = y_4 - u at m = 4
+// (yin = y_4), so only stages 2 and 4 touch acc (four fewer rows moved per step).  acc may be null when only the
 // stage values are wanted (m < 4); f null means no forcing.
 template <int KIND, int NC>
 __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int m, const cx<double>* u,
@@ -65,17 +67,15 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
       }
       const cx<double> uu = u[e];
       if (m == 4) {
-        const cx<double> a = acc[e];
-        uout[e] = mk<double>(uu.re + (a.re + K.re) / 6.0, uu.im + (a.im + K.im) / 6.0);
+        const cx<double> a = acc[e], y4 = yin[e];
+        const double k3r = y4.re - uu.re, k3i = y4.im - uu.im;
+        uout[e] = mk<double>(uu.re + (a.re + 2.0 * k3r + K.re) / 6.0, uu.im + (a.im + 2.0 * k3i + K.im) / 6.0);
       } else {
         const double w = m == 3 ? 1.0 : 0.5;
         yout[e] = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
-        if (acc != nullptr) {
-          if (m == 1) acc[e] = K;
-          else {
-            const cx<double> a = acc[e];
-            acc[e] = mk<double>(a.re + 2.0 * K.re, a.im + 2.0 * K.im);
-          }
+        if (acc != nullptr && m == 2) {
+          const cx<double> y2 = yin[e];
+          acc[e] = mk<double>(2.0 * (y2.re - uu.re) + 2.0 * K.re, 2.0 * (y2.im - uu.im) + 2.0 * K.im);
         }
       }
     }
@@ -154,8 +154,8 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
 // state with a halo of four sites (the reach of four stencil applications) sits in LDS; stage m computes the
 // padded-tile sites [m, P - m) from the previous stage's values, so the last stage covers the tile.  Writes the
 // stage inputs y2, y3, y4 and the new state uout on the tile (each may be null; uout null: the three stages only).
-// The arithmetic per site and stage is that of fwd_stage_kernel (same operand order); out-of-domain sites hold
-// zero.  uout must not alias u (neighbouring tiles read u's halo).
+// The stage values are those of fwd_stage_kernel (same operand order); the RK4 accumulator keeps the increments
+// K_m themselves instead of recovering K_1 and K_3 from stage values.  Out-of-domain sites hold zero.  uout must not alias u (neighbouring tiles read u's halo).
 //
 // Each of the 1,024 threads owns one tile site (its RK4 accumulator stays in a register) and at most one site of
 // the halo ring of the current stage (516 sites at most).  The stage values live in one LDS buffer updated in
