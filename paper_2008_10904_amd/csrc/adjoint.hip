@@ -82,17 +82,19 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
   }
 }
 
-// Reverse stage m (4..1) with opH = Z^H; see the header comment.  lam holds lambda' (read for the lambda'/3 and
-// lambda'/6 terms, m > 1); lam_out receives lambda at m = 1 (it must not alias lam or ubar).  kin = Kb_m
-// (m < 4), kout = Kb_{m-1}, ubar the running lambda' + sum yb, mu += h Re(conj(Kb_m) y_m) (mu null: skipped),
-// inj added to lambda at m = 1 (null: none).
+// Reverse stage m (4..1) with opH = Z^H; see the header comment.  lam holds lambda' (read at every stage);
+// kin = Kb_m (m < 4), kout = Kb_{m-1} (m > 1); mu += h Re(conj(Kb_m) y_m) (mu null: skipped).  No running sum is
+// kept: with yb_4 = Kb_3 - lambda'/3, yb_3 = 2 Kb_2 - 2 lambda'/3 and yb_2 = 2 Kb_1 - lambda'/3, stage 1 forms
+// lambda = -lambda'/3 + Kb_3 + 2 Kb_2 + 2 Kb_1 + yb_1 (+ inj, null: none) from k3 = Kb_3 and k2 = Kb_2 into
+// lam_out (which must not alias lam, kin, k3 or k2).
 template <int KIND, int NC>
 __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int m,
                                                         const cx<double>* __restrict__ lam,
                                                         cx<double>* __restrict__ lam_out,
                                                         const cx<double>* __restrict__ kin,
                                                         const cx<double>* __restrict__ y, cx<double>* kout,
-                                                        cx<double>* ubar, double* __restrict__ mu,
+                                                        const cx<double>* __restrict__ k3,
+                                                        const cx<double>* __restrict__ k2, double* __restrict__ mu,
                                                         const cx<double>* __restrict__ inj, double h) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= opH.nsite) return;
@@ -104,18 +106,17 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t e = b * blk + c * opH.nsite + p;
-      const cx<double> lp = m > 1 ? lam[e] : mk<double>(0.0, 0.0);
+      const cx<double> lp = lam[e];
       cx<double> kb;  // Kb_m at this point
       if (m == 4) {
         kb = mk<double>(lp.re / 6.0, lp.im / 6.0);
-        z[c] = mk<double>(z[c].re / 6.0, z[c].im / 6.0);  // Z^H (lambda'/6)
-        kout[e] = mk<double>(lp.re / 3.0 + z[c].re, lp.im / 3.0 + z[c].im);
-        ubar[e] = mk<double>(lp.re + z[c].re, lp.im + z[c].im);
+        kout[e] = mk<double>(lp.re / 3.0 + z[c].re / 6.0, lp.im / 3.0 + z[c].im / 6.0);  // Z^H (lambda'/6)
       } else {
         kb = kin[e];
-        const cx<double> ub = ubar[e];
         if (m == 1) {
-          cx<double> l = mk<double>(ub.re + z[c].re, ub.im + z[c].im);
+          const cx<double> a3 = k3[e], a2 = k2[e];
+          cx<double> l = mk<double>(a3.re + 2.0 * (a2.re + kb.re) - lp.re / 3.0 + z[c].re,
+                                    a3.im + 2.0 * (a2.im + kb.im) - lp.im / 3.0 + z[c].im);
           if (inj != nullptr) {
             l.re += inj[e].re;
             l.im += inj[e].im;
@@ -124,7 +125,6 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
         } else {
           const double w = m == 3 ? 1.0 / 3.0 : 1.0 / 6.0;
           kout[e] = mk<double>(w * lp.re + 0.5 * z[c].re, w * lp.im + 0.5 * z[c].im);
-          ubar[e] = mk<double>(ub.re + z[c].re, ub.im + z[c].im);
         }
       }
       if (mu != nullptr) {
@@ -416,12 +416,13 @@ int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void
 }
 
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
-                     const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st) {
+                     const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
+                     hipStream_t st) {
   const dim3 grid((unsigned)((opH.nsite + 255) / 256));
 #define RES_R(KIND, NC)                                                                                            \
   hipLaunchKernelGGL((rev_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, opH, k, m,                          \
                      (const cx<double>*)lam, (cx<double>*)lam_out, (const cx<double>*)kin, (const cx<double>*)y,     \
-                     (cx<double>*)kout, (cx<double>*)ubar, mu, (const cx<double>*)inj, h)
+                     (cx<double>*)kout, (const cx<double>*)k3, (const cx<double>*)k2, mu, (const cx<double>*)inj, h)
   if (opH.kind == 0) RES_R(0, 1);
   else if (opH.ncomp == 3) RES_R(1, 3);
   else RES_R(1, 1);

@@ -94,7 +94,8 @@ int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out
 // mu[p] += sum over the k rows of cols [k][n].
 int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStream_t st);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
-                     const void* y, void* kout, void* ubar, double* mu, const void* inj, double h, hipStream_t st);
+                     const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
+                     hipStream_t st);
 
 // ---- block Arnoldi (krylov.hip) ---------------------------------------------------------------------------
 int launch_xgram(const void* basis, int64_t bstride, int nb, const void* W, int64_t N, int k, const int64_t* off,

@@ -1514,10 +1514,12 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
           return fail(RES_EINVAL, "fused reverse step launch");
         continue;
       }
-      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, ub, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, ub, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ka, ub, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lrows, r - 1) : carry, ka, us, nullptr, ub, mu_grad, seed, h, st);
+      // Kb_3 in ka, Kb_2 in kb, Kb_1 in ub; stage 1 combines the three into lambda
+      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_grad, nullptr, h, st);
+      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lrows, r - 1) : carry, ub, us, nullptr, ka, kb, mu_grad, seed, h,
+                       st);
     }
     HIP_TRY(hipGetLastError());
     // forcing gradient: Fourier sums of lambda_{s+1} over the forced steps of the segment
