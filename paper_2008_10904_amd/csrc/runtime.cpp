@@ -1362,7 +1362,6 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(ws_get(op, "bw_ka", rowb, &ka));
   RES_TRY(ws_get(op, "bw_kb", rowb, &kb));
   RES_TRY(ws_get(op, "bw_ub", rowb, &ub));
-  RES_TRY(ws_get(op, "bw_lrows", (size_t)C * rowb, &lrows));
   RES_TRY(ws_get(op, "bw_carry", rowb, &carry));
   RES_TRY(ws_get(op, "bw_inj", (size_t)C * rowb, &inj));
   if (f_grad) {
@@ -1456,6 +1455,18 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       stg = nullptr;
     }
   }
+  // The lambda rows of G consecutive segments are kept together, so that the forcing gradient's projection runs on
+  // up to 256 rows at a time (64-row projections spend most of their time reading and writing the accumulator).
+  // G shrinks to what a quarter of the device memory left after the stage rows holds.
+  int64_t G_seg = std::max<int64_t>(1, std::min<int64_t>(ncp, 256 / C));
+  if (G_seg > 1) {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const auto held = op->ws.find("bw_lrows");
+    const double avail = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0);
+    G_seg = std::max<int64_t>(1, std::min<int64_t>(G_seg, (int64_t)(0.25 * avail / ((double)C * rowb))));
+  }
+  RES_TRY(ws_get(op, "bw_lrows", (size_t)(G_seg * C) * rowb, &lrows));
   auto srow = [&](int64_t r, int i) { return row(stg, 3 * r + i); };
   RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
   for (int64_t c = ncp - 1; c >= 0; --c) {
@@ -1485,8 +1496,10 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     if (mb > ma)
       RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, G, ncols, pl.pfirst + ma * pl.pstride, pl.pstride, mb - ma,
                          inj, st));
-    // lambda rows: lrows[r] = lambda_{sa + r + 1}
-    HIP_TRY(hipMemcpyAsync(row(lrows, len - 1), carry, rowb, hipMemcpyDeviceToDevice, st));
+    // lambda rows: lseg[r] = lambda_{sa + r + 1}, segment c at row (c - cg) C of its group's rows
+    const int64_t cg = c / G_seg * G_seg;
+    void* lseg = row(lrows, (c - cg) * C);
+    HIP_TRY(hipMemcpyAsync(row(lseg, len - 1), carry, rowb, hipMemcpyDeviceToDevice, st));
     for (int64_t s = sb - 1; s >= sa; --s) {
       const int64_t r = s - sa;
       void* us = row(seg, r);
@@ -1503,14 +1516,14 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);
         launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st);
       }
-      const void* lp = row(lrows, r);
+      const void* lp = row(lseg, r);
       const void* seed = nullptr;
       if (s >= pl.pfirst && (s - pl.pfirst) % pl.pstride == 0) {
         const int64_t m = (s - pl.pfirst) / pl.pstride;
         if (m < pl.pcount) seed = row(inj, m - ma);
       }
       if (fused) {
-        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lrows, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st))
+        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lseg, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st))
           return fail(RES_EINVAL, "fused reverse step launch");
         continue;
       }
@@ -1518,15 +1531,19 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_grad, nullptr, h, st);
       launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_grad, nullptr, h, st);
       launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lrows, r - 1) : carry, ub, us, nullptr, ka, kb, mu_grad, seed, h,
+      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lseg, r - 1) : carry, ub, us, nullptr, ka, kb, mu_grad, seed, h,
                        st);
     }
     HIP_TRY(hipGetLastError());
-    // forcing gradient: Fourier sums of lambda_{s+1} over the forced steps of the segment
-    const int64_t nf = std::min(sb, pl.forced_end) - sa;
-    if (f_grad && nf > 0)
-      RES_TRY(project_rows(op, 1, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, sa, 1, nf, 1.0,
-                           (double*)facc, st));
+    // forcing gradient: Fourier sums of lambda_{s+1} over the forced steps of the group, once its first segment
+    // is done
+    if (c == cg) {
+      const int64_t ga = cg * C, gb = std::min(S, (cg + G_seg) * C);
+      const int64_t nf = std::min(gb, pl.forced_end) - ga;
+      if (f_grad && nf > 0)
+        RES_TRY(project_rows(op, 1, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, ga, 1, nf, 1.0,
+                             (double*)facc, st));
+    }
   }
   if (mu_cols) launch_sum_columns(mu_cols, k, nsite, mu_grad, st);
   // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j

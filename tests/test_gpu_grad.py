@@ -71,6 +71,26 @@ def test_gl_backward_matches_oracle(method, ckpt):
     assert e[0] < 1e-10 and e[1] < 1e-6
 
 
+@pytest.mark.parametrize("ckpt", [64, 3])
+def test_gl_backward_several_projection_groups(ckpt):
+    """300 steps: the forcing gradient projects the lambda rows of up to 256 steps at a time, so checkpoints every
+    64 steps make groups of four segments and one ragged group (64 64 64 64 | 44), every 3 steps groups of 85
+    segments (255 | 45 rows)."""
+    say("case: GL N=40 backward, periodic 5 periods (300 steps), checkpoint_every", ckpt)
+    n, h, P, nw, k, w0 = 40, 0.1, 60, 3, 2, -0.4
+    dw = 2 * np.pi / (P * h)
+    run = dict(periods=5, stride=6)
+    op = gpu_gl(n, 0.2, h)
+    F, G = forcing(57, nw, k, n), forcing(58, nw, k, n)
+    fg, mg = backward(op, F, G, op.grid(w0, dw, nw), op.run("periodic", **run), ckpt)
+    L0 = O_ops.gl_operator(n, 0.2, -0.01, xl=XL_T, xr=XR_T)[0]
+    ref_f = O_grad.stepped_vjp(L0, h, w0, dw, G, "periodic", **run)
+    ref_mu = O_grad.stepped_mu_gradient(L0, np.zeros(n), h, w0, dw, F, G, "periodic", **run)
+    e = (maxrel(fg, ref_f), maxrel(mg, ref_mu))
+    say("  f_grad err %.3e  mu_grad err %.3e" % e)
+    assert e[0] < 1e-10 and e[1] < 1e-6
+
+
 def test_gl_backward_spans_several_workgroups():
     # N = 300: two 256-wide blocks of the stage kernels with a ragged tail; mu checked along random directions.
     say("case: GL N=300 on [-50, 50] backward, periodic, checkpoint_every 16")
