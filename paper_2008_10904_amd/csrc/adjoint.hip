@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= op.nsite) return;
   const int64_t blk = (int64_t)NC * op.nsite;
-  for (int b = 0; b < k; ++b) {
+  for (int b = blockIdx.y; b < k; b += gridDim.y) {  // one column per grid row
     cx<double> z[NC];
     zsite<KIND, NC>(op, yin + b * blk, p, z);
 #pragma unroll
@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
 }
 
 // Reverse stage m (4..1) with opH = Z^H; see the header comment.  lam holds lambda' (read at every stage);
-// kin = Kb_m (m < 4), kout = Kb_{m-1} (m > 1); mu += h Re(conj(Kb_m) y_m) (mu null: skipped).  No running sum is
+// kin = Kb_m (m < 4), kout = Kb_{m-1} (m > 1); mu row r += h Re(conj(Kb_m) y_m) summed over the columns of grid
+// row r (mu [rev_stage_rows(k)][nsite], null: skipped; a node's columns go to separate rows, summed afterwards).  No running sum is
 // kept: with yb_4 = Kb_3 - lambda'/3, yb_3 = 2 Kb_2 - 2 lambda'/3 and yb_2 = 2 Kb_1 - lambda'/3, stage 1 forms
 // lambda = -lambda'/3 + Kb_3 + 2 Kb_2 + 2 Kb_1 + yb_1 (+ inj, null: none) from k3 = Kb_3 and k2 = Kb_2 into
 // lam_out (which must not alias lam, kin, k3 or k2).
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
   if (p >= opH.nsite) return;
   const int64_t blk = (int64_t)NC * opH.nsite;
   double musum = 0.0;
-  for (int b = 0; b < k; ++b) {
+  for (int b = blockIdx.y; b < k; b += gridDim.y) {  // one column per grid row
     cx<double> z[NC];
     zsite<KIND, NC>(opH, (m == 4 ? lam : kin) + b * blk, p, z);
 #pragma unroll
@@ -133,13 +134,13 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
       }
     }
   }
-  if (mu != nullptr) mu[p] += h * musum;
+  if (mu != nullptr) mu[blockIdx.y * opH.nsite + p] += h * musum;
 }
 
 // ---------------------------------------------------------------------------------------------------------
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
                      void* acc, const void* f, double h, hipStream_t st) {
-  const dim3 grid((unsigned)((op.nsite + 255) / 256));
+  const dim3 grid((unsigned)((op.nsite + 255) / 256), (unsigned)std::min(k, 65535));
 #define RES_F(KIND, NC)                                                                                          \
   hipLaunchKernelGGL((fwd_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, op, k, m, (const cx<double>*)u,      \
                      (cx<double>*)uout, (const cx<double>*)yin, (cx<double>*)yout, (cx<double>*)acc, (const cx<double>*)f, h)
@@ -415,10 +416,12 @@ int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void
   return 0;
 }
 
+int rev_stage_rows(int k) { return std::min(k, 65535); }
+
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
                      hipStream_t st) {
-  const dim3 grid((unsigned)((opH.nsite + 255) / 256));
+  const dim3 grid((unsigned)((opH.nsite + 255) / 256), (unsigned)rev_stage_rows(k));
 #define RES_R(KIND, NC)                                                                                            \
   hipLaunchKernelGGL((rev_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, opH, k, m,                          \
                      (const cx<double>*)lam, (cx<double>*)lam_out, (const cx<double>*)kin, (const cx<double>*)y,     \

@@ -93,6 +93,8 @@ int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out
                       const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st);
 // mu[p] += sum over the k rows of cols [k][n].
 int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStream_t st);
+// Grid rows (and mu rows) of the reverse stage launches for k columns.
+int rev_stage_rows(int k);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
                      hipStream_t st);

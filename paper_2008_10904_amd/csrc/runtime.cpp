@@ -1405,13 +1405,16 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   // march ping-pongs between u and a second row.
   const bool fused = fwd.kind == 1 && fwd.ncomp == 1 && fwd.g.nz == 1;
   void* u2 = nullptr;
-  double* mu_cols = nullptr;  // per-column mu rows of the fused reverse steps, summed at the end
+  // per-column mu rows of the reverse steps (one row per column, or per grid row of the stage launches), summed at
+  // the end: the columns of a node run in different threads, and the sum stays deterministic
+  double* mu_cols = nullptr;
+  const int mu_rows = fused ? k : rev_stage_rows(k);
   if (fused) RES_TRY(ws_get(op, "bw_u2", rowb, &u2));
-  if (fused && mu_grad) {
+  if (mu_grad) {
     void* p;
-    RES_TRY(ws_get(op, "bw_mu_cols", (size_t)k * nsite * sizeof(double), &p));
+    RES_TRY(ws_get(op, "bw_mu_cols", (size_t)mu_rows * nsite * sizeof(double), &p));
     mu_cols = (double*)p;
-    RES_TRY(zero_device(mu_cols, (size_t)k * nsite * sizeof(double), st));
+    RES_TRY(zero_device(mu_cols, (size_t)mu_rows * nsite * sizeof(double), st));
   }
 
   // 1. forward march with checkpoints
@@ -1528,10 +1531,10 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         continue;
       }
       // Kb_3 in ka, Kb_2 in kb, Kb_1 in ub; stage 1 combines the three into lambda
-      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_grad, nullptr, h, st);
-      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lseg, r - 1) : carry, ub, us, nullptr, ka, kb, mu_grad, seed, h,
+      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_cols, nullptr, h, st);
+      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_cols, nullptr, h, st);
+      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_cols, nullptr, h, st);
+      launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lseg, r - 1) : carry, ub, us, nullptr, ka, kb, mu_cols, seed, h,
                        st);
     }
     HIP_TRY(hipGetLastError());
@@ -1545,7 +1548,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
                              (double*)facc, st));
     }
   }
-  if (mu_cols) launch_sum_columns(mu_cols, k, nsite, mu_grad, st);
+  if (mu_cols) launch_sum_columns(mu_cols, mu_rows, nsite, mu_grad, st);
   // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j
   if (f_grad) {
     void *ya, *yb;
