@@ -58,6 +58,9 @@ def parse():
                     help="--algorithm trm: RK4 steps between samples (1: the paper's every-step sampling); the window, "
                          "taper and FIR resolution stay the same (order 3000 / every), and the march takes four "
                          "steps per kernel step when every is a multiple of four")
+    ap.add_argument("--weighted", action="store_true",
+                    help="gl_periodic_n2000 with diagonal B (forcing window over the upstream 60 %%), C (observation "
+                         "window over the downstream 60 %%) and metrics W_f = W_y = dx")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -653,6 +656,9 @@ def main():
         return
     if args.plan is None:
         args.plan = "tuned" if args.workload == "gl_batched_64" else "default"
+    if args.weighted and (args.workload != "gl_periodic_n2000" or args.algorithm != "power"):
+        print("--weighted measures the block-power iteration of gl_periodic_n2000", file=sys.stderr)
+        sys.exit(2)
     if args.algorithm == "trm":
         if args.workload != "gl_paper_n200":
             print("--algorithm trm measures gl_paper_n200", file=sys.stderr)
@@ -686,7 +692,10 @@ def main():
     F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
     sweeps_per_step = cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
 
+    weights = W.gl_weights(cfg["N"]) if args.weighted else None
     op = build_op(cfg, "fp64")
+    if weights is not None:
+        op.set_weights(*weights)
     if args.step_power:
         op.set_step_power(args.step_power)
     plan64 = choose_plan(op, cfg["k"], args.plan)  # set-up: the stepper plan
@@ -726,10 +735,15 @@ def main():
         "stepper_plan": list(plan64),
         "step_power": power,
     }
+    if weights is not None:
+        out["config"]["weights"] = ("B: window over the upstream 60 %, C: window over the downstream 60 %, "
+                                    "W_f = W_y = dx (gains of C R B in the W norms)")
     del op, f64
     torch.cuda.empty_cache()
     if not args.no_mixed:
         opm = build_op(cfg, "mixed")
+        if weights is not None:
+            opm.set_weights(*weights)
         if args.step_power:
             opm.set_step_power(args.step_power)
         planm = choose_plan(opm, cfg["k"], args.plan)

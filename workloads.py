@@ -28,6 +28,8 @@ Workloads (the paper publishes no data set; every input is synthetic):
 * ``ADR3D``         3-D three-component advection-diffusion with shear coupling, 256 x 128 x 128, FP32 state,
                     96 frequencies in [0, pi/2], k = 3, periodic method, checkpoints every 64 steps.
 
+``gl_weights`` gives diagonal B, C, W_f, W_y (forcing window, observation window, grid quadrature) on the GL grid.
+
 Random forcings are complex with independent N(0,1) real and imaginary parts from NumPy's PCG64 with the
 workload seed (seed = 20081090 + index).
 """
@@ -77,6 +79,26 @@ ADR3D = dict(name="adr3d3c_256x128x128", kind="adr3d3c", nx=256, ny=128, nz=128,
              wmin=0.0, wmax=math.pi / 2, n_omega=96, method="periodic", periods=3, stride=1, tail=0,
              k=3, iters=1, precision="mixed", mu_const=-0.05, nu_s=1.0, checkpoint_every=64,
              seed=SEED_BASE + 4)
+
+
+def gl_weights(n, xl=GL_DOMAIN[0], xr=GL_DOMAIN[1]):
+    """Diagonal input, output and metric weights on the n interior nodes of the GL grid (x_i = xl + (i + 1) dx,
+    dx = (xr - xl) / (n + 1)): B a smooth window over the upstream 60 % of the domain (where forcing may act), C a
+    smooth window over the downstream 60 % (where the response is observed), W_f = W_y = dx (the quadrature of the
+    uniform grid).  The windows overlap: disjoint ones (forcing upstream of the observed region only) make C R B
+    so nearly low-rank that the four leading gains span more than 1e7 at w = 0.  Returns (b, c, wf, wy) as float64
+    arrays."""
+    dx = (xr - xl) / (n + 1)
+    x = xl + dx * np.arange(1, n + 1)
+    t = (x - xl) / (xr - xl)
+
+    def window(a, b, w):
+        return 0.5 * (np.tanh((t - a) / w) - np.tanh((t - b) / w))
+
+    b = window(0.0, 0.6, 0.05)
+    c = window(0.4, 1.0, 0.05)
+    w = np.full(n, dx)
+    return b, c, w, w.copy()
 
 
 def rng(seed):
