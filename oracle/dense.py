@@ -14,6 +14,8 @@
 * ``resolvent_rk4``      -- R_d(w) = (e^{i w h} I - P(Z))^{-1} h Q_w(Z): the exact steady response of
                             the RK4-discretised system to F e^{i w t}, i.e. the operator the time-stepped
                             method computes once transients have died out.  R_d -> R as h^4.
+* ``rk4_steady_residual`` -- e^{i w h} u - P(Z) u - h Q_w(Z) f by matrix-vector products, zero exactly when
+                            u = R_d(w) f: checks a steady response at sizes where R_d cannot be formed.
 """
 import numpy as np
 
@@ -68,3 +70,22 @@ def resolvent_rk4(L, w, h):
     n = Z.shape[0]
     return np.linalg.solve(np.exp(1j * w * h) * np.eye(n) - rk4_amplification(Z),
                            rk4_forcing_matrix(Z, w, h))
+
+
+def rk4_steady_residual(L, w, h, u, f):
+    """e^{i w h} u - P(Z) u - h Q_w(Z) f with Z = h L (sparse or dense), the polynomials of rk4_amplification and
+    rk4_forcing_matrix applied by repeated products with L."""
+    a = np.exp(1j * w * h / 2.0)
+    b = np.exp(1j * w * h)
+    u = np.asarray(u, dtype=complex)
+    f = np.asarray(f, dtype=complex)
+    z1 = h * (L @ u)
+    z2 = h * (L @ z1)
+    z3 = h * (L @ z2)
+    z4 = h * (L @ z3)
+    Pu = u + z1 + z2 / 2.0 + z3 / 6.0 + z4 / 24.0
+    g1 = h * (L @ f)
+    g2 = h * (L @ g1)
+    g3 = h * (L @ g2)
+    Qf = h * ((1 + 4 * a + b) * f + (1 + 2 * a) * g1 + (1 + a) * g2 / 2.0 + g3 / 4.0) / 6.0
+    return b * u - Pu - Qf

@@ -1,6 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times (default stepper plan for the
-N = 2000 workload, tuned plan for the batched one, whole-period forcing tables), on sampled outputs that the
-oracle computes one by one.  After its settle periods the periodic method has reached the RK4 steady state (the
+N = 2000 workload, tuned plan for the batched one, whole-period forcing tables, the 2-D step kernel on the full
+1024 x 512 grid), on sampled outputs that the oracle computes one by one, or, where R_d cannot be formed, through
+the steady-state equation e^{i w h} u - P(Z) u = h Q_w(Z) f evaluated by the oracle's matrix-vector products.  After its settle periods the periodic method has reached the RK4 steady state (the
 transient is below e^-40 for these operators), so u_hat_j = R_d(w_j) F_j and z_hat_j = R_d(w_j)^H G_j for every
 sampled frequency j, with R_d from the oracle's dense solve.  Tolerances as for the small parity tests: 1e-10 per
 response vector in FP64, 1e-3 in mixed precision."""
@@ -90,3 +91,89 @@ def test_gl_batched_64_full_size(tmp_path, monkeypatch):
         e = max(rel(u[j, c, sl], Rd @ F[j, c, sl]) for c in range(cfg["k"]))
         say("  instance %d (N=%d) j=%d  apply %.2e" % (m, n, j, e))
         assert e < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adr2d_1024x512_full_size_steady_state(precision):
+    """The 2-D operator on its full grid, periodic method (P = 500, 150 periods: the numerical abscissa of L is at
+    most max(mu - sponge) = -0.02, so the transient is below e^-30 when the last period is projected).  Every
+    frequency and column of the response must satisfy the RK4 steady-state equation; the residual is relative to
+    the forcing term h Q_w(Z) f."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr2d_coefficients
+    cfg = W.ADR2D
+    nx, ny, h, k = cfg["nx"], cfg["ny"], cfg["h"], cfg["k"]
+    P, periods, nw, w0 = 500, 150, 4, 0.2
+    dw = 2 * np.pi / (P * h)
+    say("case: full-size 2-D %d x %d periodic apply (P=%d, %d periods), %s" % (nx, ny, P, periods, precision))
+    c = adr2d_coefficients(nx, ny, Re=cfg["Re"], mu_base=cfg["mu_base"], mu_amp=cfg["mu_amp"], mu_xc=cfg["mu_xc"],
+                           mu_w2=cfg["mu_w2"], nu_s=cfg["nu_s"])
+    op = ResolventOp.grid_operator("adr2d", nx, ny, 1, c, h, precision=precision)
+    F = W.random_forcing(cfg["seed"], nw, k, nx * ny)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    u = op.apply(gpu_tensor(F, dt), op.grid(w0, dw, nw), op.run("periodic", periods=periods, stride=1))
+    u = u.cpu().numpy().astype(np.complex128)
+    op.check()
+    del op
+    release()
+    f = O_ops.adr2d_fields(nx, ny, nu_s=cfg["nu_s"])
+    mu = O_ops.adr2d_mu_default(f["X"], f["Y"], base=cfg["mu_base"], amp=cfg["mu_amp"], xc=cfg["mu_xc"],
+                                width2=cfg["mu_w2"])
+    L, _ = O_ops.adr2d_operator(nx, ny, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    Fc = F.astype(np.complex64).astype(np.complex128) if precision == "mixed" else F
+    tol = 1e-10 if precision == "fp64" else 1e-4  # measured: 3e-15 and 1.5e-6
+    worst = 0.0
+    for j in range(nw):
+        w = w0 + j * dw
+        for col in range(k):
+            r = O_dense.rk4_steady_residual(L, w, h, u[j, col], Fc[j, col])
+            q = O_dense.rk4_steady_residual(L, w, h, np.zeros_like(u[j, col]), Fc[j, col])  # -h Q_w(Z) f
+            e = float(np.linalg.norm(r) / np.linalg.norm(q))
+            worst = max(worst, e)
+            say("  j=%d col=%d  residual %.2e" % (j, col, e))
+    assert worst < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adr3d3c_256x128x128_full_size_steady_state(precision):
+    """The 3-D three-component operator on its full grid with the workload's k = 3, periodic method (P = 100,
+    100 periods).  Its eigenvalues are those of the three diagonal blocks (the shear coupling only feeds u from v
+    and w), whose abscissa is at most mu = -0.05, so the transient is below e^-49 times a polynomial factor when the
+    last period is projected.  Two frequencies, every column, against the RK4 steady-state equation."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr3d3c_coefficients
+    cfg = W.ADR3D
+    nx, ny, nz, h, k = cfg["nx"], cfg["ny"], cfg["nz"], cfg["h"], cfg["k"]
+    P, periods, nw, w0 = 100, 100, 2, 0.3
+    dw = 2 * np.pi / (P * h)
+    say("case: full-size 3-D %d x %d x %d periodic apply (P=%d, %d periods), %s" % (nx, ny, nz, P, periods,
+                                                                                  precision))
+    wake = W.wake_parameters(cfg["seed"])
+    mu = np.full((nz, ny, nx), cfg["mu_const"])
+    c = adr3d3c_coefficients(nx, ny, nz, wake, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    op = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, c, h, precision=precision)
+    N = 3 * nx * ny * nz
+    F = W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    u = op.apply(gpu_tensor(F, dt), op.grid(w0, dw, nw), op.run("periodic", periods=periods, stride=1))
+    u = u.cpu().numpy()
+    op.check()
+    del op
+    release()
+    L, _ = O_ops.adr3d3c_operator(nx, ny, nz, wake, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    worst = 0.0
+    for j in range(nw):
+        w = w0 + j * dw
+        for col in range(k):
+            f = F[j, col].astype(np.complex128)
+            r = O_dense.rk4_steady_residual(L, w, h, u[j, col].astype(np.complex128), f)
+            q = O_dense.rk4_steady_residual(L, w, h, np.zeros(N, np.complex128), f)  # -h Q_w(Z) f
+            e = float(np.linalg.norm(r) / np.linalg.norm(q))
+            worst = max(worst, e)
+            say("  j=%d col=%d  residual %.2e" % (j, col, e))
+    assert worst < tol

@@ -148,6 +148,24 @@ def test_rk4_transfer_converges_at_fourth_order():
     assert 14.5 < r1 < 17.5 and 14.5 < r2 < 17.5
 
 
+def test_rk4_steady_residual_vanishes_on_discrete_resolvent_and_converges_at_fifth_order():
+    # The matrix-free residual e^{iwh}u - P(Z)u - hQ_w(Z)f of the steady RK4 response: zero (to rounding) for
+    # u = R_d(w) f; for the continuous response u = (iwI - L)^{-1} f it is (e^{iwh} - P(Z))(R - R_d) f, an O(h)
+    # factor times an O(h^4) difference, so it drops by ~32 per halving of h.
+    L, _ = tiny_gl()
+    w = 0.4
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(L.shape[0]) + 1j * rng.standard_normal(L.shape[0])
+    for h in (0.1, 0.05):
+        Qf = dense.rk4_forcing_matrix(h * L.toarray(), w, h) @ f
+        r = dense.rk4_steady_residual(L, w, h, dense.resolvent_rk4(L, w, h) @ f, f)
+        assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(Qf)
+    u = dense.resolvent(L, w) @ f
+    res = [np.linalg.norm(dense.rk4_steady_residual(L, w, h, u, f)) for h in (0.1, 0.05, 0.025)]
+    r1, r2 = res[0] / res[1], res[1] / res[2]
+    assert 28 < r1 < 36 and 28 < r2 < 36
+
+
 def test_rk4_amplification_is_taylor_of_exponential():
     # P(z) agrees with e^z to fourth order: |P(z) - e^z| ~ |z|^5/120.
     for z in (0.01 + 0.02j, -0.02 + 0.01j):
