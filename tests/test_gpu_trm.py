@@ -353,3 +353,28 @@ def test_trm_errors():
         fir_apply(np.ones(4), F)  # odd order
     assert e.value.code == L.RES_EINVAL
     torch.cuda.synchronize()
+
+
+def test_trm_modes_at_the_benchmark_configuration():
+    """The TRM line's own configuration (the paper's GL model, N = 200, h = 0.01, every step sampled, 6,001
+    samples, 61 frequencies in [-15, 15], FIR order 3,000 in two passes, taper 1,200 + 600, C2 interpolation; FP64),
+    two iterations, against the oracle's trm_power_iteration on the same seeded start forcing."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import paper_gl_coefficients
+    cfg = W.GL_PAPER_TRM
+    say("case: TRM at the benchmark configuration (%d samples, order %d x %d), FP64, 2 iterations" % (
+        cfg["n_samples"], cfg["order"], cfg["passes"]))
+    om = np.linspace(-cfg["wmax"], cfg["wmax"], cfg["n_omega"])
+    kw = dict(order=cfg["order"], passes=cfg["passes"], pad=cfg["pad"], ramp=cfg["ramp"], margin=cfg["margin"])
+    F0 = W.random_forcing(cfg["seed"], cfg["n_samples"], cfg["k"], cfg["N"])
+    lo, d, up = paper_gl_coefficients(cfg["N"], cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision="fp64")
+    g, a, _ = op.trm_modes(gpu_tensor(F0, torch.complex128), om, 2, cfg["every"], cfg["scheme"], **kw)
+    torch.cuda.synchronize()
+    L, _ = O_ops.paper_gl_operator(cfg["N"], cfg["beta"], cfg["U"], cfg["gamma"], cfg["length"])
+    g_ref, a_ref = O_trm.trm_power_iteration(L, cfg["h"], cfg["every"], 2, F0, om, 2, **kw)[:2]
+    eg, ea = np.abs(g / g_ref - 1).max(), np.abs(a / a_ref - 1).max()
+    say("  gains %.2e  amplitudes %.2e" % (eg, ea))
+    assert eg < 1e-8 and ea < 1e-8
