@@ -227,3 +227,34 @@ def test_adr2d_1024x512_full_size_reverse_mode():
     assert abs(gd - fd) < 1e-6 * abs(fd)  # measured 5.7e-9: the O(eps^2) truncation of the central difference
     del op
     release()
+
+
+def test_gl_periodic_n2000_full_size_block_arnoldi(monkeypatch):
+    """The Arnoldi line's configuration (N = 2000, k = 4, 256 frequencies, 10 periods per run, 10 blocks of 4
+    forcings, FP64, default stepper plan): the four leading gains at sampled frequencies against the singular values
+    of the oracle's dense R_d(w_j), to the FP64 gain bound 1e-8 (measured: 6e-11 at most)."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients, snap_grid
+    monkeypatch.delenv("RESOLVENT_STEP1D", raising=False)
+    cfg = W.GL_PERIODIC
+    say("case: full-size GL N=2000 block Arnoldi, 10 blocks of k=4, FP64")
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], cfg["N"])
+    lo, d, up = gl_coefficients(cfg["N"], cfg["mu0"], cfg["mu2"])
+    op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision="fp64")
+    grid = op.grid(w0, dw, cfg["n_omega"])
+    run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+    gains, _, _, _ = op.krylov(gpu_tensor(F, torch.complex128), grid, run, 10, want_modes=False, want_hist=False)
+    op.check()
+    del op
+    release()
+    L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
+    worst = 0.0
+    for j in (0, 101, 255):
+        s = np.linalg.svd(O_dense.resolvent_rk4(L, w0 + j * dw, cfg["h"]), compute_uv=False)[:cfg["k"]]
+        e = float(np.abs(gains[0, j] / s - 1).max())
+        worst = max(worst, e)
+        say("  j=%d  gains %s  rel err %.2e" % (j, np.array2string(gains[0, j], precision=6), e))
+    assert worst < 1e-8
