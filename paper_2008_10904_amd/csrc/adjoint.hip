@@ -154,7 +154,8 @@ int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout
 // The four forward stages of one step in one launch, for a 2-D one-component grid operator: a 64 x 16 tile of the
 // state with a halo of four sites (the reach of four stencil applications) sits in LDS; stage m computes the
 // padded-tile sites [m, P - m) from the previous stage's values, so the last stage covers the tile.  Writes the
-// stage inputs y2, y3, y4 and the new state uout on the tile (each may be null; uout null: the three stages only).
+// stage inputs y2, y3, y4 and the new state uout on the tile (each may be null; uout null: the three stages only),
+// adding the row gadd to uout when given.
 // The stage values are those of fwd_stage_kernel (same operand order); the RK4 accumulator keeps the increments
 // K_m themselves instead of recovering K_1 and K_3 from stage values.  Out-of-domain sites hold zero.  uout must not alias u (neighbouring tiles read u's halo).
 //
@@ -187,7 +188,8 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
                                                           cx<double>* y2o, cx<double>* y3o, cx<double>* y4o,
                                                           const cx<double>* __restrict__ fa,
                                                           const cx<double>* __restrict__ fb,
-                                                          const cx<double>* __restrict__ fc, double h) {
+                                                          const cx<double>* __restrict__ fc, double h,
+                                                          const cx<double>* __restrict__ gadd) {
   __shared__ cx<double> U[kFsPY][kFsPX], Y[kFsPY][kFsPX];
   const int64_t nodes = nx * ny;
   const int64_t col = blockIdx.z;
@@ -238,6 +240,11 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
         acc = m == 1 ? K : mk<double>(acc.re + 2.0 * K.re, acc.im + 2.0 * K.im);
       } else {
         tv = mk<double>(uu.re + (acc.re + K.re) / 6.0, uu.im + (acc.im + K.im) / 6.0);
+        if (gadd != nullptr) {
+          const cx<double> g = gadd[col * nodes + gy * nx + gx];
+          tv.re += g.re;
+          tv.im += g.im;
+        }
       }
     }
     // one ring site (stages 1..3)
@@ -402,7 +409,7 @@ int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStre
 }
 
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
-                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st) {
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st, const void* gadd) {
   if (op.kind != 1 || op.ncomp != 1 || op.g.nz != 1 || k < 1 || k > 65535 || (uout != nullptr && uout == u))
     return -1;
   GridCoef<double> c;
@@ -412,7 +419,7 @@ int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void
   const dim3 grid((unsigned)((op.g.nx + kFsTX - 1) / kFsTX), (unsigned)((op.g.ny + kFsTY - 1) / kFsTY), (unsigned)k);
   hipLaunchKernelGGL(fwd_step2d_kernel, grid, dim3(1024), 0, st, c, op.g.nx, op.g.ny, (const cx<double>*)u,
                      (cx<double>*)uout, (cx<double>*)y2, (cx<double>*)y3, (cx<double>*)y4, (const cx<double>*)fa,
-                     (const cx<double>*)fb, (const cx<double>*)fc, h);
+                     (const cx<double>*)fb, (const cx<double>*)fc, h, (const cx<double>*)gadd);
   return 0;
 }
 

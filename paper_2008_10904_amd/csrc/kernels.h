@@ -83,9 +83,11 @@ struct AdjOpDev {
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
                      void* acc, const void* f, double h, hipStream_t st);
 // The four forward stages of one step in one launch for a 2-D one-component grid operator (stage inputs y2, y3, y4
-// and uout may each be null; uout must not alias u).  Returns -1 for other operators.
+// and uout may each be null; uout must not alias u).  gadd (null: none) is added to uout: with fa = fb = fc = null
+// the step is u' = P(Z) u + gadd, the march with pre-filtered forcing rows.  Returns -1 for other operators.
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
-                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st);
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st,
+                      const void* gadd = nullptr);
 // The four reverse stages of one step in one launch for a 2-D one-component grid operator (one workgroup per tile
 // and column; the mu contributions go to the per-column rows mu_cols [k][nodes]; lam_out must not alias lam).
 // Returns -1 for other operators.
