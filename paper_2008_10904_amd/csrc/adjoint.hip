@@ -45,12 +45,14 @@ __device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __re
 // m=3: yout = u + K_3;  m=4: uout = u + (acc + 2 K_3 + K_4)/6 (uout may equal u).  The earlier stage increments
 // are recovered from the stage values, K_1 = 2 (y_2 - u) at m = 2 (yin = y_2) and K_3 = y_4 - u at m = 4
 // (yin = y_4), so only stages 2 and 4 touch acc (four fewer rows moved per step).  acc may be null when only the
-// stage values are wanted (m < 4); f null means no forcing.
+// stage values are wanted (m < 4); f null means no forcing.  gadd (m = 4, null: none) is added to uout: with f null
+// at every stage the step is u' = P(Z) u + gadd, the march with pre-filtered forcing rows.
 template <int KIND, int NC>
 __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int m, const cx<double>* u,
                                                         cx<double>* uout, const cx<double>* __restrict__ yin,
                                                         cx<double>* yout,
-                                                        cx<double>* acc, const cx<double>* __restrict__ f, double h) {
+                                                        cx<double>* acc, const cx<double>* __restrict__ f, double h,
+                                                        const cx<double>* __restrict__ gadd) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= op.nsite) return;
   const int64_t blk = (int64_t)NC * op.nsite;
@@ -69,7 +71,12 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
       if (m == 4) {
         const cx<double> a = acc[e], y4 = yin[e];
         const double k3r = y4.re - uu.re, k3i = y4.im - uu.im;
-        uout[e] = mk<double>(uu.re + (a.re + 2.0 * k3r + K.re) / 6.0, uu.im + (a.im + 2.0 * k3i + K.im) / 6.0);
+        cx<double> un = mk<double>(uu.re + (a.re + 2.0 * k3r + K.re) / 6.0, uu.im + (a.im + 2.0 * k3i + K.im) / 6.0);
+        if (gadd != nullptr) {
+          un.re += gadd[e].re;
+          un.im += gadd[e].im;
+        }
+        uout[e] = un;
       } else {
         const double w = m == 3 ? 1.0 : 0.5;
         yout[e] = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
@@ -139,11 +146,12 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
 
 // ---------------------------------------------------------------------------------------------------------
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
-                     void* acc, const void* f, double h, hipStream_t st) {
+                     void* acc, const void* f, double h, hipStream_t st, const void* gadd) {
   const dim3 grid((unsigned)((op.nsite + 255) / 256), (unsigned)std::min(k, 65535));
 #define RES_F(KIND, NC)                                                                                          \
   hipLaunchKernelGGL((fwd_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, op, k, m, (const cx<double>*)u,      \
-                     (cx<double>*)uout, (const cx<double>*)yin, (cx<double>*)yout, (cx<double>*)acc, (const cx<double>*)f, h)
+                     (cx<double>*)uout, (const cx<double>*)yin, (cx<double>*)yout, (cx<double>*)acc,                \
+                     (const cx<double>*)f, h, (const cx<double>*)gadd)
   if (op.kind == 0) RES_F(0, 1);
   else if (op.ncomp == 3) RES_F(1, 3);
   else RES_F(1, 1);

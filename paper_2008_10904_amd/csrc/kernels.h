@@ -81,7 +81,7 @@ struct AdjOpDev {
   GridOpDev g;
 };
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
-                     void* acc, const void* f, double h, hipStream_t st);
+                     void* acc, const void* f, double h, hipStream_t st, const void* gadd = nullptr);
 // The four forward stages of one step in one launch for a 2-D one-component grid operator (stage inputs y2, y3, y4
 // and uout may each be null; uout must not alias u).  gadd (null: none) is added to uout: with fa = fb = fc = null
 // the step is u' = P(Z) u + gadd, the march with pre-filtered forcing rows.  Returns -1 for other operators.

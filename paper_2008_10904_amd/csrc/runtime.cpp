@@ -1372,25 +1372,19 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(phase_table64(op, pl.P, &btab));
   if (mu_grad) RES_TRY(zero_device(mu_grad, (size_t)nsite * sizeof(double), st));
   auto row = [&](void* base, int64_t r) { return (void*)((char*)base + (size_t)r * rowb); };
-  // raw forcing of steps [sa, sb): half-step samples 2 sa .. 2 sb.  The GEMM works on 64-row tiles, so the
-  // 2 C + 1 samples of a whole segment would take a third tile for a single row.  A sample shared with the segment
-  // synthesised just before is copied instead: shared < 0, the first sample is the last one (row 2 C) of the
-  // previous segment in time (forward order); shared > 0, the last sample is the first one (row 0) of the next
-  // segment in time (reverse order).
-  auto synth_segment = [&](int64_t sa, int64_t sb, int shared) -> int {
+  // raw forcing of steps [sa, sb) for the segment recomputation: half-step samples 2 sa .. 2 sb.  The GEMM works
+  // on 64-row tiles, so the 2 C + 1 samples of a whole segment would take a third tile for a single row: with
+  // `shared`, the last sample is the first one (row 0) of the segment synthesised just before (the next one in
+  // time: segments are visited in reverse) and is copied instead.
+  auto synth_segment = [&](int64_t sa, int64_t sb, bool shared) -> int {
     if (sa >= pl.forced_end) return RES_OK;
     const int64_t len = sb - sa;
-    int64_t r0 = 0, n = 2 * len + 1;
-    if (shared < 0) {
-      HIP_TRY(hipMemcpyAsync(row(frow, 0), row(frow, 2 * C), rowb, hipMemcpyDeviceToDevice, st));
-      r0 = 1;
-      --n;
-    } else if (shared > 0) {
+    int64_t n = 2 * len + 1;
+    if (shared) {
       HIP_TRY(hipMemcpyAsync(row(frow, 2 * len), row(frow, 0), rowb, hipMemcpyDeviceToDevice, st));
       --n;
     }
-    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa + r0, 1, n, row(frow, r0),
-                      st);
+    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa, 1, n, frow, st);
   };
   auto frc = [&](int64_t s, int64_t r, int half) -> const void* {
     return s < pl.forced_end ? row(frow, 2 * r + half) : nullptr;
@@ -1417,21 +1411,28 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     RES_TRY(zero_device(mu_cols, (size_t)mu_rows * nsite * sizeof(double), st));
   }
 
-  // 1. forward march with checkpoints.  The fused 2-D march only needs the states, so it steps
-  // u' = P(Z) u + sum_j e^{i w_j t_s} G_j with the pre-filtered forcing G_j = h Q_j(Z) F_j: one synthesised row
-  // per step instead of two half-step rows, read once by the step instead of three times.
+  // 1. forward march with checkpoints.  It only needs the states, so it steps u' = P(Z) u + sum_j e^{i w_j t_s} G_j
+  // with the pre-filtered forcing G_j = h Q_j(Z) F_j: one synthesised row per step instead of two half-step rows,
+  // read once per step instead of at every stage.
   void* Gpre = nullptr;
-  if (fused && pl.forced_end > 0) {
+  if (pl.forced_end > 0) {
     void *ya, *yb;
     RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
     RES_TRY(ws_get(op, "horner_b", (size_t)nw * rowb, &yb));
     RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &Gpre));
-    const GridOpDev& g = op->g64[0];
     const double sw0h = pl.w0 * h, sdwh = pl.dw * h;
-    if (launch_grid_horner(g, nullptr, F, 1, ya, 1, k, nw, sw0h, sdwh, h, 0, st) ||
-        launch_grid_horner(g, (const cx<double>*)ya, F, 1, yb, 1, k, nw, sw0h, sdwh, h, 1, st) ||
-        launch_grid_horner(g, (const cx<double>*)yb, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 2, st))
-      return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
+    if (is_grid(op)) {
+      const GridOpDev& g = op->g64[0];
+      if (launch_grid_horner(g, nullptr, F, 1, ya, 1, k, nw, sw0h, sdwh, h, 0, st) ||
+          launch_grid_horner(g, (const cx<double>*)ya, F, 1, yb, 1, k, nw, sw0h, sdwh, h, 1, st) ||
+          launch_grid_horner(g, (const cx<double>*)yb, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 2, st))
+        return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
+    } else {
+      const cx<double>* tri = (const cx<double>*)op->d_tri[0];
+      launch_tri_horner(tri, nullptr, F, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 0, st);
+      launch_tri_horner(tri, (const cx<double>*)ya, F, 1, yb, 1, N, k, nw, sw0h, sdwh, h, 1, st);
+      launch_tri_horner(tri, (const cx<double>*)yb, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 2, st);
+    }
   }
   RES_TRY(zero_device(u, rowb, st));
   void* ucur = u;
@@ -1439,25 +1440,21 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     const int64_t sa = c * C, sb = std::min(S, sa + C);
     HIP_TRY(hipMemcpyAsync(row(cps, c), ucur, rowb, hipMemcpyDeviceToDevice, st));
     if (c == ncp - 1) break;  // the state after the last step is not needed
-    if (fused) {
-      const int64_t nf = std::min(sb, pl.forced_end) - sa;
-      if (nf > 0) RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, Gpre, ncols, sa, 1, nf, frow, st));
-      for (int64_t s = sa; s < sb; ++s) {
+    const int64_t nf = std::min(sb, pl.forced_end) - sa;
+    if (nf > 0) RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, Gpre, ncols, sa, 1, nf, frow, st));
+    for (int64_t s = sa; s < sb; ++s) {
+      const void* g = s < pl.forced_end ? row(frow, s - sa) : nullptr;
+      if (fused) {
         void* unext = ucur == u ? u2 : u;
-        if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h, st,
-                              s < pl.forced_end ? row(frow, s - sa) : nullptr))
+        if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h, st, g))
           return fail(RES_EINVAL, "fused forward step launch");
         ucur = unext;
+        continue;
       }
-      continue;
-    }
-    RES_TRY(synth_segment(sa, sb, c > 0 ? -1 : 0));  // segments before the last one are C steps long
-    for (int64_t s = sa; s < sb; ++s) {
-      const int64_t r = s - sa;
-      launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, frc(s, r, 0), h, st);
-      launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 4, u, u, y2, nullptr, acc, frc(s, r, 2), h, st);
+      launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, nullptr, h, st);
+      launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, nullptr, h, st);
+      launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, nullptr, h, st);
+      launch_fwd_stage(fwd, k, 4, u, u, y2, nullptr, acc, nullptr, h, st, g);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -1493,7 +1490,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C), len = sb - sa;
-    RES_TRY(synth_segment(sa, sb, c + 1 < ncp && sb < pl.forced_end ? 1 : 0));
+    RES_TRY(synth_segment(sa, sb, c + 1 < ncp && sb < pl.forced_end));
     // states u_sa .. u_{sb-1}
     HIP_TRY(hipMemcpyAsync(row(seg, 0), row(cps, c), rowb, hipMemcpyDeviceToDevice, st));
     for (int64_t s = sa; s + 1 < sb; ++s) {
