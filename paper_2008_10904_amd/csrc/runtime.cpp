@@ -1416,22 +1416,21 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   // read once per step instead of at every stage.
   void* Gpre = nullptr;
   if (pl.forced_end > 0) {
-    void *ya, *yb;
+    void* ya;  // the Horner passes ping-pong between Gpre and one work block
     RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
-    RES_TRY(ws_get(op, "horner_b", (size_t)nw * rowb, &yb));
     RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &Gpre));
     const double sw0h = pl.w0 * h, sdwh = pl.dw * h;
     if (is_grid(op)) {
       const GridOpDev& g = op->g64[0];
-      if (launch_grid_horner(g, nullptr, F, 1, ya, 1, k, nw, sw0h, sdwh, h, 0, st) ||
-          launch_grid_horner(g, (const cx<double>*)ya, F, 1, yb, 1, k, nw, sw0h, sdwh, h, 1, st) ||
-          launch_grid_horner(g, (const cx<double>*)yb, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 2, st))
+      if (launch_grid_horner(g, nullptr, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 0, st) ||
+          launch_grid_horner(g, (const cx<double>*)Gpre, F, 1, ya, 1, k, nw, sw0h, sdwh, h, 1, st) ||
+          launch_grid_horner(g, (const cx<double>*)ya, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 2, st))
         return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
     } else {
       const cx<double>* tri = (const cx<double>*)op->d_tri[0];
-      launch_tri_horner(tri, nullptr, F, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 0, st);
-      launch_tri_horner(tri, (const cx<double>*)ya, F, 1, yb, 1, N, k, nw, sw0h, sdwh, h, 1, st);
-      launch_tri_horner(tri, (const cx<double>*)yb, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 2, st);
+      launch_tri_horner(tri, nullptr, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 0, st);
+      launch_tri_horner(tri, (const cx<double>*)Gpre, F, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 1, st);
+      launch_tri_horner(tri, (const cx<double>*)ya, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 2, st);
     }
   }
   RES_TRY(zero_device(u, rowb, st));
@@ -1460,7 +1459,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   HIP_TRY(hipGetLastError());
 
   // 2. reverse sweep over the segments.  The segment's forward recomputation keeps the three stage inputs of every
-  // step but its last when they fit in a quarter of the free device memory, so the reverse steps do not march them
+  // step but its last when they fit in half of the free device memory, so the reverse steps do not march them
   // again (the values are the same: the stages of a step depend only on its state and forcing).
   void* stg = nullptr;
   {
@@ -1469,7 +1468,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     const auto held = op->ws.find("bw_stages");
     const double avail = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0);
     const size_t need = (size_t)3 * C * rowb;
-    if ((double)need <= 0.25 * avail && ws_get(op, "bw_stages", need, &stg) != RES_OK) {
+    if ((double)need <= 0.5 * avail && ws_get(op, "bw_stages", need, &stg) != RES_OK) {
       g_last_error.clear();
       stg = nullptr;
     }
@@ -1569,7 +1568,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   if (f_grad) {
     void *ya, *yb;
     RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
-    RES_TRY(ws_get(op, "horner_b", (size_t)nw * rowb, &yb));
+    RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &yb));  // free again after the checkpoint march
     const double sw0h = -pl.w0 * h, sdwh = -pl.dw * h;
     if (is_grid(op)) {
       const GridOpDev& g = op->g64[1];
