@@ -177,7 +177,11 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
  * `checkpoint_every` steps).  g_hat = dJ/du_hat (device, same layout/dtype as u_hat, with the convention
  * dJ/dRe + i dJ/dIm).  Outputs: f_grad (device, same layout as f_hat, same convention) if not NULL, and
  * mu_grad (device double, RES_OP_TRIDIAG: [n_total], ADR kinds: [nz*ny*nx]) = dJ/d(real part of the diagonal)
- * if not NULL.  Supported for RES_TRANSIENT and RES_PERIODIC runs. */
+ * if not NULL.  Supported for RES_TRANSIENT and RES_PERIODIC runs.  checkpoint_every <= 0 picks about
+ * sqrt(steps).  Memory (held by the handle, FP64 whatever the precision): the forcing, seed, pre-filtered forcing
+ * and gradient blocks [n_omega][k][N] plus one Horner work block, ceil(steps / C) checkpoints and a few C-row
+ * segments of [k][N] rows (C = checkpoint_every); the three stage rows of every step of a segment are kept when
+ * they fit in half of the free device memory, else recomputed.  An allocation that fails returns RES_ENOMEM. */
 int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);
