@@ -181,7 +181,9 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
  * sqrt(steps).  Memory (held by the handle, FP64 whatever the precision): the forcing, seed, pre-filtered forcing
  * and gradient blocks [n_omega][k][N] plus one Horner work block, ceil(steps / C) checkpoints and a few C-row
  * segments of [k][N] rows (C = checkpoint_every); the three stage rows of every step of a segment are kept when
- * they fit in half of the free device memory, else recomputed.  An allocation that fails returns RES_ENOMEM. */
+ * they fit in half of the free device memory, else recomputed.  With mu_grad NULL only the adjoint recursion runs
+ * (the forcing gradient does not depend on the forward trajectory): no forward march, checkpoints or recomputation.
+ * An allocation that fails returns RES_ENOMEM. */
 int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);

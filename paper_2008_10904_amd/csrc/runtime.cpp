@@ -1339,9 +1339,14 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   const AdjOpDev fwd = adj_op(op, 0), rev = adj_op(op, 1);
   const int64_t nsite = fwd.nsite;
 
-  // inputs in FP64: F (as given when FP64), seed G = scale * g
+  // The adjoint recursion for lambda is linear and does not involve the forward trajectory: only the mu gradient
+  // needs the states and stage values, so without it the forcing, the forward march, its checkpoints and the
+  // segment recomputation are skipped (the forcing gradient then costs one adjoint march).
+  const bool need_states = mu_grad != nullptr;
+
+  // inputs in FP64: F (as given when FP64; only for the forward trajectory), seed G = scale * g
   const void* F = f_hat;
-  if (!op->fp64()) {
+  if (!op->fp64() && need_states) {
     void* p;
     RES_TRY(ws_get(op, "bw_F", (size_t)nw * rowb, &p));
     launch_convert(f_hat, 0, p, 1, (int64_t)nw * ncols, 1.0, st);
@@ -1351,9 +1356,12 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   void *btab_half, *btab;
   RES_TRY(ws_get(op, "bw_G", (size_t)nw * rowb, &G));
   launch_convert(g_hat, op->fp64(), G, 1, (int64_t)nw * ncols, pl.scale, st);
-  RES_TRY(ws_get(op, "bw_frow", (size_t)(2 * C + 1) * rowb, &frow));
-  RES_TRY(ws_get(op, "bw_ckpt", (size_t)ncp * rowb, &cps));
-  RES_TRY(ws_get(op, "bw_seg", (size_t)C * rowb, &seg));
+  frow = cps = seg = nullptr;
+  if (need_states) {
+    RES_TRY(ws_get(op, "bw_frow", (size_t)(2 * C + 1) * rowb, &frow));
+    RES_TRY(ws_get(op, "bw_ckpt", (size_t)ncp * rowb, &cps));
+    RES_TRY(ws_get(op, "bw_seg", (size_t)C * rowb, &seg));
+  }
   RES_TRY(ws_get(op, "bw_u", rowb, &u));
   RES_TRY(ws_get(op, "bw_acc", rowb, &acc));
   RES_TRY(ws_get(op, "bw_y2", rowb, &y2));
@@ -1415,7 +1423,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   // with the pre-filtered forcing G_j = h Q_j(Z) F_j: one synthesised row per step instead of two half-step rows,
   // read once per step instead of at every stage.
   void* Gpre = nullptr;
-  if (pl.forced_end > 0) {
+  if (need_states && pl.forced_end > 0) {
     void* ya;  // the Horner passes ping-pong between Gpre and one work block
     RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
     RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &Gpre));
@@ -1435,7 +1443,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   }
   RES_TRY(zero_device(u, rowb, st));
   void* ucur = u;
-  for (int64_t c = 0; c < ncp; ++c) {
+  for (int64_t c = 0; c < (need_states ? ncp : 0); ++c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C);
     HIP_TRY(hipMemcpyAsync(row(cps, c), ucur, rowb, hipMemcpyDeviceToDevice, st));
     if (c == ncp - 1) break;  // the state after the last step is not needed
@@ -1468,7 +1476,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     const auto held = op->ws.find("bw_stages");
     const double avail = (double)free_b + (held != op->ws.end() ? (double)held->second.bytes : 0.0);
     const size_t need = (size_t)3 * C * rowb;
-    if ((double)need <= 0.5 * avail && ws_get(op, "bw_stages", need, &stg) != RES_OK) {
+    if (need_states && (double)need <= 0.5 * avail && ws_get(op, "bw_stages", need, &stg) != RES_OK) {
       g_last_error.clear();
       stg = nullptr;
     }
@@ -1489,10 +1497,12 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(zero_device(carry, rowb, st));  // lambda_S = 0: u_S is not sampled
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t sa = c * C, sb = std::min(S, sa + C), len = sb - sa;
-    RES_TRY(synth_segment(sa, sb, c + 1 < ncp && sb < pl.forced_end));
-    // states u_sa .. u_{sb-1}
-    HIP_TRY(hipMemcpyAsync(row(seg, 0), row(cps, c), rowb, hipMemcpyDeviceToDevice, st));
-    for (int64_t s = sa; s + 1 < sb; ++s) {
+    if (need_states) {
+      RES_TRY(synth_segment(sa, sb, c + 1 < ncp && sb < pl.forced_end));
+      // states u_sa .. u_{sb-1}
+      HIP_TRY(hipMemcpyAsync(row(seg, 0), row(cps, c), rowb, hipMemcpyDeviceToDevice, st));
+    }
+    for (int64_t s = sa; need_states && s + 1 < sb; ++s) {
       const int64_t r = s - sa;
       void* us = row(seg, r);
       void* a2 = stg ? srow(r, 0) : y2;
@@ -1520,9 +1530,11 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     HIP_TRY(hipMemcpyAsync(row(lseg, len - 1), carry, rowb, hipMemcpyDeviceToDevice, st));
     for (int64_t s = sb - 1; s >= sa; --s) {
       const int64_t r = s - sa;
-      void* us = row(seg, r);
+      void* us = need_states ? row(seg, r) : nullptr;
       const void *s2 = y2, *s3 = y3, *s4 = y4;  // stage inputs of step s
-      if (stg && s + 1 < sb) {
+      if (!need_states) {
+        s2 = s3 = s4 = nullptr;
+      } else if (stg && s + 1 < sb) {
         s2 = srow(r, 0);
         s3 = srow(r, 1);
         s4 = srow(r, 2);

@@ -192,6 +192,36 @@ def test_grid3d_periodic_backward_checkpoint_64():
         assert abs(mg @ d - fd) < 1e-6 * np.abs(mg).sum() * np.abs(d).max()
 
 
+@pytest.mark.parametrize("case", ["gl", "2d", "3d"])
+def test_forcing_gradient_alone_skips_the_forward_trajectory(case):
+    """Without the mu gradient the reverse mode runs the adjoint recursion alone (no forward march, checkpoints or
+    recomputation: lambda does not depend on the trajectory).  Its forcing gradient must equal the one computed
+    beside the mu gradient (to rounding), and match the oracle's stepped VJP."""
+    import torch
+    say("case: forcing gradient without mu,", case)
+    h, P, nw, k, w0 = 0.1, 50, 3, 2, 0.1
+    dw = 2 * np.pi / (P * h)
+    run = dict(periods=2, stride=5)
+    if case == "gl":
+        op = gpu_gl(40, 0.2, h)
+        L0 = O_ops.gl_operator(40, 0.2, -0.01, xl=XL_T, xr=XR_T)[0]
+    else:
+        op, L0, _, _ = grid_case(case, h)
+    F, G = forcing(59, nw, k, op.n), forcing(60, nw, k, op.n)
+    grid, rn = op.grid(w0, dw, nw), op.run("periodic", **run)
+    f, g = gpu_tensor(F), gpu_tensor(G)
+    fg_both, _ = op.apply_backward(f, g, grid, rn, checkpoint_every=16)
+    fg_alone, mg = op.apply_backward(f, g, grid, rn, checkpoint_every=16, want_mu=False)
+    torch.cuda.synchronize()
+    op.check()
+    assert mg is None
+    say("  alone vs with mu: %.3e" % maxrel(to_np(fg_alone), to_np(fg_both)))
+    assert maxrel(to_np(fg_alone), to_np(fg_both)) < 1e-13  # same recursion; only the projection grouping may differ
+    ref = O_grad.stepped_vjp(L0, h, w0, dw, G, "periodic", **run)
+    say("  f_grad err %.3e" % maxrel(to_np(fg_alone), ref))
+    assert maxrel(to_np(fg_alone), ref) < 1e-10
+
+
 def test_grid_backward_spans_several_tiles():
     """The fused 2-D forward step of the reverse mode works on 64 x 16 tiles with halos taken from neighbouring
     tiles: a 150 x 40 grid (three ragged tiles in each direction).  The forcing gradient is checked by the exact
