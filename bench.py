@@ -290,8 +290,12 @@ def bench_grid(args):
         op.apply_backward(f, g, grid, run)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        autograd = {"forward_s": t1 - t0, "backward_s": t2 - t1,
-                    "note": "one apply and one apply_backward (forcing and mu gradients) of the full workload"}
+        op.apply_backward(f, g, grid, run, want_mu=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        autograd = {"forward_s": t1 - t0, "backward_s": t2 - t1, "backward_forcing_only_s": t3 - t2,
+                    "note": "one apply and one apply_backward (forcing and mu gradients) of the full workload; "
+                            "then the forcing gradient alone (adjoint recursion only)"}
     else:
         nw, P = 8, 64
         dw = 2 * np.pi / (P * cfg["h"])
@@ -377,9 +381,15 @@ def grad3d_half(cfg):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ok = bool(torch.isfinite(fg).all().item()) and bool(np.isfinite(mg.cpu().numpy()).all())
+    del fg, mg
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    op.apply_backward(f, g, grid, run, checkpoint_every=cfg["checkpoint_every"], want_mu=False)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
     return {"grid": [half["nx"], half["ny"], half["nz"]], "n_omega": nw, "k": k, "P": P,
             "time_steps": cfg["periods"] * P, "checkpoint_every": cfg["checkpoint_every"],
-            "forward_s": t1 - t0, "backward_s": t2 - t1, "finite": ok,
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_forcing_only_s": t4 - t3, "finite": ok,
             "note": "one apply and one apply_backward (forcing and mu gradients), periodic method, on the grid "
                     "halved in each direction"}
 
