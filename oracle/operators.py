@@ -65,12 +65,6 @@ def gl_operator(n, mu0=None, mu2=None, nu=GL_NU, gamma=GL_GAMMA, xl=-50.0, xr=50
     return L.tocsr().astype(np.complex128), x
 
 
-def gl_batched_operator(instances, nu=GL_NU, gamma=GL_GAMMA, xl=-50.0, xr=50.0):
-    """Block-diagonal L of independent GL instances, ``instances`` = list of (n, mu0, mu2)."""
-    blocks = [gl_operator(n, mu0, mu2, nu, gamma, xl, xr)[0] for (n, mu0, mu2) in instances]
-    return sp.block_diag(blocks, format="csr").astype(np.complex128)
-
-
 def paper_gl_operator(n, beta=0.1, U=6.0, gamma=1.0, length=40.0):
     """The Ginzburg-Landau model of Sec. 3 (eq. GL_timeDomain): A = U d/dx - mu(x) - gamma d2/dx2 on (0, length)
     with u = 0 at both ends, mu(x) = beta mu_c (1 - x/20) and mu_c = U^2 Re(gamma) / |gamma|^2.  All

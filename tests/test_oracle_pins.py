@@ -105,6 +105,56 @@ def test_adr3d3c_operator_matches_pde_on_smooth_function():
     assert 3.3 < errs[0] / errs[1] < 4.7
 
 
+def test_wake_shear_is_the_derivative_of_the_wake():
+    # U_y and U_z of the wake profile against central differences of its own U: second order in the step, so
+    # halving the step cuts the error by 4.  A wrong sign, a dropped factor, delta instead of delta^2 or y0 and z0
+    # swapped all break it.
+    wake = dict(amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+    y = np.linspace(-10.0, 10.0, 41)
+    Y, Z = np.meshgrid(y, y + 0.05, indexing="ij")
+    _, Uy, Uz = operators.wake_profile(Y, Z, **wake)
+    errs = []
+    for d in (2e-2, 1e-2):
+        cy = (operators.wake_profile(Y + d, Z, **wake)[0] - operators.wake_profile(Y - d, Z, **wake)[0]) / (2 * d)
+        cz = (operators.wake_profile(Y, Z + d, **wake)[0] - operators.wake_profile(Y, Z - d, **wake)[0]) / (2 * d)
+        errs.append(max(np.abs(cy - Uy).max(), np.abs(cz - Uz).max()))
+    assert errs[1] < 1e-4 * np.abs(Uy).max()
+    assert 3.8 < errs[0] / errs[1] < 4.2
+
+
+def _tiny_adr3d(mu=None):
+    wake = dict(amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+    return operators.adr3d3c_operator(5, 4, 3, wake, Re=50.0, mu=mu, Lx=8.0, lo=-4.0, hi=4.0)
+
+
+def test_node_field_expansion_is_the_operators_reaction_term():
+    # A node field mu enters the three-component operator (built block by block with Kronecker products) on the
+    # diagonal of every component block: L(mu) - L(0) = diag(expand(mu)).  A node-major expansion (repeat instead
+    # of tile) or a field on one component only breaks it.
+    g = np.random.default_rng(41)
+    mu = g.standard_normal((3, 4, 5))
+    d = (_tiny_adr3d(mu)[0] - _tiny_adr3d(np.zeros((3, 4, 5)))[0]).toarray()
+    assert np.abs(d - np.diag(gradient.expand_node_field(mu, 3))).max() < 1e-14
+
+
+def test_shared_node_field_gradient_sums_the_per_component_gradients():
+    # The gradient with respect to a node field shared by three components is the per-unknown gradient of the
+    # diagonal (central differences, one unknown of the 3 x 60 at a time) summed over the components of each node
+    # (chain rule through the expansion).  Pins the ncomp = 3 path of the oracle's mu gradient.
+    L0, _ = _tiny_adr3d(np.zeros((3, 4, 5)))
+    nodes = 60
+    h, P = 0.1, 20
+    dw = 2 * np.pi / (P * h)
+    F, G = forcing(42, 2, 2, 3 * nodes), forcing(43, 2, 2, 3 * nodes)
+    mu = np.random.default_rng(44).uniform(-0.1, 0.1, nodes)
+    kw = dict(tail=15)
+    node = gradient.stepped_mu_gradient(L0, mu, h, 0.3, dw, F, G, "transient", eps=1e-5, ncomp=3, **kw)
+    dof = gradient.stepped_mu_gradient(L0, np.tile(mu, 3), h, 0.3, dw, F, G, "transient", eps=1e-5, ncomp=1, **kw)
+    summed = dof.reshape(3, nodes).sum(axis=0)
+    assert np.abs(node - summed).max() < 1e-7 * np.abs(summed).max()
+    assert np.abs(dof.reshape(3, nodes)[1:]).max() > 1e-3 * np.abs(summed).max()  # every component contributes
+
+
 # ---------------------------------------------------------------------------------------------
 # Dense ground truth against closed forms.
 # ---------------------------------------------------------------------------------------------
