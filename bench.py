@@ -34,10 +34,15 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--accuracy-iters", type=int, default=None,
+                    help="iterations of the untimed accuracy pass against the oracle (default: the workload's own "
+                         "iteration count; 0 skips it).  The gains and modes at sampled frequencies are compared "
+                         "with the CPU oracle's same iteration, which runs in the CPU-baseline leg")
     ap.add_argument("--workload", default="gl_periodic_n2000",
-                    choices=["gl_periodic_n2000", "gl_batched_64", "adr2d_1024x512", "adr3d3c_256x128x128",
-                             "gl_paper_n200"],
-                    help="gl_periodic_n2000 (default, the headline line), gl_batched_64 (64 uneven GL instances, "
+                    choices=["gl_periodic_n2000", "gl_transient_n200", "gl_batched_64", "adr2d_1024x512",
+                             "adr3d3c_256x128x128", "gl_paper_n200"],
+                    help="gl_periodic_n2000 (default, the headline line), gl_transient_n200 (the transient-response "
+                         "method's iteration on the N = 200 GL operator), gl_batched_64 (64 uneven GL instances, "
                          "mixed precision, reported beside its FP64 form), the 2-D and 3-D grid operators, or "
                          "gl_paper_n200 (the paper's own real GL model of Sec. 3, with its power vs Arnoldi study)")
     ap.add_argument("--plan", default=None,
@@ -168,15 +173,207 @@ def cpu_baseline(cfg, w0, dw, F, seconds):
         n += 200
     dt = time.perf_counter() - t
     sweeps = cfg["N"] * cfg["k"] * cfg["n_omega"] * n / dt
-    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or str(os.cpu_count())
-    return dict(value=sweeps, unit="resolvent sweeps/s", cores=int(threads), kind="oracle",
+    return dict(value=sweeps, unit="resolvent sweeps/s", cores=oracle_threads(), kind="oracle", host=host_cpu(),
                 sample="%d forced RK4 steps of the N=%d, k=%d, %d-frequency periodic run (FP64 NumPy/SciPy), "
                        "%.1f s" % (n, cfg["N"], cfg["k"], cfg["n_omega"], dt))
 
 
+def host_cpu():
+    """Model name and L3 size of the host CPU (lscpu), for the CPU baseline's record."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "L3 cache", "CPU(s)"):
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"model": info.get("Model name"), "l3": info.get("L3 cache"), "logical_cpus": info.get("CPU(s)")}
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS") or os.cpu_count())
+
+
+def mode_errors(X, Y, gains, gap=1e-6):
+    """Per-mode error of modes X (k, N) against reference modes Y (k, N) with reference gains (k,) sorted
+    descending: min over phases of ||x e^{i phi} - y|| for unit vectors; modes in a cluster of gains closer than
+    `gap` (relative) get the 2-norm distance between the cluster's subspaces instead (a mode is unique only up to
+    a phase, and a degenerate one only as a subspace)."""
+    import numpy as np
+    X = np.asarray(X, complex)
+    Y = np.asarray(Y, complex)
+    k = X.shape[0]
+    Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
+    Yn = Y / np.linalg.norm(Y, axis=1, keepdims=True)
+    out = np.zeros(k)
+    i = 0
+    while i < k:
+        j = i + 1
+        while j < k and (gains[j - 1] - gains[j]) < gap * gains[j - 1]:
+            j += 1
+        if j == i + 1:
+            c = np.vdot(Xn[i], Yn[i])
+            out[i] = np.linalg.norm(Xn[i] * (c / abs(c) if abs(c) > 0 else 1.0) - Yn[i])
+        else:
+            Qx = np.linalg.qr(X[i:j].T)[0]
+            Qy = np.linalg.qr(Y[i:j].T)[0]
+            out[i:j] = np.linalg.norm(Qy - Qx @ (Qx.conj().T @ Qy), 2)
+        i = j
+    return out
+
+
+def accuracy(g, V, U, g_ref, V_ref, U_ref, labels):
+    """Error of every sampled gain and mode against the oracle: per sample, the relative gain errors and the mode
+    errors (mode_errors), and their maxima."""
+    import numpy as np
+    rows = []
+    for i, lab in enumerate(labels):
+        rows.append({"sample": lab, "gain_rel_err": [float(x) for x in np.abs(g[i] / g_ref[i] - 1)],
+                     "force_mode_err": [float(x) for x in mode_errors(V[i], V_ref[i], g_ref[i])],
+                     "response_mode_err": [float(x) for x in mode_errors(U[i], U_ref[i], g_ref[i])]})
+    return {"max_gain_rel_err": max(max(r["gain_rel_err"]) for r in rows),
+            "max_leading_gain_rel_err": max(r["gain_rel_err"][0] for r in rows),
+            "max_force_mode_err": max(max(r["force_mode_err"]) for r in rows),
+            "max_response_mode_err": max(max(r["response_mode_err"]) for r in rows),
+            "per_sample": rows}
+
+
+def gpu_modes_sampled(op, f0, grid, run, iters, js, sl=None, inst=0, finish_op=None):
+    """GPU block power iteration of `iters` iterations (with the FP64 Rayleigh-Ritz finish on finish_op when given);
+    gains, force and response modes at the frequencies js (and unknowns sl of instance inst)."""
+    import numpy as np
+    if finish_op is not None:
+        g, V, U, _ = op.modes_polished(finish_op, f0, grid, run, iters, want_hist=False)
+    else:
+        g, V, U, _ = op.modes(f0, grid, run, iters, want_hist=False)
+    V = V.cpu().numpy().astype(complex)
+    U = U.cpu().numpy().astype(complex)
+    sl = slice(None) if sl is None else sl
+    return g[inst][js], V[js][:, :, sl], U[js][:, :, sl]
+
+
+def oracle_sampled_reference(L, h, omegas, F_sel, iters):
+    """The CPU oracle's block power iteration (App. A) at the sampled frequencies only, from the same start, with
+    the RK4 transfer matrices R_d(w_j) from its dense solve (frequencies are independent in the block iteration,
+    and after the settle periods the periodic run applies R_d exactly).  F_sel: (n_sel, k, N).  Returns
+    (gains, V, U).  Part of the CPU-baseline leg: the oracle runs on the host, outside the timed region."""
+    from oracle.iteration import block_power_iteration, dense_rk4_applies
+    a, ad = dense_rk4_applies(L, h, omegas)
+    g, V, U, _ = block_power_iteration(a, ad, F_sel, iters)
+    return g, V, U
+
+
+TRANSIENT_REFERENCE = os.path.join(ROOT, "tests", "golden", "gl_transient_reference.json")
+
+
+def bench_transient(args):
+    """gl_transient_n200: the transient-response method (one forcing window of P = 9,896 steps and a 20,000-step
+    tail) on the N = 200 GL operator, 64 frequencies in [-2, 2], k = 1.  One step is one block-power iteration
+    (direct and adjoint run of 29,896 steps each, QR and gains), FP64, with the mixed form beside it.  The accuracy
+    pass runs the workload's 20 iterations and compares every gain, and the modes at the stored frequencies, with
+    the oracle's same iteration stored in tests/golden/gl_transient_reference.json (written by the script beside
+    it, which calls only the oracle).  The oracle is timed on whole iterations of its explicit RK4 runs."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2008_10904_amd.operators import snap_grid
+
+    cfg = W.GL_TRANSIENT
+    N, k, nw = cfg["N"], cfg["k"], cfg["n_omega"]
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], nw, cfg["h"])
+    S = P + cfg["tail"]
+    F = W.random_forcing(cfg["seed"], nw, k, N)
+    sweeps_per_step = N * k * nw * 2 * S
+    iters = cfg["iters"] if args.accuracy_iters is None else args.accuracy_iters
+    with open(TRANSIENT_REFERENCE) as fh:
+        ref = json.load(fh)
+    js = ref["sampled"]
+    g_ref = np.array(ref["gains"])
+    V_ref = np.array(ref["V_re"]) + 1j * np.array(ref["V_im"])
+    U_ref = np.array(ref["U_re"]) + 1j * np.array(ref["U_im"])
+    res = {}
+    for prec, dtype in (("fp64", torch.complex128), ("mixed", torch.complex64)):
+        op = build_op(cfg, prec)
+        plan = choose_plan(op, k, args.plan)
+        grid = op.grid(w0, dw, nw)
+        run = op.run("transient", tail=cfg["tail"])
+        f = torch.from_numpy(F).to(dtype).cuda()
+        dt, _, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
+        acc = None
+        if iters == ref["iters"]:
+            g, V, U, _ = op.modes(f, grid, run, iters, want_hist=False)
+            V = V.cpu().numpy().astype(complex)
+            U = U.cpu().numpy().astype(complex)
+            acc = accuracy(g[0][js], V[js], U[js], g_ref[js], V_ref, U_ref, js)
+            acc["max_gain_rel_err_all_frequencies"] = float(np.abs(g[0] / g_ref - 1).max())
+            del acc["per_sample"]
+        res[prec] = (dt, kt, plan, op.get_step_power(), acc)
+        del op, f
+        torch.cuda.empty_cache()
+    dt, kt, plan, power, acc64 = res["fp64"]
+    stepper_ms, stepper_n = kt["stepper"]
+    avg = stepper_ms / 1e3 / max(stepper_n, 1)
+    spl = 2 * S * args.steps / max(stepper_n, 1)
+    achieved = STEP_FLOP_PER_UNKNOWN * N * k * spl / avg / 1e12
+    peak = FP64_VECTOR_PEAK / 1e12
+    dtm, ktm, planm, _, accm = res["mixed"]
+    out = {
+        "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)", "value": sweeps_per_step / dt, "unit": "resolvent sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": N, "mu0": cfg["mu0"], "k": k, "n_omega": nw, "omega0": w0,
+                   "domega": dw, "P": P, "tail": cfg["tail"], "h": cfg["h"], "method": "transient",
+                   "step": "one block-power iteration", "time_steps_per_step": 2 * S},
+        "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "avg_launch_ms": avg * 1e3, "launches": stepper_n, "steps_per_launch": spl,
+                     "ns_per_time_step": avg / spl * 1e9},
+        "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
+        "stepper_plan": list(plan), "step_power": power,
+        "mixed": {"value": sweeps_per_step / dtm, "ms_per_step": dtm * 1e3, "dtype": "f32 step/GEMM, f64 acc",
+                  "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in ktm.items()}, "stepper_plan": list(planm)},
+        "accuracy_vs_oracle": {"iterations": iters, "sampled_omega_index": js, "fp64": acc64, "mixed": accm,
+                               "reference": "tests/golden/gl_transient_reference.json (the oracle's 20 iterations)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_transient(cfg, w0, dw, F, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_transient(cfg, w0, dw, F, seconds):
+    """The oracle's block power iteration on the same workload (explicit RK4 direct and adjoint runs of
+    P + tail steps, NumPy QR and SVD), timed on whole iterations from the same start until `seconds` have passed
+    (at least one)."""
+    from oracle.iteration import block_power_iteration, stepped_applies
+    from oracle.operators import gl_operator
+    from oracle.stepping import period_steps
+    L, _ = gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
+    a, ad = stepped_applies(L, cfg["h"], w0, dw, "transient", tail=cfg["tail"])
+    S = period_steps(dw, cfg["h"]) + cfg["tail"]
+    n, t = 0, time.perf_counter()
+    while n == 0 or time.perf_counter() - t < seconds:
+        block_power_iteration(a, ad, F, 1)
+        n += 1
+    dt = time.perf_counter() - t
+    return dict(value=cfg["N"] * cfg["k"] * cfg["n_omega"] * 2 * S * n / dt, unit="resolvent sweeps/s",
+                cores=oracle_threads(), kind="oracle", host=host_cpu(),
+                sample="%d whole iteration(s) of the oracle's block power iteration (two explicit RK4 runs of %d "
+                       "steps, N=%d, %d frequencies), %.1f s" % (n, S, cfg["N"], cfg["n_omega"], dt))
+
+
+FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector peak (packed FP32 issue; the build issues unpacked FP32)
+
+
 def bench_batched(args):
     """One block-power iteration of the batched workload (64 GL instances packed back to back, k = 2, 128
-    frequencies, periodic method, mixed precision), with the FP64 form of the same iteration beside it."""
+    frequencies, periodic method, mixed precision), with the FP64 form of the same iteration beside it.  The
+    accuracy pass runs the workload's 20 iterations (mixed, mixed with the FP64 Rayleigh-Ritz finish, FP64) and
+    compares gains and modes at three sampled instances (smallest, middle, largest) and three frequencies with the
+    oracle's same iteration.  The CPU baseline times the oracle's march on one instance of each size."""
     import numpy as np
     import torch
 
@@ -188,25 +385,45 @@ def bench_batched(args):
     inst = W.batched_instances()
     lo, d, up, off = gl_batched_coefficients(inst)
     ntot = int(off[-1])
-    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
+    k, nw = cfg["k"], cfg["n_omega"]
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], nw, cfg["h"], cfg["stride"])
     steps_per_run = cfg["periods"] * P
-    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], ntot)
-    sweeps_per_step = ntot * cfg["k"] * cfg["n_omega"] * 2 * steps_per_run
-    res, plans, powers = {}, {}, {}
+    F = W.random_forcing(cfg["seed"], nw, k, ntot)
+    sweeps_per_step = ntot * k * nw * 2 * steps_per_run
+    iters = cfg["iters"] if args.accuracy_iters is None else args.accuracy_iters
+    sizes = [n for n, _, _ in inst]
+    picks = [int(np.argmin(sizes)), len(inst) // 2, int(np.argmax(sizes))]
+    js = [0, 64, 127]
+    res, plans, powers, sampled = {}, {}, {}, {}
+    V_mixed = None
     for prec, dtype in (("mixed", torch.complex64), ("fp64", torch.complex128)):
         op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision=prec, offsets=off)
         if args.step_power:
             op.set_step_power(args.step_power)
-        plans[prec] = choose_plan(op, cfg["k"], args.plan, search_power=args.step_power is None)
+        plans[prec] = choose_plan(op, k, args.plan, search_power=args.step_power is None)
         powers[prec] = op.get_step_power()
-        grid = op.grid(w0, dw, cfg["n_omega"])
+        grid = op.grid(w0, dw, nw)
         run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
         f = torch.from_numpy(F).to(dtype).cuda()
         res[prec] = time_steps(op, f, grid, run, args.steps, args.warmup)
+        if iters > 0:
+            g, V, U, _ = op.modes(f, grid, run, iters, want_hist=False)
+            if prec == "mixed":
+                V_mixed = V.to(torch.complex128).contiguous()  # the subspace of the FP64 finish below
+            sampled[prec] = (g, V.cpu().numpy().astype(complex), U.cpu().numpy().astype(complex))
+            del V, U
+            if prec == "fp64":
+                g, V, U, _ = op.modes(V_mixed, grid, run, 1, want_hist=False)  # Rayleigh-Ritz on the mixed subspace
+                sampled["mixed_fp64_finish"] = (g, V.cpu().numpy().astype(complex), U.cpu().numpy().astype(complex))
+                del V, U, V_mixed
         del op, f
         torch.cuda.empty_cache()
     dtm, gm, ktm = res["mixed"]
     dt64, g64, kt64 = res["fp64"]
+    st_ms, st_n = ktm["stepper"]
+    avg = st_ms / 1e3 / max(st_n, 1)
+    spl = 2 * steps_per_run * args.steps / max(st_n, 1)
+    achieved = STEP_FLOP_PER_UNKNOWN * ntot * k * spl / avg
     out = {
         "metric": "resolvent sweeps/s (N*k*Nw*Nt per s)",
         "value": sweeps_per_step / dtm,
@@ -214,18 +431,86 @@ def bench_batched(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dtm * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 step/GEMM, f64 acc",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "instances": len(inst), "N_total": ntot, "k": cfg["k"],
-                   "n_omega": cfg["n_omega"], "P": P, "h": cfg["h"], "method": "periodic",
+        "config": {"workload": cfg["name"], "instances": len(inst), "N_total": ntot, "k": k,
+                   "n_omega": nw, "P": P, "h": cfg["h"], "method": "periodic",
                    "periods": cfg["periods"], "stride": cfg["stride"], "step": "one block-power iteration",
                    "time_steps_per_step": 2 * steps_per_run},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()},
+        "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 steps, FP32, all instances in one launch)",
+                     "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK, "traffic": None, "avg_launch_ms": avg * 1e3,
+                     "launches": st_n, "steps_per_launch": spl},
+        "kernel_ms_per_step": {k_: v[0] / args.steps for k_, v in ktm.items()},
         "fp64": {"value": sweeps_per_step / dt64, "ms_per_step": dt64 * 1e3, "dtype": "f64",
-                 "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt64.items()}},
-        "max_rel_gain_diff_mixed_vs_fp64": float(np.abs(gm / g64 - 1).max()),
-        "stepper_plan": {k: list(v) for k, v in plans.items()},
+                 "kernel_ms_per_step": {k_: v[0] / args.steps for k_, v in kt64.items()}},
+        "stepper_plan": {k_: list(v) for k_, v in plans.items()},
         "step_power": powers,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(cfg, inst, w0, dw, args.cpu_seconds)
+        if sampled:
+            out["accuracy_vs_oracle"] = batched_accuracy(cfg, inst, off, w0, dw, F, picks, js, iters, sampled)
     print(json.dumps(out), flush=True)
+
+
+def batched_accuracy(cfg, inst, off, w0, dw, F, picks, js, iters, sampled):
+    """Sampled instances and frequencies of the batched GPU iterations against the oracle's same iteration."""
+    import numpy as np
+    from oracle.operators import gl_operator
+    t = time.perf_counter()
+    out = {"iterations": iters, "instances": picks, "sampled_omega_index": js}
+    refs = {}
+    for m in picks:
+        n, mu0, mu2 = inst[m]
+        L, _ = gl_operator(n, mu0, mu2)
+        sl = slice(int(off[m]), int(off[m + 1]))
+        om = w0 + dw * np.asarray(js)
+        for kind in ("fp64", "mixed"):
+            Fin = F[js][:, :, sl] if kind == "fp64" else F[js][:, :, sl].astype(np.complex64).astype(np.complex128)
+            refs[(m, kind)] = oracle_sampled_reference(L, cfg["h"], om, Fin, iters)
+    for prec, (g, V, U) in sampled.items():
+        kind = "fp64" if prec == "fp64" else "mixed"
+        rows = {}
+        for m in picks:
+            sl = slice(int(off[m]), int(off[m + 1]))
+            g_ref, V_ref, U_ref = refs[(m, kind)]
+            rows["instance %d (N=%d)" % (m, inst[m][0])] = accuracy(g[m][js], V[js][:, :, sl], U[js][:, :, sl],
+                                                                      g_ref, V_ref, U_ref, js)
+        out[prec] = {"max_gain_rel_err": max(r["max_gain_rel_err"] for r in rows.values()),
+                     "max_leading_gain_rel_err": max(r["max_leading_gain_rel_err"] for r in rows.values()),
+                     "max_force_mode_err": max(r["max_force_mode_err"] for r in rows.values()),
+                     "max_response_mode_err": max(r["max_response_mode_err"] for r in rows.values()),
+                     "per_instance": {kk: {x: v for x, v in r.items() if x != "per_sample"} for kk, r in rows.items()}}
+    out["oracle_seconds"] = time.perf_counter() - t
+    out["targets"] = {"fp64_gain": 1e-8, "mixed_gain": 1e-4}
+    return out
+
+
+def cpu_baseline_batched(cfg, inst, w0, dw, seconds):
+    """The oracle's forced march (the batch's 128 frequencies, k = 2) on one instance of each size, each timed for
+    a quarter of `seconds`; the batch's oracle time per step is the sum over its instances of their sizes' step
+    times, and the rate is the batch's sweeps per step over that."""
+    import numpy as np
+    import workloads as W
+    from oracle.operators import gl_operator
+    from oracle.stepping import march
+    om = w0 + dw * np.arange(cfg["n_omega"])
+    per_step = {}
+    for n in sorted({x[0] for x in inst}):
+        _, mu0, mu2 = next(x for x in inst if x[0] == n)
+        L, _ = gl_operator(n, mu0, mu2)
+        F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], n)
+        march(L, cfg["h"], om, F, 3, lambda s: True, lambda s: False, 1.0)
+        steps, t = 0, time.perf_counter()
+        while time.perf_counter() - t < seconds / 4:
+            march(L, cfg["h"], om, F, 100, lambda s: True, lambda s: False, 1.0)
+            steps += 100
+        per_step[n] = (time.perf_counter() - t) / steps
+    t_step = sum(per_step[x[0]] for x in inst)
+    ntot = sum(x[0] for x in inst)
+    return dict(value=ntot * cfg["k"] * cfg["n_omega"] / t_step, unit="resolvent sweeps/s", cores=oracle_threads(),
+                kind="oracle", host=host_cpu(),
+                sample="forced RK4 steps of one instance of each size (%s), %.1f s each; batch time per step = sum "
+                       "over the 64 instances (%.3g s)" % (",".join(str(n) for n in per_step), seconds / 4, t_step))
 
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
@@ -247,39 +532,42 @@ def grid_op(cfg, precision):
 
 
 def bench_grid(args):
-    """Grid workloads.  adr2d_1024x512: one full block-power iteration (transient method, mixed precision).
-    adr3d3c_256x128x128: the full-size state does not leave room for a whole iteration's FP64 blocks in one GPU's
-    memory, so the stepping is measured alone: one apply of 64 forced steps at the full grid (8 frequencies,
-    P = 64), reported per step; the Fourier work scales with the frequency count and is reported separately by
-    the iteration of the 2-D workload.  Both report the HBM roofline of the Horner-stage kernel against the
-    algorithmic bytes of a step (read and write the state, read one forcing row)."""
+    """Grid workloads, one step = one block-power iteration (direct and adjoint run, QR and gains), mixed precision.
+    adr2d_1024x512: transient method (P = 19,949 plus a 15,000-step tail), 128 frequencies, k = 2; then one forward
+    apply and its reverse mode (forcing and mu gradients).  adr3d3c_256x128x128: the 3-D workload's own run shape:
+    96 frequencies, k = 3, periodic method with three periods of P = 3,800 steps, the last projected every 38th
+    step; its forcing is drawn on the device (workloads.random_forcing_device).  Both report the HBM roofline of
+    the step kernel against the algorithmic bytes of a step (read and write the state, read one forcing row)."""
     import numpy as np
     import torch
 
     import workloads as W
-    from paper_2008_10904_amd import _lib as L
     from paper_2008_10904_amd.operators import snap_grid
 
-    cfg = W.ADR2D if args.workload == "adr2d_1024x512" else W.ADR3D
+    three = args.workload != "adr2d_1024x512"
+    cfg = W.ADR3D if three else W.ADR2D
     op = grid_op(cfg, cfg["precision"])
-    ncomp = 3 if cfg["kind"] == "adr3d3c" else 1
+    ncomp = 3 if three else 1
     nodes = cfg["nx"] * cfg["ny"] * cfg.get("nz", 1)
     N = ncomp * nodes
-    k = cfg["k"]
+    k, nw = cfg["k"], cfg["n_omega"]
     csize = 8  # complex64 state
-    if cfg["kind"] == "adr2d":
-        w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], cfg["n_omega"], cfg["h"], cfg["stride"])
-        nw = cfg["n_omega"]
+    w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], nw, cfg["h"], cfg["stride"])
+    if three:
+        run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
+        steps_per_run = cfg["periods"] * P
+        f = W.random_forcing_device(cfg["seed"], nw, k, N, torch.complex64, "cuda")
+    else:
         run = op.run("transient", tail=cfg["tail"])
         steps_per_run = P + cfg["tail"]
-        F = W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)
-        f = torch.from_numpy(F).cuda()
-        grid = op.grid(w0, dw, nw)
-        dt, gains, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
-        time_steps_total = 2 * steps_per_run * args.steps
-        value = N * k * nw * 2 * steps_per_run / dt
-        step_desc = "one block-power iteration"
-        # forward plus reverse mode (the C4 gradient path): one apply and one apply_backward with the forcing and
+        f = torch.from_numpy(W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)).cuda()
+    grid = op.grid(w0, dw, nw)
+    dt, gains, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
+    time_steps_total = 2 * steps_per_run * args.steps
+    value = N * k * nw * 2 * steps_per_run / dt
+    autograd = None
+    if not three:
+        # forward plus reverse mode (the 2-D gradient path): one apply and one apply_backward with the forcing and
         # mu gradients, checkpoints every ~sqrt(steps), timed outside the iteration above
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -296,33 +584,7 @@ def bench_grid(args):
         autograd = {"forward_s": t1 - t0, "backward_s": t2 - t1, "backward_forcing_only_s": t3 - t2,
                     "note": "one apply and one apply_backward (forcing and mu gradients) of the full workload; "
                             "then the forcing gradient alone (adjoint recursion only)"}
-    else:
-        nw, P = 8, 64
-        dw = 2 * np.pi / (P * cfg["h"])
-        F = W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)
-        f = torch.from_numpy(F).cuda()
-        del F
-        grid = op.grid(cfg["wmin"], dw, nw)
-        run = op.run("transient", tail=0)
-        out_u = op.apply(f, grid, run)
-        torch.cuda.synchronize()
-        op.set_timing(True)
-        for kind in range(4):
-            op.timing(kind)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            op.apply(f, grid, run, out=out_u)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
-                                                       ("synthesis", L.RES_TIMING_SYNTHESIS),
-                                                       ("projection", L.RES_TIMING_PROJECTION))}
-        op.set_timing(False)
-        time_steps_total = P * args.steps
-        steps_per_run = P
-        value = N * k * cfg["n_omega"] * P / (kt["stepper"][0] / 1e3 / args.steps)
-        step_desc = "stepping of one 64-step apply (value: sweeps/s of the stepping alone at 96 frequencies)"
-    kernel_name = ("grid_step2d_kernel (one RK4 step per launch)" if cfg["kind"] == "adr2d"
+    kernel_name = ("grid_step2d_kernel (one RK4 step per launch)" if not three
                    else "grid_pair3d_kernel x2 (one RK4 step: two launches of two Horner stages)")
     step_s = kt["stepper"][0] / 1e3 / time_steps_total
     alg_bytes = 3 * csize * N * k  # read u, write u, read one forcing row
@@ -333,21 +595,60 @@ def bench_grid(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 step/GEMM, f64 acc",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["ny"], cfg.get("nz", 1)], "components": ncomp,
-                   "k": k, "n_omega": nw, "P": P, "h": cfg["h"], "step": step_desc,
-                   "time_steps_per_step": time_steps_total // args.steps},
+                   "k": k, "n_omega": nw, "P": P, "h": cfg["h"], "method": cfg["method"],
+                   "periods": cfg["periods"] if three else None, "tail": None if three else cfg["tail"],
+                   "stride": cfg["stride"], "step": "one block-power iteration",
+                   "time_steps_per_step": 2 * steps_per_run},
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                      "us_per_time_step": step_s * 1e6, "algorithmic_bytes_per_step": alg_bytes},
         "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
     }
-    if cfg["kind"] == "adr2d":
+    del f
+    op = None
+    torch.cuda.empty_cache()
+    if autograd is not None:
         out["autograd"] = autograd
     else:
-        del f, out_u
-        op = None
-        torch.cuda.empty_cache()
         out["autograd"] = grad3d_half(cfg)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_grid(cfg, w0, dw, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_grid(cfg, w0, dw, seconds):
+    """The oracle's forced RK4 march (sparse L, all frequencies synthesised per stage) of the grid workload, timed
+    on chunks of steps until `seconds` have passed.  The 2-D workload runs at full size; the 3-D one on the grid
+    halved in each direction (one eighth of the unknowns: its full-size forcing, 58 GB in FP64, and the oracle's
+    copies of it do not fit the host's memory), which leaves the oracle's rate per unknown unchanged (every part
+    of its step is linear in the unknowns)."""
+    import numpy as np
+    import workloads as W
+    from oracle import operators as O_ops
+    from oracle.stepping import march
+    if cfg["kind"] == "adr2d":
+        f = O_ops.adr2d_fields(cfg["nx"], cfg["ny"], nu_s=cfg["nu_s"])
+        mu = O_ops.adr2d_mu_default(f["X"], f["Y"], base=cfg["mu_base"], amp=cfg["mu_amp"], xc=cfg["mu_xc"],
+                                    width2=cfg["mu_w2"])
+        L, _ = O_ops.adr2d_operator(cfg["nx"], cfg["ny"], Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+        shape = (cfg["nx"], cfg["ny"], 1)
+    else:
+        shape = (cfg["nx"] // 2, cfg["ny"] // 2, cfg["nz"] // 2)
+        L, _ = O_ops.adr3d3c_operator(*shape, W.wake_parameters(cfg["seed"]), Re=cfg["Re"],
+                                      mu=np.full(shape[::-1], cfg["mu_const"]), nu_s=cfg["nu_s"])
+    N = L.shape[0]
+    F = W.random_forcing(cfg["seed"], cfg["n_omega"], cfg["k"], N)
+    om = w0 + dw * np.arange(cfg["n_omega"])
+    march(L, cfg["h"], om, F, 1, lambda s: True, lambda s: False, 1.0)
+    steps, t = 0, time.perf_counter()
+    while steps == 0 or time.perf_counter() - t < seconds:
+        march(L, cfg["h"], om, F, 2, lambda s: True, lambda s: False, 1.0)
+        steps += 2
+    dt = time.perf_counter() - t
+    return dict(value=N * cfg["k"] * cfg["n_omega"] * steps / dt, unit="resolvent sweeps/s", cores=oracle_threads(),
+                kind="oracle", host=host_cpu(),
+                sample="%d forced RK4 steps of the oracle on the %s grid (%d unknowns, k=%d, %d frequencies), %.1f s"
+                       % (steps, "x".join(map(str, shape)), N, cfg["k"], cfg["n_omega"], dt))
 
 
 def grad3d_half(cfg):
@@ -684,6 +985,9 @@ def main():
     if args.workload == "gl_batched_64":
         bench_batched(args)
         return
+    if args.workload == "gl_transient_n200":
+        bench_transient(args)
+        return
     if args.workload == "gl_paper_n200":
         bench_paper(args)
         return
@@ -748,6 +1052,11 @@ def main():
     if weights is not None:
         out["config"]["weights"] = ("B: window over the upstream 60 %, C: window over the downstream 60 %, "
                                     "W_f = W_y = dx (gains of C R B in the W norms)")
+    iters = cfg["iters"] if args.accuracy_iters is None else args.accuracy_iters
+    js = [0, 101, 128, 255]  # both band edges, an inner frequency and the centre (omega ~ 0)
+    sampled = {}
+    if iters > 0:
+        sampled["fp64"] = gpu_modes_sampled(op, f64, grid, run, iters, js)
     del op, f64
     torch.cuda.empty_cache()
     if not args.no_mixed:
@@ -760,13 +1069,34 @@ def main():
         f32 = torch.from_numpy(F).to(torch.complex64).cuda()
         dtm, gainsm, ktm = time_steps(opm, f32, grid, run, args.steps, args.warmup)
         out["mixed"] = {"value": sweeps_per_step / dtm, "ms_per_step": dtm * 1e3, "dtype": "f32 step/GEMM, f64 acc",
-                        "max_rel_gain_diff_vs_fp64": float(np.abs(gainsm / gains64 - 1).max()),
                         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktm.items()},
                         "stepper_plan": list(planm)}
+        if iters > 0:
+            sampled["mixed"] = gpu_modes_sampled(opm, f32, grid, run, iters, js)
         del opm, f32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, w0, dw, F, args.cpu_seconds)
+        if sampled and weights is None:
+            out["accuracy_vs_oracle"] = headline_accuracy(cfg, w0, dw, F, js, iters, sampled)
     print(json.dumps(out), flush=True)
+
+
+def headline_accuracy(cfg, w0, dw, F, js, iters, sampled):
+    """Gains and modes of the GPU iterations at the sampled frequencies against the oracle's same iteration (FP64;
+    the mixed path's oracle starts from the complex64-rounded forcing it was given)."""
+    import numpy as np
+    from oracle import operators as O_ops
+    L, _ = O_ops.gl_operator(cfg["N"], cfg["mu0"], cfg["mu2"])
+    om = w0 + dw * np.asarray(js)
+    t = time.perf_counter()
+    out = {"iterations": iters, "sampled_omega_index": list(js), "sampled_omega": [float(w) for w in om]}
+    for prec, (g, V, U) in sampled.items():
+        F_sel = F[js] if prec == "fp64" else F[js].astype(np.complex64).astype(np.complex128)
+        g_ref, V_ref, U_ref = oracle_sampled_reference(L, cfg["h"], om, F_sel, iters)
+        out[prec] = accuracy(g, V, U, g_ref, V_ref, U_ref, [int(j) for j in js])
+    out["oracle_seconds"] = time.perf_counter() - t
+    out["targets"] = {"fp64_gain": 1e-8, "mixed_gain": 1e-4}
+    return out
 
 
 if __name__ == "__main__":

@@ -45,10 +45,12 @@ int launch_step1d(const Step1DArgs& a, hipStream_t st);
 int launch_fill_empty(void* xbuf, int fp64, int64_t count, hipStream_t st);
 int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                       int out_fp64, int64_t N, int k, int nw, double sw0h, double sdwh, double h, int pass,
-                      hipStream_t st);
+                      hipStream_t st, int j0 = 0);
 // y = P x + e^{i sw_j h i} G over [n_w][k][N] FP64 blocks (multi-step forcing combination; band FP64 [N][9])
+// The Horner launchers take blocks of frequencies j0 .. j0 + nw - 1 (w_j = w0 + j dw): the pointers address
+// block j0, the phases use the global index.
 int launch_band_horner(const cx<double>* band, const cx<double>* x, const cx<double>* G, void* y, int out_fp64,
-                       int64_t N, int k, int nw, double sw0h, double sdwh, int i, hipStream_t st);
+                       int64_t N, int k, int nw, double sw0h, double sdwh, int i, hipStream_t st, int j0 = 0);
 
 // ---- 2-D / 3-D stencils -------------------------------------------------------------------------------
 // Device coefficients of Z = h L on an nx*ny*nz grid (real, working precision or FP64): per x-line
@@ -68,7 +70,8 @@ int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const
 int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
                        double phi, void* snap, hipStream_t st);
 int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
-                       int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st);
+                       int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st,
+                       int j0 = 0);
 
 // ---- discrete adjoint (reverse-mode) stage kernels, FP64 -----------------------------------------------
 // kind 0: three-point complex operator, tri = [nsite][3] (lower, diag, upper) of Z (or Z^H); kind 1: grid

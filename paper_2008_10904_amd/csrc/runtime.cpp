@@ -843,6 +843,63 @@ int run_power(const resolvent_op* op, const Plan& pl) {
   return (int)m;
 }
 
+// G_j = h Q_j(Z) F_j by three Horner passes in FP64 (and, when M > 1, the combined forcing of M steps,
+// sum_{r<M} e^{i sigma w_j r h} P^(M-1-r) G_j, by M - 1 Horner passes of P(Z)), written in the working precision.
+// Each frequency's pre-filter is independent, so the FP64 work blocks hold a group of frequencies at a time, as
+// many as fit in RESOLVENT_HORNER_BUDGET_GB (default 8 GiB): the 3-D workload's [96][3][12.6M] blocks would take
+// 58 GB each.
+int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, void* G, int sigma, int M,
+              hipStream_t st) {
+  const int64_t N = op->N;
+  const int64_t ncols = (int64_t)k * N;
+  const int nw = pl.nw;
+  const int s = sigma > 0 ? 0 : 1;
+  const int nbuf = M > 2 ? 3 : 2;
+  const double budget = env_double("RESOLVENT_HORNER_BUDGET_GB", 8.0) * 1073741824.0;
+  const double per_freq = (double)nbuf * (double)ncols * sizeof(cd);
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(budget / per_freq)));
+  void *y1, *y2, *y3 = nullptr;
+  RES_TRY(ws_get(op, "horner_a", (size_t)chunk * ncols * sizeof(cd), &y1));
+  RES_TRY(ws_get(op, "horner_b", (size_t)chunk * ncols * sizeof(cd), &y2));
+  if (M > 2) RES_TRY(ws_get(op, "horner_c", (size_t)chunk * ncols * sizeof(cd), &y3));
+  const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
+  const size_t in_es = in_fp64 ? sizeof(cd) : sizeof(std::complex<float>);
+  for (int j0 = 0; j0 < nw; j0 += chunk) {
+    const int nc = std::min(chunk, nw - j0);
+    const void* inc = (const char*)in + (size_t)j0 * ncols * in_es;
+    void* Gc = (char*)G + (size_t)j0 * ncols * op->wsize();
+    if (is_grid(op)) {
+      const GridOpDev& g = op->g64[s];
+      if (launch_grid_horner(g, nullptr, inc, in_fp64, y1, 1, k, nc, sw0h, sdwh, op->h, 0, st, j0) ||
+          launch_grid_horner(g, (const cx<double>*)y1, inc, in_fp64, y2, 1, k, nc, sw0h, sdwh, op->h, 1, st, j0) ||
+          launch_grid_horner(g, (const cx<double>*)y2, inc, in_fp64, Gc, op->fp64(), k, nc, sw0h, sdwh, op->h, 2, st,
+                             j0))
+        return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
+      continue;
+    }
+    const cx<double>* tri = (const cx<double>*)op->d_tri[s];
+    launch_tri_horner(tri, nullptr, inc, in_fp64, y1, 1, N, k, nc, sw0h, sdwh, op->h, 0, st, j0);
+    launch_tri_horner(tri, (const cx<double>*)y1, inc, in_fp64, y2, 1, N, k, nc, sw0h, sdwh, op->h, 1, st, j0);
+    if (M == 1) {
+      launch_tri_horner(tri, (const cx<double>*)y2, inc, in_fp64, Gc, op->fp64(), N, k, nc, sw0h, sdwh, op->h, 2, st,
+                        j0);
+      continue;
+    }
+    // G in FP64, then G^(M) = sum_{r<M} e^{i sw_j r h} P^(M-1-r) G by M-1 Horner passes of P (the last one writes
+    // the working precision)
+    launch_tri_horner(tri, (const cx<double>*)y2, inc, in_fp64, y1, 1, N, k, nc, sw0h, sdwh, op->h, 2, st, j0);
+    const cx<double>* band = (const cx<double>*)op->d_band64[s];
+    const cx<double>* x = (const cx<double>*)y1;
+    for (int i = 1; i < M; ++i) {
+      const bool last = i == M - 1;
+      void* out = last ? Gc : (i & 1 ? y2 : y3);
+      launch_band_horner(band, x, (const cx<double>*)y1, out, last ? op->fp64() : 1, N, k, nc, sw0h, sdwh, i, st, j0);
+      x = (const cx<double>*)out;
+    }
+  }
+  return RES_OK;
+}
+
 // One time-marched run: acc[j][c][:] = R_d(sigma w_j)-run of in[j][c][:], with L (sigma = +1) or L^H (sigma = -1).
 // `in` is [nw][k][N] complex of dtype in_fp64; acc is FP64 [nw][k][N] and is overwritten.
 int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, double* acc, int sigma,
@@ -853,42 +910,11 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   const int s = sigma > 0 ? 0 : 1;
   const size_t ws = op->wsize();
   const int M = run_power(op, pl);  // RK4 steps per kernel step; forcing rows and samples count kernel steps
-  void *y1, *y2, *G, *btab;
-  RES_TRY(ws_get(op, "horner_a", (size_t)nw * ncols * sizeof(cd), &y1));
-  RES_TRY(ws_get(op, "horner_b", (size_t)nw * ncols * sizeof(cd), &y2));
+  void *G, *btab;
   RES_TRY(ws_get(op, "G", (size_t)nw * ncols * ws, &G));
   RES_TRY(phase_table(op, pl.P, &btab));
-  // G_j = h Q_j(Z) F_j  (three Horner passes)
-  const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
-  if (is_grid(op)) {
-    const GridOpDev& g = op->g64[s];
-    if (launch_grid_horner(g, nullptr, in, in_fp64, y1, 1, k, nw, sw0h, sdwh, op->h, 0, st) ||
-        launch_grid_horner(g, (const cx<double>*)y1, in, in_fp64, y2, 1, k, nw, sw0h, sdwh, op->h, 1, st) ||
-        launch_grid_horner(g, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), k, nw, sw0h, sdwh, op->h, 2, st))
-      return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
-    op->march_grid = &op->gw[s];
-  } else {
-    const cx<double>* tri = (const cx<double>*)op->d_tri[s];
-    launch_tri_horner(tri, nullptr, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 0, st);
-    launch_tri_horner(tri, (const cx<double>*)y1, in, in_fp64, y2, 1, N, k, nw, sw0h, sdwh, op->h, 1, st);
-    if (M == 1) {
-      launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, G, op->fp64(), N, k, nw, sw0h, sdwh, op->h, 2, st);
-    } else {
-      // G in FP64, then G^(M) = sum_{r<M} e^{i sw_j r h} P^(M-1-r) G by M-1 Horner passes of P (the last one writes
-      // the working precision)
-      void* y3 = nullptr;
-      if (M > 2) RES_TRY(ws_get(op, "horner_c", (size_t)nw * ncols * sizeof(cd), &y3));
-      launch_tri_horner(tri, (const cx<double>*)y2, in, in_fp64, y1, 1, N, k, nw, sw0h, sdwh, op->h, 2, st);
-      const cx<double>* band = (const cx<double>*)op->d_band64[s];
-      const cx<double>* x = (const cx<double>*)y1;
-      for (int i = 1; i < M; ++i) {
-        const bool last = i == M - 1;
-        void* out = last ? G : (i & 1 ? y2 : y3);
-        launch_band_horner(band, x, (const cx<double>*)y1, out, last ? op->fp64() : 1, N, k, nw, sw0h, sdwh, i, st);
-        x = (const cx<double>*)out;
-      }
-    }
-  }
+  RES_TRY(prefilter(op, pl, k, in, in_fp64, G, sigma, M, st));
+  if (is_grid(op)) op->march_grid = &op->gw[s];
   HIP_TRY(hipGetLastError());
   trace_norm("run input", in, (int64_t)nw * ncols, in_fp64, st);
   trace_norm("G = hQ(Z) F", G, (int64_t)nw * ncols, op->fp64(), st);
@@ -2216,7 +2242,13 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
   // march frequency j with its input scaled by 1/sqrt(sigma_1(j)) from the previous iteration and unscale the
   // result, which balances the response amplitudes (large gains) against the forcing amplitudes (small gains)
   // across frequencies -- the frequency normalisation of Sec. 2.2, applied between iterations.  Exact in exact
-  // arithmetic (the runs are linear); the QR and SVD see unscaled blocks.
+  // arithmetic (the runs are linear); the QR and SVD see unscaled blocks.  Only for the periodic method: there
+  // each frequency's response depends on its own forcing alone (the run applies R_d(w_j) block by block), while
+  // the transient method's truncated tail leaks every frequency into its neighbours, so scaling frequency j's input
+  // by its own weight and unscaling the output by the weight of j' would change the leakage terms and with them
+  // the iterated map (by 2e-7 relative on the N = 200 transient workload, where the ratio of the largest to the
+  // smallest gain is 100).
+  const bool weigh = pl.method == RES_PERIODIC;
   void* fac;
   RES_TRY(ws_get(op, "modes_fac", (size_t)op->ninst * nw * sizeof(double), &fac));
   // Weighted run: the input block is scaled in place (restored afterwards when keep_input) and the output unscaled.
@@ -2267,7 +2299,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
     op->capturing = true;
-    int rc = iteration(false, true, hs_prev, hs_cur, op->cap_stream);
+    int rc = iteration(false, weigh, hs_prev, hs_cur, op->cap_stream);
     op->capturing = false;
     const hipError_t ec = hipStreamEndCapture(op->cap_stream, &graph);
     if (rc == RES_OK && ec != hipSuccess) rc = fail(RES_EHIP, std::string("graph capture: ") + hipGetErrorString(ec));
@@ -2297,7 +2329,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
     (void)hipGetLastError();
     RES_TRY(rc);
   }
-  for (; it < iters; ++it) RES_TRY(iteration(it == iters - 1, true, hslot(it - 1), hslot(it), st));
+  for (; it < iters; ++it) RES_TRY(iteration(it == iters - 1, weigh, hslot(it - 1), hslot(it), st));
   if (hist) {
     // norm estimate of the last iteration from the Gram of the final F_hat
     const int nsplit = nsplit_for(max_instance_len(op));
@@ -2360,8 +2392,9 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
   // frequencies in one FP32 state, so the direct run takes B_i scaled by sigma_1^{-1/2} and the adjoint run takes
   // R B_i (amplitude sigma) scaled by sigma_1^{-3/2} (sigma_1 from the previous block's estimates), and their
   // outputs are unscaled.  FP64 runs are not weighted: the later basis blocks come from strongly cancelling
-  // differences, which would turn the rescaling's rounding into differences of 1e-9 in the estimates.
-  const bool weigh = !op->fp64();
+  // differences, which would turn the rescaling's rounding into differences of 1e-9 in the estimates.  Transient
+  // runs are not weighted either (their tail couples the frequencies; see resolvent_modes).
+  const bool weigh = !op->fp64() && pl.method == RES_PERIODIC;
   void *fd, *fa, *tmp;
   RES_TRY(ws_get(op, "kry_fd", (size_t)ninst * nw * sizeof(double), &fd));
   RES_TRY(ws_get(op, "kry_fa", (size_t)ninst * nw * sizeof(double), &fa));

@@ -313,7 +313,8 @@ template <typename TF, typename TO, int NC>
 __global__ __launch_bounds__(256) void grid_horner_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int64_t nz,
                                                           const cx<double>* __restrict__ yin,
                                                           const cx<TF>* __restrict__ F, cx<TO>* __restrict__ yout,
-                                                          int k, int nw, double sw0h, double sdwh, double h, int pass) {
+                                                          int k, int nw, double sw0h, double sdwh, double h, int pass,
+                                                          int j0) {
   const int64_t nodes = nx * ny * nz;
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= nodes) return;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) void grid_horner_kernel(GridCoef<double> Cf, i
   const int b = blockIdx.y;  // block = j * k + column
   const int j = b / k;
   double sa, ca;
-  sincos(0.5 * (sw0h + (double)j * sdwh), &sa, &ca);
+  sincos(0.5 * (sw0h + (double)(j0 + j) * sdwh), &sa, &ca);
   const cx<double> a = mk<double>(ca, sa);
   const cx<double> bb = cmul(a, a);
   cx<double> zx[NC];
@@ -439,14 +440,15 @@ int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const
 }
 
 int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
-                       int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st) {
+                       int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st,
+                       int j0) {
   const int64_t nodes = g64.nx * g64.ny * g64.nz;
   if ((int64_t)nw * k > 65535) return -1;
   const dim3 grid((unsigned)((nodes + 255) / 256), (unsigned)(nw * k));
   GridCoef<double> c = coef_of<double>(g64, 1);
 #define RES_GH(TF, TO, NC)                                                                                        \
   hipLaunchKernelGGL((grid_horner_kernel<TF, TO, NC>), grid, dim3(256), 0, st, c, g64.nx, g64.ny, g64.nz, yin,    \
-                     (const cx<TF>*)F, (cx<TO>*)yout, k, nw, sw0h, sdwh, h, pass)
+                     (const cx<TF>*)F, (cx<TO>*)yout, k, nw, sw0h, sdwh, h, pass, j0)
 #define RES_GH2(TF, TO) \
   if (g64.ncomp == 3) RES_GH(TF, TO, 3); else RES_GH(TF, TO, 1)
   if (f_fp64 && out_fp64) { RES_GH2(double, double); }

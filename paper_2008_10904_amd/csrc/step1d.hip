@@ -39,14 +39,14 @@ __global__ __launch_bounds__(256) void tri_horner_kernel(const cx<double>* __res
                                                          const cx<double>* __restrict__ yin,
                                                          const cx<TF>* __restrict__ F, cx<TO>* __restrict__ yout,
                                                          int64_t N, int32_t k, int32_t nw, double sw0h, double sdwh,
-                                                         double h, int pass) {
+                                                         double h, int pass, int32_t j0) {
   const int64_t total = (int64_t)nw * k * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t n = e % N;
     const int64_t j = e / ((int64_t)k * N);
     double sa, ca;
-    sincos(0.5 * (sw0h + (double)j * sdwh), &sa, &ca);
+    sincos(0.5 * (sw0h + (double)(j0 + j) * sdwh), &sa, &ca);
     const cx<double> a = mk<double>(ca, sa);
     const cx<double> b = cmul(a, a);
     const cx<double> one = mk<double>(1.0, 0.0);
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void band_horner_kernel(const cx<double>* __re
                                                           const cx<double>* __restrict__ x,
                                                           const cx<double>* __restrict__ G, cx<TO>* __restrict__ y,
                                                           int64_t N, int32_t k, int32_t nw, double sw0h, double sdwh,
-                                                          int i) {
+                                                          int i, int32_t j0) {
   const int64_t total = (int64_t)nw * k * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void band_horner_kernel(const cx<double>* __re
     for (int d = -kBandRadius; d <= kBandRadius; ++d)
       if (n + d >= 0 && n + d < N) acc = cfma(band[n * kBandWidth + d + kBandRadius], x[e + d], acc);
     double sn, cs;
-    sincos((double)i * (sw0h + (double)j * sdwh), &sn, &cs);
+    sincos((double)i * (sw0h + (double)(j0 + j) * sdwh), &sn, &cs);
     acc = cfma(mk<double>(cs, sn), G[e], acc);
     y[e] = ccast<TO>(acc);
   }
@@ -149,13 +149,13 @@ int step1d_capacity(int cfg) {
 
 int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                       int out_fp64, int64_t N, int k, int nw, double sw0h, double sdwh, double h, int pass,
-                      hipStream_t st) {
+                      hipStream_t st, int j0) {
   const int64_t total = (int64_t)nw * k * N;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
 #define RES_TH(TF, TO)                                                                                         \
   hipLaunchKernelGGL((tri_horner_kernel<TF, TO>), dim3((unsigned)blocks), dim3(256), 0, st, tri, yin,         \
-                     (const cx<TF>*)F, (cx<TO>*)yout, N, k, nw, sw0h, sdwh, h, pass)
+                     (const cx<TF>*)F, (cx<TO>*)yout, N, k, nw, sw0h, sdwh, h, pass, j0)
   if (f_fp64 && out_fp64) RES_TH(double, double);
   else if (f_fp64 && !out_fp64) RES_TH(double, float);
   else if (!f_fp64 && out_fp64) RES_TH(float, double);
@@ -166,16 +166,16 @@ int launch_tri_horner(const cx<double>* tri, const cx<double>* yin, const void* 
 
 
 int launch_band_horner(const cx<double>* band, const cx<double>* x, const cx<double>* G, void* y, int out_fp64,
-                       int64_t N, int k, int nw, double sw0h, double sdwh, int i, hipStream_t st) {
+                       int64_t N, int k, int nw, double sw0h, double sdwh, int i, hipStream_t st, int j0) {
   const int64_t total = (int64_t)nw * k * N;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (out_fp64)
     hipLaunchKernelGGL((band_horner_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, st, band, x, G,
-                       (cx<double>*)y, N, k, nw, sw0h, sdwh, i);
+                       (cx<double>*)y, N, k, nw, sw0h, sdwh, i, j0);
   else
     hipLaunchKernelGGL((band_horner_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, st, band, x, G,
-                       (cx<float>*)y, N, k, nw, sw0h, sdwh, i);
+                       (cx<float>*)y, N, k, nw, sw0h, sdwh, i, j0);
   return 0;
 }
 

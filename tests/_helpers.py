@@ -35,3 +35,34 @@ def gpu_tensor(x, dtype=None):
     if dtype is not None:
         t = t.to(dtype)
     return t.cuda()
+
+
+def mode_errors(X, Y, gains, gap=1e-6):
+    """Per-mode error of modes X against reference modes Y, both (k, N) for one frequency, with the reference
+    gains (k,) sorted descending.  A mode is unique up to a phase factor, so a simple mode's error is
+    min over phi of ||x e^{i phi} - y|| / ||y|| (both normalised).  Modes whose gains lie within a relative gap
+    `gap` of each other span a subspace but are not unique one by one; each mode of such a cluster gets the
+    distance between the cluster's orthogonal projectors (2-norm), which is the sine of the largest principal
+    angle.  Returns an array (k,)."""
+    X = np.asarray(X, complex)
+    Y = np.asarray(Y, complex)
+    k = X.shape[0]
+    Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
+    Yn = Y / np.linalg.norm(Y, axis=1, keepdims=True)
+    out = np.zeros(k)
+    i = 0
+    while i < k:
+        j = i + 1
+        while j < k and (gains[j - 1] - gains[j]) < gap * gains[j - 1]:
+            j += 1
+        if j == i + 1:
+            c = np.vdot(Xn[i], Yn[i])
+            ph = c / abs(c) if abs(c) > 0 else 1.0
+            out[i] = np.linalg.norm(Xn[i] * ph - Yn[i])
+        else:
+            Qx = np.linalg.qr(X[i:j].T)[0]
+            Qy = np.linalg.qr(Y[i:j].T)[0]
+            resid = Qy - Qx @ (Qx.conj().T @ Qy)  # the part of the reference subspace outside span X
+            out[i:j] = float(np.linalg.norm(resid, 2))
+        i = j
+    return out

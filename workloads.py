@@ -26,7 +26,9 @@ Workloads (the paper publishes no data set; every input is synthetic):
                     (resolution about 0.2 rad per time unit) applied in two passes, 61 analysis frequencies in
                     [-15, 15], C2 interpolation, k = 1.
 * ``ADR3D``         3-D three-component advection-diffusion with shear coupling, 256 x 128 x 128, FP32 state,
-                    96 frequencies in [0, pi/2], k = 3, periodic method, checkpoints every 64 steps.
+                    96 frequencies in [0, pi/2] (P = 3,800 steps of h = 0.1), k = 3, periodic method with three
+                    periods, the last one projected every 38th step (100 samples for 96 frequencies), checkpoints
+                    every 64 steps for the gradient.
 
 ``gl_weights`` gives diagonal B, C, W_f, W_y (forcing window, observation window, grid quadrature) on the GL grid.
 
@@ -76,7 +78,7 @@ GL_PAPER_TRM = dict(name="gl_paper_trm_n200", kind="gl_paper", N=200, U=6.0, gam
                     margin=3.0, scheme="C2", k=1, iters=8, precision="fp64", seed=SEED_BASE + 6)
 
 ADR3D = dict(name="adr3d3c_256x128x128", kind="adr3d3c", nx=256, ny=128, nz=128, Re=200.0, h=0.1,
-             wmin=0.0, wmax=math.pi / 2, n_omega=96, method="periodic", periods=3, stride=1, tail=0,
+             wmin=0.0, wmax=math.pi / 2, n_omega=96, method="periodic", periods=3, stride=38, tail=0,
              k=3, iters=1, precision="mixed", mu_const=-0.05, nu_s=1.0, checkpoint_every=64,
              seed=SEED_BASE + 4)
 
@@ -111,6 +113,22 @@ def random_forcing(seed, n_omega, k, n, dtype=np.complex128):
     re = g.standard_normal((n_omega, k, n))
     im = g.standard_normal((n_omega, k, n))
     return (re + 1j * im).astype(dtype)
+
+
+def random_forcing_device(seed, n_omega, k, n, dtype, device):
+    """F[j, c, :] with independent N(0,1) real and imaginary parts drawn on the device by torch's Philox generator
+    seeded with `seed`, one frequency at a time (for inputs too large to draw on the host, such as the 3-D
+    workload's 96 x 3 x 12.6 M forcing).  dtype: torch.complex64 or torch.complex128."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    real = torch.float32 if dtype == torch.complex64 else torch.float64
+    out = torch.empty((n_omega, k, n), dtype=dtype, device=device)
+    for j in range(n_omega):
+        re = torch.randn((k, n), generator=g, dtype=real, device=device)
+        im = torch.randn((k, n), generator=g, dtype=real, device=device)
+        out[j] = torch.complex(re, im)
+    return out
 
 
 def batched_draws(cfg, count):
