@@ -26,6 +26,7 @@
 #ifndef RESOLVENT_H
 #define RESOLVENT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -135,6 +136,23 @@ int resolvent_op_set_diagonal(resolvent_op* op, const double* values, int32_t on
  * precision, see above); they may not alias. */
 int resolvent_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                     const void* f_hat, void* u_hat, void* stream);
+
+/* resolvent_apply for callers that cannot allocate device memory: code under HIP graph capture (it may be
+ * captured without a prior uncaptured call), tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, layout, ownership and results as resolvent_apply (up to rounding: the forcing may be synthesised
+ * in tiles where resolvent_apply holds a whole period, and the stepper relaunches at every neighbour exchange
+ * unless the handle already holds its exchange area).  Its workspace is one fixed device array of
+ * RESOLVENT_NOALLOC_SCRATCH_BYTES that the library defines; each GPU the library runs on holds its own copy from
+ * the first call on it until the process ends.  The call allocates and frees nothing, on the device or through
+ * any allocating library routine.  Every call on a GPU uses that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other handles, other host threads) race and give wrong
+ * results; serialise them.  The workspace a run needs grows with n_omega * k * N (the pre-filtered forcing, and for
+ * RES_MIXED handles the FP64 accumulator, are whole blocks of that size); a run that needs more than the array
+ * holds returns RES_EINVAL with the byte counts in resolvent_last_error before any work is queued.  Also
+ * RES_EINVAL when the current device is not the one the handle was created on.  Asynchronous on `stream`. */
+#define RESOLVENT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int resolvent_apply_noalloc(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                            const void* f_hat, void* u_hat, void* stream);
 
 /* z_hat[j] = R_d(w_j)^H g_hat[j]: the adjoint run (Sec. 2.1, eq. adsystemFreqDomain): L^H marched with the
  * frequencies negated (equivalent to the paper's backward integration in reversed time). */

@@ -41,6 +41,8 @@ SIGNATURES = {
     "resolvent_op_decay_time": (c_double, [c_void_p]),
     "resolvent_op_set_diagonal": (c_int32, [c_void_p, _dp, c_int32, c_void_p]),
     "resolvent_apply": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p, c_void_p]),
+    "resolvent_apply_noalloc": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
+                                          c_void_p]),
     "resolvent_adjoint_apply": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                           c_void_p]),
     "resolvent_modes": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_int32, c_void_p, _dp,

@@ -135,6 +135,18 @@ class ResolventOp:
         """u_hat[j] = R_d(w_j) f_hat[j] for all frequencies in one direct run."""
         return self._apply(f_hat, grid, run, out, adjoint=False)
 
+    def apply_noalloc(self, f_hat, grid, run, out):
+        """apply(f_hat, grid, run) through resolvent_apply_noalloc: the library allocates nothing and takes its
+        workspace from its fixed per-GPU scratch array; `out` (like f_hat) must be given.  Calls that overlap on one
+        GPU race on that array."""
+        nw, k = grid.n_omega, f_hat.shape[1]
+        self._check_io(f_hat, nw, k)
+        self._check_io(out, nw, k)
+        check(self._lib.resolvent_apply_noalloc(self._h, ctypes.byref(grid), ctypes.byref(run), k,
+                                                ctypes.c_void_p(f_hat.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                self._stream_ptr()))
+        return out
+
     def adjoint_apply(self, g_hat, grid, run, out=None):
         """z_hat[j] = R_d(w_j)^H g_hat[j] in one adjoint run."""
         return self._apply(g_hat, grid, run, out, adjoint=True)

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libresolvent.so")
 SOURCES = ["step1d.hip", "step1d_m2.hip", "step1d_m4.hip", "stencil.hip", "phase_gemm.hip", "qr.hip", "krylov.hip", "adjoint.hip",
-           "trm.hip", "runtime.cpp"]
+           "trm.hip", "noalloc.hip", "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RESOLVENT_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -134,6 +134,8 @@ struct PhaseGemmArgs {
 };
 int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st);
 int launch_reduce_partials(const void* part, void* acc, int64_t count, int nsplit, double scale, hipStream_t st);
+// Phase table t[m] = e^{2 pi i m / P}, m < P (working precision), computed on the device.
+int launch_phase_table(void* t, int fp64, int64_t P, hipStream_t st);
 
 // ---- per-frequency QR / SVD ----------------------------------------------------------------------------
 int gram_km(int k);

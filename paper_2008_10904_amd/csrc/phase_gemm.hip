@@ -17,6 +17,8 @@
 // one chunk ahead of the matrix-core work.  Workgroups walk the M tiles of one column tile on one XCD.  The
 // projection can split K over gridDim.y, writing FP64 partial tiles that a reduction adds into the FP64
 // accumulator.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -281,6 +283,24 @@ int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL((phase_gemm_kernel<double, 1>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((phase_gemm_kernel<float, 1>), grid, dim3(256), 0, st, a);
   }
+  return 0;
+}
+
+// t[m] = e^{2 pi i m / P} for m < P in the working precision, evaluated in FP64 on the device.
+template <typename R>
+__global__ __launch_bounds__(256) void phase_table_kernel(cx<R>* __restrict__ t, int64_t P) {
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < P; m += (int64_t)gridDim.x * blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)P, &sn, &cs);
+    t[m] = ccast<R>(mk<double>(cs, sn));
+  }
+}
+
+int launch_phase_table(void* t, int fp64, int64_t P, hipStream_t st) {
+  if (P <= 0) return -1;
+  const unsigned grid = (unsigned)std::min<int64_t>(4096, (P + 255) / 256);
+  if (fp64) hipLaunchKernelGGL(phase_table_kernel<double>, dim3(grid), dim3(256), 0, st, (cx<double>*)t, P);
+  else hipLaunchKernelGGL(phase_table_kernel<float>, dim3(grid), dim3(256), 0, st, (cx<float>*)t, P);
   return 0;
 }
 

@@ -15,6 +15,7 @@
 
 #include "../../include/resolvent.h"
 #include "kernels.h"
+#include "runtime_internal.h"
 
 using namespace res;
 typedef std::complex<double> cd;
@@ -79,6 +80,24 @@ Band band_mul(const Band& A, const Band& B) {
   return C;
 }
 
+// Workspace carved from a caller-independent fixed device array (the no-allocation apply): named slots are handed
+// out front to back, 256-byte aligned, and the run's buffer sizes follow `ArenaSizes` instead of the free device
+// memory.
+struct ArenaSizes {
+  int horner_chunk = 1;        // frequencies per FP64 pre-filter block
+  int64_t snap_rows = 0;       // snapshot rows buffered between projection flushes
+  bool table = false;          // whole forcing period as one table (else tiles)
+  int64_t tile_rows = 0;       // kernel steps per forcing tile
+  int64_t max_nsplit = 1;      // split-K limit of the projection (its FP64 partials live in the arena too)
+  size_t total = 0;            // bytes of all slots, alignment included
+};
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  std::map<std::string, std::pair<void*, size_t>> slots;
+  ArenaSizes sz;
+};
+
 }  // namespace
 
 struct resolvent_op {
@@ -140,6 +159,9 @@ struct resolvent_op {
   std::vector<double> trm_om, trm_D;
   std::vector<cd> trm_E;
   cd trm_one = cd(1.0, 0.0);
+  int device = 0;                        // the device the handle was created on
+  Arena* arena = nullptr;                 // set while a no-allocation call runs: the workspace comes from it
+  hipStream_t arena_stream = nullptr;     // that call's stream
   bool fp64() const { return prec == RES_FP64; }
   size_t wsize() const { return fp64() ? 16 : 8; }  // bytes per complex in working precision
 };
@@ -153,6 +175,22 @@ std::vector<void*>& retired_exchange_areas() {
 }
 
 int ws_get(resolvent_op* op, const std::string& name, size_t bytes, void** out) {
+  if (op->arena) {
+    Arena& a = *op->arena;
+    auto it = a.slots.find(name);
+    if (it != a.slots.end() && it->second.second >= bytes) {
+      *out = it->second.first;
+      return RES_OK;
+    }
+    const size_t off = (a.used + 255) & ~(size_t)255;
+    if (off + bytes > a.cap)
+      return fail(RES_EINVAL, "no-allocation scratch exhausted at '" + name + "' (" + std::to_string(off + bytes) +
+                              " of " + std::to_string(a.cap) + " bytes)");
+    a.slots[name] = {a.base + off, bytes};
+    a.used = off + bytes;
+    *out = a.base + off;
+    return RES_OK;
+  }
   DevBuf& b = op->ws[name];
   if (b.bytes < bytes) {
     if (op->capturing)
@@ -179,7 +217,7 @@ struct TimedLaunch {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   TimedLaunch(resolvent_op* o, int k, hipStream_t s) : op(o), kind(k), st(s) {
-    if (!op->timing || op->capturing) return;
+    if (!op->timing || op->capturing || op->arena) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       a = b = nullptr;
       return;
@@ -455,6 +493,12 @@ int phase_table(resolvent_op* op, int64_t P, void** out) {
     *out = it->second;
     return RES_OK;
   }
+  if (op->arena) {  // built on the device, stream-ordered, into the arena (no host staging buffer to keep alive)
+    RES_TRY(ws_get(op, "phase_table", (size_t)P * op->wsize(), out));
+    launch_phase_table(*out, op->fp64(), P, op->arena_stream);
+    HIP_TRY(hipGetLastError());
+    return RES_OK;
+  }
   if (op->capturing) return fail(RES_EINVAL, "phase table must be built by an uncaptured call first");
   void* d = nullptr;
   if (op->fp64()) {
@@ -584,6 +628,7 @@ int project_rows(resolvent_op* op, int fp64, int nw, int64_t P, double w0h, int 
   int64_t nsplit = 1;
   if (tiles < 1024) nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, (count + 63) / 64);
   if (nsplit < 1) nsplit = 1;
+  if (op->arena) nsplit = std::min<int64_t>(nsplit, op->arena->sz.max_nsplit);
   const int64_t kps = ((count + nsplit - 1) / nsplit + 15) / 16 * 16;
   nsplit = (count + kps - 1) / kps;
   a.k_per_split = kps;
@@ -697,6 +742,10 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     // is never freed once a kernel has used it (an outgrown area is retired, not released); it is reclaimed when
     // the process ends.  Every slot starts empty for each launch.
     const size_t need = (size_t)4 * ncols * op->wsize();  // [2 buffers][2 directions][ncols]
+    if (op->arena && op->xch_bytes < need) persist = false;  // no allocation: relaunch at every exchange instead
+  }
+  if (persist) {
+    const size_t need = (size_t)4 * ncols * op->wsize();
     if (op->xch_bytes < need) {
       if (op->capturing) return fail(RES_EINVAL, "exchange area must be allocated by an uncaptured call first");
       void* p = nullptr;
@@ -810,7 +859,7 @@ int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStre
     *nseg = 0;
     return RES_OK;
   }
-  if (op->segs_dev_k == k && op->segs_dev_version == op->plan_version) {
+  if (!op->arena && op->segs_dev_k == k && op->segs_dev_version == op->plan_version) {
     *nseg = (int64_t)k * (int64_t)op->segs.size();
     return ws_get(op, "segs", (size_t)*nseg * sizeof(Seg1D), dsegs);
   }
@@ -828,8 +877,10 @@ int upload_regions(resolvent_op* op, int k, void** dsegs, int64_t* nseg, hipStre
   RES_TRY(ws_get(op, "segs", segs.size() * sizeof(Seg1D), dsegs));
   HIP_TRY(hipMemcpyAsync(*dsegs, segs.data(), segs.size() * sizeof(Seg1D), hipMemcpyHostToDevice, st));
   *nseg = (int64_t)segs.size();
-  op->segs_dev_k = k;
-  op->segs_dev_version = op->plan_version;
+  if (!op->arena) {  // the arena's slot is not the handle's cached copy
+    op->segs_dev_k = k;
+    op->segs_dev_version = op->plan_version;
+  }
   return RES_OK;
 }
 
@@ -857,7 +908,8 @@ int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp
   const int nbuf = M > 2 ? 3 : 2;
   const double budget = env_double("RESOLVENT_HORNER_BUDGET_GB", 8.0) * 1073741824.0;
   const double per_freq = (double)nbuf * (double)ncols * sizeof(cd);
-  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(budget / per_freq)));
+  const int chunk = op->arena ? std::min(nw, op->arena->sz.horner_chunk)
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(budget / per_freq)));
   void *y1, *y2, *y3 = nullptr;
   RES_TRY(ws_get(op, "horner_a", (size_t)chunk * ncols * sizeof(cd), &y1));
   RES_TRY(ws_get(op, "horner_b", (size_t)chunk * ncols * sizeof(cd), &y2));
@@ -933,7 +985,9 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   // RESOLVENT_SNAP_BUDGET_GB overrides it.  It is taken before the forcing table, whose budget sees what is left.
   const int64_t snap_ld = ncols + 1;
   double snap_budget;
-  if (std::getenv("RESOLVENT_SNAP_BUDGET_GB")) {
+  if (op->arena) {
+    snap_budget = (double)op->arena->sz.snap_rows * (double)snap_ld * (double)ws;
+  } else if (std::getenv("RESOLVENT_SNAP_BUDGET_GB")) {
     snap_budget = env_double("RESOLVENT_SNAP_BUDGET_GB", 2.0) * 1073741824.0;
   } else {
     size_t free_b = 0, total_b = 0;
@@ -953,7 +1007,9 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   // is the free device memory (plus the table this handle already holds) minus a reserve for the rest of the
   // run; RESOLVENT_TABLE_BUDGET_GB overrides it.
   double table_budget;
-  if (std::getenv("RESOLVENT_TABLE_BUDGET_GB")) {
+  if (op->arena) {
+    table_budget = op->arena->sz.table ? 1e300 : -1.0;
+  } else if (std::getenv("RESOLVENT_TABLE_BUDGET_GB")) {
     table_budget = env_double("RESOLVENT_TABLE_BUDGET_GB", 0.0) * 1073741824.0;
   } else {
     size_t free_b = 0, total_b = 0;
@@ -992,7 +1048,8 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     trace_norm("forcing table", frc, table_rows * ncols, op->fp64(), st);
   } else {
     const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
-    tile_rows = std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));  // kernel steps per tile
+    tile_rows = op->arena ? op->arena->sz.tile_rows
+                          : std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));  // steps per tile
     RES_TRY(ws_get(op, "forcing", (size_t)(tile_rows + 16) * ncols * ws, &frc));  // + prefetch padding rows
   }
 
@@ -2011,6 +2068,76 @@ int trm_modes(resolvent_op* op, int k, int64_t n, int every, int scheme, const v
 
 }  // namespace
 
+namespace {
+
+// Workspace sizes of one direct run in a fixed arena of `cap` bytes (the no-allocation apply): the slots a run takes
+// from ws_get, with the flexible buffers (pre-filter blocks, snapshot rows, forcing tiles, projection partials)
+// sized from what the fixed ones leave.  RES_EINVAL with the byte counts when even the smallest layout does not fit.
+int arena_sizes(const resolvent_op* op, const Plan& pl, int k, size_t cap, ArenaSizes* out) {
+  const double ws = (double)op->wsize();
+  const double ncols = (double)k * (double)op->N;
+  const int M = run_power(op, pl);
+  const int nw = pl.nw;
+  auto al = [](double b) { return std::ceil(b / 256.0) * 256.0; };
+  double fixed = al(nw * ncols * ws)                                   // G
+                 + al((double)pl.P * ws)                               // phase table
+                 + 2 * al(ncols * ws);                                 // state0, state1
+  if (!op->fp64()) fixed += al(nw * ncols * 16.0);                     // FP64 accumulator of the complex64 output
+  if (op->weighted) fixed += al(nw * ncols * 16.0);                    // scaled input block
+  if (is_grid(op) && op->ncomp == 3) fixed += al(ncols * ws);          // third-stage input of the 3-D step
+  if (!is_grid(op)) fixed += al((double)k * op->segs.size() * sizeof(Seg1D));
+  const double room = (double)cap - fixed;
+  const int nbuf = M > 2 ? 3 : 2;
+  const double snap_ld = ncols + 1;
+  const int64_t table_rows = std::min<int64_t>(pl.P, pl.forced_end) / M;
+  ArenaSizes z;
+  z.horner_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(room / 8 / (nbuf * ncols * 16.0))));
+  z.snap_rows = std::min<int64_t>(pl.pcount, std::max<int64_t>(64, (int64_t)(room / 8 / (snap_ld * ws))));
+  z.table = (double)table_rows * ncols * ws <= room / 4;
+  z.tile_rows = std::max<int64_t>(64, (int64_t)(room / 8 / (ncols * ws)));
+  z.max_nsplit = std::max<int64_t>(1, (int64_t)(room / 8 / (nw * ncols * 16.0)));
+  double total = fixed + nbuf * al(z.horner_chunk * ncols * 16.0) + al((double)z.snap_rows * snap_ld * ws) +
+                 (z.table ? al((double)table_rows * ncols * ws) : al((double)(z.tile_rows + 16) * ncols * ws)) +
+                 (z.max_nsplit > 1 ? al((double)z.max_nsplit * nw * ncols * 16.0) : 0.0);
+  if (total > (double)cap)
+    return fail(RES_EINVAL, "resolvent_apply_noalloc: this run needs at least " + std::to_string((long long)total) +
+                            " bytes of workspace and the no-allocation scratch holds " + std::to_string(cap) +
+                            "; use resolvent_apply");
+  z.total = (size_t)total;
+  *out = z;
+  return RES_OK;
+}
+
+}  // namespace
+
+// resolvent_apply with every workspace buffer carved from [base, base + cap) (device memory the caller keeps for
+// the process): see resolvent_apply_noalloc in noalloc.hip.
+int res_apply_in_scratch(resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, int32_t k,
+                         const void* f_hat, void* u_hat, void* base, size_t cap, void* stream) {
+  g_last_error.clear();
+  if (!op || !g || !r || !f_hat || !u_hat || !base) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != op->device) return fail(RES_EINVAL, "the current device is not the one the handle was created on");
+  Plan pl;
+  RES_TRY(make_plan(op, g, r, &pl));
+  ArenaSizes z;
+  RES_TRY(arena_sizes(op, pl, k, cap, &z));
+  Arena a;
+  a.base = (char*)base;
+  a.cap = cap;
+  a.sz = z;
+  op->arena = &a;
+  op->arena_stream = (hipStream_t)stream;
+  const int rc = apply_common(op, g, r, k, f_hat, u_hat, +1, (hipStream_t)stream);
+  op->arena = nullptr;
+  op->arena_stream = nullptr;
+  return rc;
+}
+
+int res_fail(int code, const char* msg) { return fail(code, msg); }
+
 // =====================================================================================================
 // C ABI
 // =====================================================================================================
@@ -2042,6 +2169,10 @@ int resolvent_op_create(const resolvent_op_desc* d, void* stream, resolvent_op**
   if (d->precision != RES_FP64 && d->precision != RES_MIXED) return fail(RES_EINVAL, "bad precision");
   hipStream_t st = (hipStream_t)stream;
   resolvent_op* op = new resolvent_op();
+  if (hipGetDevice(&op->device) != hipSuccess) {
+    delete op;
+    return fail(RES_EHIP, "hipGetDevice failed");
+  }
   op->kind = d->kind;
   op->prec = d->precision;
   op->h = d->h;
