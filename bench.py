@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--weighted", action="store_true",
                     help="gl_periodic_n2000 with diagonal B (forcing window over the upstream 60 %%), C (observation "
                          "window over the downstream 60 %%) and metrics W_f = W_y = dx")
+    ap.add_argument("--no-autograd", action="store_true",
+                    help="grid workloads: skip the reverse-mode part (apply_backward) after the timed iterations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -566,7 +568,7 @@ def bench_grid(args):
     time_steps_total = 2 * steps_per_run * args.steps
     value = N * k * nw * 2 * steps_per_run / dt
     autograd = None
-    if not three:
+    if not three and not args.no_autograd:
         # forward plus reverse mode (the 2-D gradient path): one apply and one apply_backward with the forcing and
         # mu gradients, checkpoints every ~sqrt(steps), timed outside the iteration above
         torch.cuda.synchronize()
@@ -609,7 +611,7 @@ def bench_grid(args):
     torch.cuda.empty_cache()
     if autograd is not None:
         out["autograd"] = autograd
-    else:
+    elif three and not args.no_autograd:
         out["autograd"] = grad3d_half(cfg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_grid(cfg, w0, dw, args.cpu_seconds)

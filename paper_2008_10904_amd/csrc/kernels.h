@@ -61,11 +61,21 @@ struct GridOpDev {
   const void* cxm; const void* cxp; const void* cym; const void* cyp; const void* czm; const void* czp;
   const void* d;
   const void* K;
+  int kmask;  // bit c*3+c' set when K[.][c][c'] is nonzero on some line (0 without coupling)
+  // FP32 three-component sets: the line coefficients packed per line, [lines][8] = cxm cxp cym cyp czm czp kA kB,
+  // with (kA, kB) = (K01, K02) when kv = 1 (the shear terms of the first component), (K10, K20) when kv = 2 (their
+  // transpose), unused otherwise (kv = 0: no coupling, 3: general, read from K); null for other sets
+  const void* lc;
+  int kv;
 };
 // Two Horner stages of a 3-D three-component operator in one launch, marching along z (see stencil.hip): pass 1
 // (second = 0) writes the third stage's input from u, pass 2 the new state from vin and u (out != u).
 int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const void* vin, void* out, int second,
                        const void* frc, double phr, double phi, void* snap, hipStream_t st);
+// Whole RK4 step of a 3-D three-component operator in one launch (four stages pipelined along z), FP32 state;
+// uout != uin.  Returns -1 for other operators.
+int launch_grid_step3d(const GridOpDev& g, int k, const void* uin, void* uout, const void* frc, double phr,
+                       double phi, void* snap, hipStream_t st);
 // Whole RK4 step of a 2-D one-component operator in one launch (LDS temporal blocking); uout != uin.
 int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
                        double phi, void* snap, hipStream_t st);

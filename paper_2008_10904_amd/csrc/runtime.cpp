@@ -382,6 +382,22 @@ int build_grid_coefficients(resolvent_op* op) {
       RES_TRY(up(X[5], f64, &g.czp));
       RES_TRY(up(op->gd, f64, &g.d));
       RES_TRY(up(K, f64, &g.K));
+      g.kmask = 0;
+      for (size_t i = 0; i < K.size(); ++i)
+        if (K[i] != 0.0) g.kmask |= 1 << (int)(i % 9);
+      g.kv = K.empty() || g.kmask == 0 ? 0 : (g.kmask & ~0x006) == 0 ? 1 : (g.kmask & ~0x048) == 0 ? 2 : 3;
+      g.lc = nullptr;
+      if (!f64 && op->ncomp == 3) {  // packed line coefficients of the one-launch FP32 step
+        std::vector<double> pk((size_t)nl * 8, 0.0);
+        for (int64_t l = 0; l < nl; ++l) {
+          for (int a = 0; a < 6; ++a) pk[l * 8 + a] = X[a][l];
+          if (g.kv == 1 || g.kv == 2) {
+            pk[l * 8 + 6] = K[l * 9 + (g.kv == 1 ? 1 : 3)];
+            pk[l * 8 + 7] = K[l * 9 + (g.kv == 1 ? 2 : 6)];
+          }
+        }
+        RES_TRY(up(pk, false, &g.lc));
+      }
     }
   }
   (void)nn;
@@ -809,18 +825,20 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
 }
 
 // March n steps of all k columns of a grid operator (Z or Z^H chosen by op->march_grid), the state ping-ponging
-// between state0 and state1: 2-D one-component operators take one fused launch per step, 3-D three-component
-// operators two launches of two Horner stages each (the second writes the new state).
+// between state0 and state1: 2-D one-component operators take one fused launch per step, and so do 3-D
+// three-component operators with an FP32 state (the four stages pipelined along z); FP64 3-D states take two
+// launches of two Horner stages each (the second writes the new state).
 int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const SnapSpec& ss, hipStream_t st) {
   const int64_t ncols = (int64_t)k * op->N;
   const size_t ws = op->wsize();
   const GridOpDev& g = *op->march_grid;
   const bool fused = g.ncomp == 1 && g.nz == 1;
+  const bool fused3 = g.ncomp == 3 && !op->fp64();  // one launch per step (FP32 state); FP64 takes two passes
   void* sb[2];
   void* v2 = nullptr;
   RES_TRY(ws_get(op, "state0", (size_t)ncols * ws, &sb[0]));
   RES_TRY(ws_get(op, "state1", (size_t)ncols * ws, &sb[1]));
-  if (!fused) RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v2));
+  if (!fused && !fused3) RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v2));
   TimedLaunch tl(op, RES_TIMING_STEPPER, st);
   int64_t next = (ss.snap != nullptr && ss.count > 0) ? ss.first : -1, m = 0;
   for (int64_t t = 0; t < n; ++t) {
@@ -841,6 +859,9 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
     if (fused) {
       if (launch_grid_step2d(g, op->fp64(), k, uin, uout, frow, fs.phi.real(), fs.phi.imag(), srow, st))
         return fail(RES_EINVAL, "2-D step launch");
+    } else if (fused3) {
+      if (launch_grid_step3d(g, k, uin, uout, frow, fs.phi.real(), fs.phi.imag(), srow, st))
+        return fail(RES_EINVAL, "3-D step launch");
     } else if (launch_grid_pair3d(g, op->fp64(), k, uin, nullptr, v2, 0, nullptr, 0, 0, nullptr, st) ||
                launch_grid_pair3d(g, op->fp64(), k, uin, v2, uout, 1, frow, fs.phi.real(), fs.phi.imag(), srow,
                                   st)) {

@@ -308,6 +308,232 @@ __global__ __launch_bounds__(TX * TY) void grid_pair3d_kernel(GridCoef<R> Cf, in
   }
 }
 
+// Whole RK4 step of the 3-D three-component operator in one launch, marching along z (FP32 state).
+//
+// The four Horner stages v1 = u + Z u/4, v2 = u + Z v1/3, v3 = u + Z v2/2, u' = u + Z v3 + phi frc are pipelined
+// over the planes: at plane step a the workgroup evaluates v1 at plane a-1, v2 at a-2, v3 at a-3 and the new
+// state at a-4, each from the previous stage's planes just above and below it, so the state is read once and
+// written once per step and no stage value leaves the chip (a stage has radius 1 in z, hence the lag of one plane
+// per stage).  A workgroup of 64 x TY threads covers a 64 x TY window of (x, y) nodes of one state column; wave w
+// holds window row w, lane l window column l.  Stage m is valid on the window shrunk by m nodes per side (halo 4 =
+// the reach of four stages), so the output tile is the 56 x (TY - 8) interior, and the waves of rows outside stage
+// m's rows skip it (the skipped work balances over the four SIMDs: row w runs on SIMD w mod 4); so do the waves of
+// rows outside the grid, whose values stay zero.
+//
+// Where the operands come from: the x neighbours are the lanes next door, moved by DPP wave shifts (no LDS); the y
+// neighbours are other waves' rows, read from that stage's plane in LDS (one buffer per stage, published once per
+// plane step); the z neighbours and the centre are per-thread registers.  The three register roles of each stage
+// (plane below, centre, plane just computed) rotate with period three, so the plane loop is unrolled three times
+// and the rotation is a renaming, not a copy; the Horner bases u(a-3) and u(a-4) sit in a two-plane LDS ring that
+// each thread reads for its own node only.  A row's line coefficients are wave-uniform: one packed scalar load per
+// stage (GridOpDev::lc).  Two LDS-only barriers per plane step (before the stage planes are read and before they
+// are overwritten) leave the global loads and stores in flight; the next step's state plane and diagonal and the
+// forcing of the output nodes are loaded at the top of a step and consumed at its end.  Values outside the grid are zero (homogeneous
+// Dirichlet): only the first and last tile in x hold lanes outside it, and only they mask.  Operation order per
+// component as apply_z: diagonal, -x, +x, -y, +y, -z, +z, then the coupling; KV selects its pattern (0: none; 1:
+// the shear terms K01, K02 of the first component; 2: their transpose K10, K20 in Z^H; 3: all nine, read from K).
+// u' goes to a buffer other than u (windows read u at halo nodes that neighbouring tiles update); the snapshot (if
+// any) takes u.
+struct alignas(32) LineCoef8 {
+  float v[8];  // cxm cxp cym cyp czm czp kA kB
+};
+
+// Value of lane l - 1 (dir = 0) or l + 1 (dir = 1) of the wave, 0 beyond its ends.
+template <int DIR> __device__ __forceinline__ float lane_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), DIR == 0 ? 0x138 : 0x130, 0xf, 0xf, true));
+}
+
+template <int TY, int KV>
+__global__ __launch_bounds__(64 * TY) void grid_step3d_kernel(GridCoef<float> Cf, const LineCoef8* __restrict__ lc,
+                                                              int64_t nx, int64_t ny, int64_t nz, int64_t ncol,
+                                                              const cx<float>* __restrict__ u,
+                                                              cx<float>* __restrict__ out,
+                                                              const cx<float>* __restrict__ frc, float phr, float phi,
+                                                              cx<float>* __restrict__ snap) {
+  constexpr int H = 4, TX = 64, OX = TX - 2 * H, OY = TY - 2 * H, NC = 3;
+  __shared__ cx<float> Ls[4][NC][TY][TX];
+  __shared__ cx<float> Us[2][NC][TY][TX];
+  const int lx = threadIdx.x & 63;
+  const int wy = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // window row: uniform across the wave
+  // 32-bit offsets inside one column (the launcher checks 3 * nodes < 2^31); 64-bit only for the column base
+  const int nodes = (int)(nx * ny * nz), sz = (int)(nx * ny), nx32 = (int)nx, ny32 = (int)ny, nz32 = (int)nz;
+  // Tile order: workgroups are dealt to the eight XCDs in turn (id mod 8); each XCD takes a contiguous run of
+  // tiles (x fastest, then y, then column), so tiles whose halos overlap march side by side and share its L2.
+  const int64_t gx = (nx + OX - 1) / OX, gy = (ny + OY - 1) / OY, ntile = gx * gy * ncol;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * ((ntile + 7) / 8) + (blockIdx.x >> 3);
+  if (tile >= ntile) return;  // padding of the grid to a multiple of 8 (whole workgroup)
+  const int tx = (int)(tile % gx), ty = (int)((tile / gx) % gy);
+  const int64_t b = tile / (gx * gy);
+  const int x0w = tx * OX - H;                      // first window column (uniform)
+  const int ix = x0w + lx, iy = ty * OY - H + wy;   // iy uniform
+  const bool yin = iy >= 0 && iy < ny32;            // uniform
+  const bool xin = ix >= 0 && ix < nx32;
+  const bool xedge = x0w < 0 || x0w + TX > nx32;    // uniform: this tile has lanes outside the grid
+  const int iyc = yin ? iy : 0;
+  const uint32_t pxy = (uint32_t)(iyc * nx32 + (xin ? ix : 0));  // this lane's node in a plane (clamped)
+  const int64_t cb = b * NC * (int64_t)nodes;
+  const cx<float>* __restrict__ ucol = u + cb;
+  const cx<float>* __restrict__ fcol = frc != nullptr ? frc + cb : nullptr;
+  cx<float>* __restrict__ ocol = out + cb;
+  cx<float>* __restrict__ scol = snap != nullptr ? snap + cb : nullptr;
+  const cx<float> zero = mk<float>(0.f, 0.f);
+  const int yl = wy > 0 ? wy - 1 : 0, yr = wy < TY - 1 ? wy + 1 : TY - 1;
+  // window rows on which stage m (1..4) is evaluated (none for rows outside the grid)
+  auto row_ok = [&](int m) { return yin && wy >= m && wy < TY - m; };
+  auto zc = [&](int z) -> int { return z < 0 ? 0 : (z >= nz32 ? nz32 - 1 : z); };
+  auto zin = [&](int z) { return z >= 0 && z < nz32; };
+
+  struct V3 {
+    cx<float> c[NC];
+  };
+  auto ld3 = [&](const cx<float>* __restrict__ col, int z) -> V3 {  // clamped plane, unconditional
+    V3 r;
+    const int o = zc(z) * sz;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r.c[c] = (col + (int64_t)(c * nodes + o))[pxy];
+    return r;
+  };
+  auto mask_x = [&](V3& v) {  // zero at lanes outside the grid (first and last tile in x only)
+    if (xedge) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v.c[c] = csel(xin, v.c[c], zero);
+    }
+  };
+  auto zero3 = [&](V3& v) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v.c[c] = zero;
+  };
+  // base + s * (Z x) at this thread's node of plane z: centre x0 and z neighbours xm, xp from registers, x
+  // neighbours by lane shifts of x0, y neighbours from LDS stage buffer S
+  auto stage = [&](int S, int z, const V3& xm, const V3& x0, const V3& xp, const V3& base, float dd, float s) -> V3 {
+    const int l = z * ny32 + iyc;
+    const LineCoef8 q = lc[l];
+    const float cxm = q.v[0], cxp = q.v[1], cym = q.v[2], cyp = q.v[3], czm = q.v[4], czp = q.v[5];
+    V3 zv;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      cx<float> acc = mk<float>(dd * x0.c[c].re, dd * x0.c[c].im);
+      const cx<float> sn = Ls[S][c][yl][lx], nn = Ls[S][c][yr][lx];
+      acc.re += cxm * lane_shift<0>(x0.c[c].re); acc.im += cxm * lane_shift<0>(x0.c[c].im);
+      acc.re += cxp * lane_shift<1>(x0.c[c].re); acc.im += cxp * lane_shift<1>(x0.c[c].im);
+      acc.re += cym * sn.re; acc.im += cym * sn.im;
+      acc.re += cyp * nn.re; acc.im += cyp * nn.im;
+      acc.re += czm * xm.c[c].re; acc.im += czm * xm.c[c].im;
+      acc.re += czp * xp.c[c].re; acc.im += czp * xp.c[c].im;
+      zv.c[c] = acc;
+    }
+    if (KV == 1) {  // first component: + K01 x_1 + K02 x_2
+      zv.c[0].re += q.v[6] * x0.c[1].re; zv.c[0].im += q.v[6] * x0.c[1].im;
+      zv.c[0].re += q.v[7] * x0.c[2].re; zv.c[0].im += q.v[7] * x0.c[2].im;
+    } else if (KV == 2) {  // second and third components: + K10 x_0, + K20 x_0
+      zv.c[1].re += q.v[6] * x0.c[0].re; zv.c[1].im += q.v[6] * x0.c[0].im;
+      zv.c[2].re += q.v[7] * x0.c[0].re; zv.c[2].im += q.v[7] * x0.c[0].im;
+    } else if (KV == 3) {
+      const float* Kl = Cf.K + (int64_t)l * 9;
+      V3 add;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        add.c[c] = zv.c[c];
+#pragma unroll
+        for (int cp = 0; cp < NC; ++cp) {
+          add.c[c].re += Kl[c * 3 + cp] * x0.c[cp].re;
+          add.c[c].im += Kl[c * 3 + cp] * x0.c[cp].im;
+        }
+      }
+      zv = add;
+    }
+    V3 r;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r.c[c] = mk<float>(base.c[c].re + s * zv.c[c].re, base.c[c].im + s * zv.c[c].im);
+    mask_x(r);
+    return r;
+  };
+
+  const bool interior = yin && xin && lx >= H && lx < TX - H && wy >= H && wy < TY - H;
+  const bool forced = fcol != nullptr && interior;  // only the output nodes read the forcing
+  float d4 = 0.f, d3 = 0.f, d2 = 0.f, d1 = 0.f;
+  // One plane step.  On entry: LDS stage buffers 0..3 hold u(a-1), v1(a-2), v2(a-3), v3(a-4) and registers
+  // uZp = u(a), uC = u(a-1), uZm = u(a-2), vmZm = vm at the plane below the stage's centre, vmC = vm at the centre;
+  // vmN receives the stage's new plane.  On exit uZm holds u(a+1) and the roles have moved by one: the next step
+  // takes (uZm, uZp, uC) as (uZp, uC, uZm) and (vmC, vmN, vmZm) as (vmZm, vmC, vmN).  A stage that is skipped
+  // (plane outside the grid) leaves a zero plane behind.
+  auto step = [&](int a, V3& uZp, V3& uC, V3& uZm, V3& v1Zm, V3& v1C, V3& v1N, V3& v2Zm, V3& v2C, V3& v2N,
+                  V3& v3Zm, V3& v3C, V3& v3N) {
+    lds_barrier();  // the stage planes of this step are published
+    // operands of the next step: the state plane a+1, the diagonal of plane a; the forcing of plane a-4
+    const V3 un = ld3(ucol, a + 1);
+    const float dn = Cf.d[(int64_t)zc(a) * sz + pxy];
+    V3 f4;
+    if (forced) f4 = ld3(fcol, a - 4);
+    if (row_ok(1) && zin(a - 1)) v1N = stage(0, a - 1, uZm, uC, uZp, uC, d1, 0.25f);
+    else zero3(v1N);
+    if (row_ok(2) && zin(a - 2)) v2N = stage(1, a - 2, v1Zm, v1C, v1N, uZm, d2, 1.f / 3.f);
+    else zero3(v2N);
+    V3 u3, u4;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u3.c[c] = Us[(a - 1) & 1][c][wy][lx];
+      u4.c[c] = Us[a & 1][c][wy][lx];
+    }
+    if (row_ok(3) && zin(a - 3)) v3N = stage(2, a - 3, v2Zm, v2C, v2N, u3, d3, 0.5f);
+    else zero3(v3N);
+    if (row_ok(4) && zin(a - 4)) {
+      V3 r = stage(3, a - 4, v3Zm, v3C, v3N, u4, d4, 1.f);
+      if (interior) {
+        const int e = (a - 4) * sz;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          if (forced) {
+            const cx<float> f = f4.c[c];
+            r.c[c].re += phr * f.re - phi * f.im;
+            r.c[c].im += phr * f.im + phi * f.re;
+          }
+          if (scol != nullptr) (scol + (int64_t)(c * nodes + e))[pxy] = u4.c[c];
+          (ocol + (int64_t)(c * nodes + e))[pxy] = r.c[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Us[a & 1][c][wy][lx] = uZm.c[c];  // u(a-2): read as u(a-3), then u(a-4)
+    lds_barrier();  // every read of the stage planes is done before they are overwritten
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Ls[0][c][wy][lx] = uZp.c[c];
+      Ls[1][c][wy][lx] = v1N.c[c];
+      Ls[2][c][wy][lx] = v2N.c[c];
+      Ls[3][c][wy][lx] = v3N.c[c];
+    }
+    if (yin && zin(a + 1)) {
+      uZm = un;
+      mask_x(uZm);
+    } else {
+      zero3(uZm);
+    }
+    d4 = d3; d3 = d2; d2 = d1; d1 = dn;
+  };
+
+  V3 A, B, C, P1, Q1, R1, P2, Q2, R2, P3, Q3, R3;
+  zero3(A); zero3(B); zero3(C);
+  zero3(P1); zero3(Q1); zero3(R1); zero3(P2); zero3(Q2); zero3(R2); zero3(P3); zero3(Q3); zero3(R3);
+  if (yin) {
+    A = ld3(ucol, 0);  // u(0); u(-1) = u(-2) = 0
+    mask_x(A);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int S = 0; S < 4; ++S) Ls[S][c][wy][lx] = zero;
+  const int steps = nz32 + 4;
+  int a = 0;
+  for (; a + 2 < steps; a += 3) {
+    step(a, A, B, C, P1, Q1, R1, P2, Q2, R2, P3, Q3, R3);
+    step(a + 1, C, A, B, Q1, R1, P1, Q2, R2, P2, Q3, R3, P3);
+    step(a + 2, B, C, A, R1, P1, Q1, R2, P2, Q2, R3, P3, Q3);
+  }
+  if (a < steps) step(a, A, B, C, P1, Q1, R1, P2, Q2, R2, P3, Q3, R3);
+  if (a + 1 < steps) step(a + 1, C, A, B, Q1, R1, P1, Q2, R2, P2, Q3, R3, P3);
+}
+
 // One Horner pass of G = h Q_j(Z) F over [n_w][k] blocks (see tri_horner_kernel for the coefficients).
 template <typename TF, typename TO, int NC>
 __global__ __launch_bounds__(256) void grid_horner_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny, int64_t nz,
@@ -436,6 +662,29 @@ int launch_grid_pair3d(const GridOpDev& g, int fp64, int k, const void* u, const
     if (second) RES_P3(float, true, 64, 16); else RES_P3(float, false, 64, 16);
   }
 #undef RES_P3
+  return 0;
+}
+
+int launch_grid_step3d(const GridOpDev& g, int k, const void* uin, void* uout, const void* frc, double phr,
+                       double phi, void* snap, hipStream_t st) {
+  constexpr int TY = 16;  // 16 waves: a 64 x 16 window, 56 x 8 output nodes per plane
+  if (g.ncomp != 3 || k < 1 || 3 * g.nx * g.ny * g.nz >= ((int64_t)1 << 31)) return -1;
+  const int64_t tiles = ((g.nx + 55) / 56) * ((g.ny + TY - 9) / (TY - 8)) * k;
+  if (tiles > 0x7ffffff0) return -1;
+  if (g.lc == nullptr) return -1;
+  const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+#define RES_S3(KV)                                                                                                \
+  hipLaunchKernelGGL((grid_step3d_kernel<TY, KV>), grid, dim3(64 * TY), 0, st, coef_of<float>(g, 0),             \
+                     (const LineCoef8*)g.lc, g.nx, g.ny, g.nz, (int64_t)k, (const cx<float>*)uin, (cx<float>*)uout, \
+                     (const cx<float>*)frc, (float)phr, (float)phi, (cx<float>*)snap)
+  // coupling pattern: the shear terms of the first component (Z), their transpose (Z^H), none, or general
+  switch (g.kv) {
+    case 0: RES_S3(0); break;
+    case 1: RES_S3(1); break;
+    case 2: RES_S3(2); break;
+    default: RES_S3(3); break;
+  }
+#undef RES_S3
   return 0;
 }
 

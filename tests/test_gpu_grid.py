@@ -98,6 +98,34 @@ def test_3d_tiles_and_z_chunks_match_oracle(prec, shape):
     assert e < (1e-10 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("shape", [(130, 21, 5), (60, 9, 40)])
+def test_3d_fused_step_matches_oracle(shape):
+    """The one-launch 3-D step of FP32 states (four stages pipelined along z): grids with ragged x and y tiles (56 x 8
+    output nodes), fewer planes than the pipeline depth or many, two columns; direct (shear coupling of the first
+    component), adjoint (its transpose) and transient runs against the oracle's four-stage march.  Bar 1e-4 per
+    response vector (FP32 rounding, measured about 1e-6)."""
+    import torch
+    nx, ny, nz = shape
+    say("case: 3-D fused FP32 step", shape)
+    op, L = make3d(nx, ny, nz, 0.1, "mixed")
+    h, P, nw, k = 0.1, 100, 2, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(25, nw, k, op.n)
+    f = gpu_tensor(F, torch.complex64)
+    grid = op.grid(0.1, dw, nw)
+    up = to_np(op.apply(f, grid, op.run("periodic", periods=3, stride=25)))
+    za = to_np(op.adjoint_apply(f, grid, op.run("periodic", periods=3, stride=25)))
+    ut = to_np(op.apply(f, grid, op.run("transient", tail=60)))
+    torch.cuda.synchronize()
+    Fr = F.astype(np.complex64).astype(np.complex128)
+    rp = O_st.run(L, h, 0.1, dw, Fr, "periodic", periods=3, stride=25)
+    ra = O_st.run(L, h, 0.1, dw, Fr, "periodic", periods=3, stride=25, adjoint=True)
+    rt = O_st.run(L, h, 0.1, dw, Fr, "transient", tail=60)
+    e = (per_freq_relerr(up, rp), per_freq_relerr(za, ra), per_freq_relerr(ut, rt))
+    say("  errors", e)
+    assert max(e) < 1e-4
+
+
 @pytest.mark.parametrize("case", ["2d", "3d"])
 def test_modes_match_oracle(case):
     import torch

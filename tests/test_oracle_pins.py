@@ -105,6 +105,26 @@ def test_adr3d3c_operator_matches_pde_on_smooth_function():
     assert 3.3 < errs[0] / errs[1] < 4.7
 
 
+def test_input_fields_take_their_defining_values():
+    # The sponge ramp is 0 at least w = frac (hi - lo) inside both ends, 1 at an end and linear in between; the
+    # 2-D sponge is nu_s max(r_x, r_y)^2; the reaction bump peaks at base + amp at (xc, 0) and falls to base; the
+    # wake deficit is amp at (y0, z0) and vanishes far away.  Interior grids exclude the end points.
+    s = np.array([0.0, 0.5, 1.0, 2.0, 5.0, 9.5, 10.0])
+    assert np.allclose(operators.sponge_ramp(s, 0.0, 10.0, 0.1), [1.0, 0.5, 0.0, 0.0, 0.0, 0.5, 1.0], atol=1e-15)
+    x, d = operators.uniform_interior_grid(9, 0.0, 40.0)
+    assert d == 4.0 and x[0] == 4.0 and x[-1] == 36.0
+    f = operators.adr2d_fields(79, 39, nu_s=2.0)  # dx = 0.5, dy = 0.5: node (x, y) = (0.5 (i+1), -10 + 0.5 (j+1))
+    assert f["sponge"][19, 39] == 0.0  # (20, 0): interior
+    # ramp widths 4 in x (0.1 of 40) and 2 in y (0.1 of 20)
+    assert abs(f["sponge"][0, 0] - 2.0 * 0.875 ** 2) < 1e-14  # (0.5, -9.5): r_x = 3.5/4, r_y = 1.5/2
+    assert abs(f["sponge"][1, 2] - 2.0 * 0.625 ** 2) < 1e-14  # (1.5, -9): r_x = 2.5/4, r_y = 1/2
+    assert abs(operators.adr2d_mu_default(10.0, 0.0, base=-0.1, amp=0.08) - (-0.02)) < 1e-15
+    assert abs(operators.adr2d_mu_default(30.0, 9.0, base=-0.1, amp=0.08) + 0.1) < 1e-15
+    U, _, _ = operators.wake_profile(np.array([0.2, 9.0]), np.array([-0.3, 9.0]), amp=0.5, delta=2.0, y0=0.2, z0=-0.3)
+    assert abs(U[0] - 0.5) < 1e-15 and abs(U[1] - 1.0) < 1e-15
+    assert abs(operators.gl_mu(np.array(10.0), 0.3, -0.01) - (0.3 - 0.04 - 0.5)) < 1e-15
+
+
 def test_wake_shear_is_the_derivative_of_the_wake():
     # U_y and U_z of the wake profile against central differences of its own U: second order in the step, so
     # halving the step cuts the error by 4.  A wrong sign, a dropped factor, delta instead of delta^2 or y0 and z0
