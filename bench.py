@@ -374,7 +374,7 @@ def bench_batched(args):
     """One block-power iteration of the batched workload (64 GL instances packed back to back, k = 2, 128
     frequencies, periodic method, mixed precision), with the FP64 form of the same iteration beside it.  The
     accuracy pass runs the workload's 20 iterations (mixed, mixed with the FP64 Rayleigh-Ritz finish, FP64) and
-    compares gains and modes at three sampled instances (smallest, middle, largest) and three frequencies with the
+    compares gains and modes at every eighth instance (eight, all four sizes) and three frequencies with the
     oracle's same iteration.  The CPU baseline times the oracle's march on one instance of each size."""
     import numpy as np
     import torch
@@ -393,8 +393,7 @@ def bench_batched(args):
     F = W.random_forcing(cfg["seed"], nw, k, ntot)
     sweeps_per_step = ntot * k * nw * 2 * steps_per_run
     iters = cfg["iters"] if args.accuracy_iters is None else args.accuracy_iters
-    sizes = [n for n, _, _ in inst]
-    picks = [int(np.argmin(sizes)), len(inst) // 2, int(np.argmax(sizes))]
+    picks = list(range(0, len(inst), 8))  # every eighth instance: all four sizes, the stiffest included
     js = [0, 64, 127]
     res, plans, powers, sampled = {}, {}, {}, {}
     V_mixed = None
@@ -612,7 +611,7 @@ def bench_grid(args):
     if autograd is not None:
         out["autograd"] = autograd
     elif three and not args.no_autograd:
-        out["autograd"] = grad3d_half(cfg)
+        out["autograd"] = grad3d(cfg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_grid(cfg, w0, dw, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -653,24 +652,23 @@ def cpu_baseline_grid(cfg, w0, dw, seconds):
                        % (steps, "x".join(map(str, shape)), N, cfg["k"], cfg["n_omega"], dt))
 
 
-def grad3d_half(cfg):
-    """Forward plus reverse mode of the 3-D workload's gradient pattern: one apply of the periodic method (all
-    periods, 96 frequencies, k = 3) and one apply_backward with forcing and mu gradients, checkpoints every 64
-    steps.  The reverse mode keeps FP64 rows (forcing, seed and gradient blocks, 64-step segments, checkpoints),
-    which at the full grid need more memory than one GPU holds, so this runs the same operator on the grid
-    halved in each direction (128 x 64 x 64, one eighth of the state)."""
+def grad3d(cfg):
+    """Forward plus reverse mode of the 3-D workload's gradient pattern on its full grid: one apply of the periodic
+    method (all periods, 96 frequencies, k = 3) and one apply_backward with forcing and mu gradients, checkpoints
+    every 64 steps, mixed precision (FP32 rows, FP64 arithmetic and accumulation; the mode runs the columns in
+    chunks when the rows of all three do not fit beside the inputs).  With g = u / |u| (dJ/du_hat of
+    J = sum |u_hat|) the duality <A^H g, f> = <g, A f> = J checks the forcing gradient at no extra cost."""
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2008_10904_amd.operators import snap_grid
 
-    half = dict(cfg, nx=cfg["nx"] // 2, ny=cfg["ny"] // 2, nz=cfg["nz"] // 2)
-    op = grid_op(half, cfg["precision"])
-    N = 3 * half["nx"] * half["ny"] * half["nz"]
+    op = grid_op(cfg, cfg["precision"])
+    N = 3 * cfg["nx"] * cfg["ny"] * cfg["nz"]
     nw, k = cfg["n_omega"], cfg["k"]
     w0, dw, P = snap_grid(cfg["wmin"], cfg["wmax"], nw, cfg["h"], cfg["stride"])
-    f = torch.from_numpy(W.random_forcing(cfg["seed"], nw, k, N, dtype=np.complex64)).cuda()
+    f = W.random_forcing_device(cfg["seed"], nw, k, N, torch.complex64, "cuda")
     grid = op.grid(w0, dw, nw)
     run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
     torch.cuda.synchronize()
@@ -678,11 +676,16 @@ def grad3d_half(cfg):
     u = op.apply(f, grid, run)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    J = float(u.abs().to(torch.float64).sum().item())
     g = (u / u.abs().clamp_min(1e-30)).contiguous()  # dJ/du_hat of J = sum |u_hat|
     del u
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t1b = time.perf_counter()
     fg, mg = op.apply_backward(f, g, grid, run, checkpoint_every=cfg["checkpoint_every"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    dual = complex(torch.vdot(fg.flatten().to(torch.complex128), f.flatten().to(torch.complex128)).item())
     ok = bool(torch.isfinite(fg).all().item()) and bool(np.isfinite(mg.cpu().numpy()).all())
     del fg, mg
     torch.cuda.synchronize()
@@ -690,11 +693,11 @@ def grad3d_half(cfg):
     op.apply_backward(f, g, grid, run, checkpoint_every=cfg["checkpoint_every"], want_mu=False)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
-    return {"grid": [half["nx"], half["ny"], half["nz"]], "n_omega": nw, "k": k, "P": P,
-            "time_steps": cfg["periods"] * P, "checkpoint_every": cfg["checkpoint_every"],
-            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_forcing_only_s": t4 - t3, "finite": ok,
-            "note": "one apply and one apply_backward (forcing and mu gradients), periodic method, on the grid "
-                    "halved in each direction"}
+    return {"grid": [cfg["nx"], cfg["ny"], cfg["nz"]], "n_omega": nw, "k": k, "P": P,
+            "time_steps": cfg["periods"] * P, "checkpoint_every": cfg["checkpoint_every"], "rows": "fp32",
+            "forward_s": t1 - t0, "backward_s": t2 - t1b, "backward_forcing_only_s": t4 - t3, "finite": ok,
+            "duality_rel": abs(dual - J) / J,
+            "note": "one apply and one apply_backward (forcing and mu gradients), periodic method, full grid"}
 
 
 def bench_krylov(args):
@@ -1051,6 +1054,10 @@ def main():
         "stepper_plan": list(plan64),
         "step_power": power,
     }
+    out["roofline"]["ns_per_rk4_step"] = avg_launch_s / steps_per_launch * 1e9
+    floor = latency_floor(cfg, power)
+    floor["headline_over_floor"] = out["roofline"]["ns_per_rk4_step"] / floor["ns_per_rk4_step"]
+    out["roofline"]["latency_floor"] = floor
     if weights is not None:
         out["config"]["weights"] = ("B: window over the upstream 60 %, C: window over the downstream 60 %, "
                                     "W_f = W_y = dx (gains of C R B in the W norms)")
@@ -1081,6 +1088,36 @@ def main():
         if sampled and weights is None:
             out["accuracy_vs_oracle"] = headline_accuracy(cfg, w0, dw, F, js, iters, sampled)
     print(json.dumps(out), flush=True)
+
+
+def latency_floor(cfg, step_power):
+    """The 1-D stepper's dependent-step latency without neighbour exchange: a column of 256 unknowns of the same GL
+    family (one workgroup per column: no halo, no exchange), k = 4, the same step power and precision (FP64),
+    marched through one forced period of P = 65,536 steps with 16 frequencies.  Returns ns per RK4 step of the
+    stepper launches (HIP events on the library's stream).  The headline march differs from it by the neighbour
+    exchange and the halo's redundant work, so the ratio of the two says how far the stepper is from its own
+    latency bound."""
+    import numpy as np
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd import _lib as L
+    from paper_2008_10904_amd.operators import gl_coefficients
+    n, P, nw = 256, 65536, 16
+    lo, d, up = gl_coefficients(n, cfg["mu0"], cfg["mu2"])
+    op = ResolventOp.tridiagonal(lo, d, up, cfg["h"], precision="fp64")
+    op.set_step_power(step_power)
+    grid = op.grid(-1.0, 2 * np.pi / (P * cfg["h"]), nw)
+    run = op.run("periodic", periods=1, stride=P // nw)
+    f = torch.ones((nw, cfg["k"], n), dtype=torch.complex128, device="cuda")
+    op.apply(f, grid, run)  # warm-up
+    torch.cuda.synchronize()
+    op.set_timing(True)
+    op.timing(L.RES_TIMING_STEPPER)
+    op.apply(f, grid, run)
+    ms, launches = op.timing(L.RES_TIMING_STEPPER)
+    op.set_timing(False)
+    return {"ns_per_rk4_step": ms * 1e6 / P, "unknowns": n, "k": cfg["k"], "step_power": step_power,
+            "note": "one workgroup per column, no neighbour exchange: the latency of the dependent step chain"}
 
 
 def headline_accuracy(cfg, w0, dw, F, js, iters, sampled):

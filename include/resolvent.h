@@ -196,15 +196,27 @@ int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolve
  * dJ/dRe + i dJ/dIm).  Outputs: f_grad (device, same layout as f_hat, same convention) if not NULL, and
  * mu_grad (device double, RES_OP_TRIDIAG: [n_total], ADR kinds: [nz*ny*nx]) = dJ/d(real part of the diagonal)
  * if not NULL.  Supported for RES_TRANSIENT and RES_PERIODIC runs.  checkpoint_every <= 0 picks about
- * sqrt(steps).  Memory (held by the handle, FP64 whatever the precision): the forcing, seed, pre-filtered forcing
- * and gradient blocks [n_omega][k][N] plus one Horner work block, ceil(steps / C) checkpoints and a few C-row
- * segments of [k][N] rows (C = checkpoint_every); the three stage rows of every step of a segment are kept when
- * they fit in half of the free device memory, else recomputed.  With mu_grad NULL only the adjoint recursion runs
- * (the forcing gradient does not depend on the forward trajectory): no forward march, checkpoints or recomputation.
- * An allocation that fails returns RES_ENOMEM. */
+ * sqrt(steps).  Arithmetic is FP64 and both gradients accumulate in FP64; the rows the mode stores (states,
+ * checkpoints, stage values, adjoint states, synthesised forcing and seed rows) are FP64 for RES_FP64 operators and
+ * FP32 for RES_MIXED ones (FP64 with resolvent_op_set_backward_rows(op, 1)).  Memory (held by the handle): the
+ * seed, pre-filtered forcing and (mixed operators, or chunked columns) forcing blocks [n_omega][kc][N] in the row
+ * precision, the FP64 gradient accumulator [n_omega][kc][N], Horner work blocks within
+ * RESOLVENT_HORNER_BUDGET_GB, ceil(steps / C) checkpoints and a few C-row segments of [kc][N] rows
+ * (C = checkpoint_every).  The columns evolve independently, so when the rows of all k columns do not fit the
+ * mode frees the handle's forward workspace and then runs the columns in chunks of kc < k (the mu gradient sums
+ * over the chunks; RESOLVENT_BACKWARD_COLUMNS = kc forces a chunk size).  The three stage rows of every step of a
+ * segment are kept when they fit in half of the free device memory, else recomputed.  With mu_grad NULL only the
+ * adjoint recursion runs (the forcing gradient does not depend on the forward trajectory): no forward march,
+ * checkpoints or recomputation.  An allocation that fails returns RES_ENOMEM. */
 int resolvent_apply_backward(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                              const void* f_hat, const void* g_hat, void* f_grad, double* mu_grad,
                              int32_t checkpoint_every, void* stream);
+
+/* Row precision of resolvent_apply_backward for a RES_MIXED operator: fp64 != 0 keeps its rows in FP64 (twice the
+ * memory and traffic; gradients then agree with the FP64 operator's to the rounding of the forward run's
+ * coefficients), 0 (the default) in FP32.  No effect on RES_FP64 operators.  Reverse-mode differentiation is an
+ * extension of the paper's method (it differentiates the time-stepped run of Sec. 2.3). */
+int resolvent_op_set_backward_rows(resolvent_op* op, int32_t fp64);
 
 /* HIP graphs.  resolvent_apply, resolvent_adjoint_apply and resolvent_apply_backward may be recorded into a
  * caller's graph (stream capture) once an uncaptured call with the same sizes has sized the handle's workspace:

@@ -53,6 +53,7 @@ SIGNATURES = {
                                            c_void_p, _dp, c_int32, c_void_p]),
     "resolvent_op_check": (c_int32, [c_void_p, c_void_p]),
     "resolvent_op_set_graphs": (c_int32, [c_void_p, c_int32]),
+    "resolvent_op_set_backward_rows": (c_int32, [c_void_p, c_int32]),
     "resolvent_op_get_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_plan": (c_int32, [c_void_p, POINTER(c_int32)]),
     "resolvent_op_set_step_power": (c_int32, [c_void_p, c_int32]),

@@ -265,6 +265,11 @@ class ResolventOp:
         """resolvent_modes replays its middle iterations from one captured HIP graph."""
         check(self._lib.resolvent_op_set_graphs(self._h, 1 if enable else 0))
 
+    def set_backward_rows(self, fp64=True):
+        """Row precision of apply_backward for a mixed-precision operator: FP64 rows (fp64=True) or FP32 rows (the
+        default); the arithmetic and the gradient accumulation are FP64 either way."""
+        check(self._lib.resolvent_op_set_backward_rows(self._h, 1 if fp64 else 0))
+
     # ---- stepper plan and autotuner (1-D operators) ------------------------------------------------------------
     def get_plan(self):
         """(configuration, owned unknowns per workgroup, steps between exchanges, persistent) in effect."""

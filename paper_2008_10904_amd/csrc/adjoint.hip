@@ -1,4 +1,7 @@
-// Discrete adjoint of the RK4 march (reverse-mode differentiation of a time-stepped run), FP64.
+// Discrete adjoint of the RK4 march (reverse-mode differentiation of a time-stepped run).  The arithmetic and the
+// reaction-field gradient are FP64; the rows (states, stage values, lambda, forcing and seed rows) are stored as T:
+// FP64, or FP32 for mixed-precision operators (half the memory and traffic; every value is rounded to FP32 when
+// it is stored, as in the forward march).
 //
 // With Z = h L, K_i = Z y_i + h f_i and the classical stages y_1 = u, y_2 = u + K_1/2, y_3 = u + K_2/2,
 // y_4 = u + K_3, u' = u + (K_1 + 2 K_2 + 2 K_3 + K_4)/6, the gradient lambda' = dJ/du' (convention dJ/dRe + i dJ/dIm)
@@ -21,14 +24,14 @@
 namespace res {
 
 // (Z x)[site] for column base x.  KIND 0: three-point complex operator (tri = [N][3]); KIND 1: structured grid.
-template <int KIND, int NC>
-__device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __restrict__ x, int64_t p,
+template <int KIND, int NC, typename T>
+__device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<T>* __restrict__ x, int64_t p,
                                       cx<double> out[NC]) {
   if (KIND == 0) {
     const cx<double>* tri = (const cx<double>*)op.tri;
-    cx<double> acc = cmul(tri[3 * p + 1], x[p]);
-    if (p > 0) acc = cfma(tri[3 * p], x[p - 1], acc);
-    if (p + 1 < op.nsite) acc = cfma(tri[3 * p + 2], x[p + 1], acc);
+    cx<double> acc = cmul(tri[3 * p + 1], ccast<double>(x[p]));
+    if (p > 0) acc = cfma(tri[3 * p], ccast<double>(x[p - 1]), acc);
+    if (p + 1 < op.nsite) acc = cfma(tri[3 * p + 2], ccast<double>(x[p + 1]), acc);
     out[0] = acc;
   } else {
     GridCoef<double> c;
@@ -37,7 +40,7 @@ __device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __re
     c.d = (const double*)op.g.d; c.K = (const double*)op.g.K;
     const int64_t nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
     const int64_t ix = p % nx, l = p / nx, iy = l % ny, iz = l / ny;
-    apply_z<double, NC>(c, x, op.nsite, nx, ny, nz, ix, iy, iz, p, l, out);
+    apply_z<double, NC, T>(c, x, op.nsite, nx, ny, nz, ix, iy, iz, p, l, out);
   }
 }
 
@@ -47,42 +50,44 @@ __device__ __forceinline__ void zsite(const AdjOpDev& op, const cx<double>* __re
 // (yin = y_4), so only stages 2 and 4 touch acc (four fewer rows moved per step).  acc may be null when only the
 // stage values are wanted (m < 4); f null means no forcing.  gadd (m = 4, null: none) is added to uout: with f null
 // at every stage the step is u' = P(Z) u + gadd, the march with pre-filtered forcing rows.
-template <int KIND, int NC>
-__global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int m, const cx<double>* u,
-                                                        cx<double>* uout, const cx<double>* __restrict__ yin,
-                                                        cx<double>* yout,
-                                                        cx<double>* acc, const cx<double>* __restrict__ f, double h,
-                                                        const cx<double>* __restrict__ gadd) {
+template <int KIND, int NC, typename T>
+__global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int m, const cx<T>* u,
+                                                        cx<T>* uout, const cx<T>* __restrict__ yin,
+                                                        cx<T>* yout,
+                                                        cx<T>* acc, const cx<T>* __restrict__ f, double h,
+                                                        const cx<T>* __restrict__ gadd) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= op.nsite) return;
   const int64_t blk = (int64_t)NC * op.nsite;
   for (int b = blockIdx.y; b < k; b += gridDim.y) {  // one column per grid row
     cx<double> z[NC];
-    zsite<KIND, NC>(op, yin + b * blk, p, z);
+    zsite<KIND, NC, T>(op, yin + b * blk, p, z);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t e = b * blk + c * op.nsite + p;
       cx<double> K = z[c];
       if (f != nullptr) {
-        K.re += h * f[e].re;
-        K.im += h * f[e].im;
+        const cx<double> fv = ccast<double>(f[e]);
+        K.re += h * fv.re;
+        K.im += h * fv.im;
       }
-      const cx<double> uu = u[e];
+      const cx<double> uu = ccast<double>(u[e]);
       if (m == 4) {
-        const cx<double> a = acc[e], y4 = yin[e];
+        const cx<double> a = ccast<double>(acc[e]), y4 = ccast<double>(yin[e]);
         const double k3r = y4.re - uu.re, k3i = y4.im - uu.im;
         cx<double> un = mk<double>(uu.re + (a.re + 2.0 * k3r + K.re) / 6.0, uu.im + (a.im + 2.0 * k3i + K.im) / 6.0);
         if (gadd != nullptr) {
-          un.re += gadd[e].re;
-          un.im += gadd[e].im;
+          const cx<double> g = ccast<double>(gadd[e]);
+          un.re += g.re;
+          un.im += g.im;
         }
-        uout[e] = un;
+        uout[e] = ccast<T>(un);
       } else {
         const double w = m == 3 ? 1.0 : 0.5;
-        yout[e] = mk<double>(uu.re + w * K.re, uu.im + w * K.im);
+        yout[e] = ccast<T>(mk<double>(uu.re + w * K.re, uu.im + w * K.im));
         if (acc != nullptr && m == 2) {
-          const cx<double> y2 = yin[e];
-          acc[e] = mk<double>(2.0 * (y2.re - uu.re) + 2.0 * K.re, 2.0 * (y2.im - uu.im) + 2.0 * K.im);
+          const cx<double> y2 = ccast<double>(yin[e]);
+          acc[e] = ccast<T>(mk<double>(2.0 * (y2.re - uu.re) + 2.0 * K.re, 2.0 * (y2.im - uu.im) + 2.0 * K.im));
         }
       }
     }
@@ -95,48 +100,49 @@ __global__ __launch_bounds__(256) void fwd_stage_kernel(AdjOpDev op, int k, int 
 // kept: with yb_4 = Kb_3 - lambda'/3, yb_3 = 2 Kb_2 - 2 lambda'/3 and yb_2 = 2 Kb_1 - lambda'/3, stage 1 forms
 // lambda = -lambda'/3 + Kb_3 + 2 Kb_2 + 2 Kb_1 + yb_1 (+ inj, null: none) from k3 = Kb_3 and k2 = Kb_2 into
 // lam_out (which must not alias lam, kin, k3 or k2).
-template <int KIND, int NC>
+template <int KIND, int NC, typename T>
 __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int m,
-                                                        const cx<double>* __restrict__ lam,
-                                                        cx<double>* __restrict__ lam_out,
-                                                        const cx<double>* __restrict__ kin,
-                                                        const cx<double>* __restrict__ y, cx<double>* kout,
-                                                        const cx<double>* __restrict__ k3,
-                                                        const cx<double>* __restrict__ k2, double* __restrict__ mu,
-                                                        const cx<double>* __restrict__ inj, double h) {
+                                                        const cx<T>* __restrict__ lam,
+                                                        cx<T>* __restrict__ lam_out,
+                                                        const cx<T>* __restrict__ kin,
+                                                        const cx<T>* __restrict__ y, cx<T>* kout,
+                                                        const cx<T>* __restrict__ k3,
+                                                        const cx<T>* __restrict__ k2, double* __restrict__ mu,
+                                                        const cx<T>* __restrict__ inj, double h) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= opH.nsite) return;
   const int64_t blk = (int64_t)NC * opH.nsite;
   double musum = 0.0;
   for (int b = blockIdx.y; b < k; b += gridDim.y) {  // one column per grid row
     cx<double> z[NC];
-    zsite<KIND, NC>(opH, (m == 4 ? lam : kin) + b * blk, p, z);
+    zsite<KIND, NC, T>(opH, (m == 4 ? lam : kin) + b * blk, p, z);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t e = b * blk + c * opH.nsite + p;
-      const cx<double> lp = lam[e];
+      const cx<double> lp = ccast<double>(lam[e]);
       cx<double> kb;  // Kb_m at this point
       if (m == 4) {
         kb = mk<double>(lp.re / 6.0, lp.im / 6.0);
-        kout[e] = mk<double>(lp.re / 3.0 + z[c].re / 6.0, lp.im / 3.0 + z[c].im / 6.0);  // Z^H (lambda'/6)
+        kout[e] = ccast<T>(mk<double>(lp.re / 3.0 + z[c].re / 6.0, lp.im / 3.0 + z[c].im / 6.0));  // Z^H (lambda'/6)
       } else {
-        kb = kin[e];
+        kb = ccast<double>(kin[e]);
         if (m == 1) {
-          const cx<double> a3 = k3[e], a2 = k2[e];
+          const cx<double> a3 = ccast<double>(k3[e]), a2 = ccast<double>(k2[e]);
           cx<double> l = mk<double>(a3.re + 2.0 * (a2.re + kb.re) - lp.re / 3.0 + z[c].re,
                                     a3.im + 2.0 * (a2.im + kb.im) - lp.im / 3.0 + z[c].im);
           if (inj != nullptr) {
-            l.re += inj[e].re;
-            l.im += inj[e].im;
+            const cx<double> q = ccast<double>(inj[e]);
+            l.re += q.re;
+            l.im += q.im;
           }
-          lam_out[e] = l;
+          lam_out[e] = ccast<T>(l);
         } else {
           const double w = m == 3 ? 1.0 / 3.0 : 1.0 / 6.0;
-          kout[e] = mk<double>(w * lp.re + 0.5 * z[c].re, w * lp.im + 0.5 * z[c].im);
+          kout[e] = ccast<T>(mk<double>(w * lp.re + 0.5 * z[c].re, w * lp.im + 0.5 * z[c].im));
         }
       }
       if (mu != nullptr) {
-        const cx<double> yy = y[e];
+        const cx<double> yy = ccast<double>(y[e]);
         musum += kb.re * yy.re + kb.im * yy.im;  // Re(conj(kb) y)
       }
     }
@@ -146,15 +152,19 @@ __global__ __launch_bounds__(256) void rev_stage_kernel(AdjOpDev opH, int k, int
 
 // ---------------------------------------------------------------------------------------------------------
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
-                     void* acc, const void* f, double h, hipStream_t st, const void* gadd) {
+                     void* acc, const void* f, double h, hipStream_t st, const void* gadd, int rows64) {
   const dim3 grid((unsigned)((op.nsite + 255) / 256), (unsigned)std::min(k, 65535));
-#define RES_F(KIND, NC)                                                                                          \
-  hipLaunchKernelGGL((fwd_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, op, k, m, (const cx<double>*)u,      \
-                     (cx<double>*)uout, (const cx<double>*)yin, (cx<double>*)yout, (cx<double>*)acc,                \
-                     (const cx<double>*)f, h, (const cx<double>*)gadd)
-  if (op.kind == 0) RES_F(0, 1);
-  else if (op.ncomp == 3) RES_F(1, 3);
-  else RES_F(1, 1);
+#define RES_F(KIND, NC, T)                                                                                       \
+  hipLaunchKernelGGL((fwd_stage_kernel<KIND, NC, T>), grid, dim3(256), 0, st, op, k, m, (const cx<T>*)u,        \
+                     (cx<T>*)uout, (const cx<T>*)yin, (cx<T>*)yout, (cx<T>*)acc, (const cx<T>*)f, h,             \
+                     (const cx<T>*)gadd)
+#define RES_F2(T)                      \
+  if (op.kind == 0) RES_F(0, 1, T);    \
+  else if (op.ncomp == 3) RES_F(1, 3, T); \
+  else RES_F(1, 1, T)
+  if (rows64) { RES_F2(double); }
+  else { RES_F2(float); }
+#undef RES_F2
 #undef RES_F
   return 0;
 }
@@ -191,13 +201,14 @@ __device__ __forceinline__ void ring_site(int m, int i, int* py, int* px) {
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny,
-                                                          const cx<double>* __restrict__ u, cx<double>* uout,
-                                                          cx<double>* y2o, cx<double>* y3o, cx<double>* y4o,
-                                                          const cx<double>* __restrict__ fa,
-                                                          const cx<double>* __restrict__ fb,
-                                                          const cx<double>* __restrict__ fc, double h,
-                                                          const cx<double>* __restrict__ gadd) {
+                                                          const cx<T>* __restrict__ u, cx<T>* uout,
+                                                          cx<T>* y2o, cx<T>* y3o, cx<T>* y4o,
+                                                          const cx<T>* __restrict__ fa,
+                                                          const cx<T>* __restrict__ fb,
+                                                          const cx<T>* __restrict__ fc, double h,
+                                                          const cx<T>* __restrict__ gadd) {
   __shared__ cx<double> U[kFsPY][kFsPX], Y[kFsPY][kFsPX];
   const int64_t nodes = nx * ny;
   const int64_t col = blockIdx.z;
@@ -206,7 +217,8 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
   for (int i = threadIdx.x; i < kFsPX * kFsPY; i += blockDim.x) {
     const int py = i / kFsPX, px = i - py * kFsPX;
     const int64_t gx = gx0 + px, gy = gy0 + py;
-    const cx<double> v = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? u[col * nodes + gy * nx + gx] : zero;
+    const cx<double> v =
+        (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? ccast<double>(u[col * nodes + gy * nx + gx]) : zero;
     U[py][px] = v;
     Y[py][px] = v;
   }
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
   const int tpy = kFsH + t / kFsTX, tpx = kFsH + t % kFsTX;  // the thread's tile site
   cx<double> acc = zero;
   // K = Z x + h f at padded site (py, px) of the LDS buffer x (apply_z order: diagonal, x-, x+, y-, y+)
-  auto stage_k = [&](cx<double>(*X)[kFsPX], const cx<double>* f, int py, int px, int64_t gx, int64_t gy) {
+  auto stage_k = [&](cx<double>(*X)[kFsPX], const cx<T>* f, int py, int px, int64_t gx, int64_t gy) {
     const int64_t p = gy * nx + gx;
     const double dd = Cf.d[p], cxm = Cf.cxm[gy], cxp = Cf.cxp[gy], cym = Cf.cym[gy], cyp = Cf.cyp[gy];
     const cx<double> sv = X[py][px];
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
     if (gy > 0) { const cx<double> q = X[py - 1][px]; K.re += cym * q.re; K.im += cym * q.im; }
     if (gy + 1 < ny) { const cx<double> q = X[py + 1][px]; K.re += cyp * q.re; K.im += cyp * q.im; }
     if (f != nullptr) {
-      const cx<double> fv = f[col * nodes + p];
+      const cx<double> fv = ccast<double>(f[col * nodes + p]);
       K.re += h * fv.re;
       K.im += h * fv.im;
     }
@@ -233,8 +245,8 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
   };
   const int mlast = uout != nullptr ? 4 : 3;
   for (int m = 1; m <= mlast; ++m) {
-    const cx<double>* f = m == 1 ? fa : (m == 4 ? fc : fb);
-    cx<double>* go = m == 1 ? y2o : (m == 2 ? y3o : (m == 3 ? y4o : uout));
+    const cx<T>* f = m == 1 ? fa : (m == 4 ? fc : fb);
+    cx<T>* go = m == 1 ? y2o : (m == 2 ? y3o : (m == 3 ? y4o : uout));
     const double w = m == 3 ? 1.0 : 0.5;
     // the tile site
     const int64_t gx = gx0 + tpx, gy = gy0 + tpy;
@@ -249,7 +261,7 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
       } else {
         tv = mk<double>(uu.re + (acc.re + K.re) / 6.0, uu.im + (acc.im + K.im) / 6.0);
         if (gadd != nullptr) {
-          const cx<double> g = gadd[col * nodes + gy * nx + gx];
+          const cx<double> g = ccast<double>(gadd[col * nodes + gy * nx + gx]);
           tv.re += g.re;
           tv.im += g.im;
         }
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
       Y[tpy][tpx] = tv;
       if (has_ring) Y[rpy][rpx] = rv;
     }
-    if (tin && go != nullptr) go[col * nodes + gy * nx + gx] = tv;
+    if (tin && go != nullptr) go[col * nodes + gy * nx + gx] = ccast<T>(tv);
     __syncthreads();
   }
 }
@@ -287,13 +299,14 @@ __global__ __launch_bounds__(1024) void fwd_step2d_kernel(GridCoef<double> Cf, i
 // the mu contributions h Re(conj(Kb_m) y_m) stay in registers on the tile.  One workgroup per tile and column; a
 // node's mu contributions of the step are summed over the stages and added to the column's own partial row
 // mu_cols[column][node] (summed over the columns once at the end, without atomics).  lam_out must not alias lam.
+template <typename T>
 __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, int64_t nx, int64_t ny,
-                                                          const cx<double>* __restrict__ lam, cx<double>* lam_out,
-                                                          const cx<double>* __restrict__ y2,
-                                                          const cx<double>* __restrict__ y3,
-                                                          const cx<double>* __restrict__ y4,
-                                                          const cx<double>* __restrict__ u, double* mu_cols,
-                                                          const cx<double>* __restrict__ inj, double h) {
+                                                          const cx<T>* __restrict__ lam, cx<T>* lam_out,
+                                                          const cx<T>* __restrict__ y2,
+                                                          const cx<T>* __restrict__ y3,
+                                                          const cx<T>* __restrict__ y4,
+                                                          const cx<T>* __restrict__ u, double* mu_cols,
+                                                          const cx<T>* __restrict__ inj, double h) {
   __shared__ cx<double> L[kFsPY][kFsPX], KB[kFsPY][kFsPX];
   double* mu = mu_cols != nullptr ? mu_cols + (int64_t)blockIdx.z * nx * ny : nullptr;
   const int64_t nodes = nx * ny;
@@ -328,14 +341,14 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
     for (int i = t; i < kFsPX * kFsPY; i += blockDim.x) {
       const int py = i / kFsPX, px = i - py * kFsPX;
       const int64_t gx = gx0 + px, gy = gy0 + py;
-      L[py][px] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? lam[cb + gy * nx + gx] : zero;
+      L[py][px] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? ccast<double>(lam[cb + gy * nx + gx]) : zero;
     }
     __syncthreads();
     cx<double> ub = zero;
     for (int s = 1; s <= 4; ++s) {
       cx<double>(*X)[kFsPX] = s == 1 ? L : KB;
       const double xs = s == 1 ? 1.0 / 6.0 : 1.0;  // Kb_4 = lambda'/6
-      const cx<double>* ys = s == 1 ? y4 : (s == 2 ? y3 : (s == 3 ? y2 : u));
+      const cx<T>* ys = s == 1 ? y4 : (s == 2 ? y3 : (s == 3 ? y2 : u));
       cx<double> tv = zero;
       if (tin) {
         const cx<double> lp = L[tpy][tpx];
@@ -344,7 +357,7 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
         const cx<double> kx = X[tpy][tpx];
         const cx<double> kb = mk<double>(xs * kx.re, xs * kx.im);  // Kb_m at the tile site
         if (mu != nullptr) {
-          const cx<double> yy = ys[cb + tp];
+          const cx<double> yy = ccast<double>(ys[cb + tp]);
           musum += kb.re * yy.re + kb.im * yy.im;
         }
         if (s == 1) ub = mk<double>(lp.re + z.re, lp.im + z.im);
@@ -372,10 +385,11 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
       } else if (tin) {
         cx<double> l = tv;
         if (inj != nullptr) {
-          l.re += inj[cb + tp].re;
-          l.im += inj[cb + tp].im;
+          const cx<double> q = ccast<double>(inj[cb + tp]);
+          l.re += q.re;
+          l.im += q.im;
         }
-        lam_out[cb + tp] = l;
+        lam_out[cb + tp] = ccast<T>(l);
       }
       __syncthreads();
     }
@@ -384,7 +398,8 @@ __global__ __launch_bounds__(1024) void rev_step2d_kernel(GridCoef<double> Cf, i
 }
 
 int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
-                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st) {
+                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st,
+                      int rows64) {
   if (opH.kind != 1 || opH.ncomp != 1 || opH.g.nz != 1 || k < 1 || k > 65535 || lam_out == lam) return -1;
   GridCoef<double> c;
   c.cxm = (const double*)opH.g.cxm; c.cxp = (const double*)opH.g.cxp; c.cym = (const double*)opH.g.cym;
@@ -392,9 +407,13 @@ int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out
   c.d = (const double*)opH.g.d; c.K = (const double*)opH.g.K;
   const dim3 grid((unsigned)((opH.g.nx + kFsTX - 1) / kFsTX), (unsigned)((opH.g.ny + kFsTY - 1) / kFsTY),
                   (unsigned)k);
-  hipLaunchKernelGGL(rev_step2d_kernel, grid, dim3(1024), 0, st, c, opH.g.nx, opH.g.ny, (const cx<double>*)lam,
-                     (cx<double>*)lam_out, (const cx<double>*)y2, (const cx<double>*)y3, (const cx<double>*)y4,
-                     (const cx<double>*)u, mu_cols, (const cx<double>*)inj, h);
+#define RES_RS(T)                                                                                                \
+  hipLaunchKernelGGL(rev_step2d_kernel<T>, grid, dim3(1024), 0, st, c, opH.g.nx, opH.g.ny, (const cx<T>*)lam,     \
+                     (cx<T>*)lam_out, (const cx<T>*)y2, (const cx<T>*)y3, (const cx<T>*)y4, (const cx<T>*)u,      \
+                     mu_cols, (const cx<T>*)inj, h)
+  if (rows64) RES_RS(double);
+  else RES_RS(float);
+#undef RES_RS
   return 0;
 }
 
@@ -417,7 +436,8 @@ int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStre
 }
 
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
-                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st, const void* gadd) {
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st, const void* gadd,
+                      int rows64) {
   if (op.kind != 1 || op.ncomp != 1 || op.g.nz != 1 || k < 1 || k > 65535 || (uout != nullptr && uout == u))
     return -1;
   GridCoef<double> c;
@@ -425,9 +445,13 @@ int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void
   c.cyp = (const double*)op.g.cyp; c.czm = (const double*)op.g.czm; c.czp = (const double*)op.g.czp;
   c.d = (const double*)op.g.d; c.K = (const double*)op.g.K;
   const dim3 grid((unsigned)((op.g.nx + kFsTX - 1) / kFsTX), (unsigned)((op.g.ny + kFsTY - 1) / kFsTY), (unsigned)k);
-  hipLaunchKernelGGL(fwd_step2d_kernel, grid, dim3(1024), 0, st, c, op.g.nx, op.g.ny, (const cx<double>*)u,
-                     (cx<double>*)uout, (cx<double>*)y2, (cx<double>*)y3, (cx<double>*)y4, (const cx<double>*)fa,
-                     (const cx<double>*)fb, (const cx<double>*)fc, h, (const cx<double>*)gadd);
+#define RES_FS(T)                                                                                                \
+  hipLaunchKernelGGL(fwd_step2d_kernel<T>, grid, dim3(1024), 0, st, c, op.g.nx, op.g.ny, (const cx<T>*)u,         \
+                     (cx<T>*)uout, (cx<T>*)y2, (cx<T>*)y3, (cx<T>*)y4, (const cx<T>*)fa, (const cx<T>*)fb,          \
+                     (const cx<T>*)fc, h, (const cx<T>*)gadd)
+  if (rows64) RES_FS(double);
+  else RES_FS(float);
+#undef RES_FS
   return 0;
 }
 
@@ -435,15 +459,19 @@ int rev_stage_rows(int k) { return std::min(k, 65535); }
 
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
-                     hipStream_t st) {
+                     hipStream_t st, int rows64) {
   const dim3 grid((unsigned)((opH.nsite + 255) / 256), (unsigned)rev_stage_rows(k));
-#define RES_R(KIND, NC)                                                                                            \
-  hipLaunchKernelGGL((rev_stage_kernel<KIND, NC>), grid, dim3(256), 0, st, opH, k, m,                          \
-                     (const cx<double>*)lam, (cx<double>*)lam_out, (const cx<double>*)kin, (const cx<double>*)y,     \
-                     (cx<double>*)kout, (const cx<double>*)k3, (const cx<double>*)k2, mu, (const cx<double>*)inj, h)
-  if (opH.kind == 0) RES_R(0, 1);
-  else if (opH.ncomp == 3) RES_R(1, 3);
-  else RES_R(1, 1);
+#define RES_R(KIND, NC, T)                                                                                         \
+  hipLaunchKernelGGL((rev_stage_kernel<KIND, NC, T>), grid, dim3(256), 0, st, opH, k, m, (const cx<T>*)lam,     \
+                     (cx<T>*)lam_out, (const cx<T>*)kin, (const cx<T>*)y, (cx<T>*)kout, (const cx<T>*)k3,         \
+                     (const cx<T>*)k2, mu, (const cx<T>*)inj, h)
+#define RES_R2(T)                      \
+  if (opH.kind == 0) RES_R(0, 1, T);   \
+  else if (opH.ncomp == 3) RES_R(1, 3, T); \
+  else RES_R(1, 1, T)
+  if (rows64) { RES_R2(double); }
+  else { RES_R2(float); }
+#undef RES_R2
 #undef RES_R
   return 0;
 }

@@ -11,9 +11,10 @@ template <typename R> struct GridCoef {
   const R* K;  // [lines][3][3] or null
 };
 
-// (Z x)_c at node p of column block b; x laid out [block][ncomp][nodes].
-template <typename R, int NC>
-__device__ __forceinline__ void apply_z(const GridCoef<R>& Cf, const cx<R>* __restrict__ x, int64_t nodes, int64_t nx,
+// (Z x)_c at node p of column block b; x laid out [block][ncomp][nodes], stored as X and converted to R (the
+// coefficient and arithmetic type).
+template <typename R, int NC, typename X = R>
+__device__ __forceinline__ void apply_z(const GridCoef<R>& Cf, const cx<X>* __restrict__ x, int64_t nodes, int64_t nx,
                                         int64_t ny, int64_t nz, int64_t ix, int64_t iy, int64_t iz, int64_t p, int64_t l,
                                         cx<R> out[NC]) {
   const R cxm = Cf.cxm[l], cxp = Cf.cxp[l], cym = Cf.cym[l], cyp = Cf.cyp[l];
@@ -23,16 +24,16 @@ __device__ __forceinline__ void apply_z(const GridCoef<R>& Cf, const cx<R>* __re
   cx<R> self[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const cx<R>* xc = x + c * nodes + p;
-    cx<R> s = xc[0];
+    const cx<X>* xc = x + c * nodes + p;
+    cx<R> s = ccast<R>(xc[0]);
     self[c] = s;
     cx<R> acc = mk<R>(dd * s.re, dd * s.im);
-    if (ix > 0) { const cx<R> t = xc[-1]; acc.re += cxm * t.re; acc.im += cxm * t.im; }
-    if (ix + 1 < nx) { const cx<R> t = xc[1]; acc.re += cxp * t.re; acc.im += cxp * t.im; }
-    if (iy > 0) { const cx<R> t = xc[-sy]; acc.re += cym * t.re; acc.im += cym * t.im; }
-    if (iy + 1 < ny) { const cx<R> t = xc[sy]; acc.re += cyp * t.re; acc.im += cyp * t.im; }
-    if (iz > 0) { const cx<R> t = xc[-sz]; acc.re += czm * t.re; acc.im += czm * t.im; }
-    if (iz + 1 < nz) { const cx<R> t = xc[sz]; acc.re += czp * t.re; acc.im += czp * t.im; }
+    if (ix > 0) { const cx<R> t = ccast<R>(xc[-1]); acc.re += cxm * t.re; acc.im += cxm * t.im; }
+    if (ix + 1 < nx) { const cx<R> t = ccast<R>(xc[1]); acc.re += cxp * t.re; acc.im += cxp * t.im; }
+    if (iy > 0) { const cx<R> t = ccast<R>(xc[-sy]); acc.re += cym * t.re; acc.im += cym * t.im; }
+    if (iy + 1 < ny) { const cx<R> t = ccast<R>(xc[sy]); acc.re += cyp * t.re; acc.im += cyp * t.im; }
+    if (iz > 0) { const cx<R> t = ccast<R>(xc[-sz]); acc.re += czm * t.re; acc.im += czm * t.im; }
+    if (iz + 1 < nz) { const cx<R> t = ccast<R>(xc[sz]); acc.re += czp * t.re; acc.im += czp * t.im; }
     out[c] = acc;
   }
   if (NC == 3 && Cf.K != nullptr) {

@@ -83,9 +83,10 @@ int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* 
                        int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st,
                        int j0 = 0);
 
-// ---- discrete adjoint (reverse-mode) stage kernels, FP64 -----------------------------------------------
+// ---- discrete adjoint (reverse-mode) stage kernels ------------------------------------------------------
 // kind 0: three-point complex operator, tri = [nsite][3] (lower, diag, upper) of Z (or Z^H); kind 1: grid
 // operator g (FP64 coefficients), nsite = nodes, ncomp components per node.  Columns are [k][ncomp][nsite].
+// FP64 arithmetic and mu accumulation; the rows are complex FP64 if rows64, else complex FP32.
 struct AdjOpDev {
   int kind;
   int ncomp;
@@ -94,25 +95,26 @@ struct AdjOpDev {
   GridOpDev g;
 };
 int launch_fwd_stage(const AdjOpDev& op, int k, int m, const void* u, void* uout, const void* yin, void* yout,
-                     void* acc, const void* f, double h, hipStream_t st, const void* gadd = nullptr);
+                     void* acc, const void* f, double h, hipStream_t st, const void* gadd, int rows64);
 // The four forward stages of one step in one launch for a 2-D one-component grid operator (stage inputs y2, y3, y4
 // and uout may each be null; uout must not alias u).  gadd (null: none) is added to uout: with fa = fb = fc = null
 // the step is u' = P(Z) u + gadd, the march with pre-filtered forcing rows.  Returns -1 for other operators.
 int launch_fwd_step2d(const AdjOpDev& op, int k, const void* u, void* uout, void* y2, void* y3, void* y4,
-                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st,
-                      const void* gadd = nullptr);
+                      const void* fa, const void* fb, const void* fc, double h, hipStream_t st, const void* gadd,
+                      int rows64);
 // The four reverse stages of one step in one launch for a 2-D one-component grid operator (one workgroup per tile
 // and column; the mu contributions go to the per-column rows mu_cols [k][nodes]; lam_out must not alias lam).
 // Returns -1 for other operators.
 int launch_rev_step2d(const AdjOpDev& opH, int k, const void* lam, void* lam_out, const void* y2, const void* y3,
-                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st);
+                      const void* y4, const void* u, double* mu_cols, const void* inj, double h, hipStream_t st,
+                      int rows64);
 // mu[p] += sum over the k rows of cols [k][n].
 int launch_sum_columns(const double* cols, int k, int64_t n, double* mu, hipStream_t st);
 // Grid rows (and mu rows) of the reverse stage launches for k columns.
 int rev_stage_rows(int k);
 int launch_rev_stage(const AdjOpDev& opH, int k, int m, const void* lam, void* lam_out, const void* kin,
                      const void* y, void* kout, const void* k3, const void* k2, double* mu, const void* inj, double h,
-                     hipStream_t st);
+                     hipStream_t st, int rows64);
 
 // ---- block Arnoldi (krylov.hip) ---------------------------------------------------------------------------
 int launch_xgram(const void* basis, int64_t bstride, int nb, const void* W, int64_t N, int k, const int64_t* off,

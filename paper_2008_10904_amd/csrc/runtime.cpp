@@ -154,6 +154,7 @@ struct resolvent_op {
   // diagonal B, C and metrics W_f, W_y (resolvent_op_set_weights): rows of d_wsc, each [N] FP64
   bool weighted = false;
   void* d_wsc = nullptr;
+  bool rev_rows64 = false;               // reverse mode of a mixed-precision operator keeps FP64 rows
   int scale_role = 0;                    // 0: apply/adjoint_apply (y = C R B f), 1: gains and modes (Euclidean R~)
   // host sources of the TRM driver's asynchronous uploads, kept in the handle so that they outlive the copies
   std::vector<double> trm_om, trm_D;
@@ -919,9 +920,9 @@ int run_power(const resolvent_op* op, const Plan& pl) {
 // sum_{r<M} e^{i sigma w_j r h} P^(M-1-r) G_j, by M - 1 Horner passes of P(Z)), written in the working precision.
 // Each frequency's pre-filter is independent, so the FP64 work blocks hold a group of frequencies at a time, as
 // many as fit in RESOLVENT_HORNER_BUDGET_GB (default 8 GiB): the 3-D workload's [96][3][12.6M] blocks would take
-// 58 GB each.
+// 58 GB each.  G is written in FP64 if out_fp64 > 0, FP32 if out_fp64 == 0, the working precision if it is < 0.
 int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64, void* G, int sigma, int M,
-              hipStream_t st) {
+              hipStream_t st, int out_fp64 = -1) {
   const int64_t N = op->N;
   const int64_t ncols = (int64_t)k * N;
   const int nw = pl.nw;
@@ -937,16 +938,17 @@ int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp
   if (M > 2) RES_TRY(ws_get(op, "horner_c", (size_t)chunk * ncols * sizeof(cd), &y3));
   const double sw0h = sigma * pl.w0 * op->h, sdwh = sigma * pl.dw * op->h;
   const size_t in_es = in_fp64 ? sizeof(cd) : sizeof(std::complex<float>);
+  const int o64 = out_fp64 < 0 ? op->fp64() : (out_fp64 > 0 ? 1 : 0);
+  const size_t out_es = o64 ? sizeof(cd) : sizeof(std::complex<float>);
   for (int j0 = 0; j0 < nw; j0 += chunk) {
     const int nc = std::min(chunk, nw - j0);
     const void* inc = (const char*)in + (size_t)j0 * ncols * in_es;
-    void* Gc = (char*)G + (size_t)j0 * ncols * op->wsize();
+    void* Gc = (char*)G + (size_t)j0 * ncols * out_es;
     if (is_grid(op)) {
       const GridOpDev& g = op->g64[s];
       if (launch_grid_horner(g, nullptr, inc, in_fp64, y1, 1, k, nc, sw0h, sdwh, op->h, 0, st, j0) ||
           launch_grid_horner(g, (const cx<double>*)y1, inc, in_fp64, y2, 1, k, nc, sw0h, sdwh, op->h, 1, st, j0) ||
-          launch_grid_horner(g, (const cx<double>*)y2, inc, in_fp64, Gc, op->fp64(), k, nc, sw0h, sdwh, op->h, 2, st,
-                             j0))
+          launch_grid_horner(g, (const cx<double>*)y2, inc, in_fp64, Gc, o64, k, nc, sw0h, sdwh, op->h, 2, st, j0))
         return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
       continue;
     }
@@ -954,8 +956,7 @@ int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp
     launch_tri_horner(tri, nullptr, inc, in_fp64, y1, 1, N, k, nc, sw0h, sdwh, op->h, 0, st, j0);
     launch_tri_horner(tri, (const cx<double>*)y1, inc, in_fp64, y2, 1, N, k, nc, sw0h, sdwh, op->h, 1, st, j0);
     if (M == 1) {
-      launch_tri_horner(tri, (const cx<double>*)y2, inc, in_fp64, Gc, op->fp64(), N, k, nc, sw0h, sdwh, op->h, 2, st,
-                        j0);
+      launch_tri_horner(tri, (const cx<double>*)y2, inc, in_fp64, Gc, o64, N, k, nc, sw0h, sdwh, op->h, 2, st, j0);
       continue;
     }
     // G in FP64, then G^(M) = sum_{r<M} e^{i sw_j r h} P^(M-1-r) G by M-1 Horner passes of P (the last one writes
@@ -966,7 +967,7 @@ int prefilter(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp
     for (int i = 1; i < M; ++i) {
       const bool last = i == M - 1;
       void* out = last ? Gc : (i & 1 ? y2 : y3);
-      launch_band_horner(band, x, (const cx<double>*)y1, out, last ? op->fp64() : 1, N, k, nc, sw0h, sdwh, i, st, j0);
+      launch_band_horner(band, x, (const cx<double>*)y1, out, last ? o64 : 1, N, k, nc, sw0h, sdwh, i, st, j0);
       x = (const cx<double>*)out;
     }
   }
@@ -1431,35 +1432,23 @@ AdjOpDev adj_op(const resolvent_op* op, int s) {
   return a;
 }
 
-int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const void* g_hat, void* f_grad,
-             double* mu_grad, int64_t C, hipStream_t st) {
+// One chunk of kc columns.  F: raw forcing rows [nw][kc][N] in the row precision (null without mu_grad); G: the
+// scaled seed in the row precision; f_out: forcing gradient [nw][kc][N] in the working precision, or null; mu_grad
+// (FP64 [nsite]) receives += this chunk's contribution.  Every row buffer holds the row precision: FP64 (r64), or
+// FP32 with FP64 arithmetic in the kernels and FP64 accumulation of both gradients.
+int backward_chunk(resolvent_op* op, const Plan& pl, int k, int r64, const void* F, const void* G, void* f_out,
+                   double* mu_grad, int64_t C, hipStream_t st) {
   const int64_t N = op->N, ncols = (int64_t)k * N, S = pl.S;
   const int nw = pl.nw;
-  const size_t rowb = (size_t)ncols * sizeof(cd);
+  const size_t rowb = (size_t)ncols * (r64 ? sizeof(cd) : sizeof(std::complex<float>));
   const double h = op->h;
-  if (C <= 0) C = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)S)));
-  C = std::min<int64_t>(C, S);
   const int64_t ncp = (S + C - 1) / C;
   const AdjOpDev fwd = adj_op(op, 0), rev = adj_op(op, 1);
   const int64_t nsite = fwd.nsite;
-
-  // The adjoint recursion for lambda is linear and does not involve the forward trajectory: only the mu gradient
-  // needs the states and stage values, so without it the forcing, the forward march, its checkpoints and the
-  // segment recomputation are skipped (the forcing gradient then costs one adjoint march).
   const bool need_states = mu_grad != nullptr;
 
-  // inputs in FP64: F (as given when FP64; only for the forward trajectory), seed G = scale * g
-  const void* F = f_hat;
-  if (!op->fp64() && need_states) {
-    void* p;
-    RES_TRY(ws_get(op, "bw_F", (size_t)nw * rowb, &p));
-    launch_convert(f_hat, 0, p, 1, (int64_t)nw * ncols, 1.0, st);
-    F = p;
-  }
-  void *G, *frow, *cps, *seg, *u, *acc, *y2, *y3, *y4, *ka, *kb, *ub, *lrows, *carry, *inj, *facc = nullptr;
-  void *btab_half, *btab;
-  RES_TRY(ws_get(op, "bw_G", (size_t)nw * rowb, &G));
-  launch_convert(g_hat, op->fp64(), G, 1, (int64_t)nw * ncols, pl.scale, st);
+  void *frow, *cps, *seg, *u, *acc, *y2, *y3, *y4, *ka, *kb, *ub, *lrows, *carry, *inj, *facc = nullptr;
+  void *btab_half = nullptr, *btab;
   frow = cps = seg = nullptr;
   if (need_states) {
     RES_TRY(ws_get(op, "bw_frow", (size_t)(2 * C + 1) * rowb, &frow));
@@ -1476,13 +1465,17 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   RES_TRY(ws_get(op, "bw_ub", rowb, &ub));
   RES_TRY(ws_get(op, "bw_carry", rowb, &carry));
   RES_TRY(ws_get(op, "bw_inj", (size_t)C * rowb, &inj));
-  if (f_grad) {
-    RES_TRY(ws_get(op, "bw_facc", (size_t)nw * rowb, &facc));
-    RES_TRY(zero_device(facc, (size_t)nw * rowb, st));
+  if (f_out) {
+    RES_TRY(ws_get(op, "bw_facc", (size_t)nw * ncols * sizeof(cd), &facc));
+    RES_TRY(zero_device(facc, (size_t)nw * ncols * sizeof(cd), st));
   }
-  RES_TRY(phase_table64(op, 2 * pl.P, &btab_half));
-  RES_TRY(phase_table64(op, pl.P, &btab));
-  if (mu_grad) RES_TRY(zero_device(mu_grad, (size_t)nsite * sizeof(double), st));
+  if (r64) {
+    if (need_states) RES_TRY(phase_table64(op, 2 * pl.P, &btab_half));
+    RES_TRY(phase_table64(op, pl.P, &btab));
+  } else {
+    if (need_states) RES_TRY(phase_table(op, 2 * pl.P, &btab_half));
+    RES_TRY(phase_table(op, pl.P, &btab));
+  }
   auto row = [&](void* base, int64_t r) { return (void*)((char*)base + (size_t)r * rowb); };
   // raw forcing of steps [sa, sb) for the segment recomputation: half-step samples 2 sa .. 2 sb.  The GEMM works
   // on 64-row tiles, so the 2 C + 1 samples of a whole segment would take a third tile for a single row: with
@@ -1496,7 +1489,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       HIP_TRY(hipMemcpyAsync(row(frow, 2 * len), row(frow, 0), rowb, hipMemcpyDeviceToDevice, st));
       --n;
     }
-    return synth_rows(1, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa, 1, n, frow, st);
+    return synth_rows(r64, nw, 2 * pl.P, pl.w0 * h * 0.5, +1, btab_half, F, ncols, 2 * sa, 1, n, frow, st);
   };
   auto frc = [&](int64_t s, int64_t r, int half) -> const void* {
     return s < pl.forced_end ? row(frow, 2 * r + half) : nullptr;
@@ -1524,26 +1517,12 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   }
 
   // 1. forward march with checkpoints.  It only needs the states, so it steps u' = P(Z) u + sum_j e^{i w_j t_s} G_j
-  // with the pre-filtered forcing G_j = h Q_j(Z) F_j: one synthesised row per step instead of two half-step rows,
-  // read once per step instead of at every stage.
+  // with the pre-filtered forcing G_j = h Q_j(Z) F_j (FP64 Horner passes, stored in the row precision): one
+  // synthesised row per step instead of two half-step rows, read once per step instead of at every stage.
   void* Gpre = nullptr;
   if (need_states && pl.forced_end > 0) {
-    void* ya;  // the Horner passes ping-pong between Gpre and one work block
-    RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
     RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &Gpre));
-    const double sw0h = pl.w0 * h, sdwh = pl.dw * h;
-    if (is_grid(op)) {
-      const GridOpDev& g = op->g64[0];
-      if (launch_grid_horner(g, nullptr, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 0, st) ||
-          launch_grid_horner(g, (const cx<double>*)Gpre, F, 1, ya, 1, k, nw, sw0h, sdwh, h, 1, st) ||
-          launch_grid_horner(g, (const cx<double>*)ya, F, 1, Gpre, 1, k, nw, sw0h, sdwh, h, 2, st))
-        return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
-    } else {
-      const cx<double>* tri = (const cx<double>*)op->d_tri[0];
-      launch_tri_horner(tri, nullptr, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 0, st);
-      launch_tri_horner(tri, (const cx<double>*)Gpre, F, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 1, st);
-      launch_tri_horner(tri, (const cx<double>*)ya, F, 1, Gpre, 1, N, k, nw, sw0h, sdwh, h, 2, st);
-    }
+    RES_TRY(prefilter(op, pl, k, F, r64, Gpre, +1, 1, st, r64));
   }
   RES_TRY(zero_device(u, rowb, st));
   void* ucur = u;
@@ -1552,20 +1531,21 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     HIP_TRY(hipMemcpyAsync(row(cps, c), ucur, rowb, hipMemcpyDeviceToDevice, st));
     if (c == ncp - 1) break;  // the state after the last step is not needed
     const int64_t nf = std::min(sb, pl.forced_end) - sa;
-    if (nf > 0) RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, Gpre, ncols, sa, 1, nf, frow, st));
+    if (nf > 0) RES_TRY(synth_rows(r64, nw, pl.P, pl.w0 * h, +1, btab, Gpre, ncols, sa, 1, nf, frow, st));
     for (int64_t s = sa; s < sb; ++s) {
       const void* g = s < pl.forced_end ? row(frow, s - sa) : nullptr;
       if (fused) {
         void* unext = ucur == u ? u2 : u;
-        if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h, st, g))
+        if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h, st, g,
+                              r64))
           return fail(RES_EINVAL, "fused forward step launch");
         ucur = unext;
         continue;
       }
-      launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, nullptr, h, st);
-      launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, nullptr, h, st);
-      launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, nullptr, h, st);
-      launch_fwd_stage(fwd, k, 4, u, u, y2, nullptr, acc, nullptr, h, st, g);
+      launch_fwd_stage(fwd, k, 1, u, nullptr, u, y2, acc, nullptr, h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 2, u, nullptr, y2, y3, acc, nullptr, h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 3, u, nullptr, y3, y2, acc, nullptr, h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 4, u, u, y2, nullptr, acc, nullptr, h, st, g, r64);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -1614,20 +1594,20 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
       void* a4 = stg ? srow(r, 2) : y2;
       if (fused) {
         if (launch_fwd_step2d(fwd, k, us, row(seg, r + 1), stg ? a2 : nullptr, stg ? a3 : nullptr,
-                              stg ? a4 : nullptr, frc(s, r, 0), frc(s, r, 1), frc(s, r, 2), h, st))
+                              stg ? a4 : nullptr, frc(s, r, 0), frc(s, r, 1), frc(s, r, 2), h, st, nullptr, r64))
           return fail(RES_EINVAL, "fused forward step launch");
         continue;
       }
-      launch_fwd_stage(fwd, k, 1, us, nullptr, us, a2, acc, frc(s, r, 0), h, st);
-      launch_fwd_stage(fwd, k, 2, us, nullptr, a2, a3, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 3, us, nullptr, a3, a4, acc, frc(s, r, 1), h, st);
-      launch_fwd_stage(fwd, k, 4, us, row(seg, r + 1), a4, nullptr, acc, frc(s, r, 2), h, st);
+      launch_fwd_stage(fwd, k, 1, us, nullptr, us, a2, acc, frc(s, r, 0), h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 2, us, nullptr, a2, a3, acc, frc(s, r, 1), h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 3, us, nullptr, a3, a4, acc, frc(s, r, 1), h, st, nullptr, r64);
+      launch_fwd_stage(fwd, k, 4, us, row(seg, r + 1), a4, nullptr, acc, frc(s, r, 2), h, st, nullptr, r64);
     }
     // projection seeds of the sampled steps in [sa, sb)
     const int64_t ma = first_m_at_or_after(sa), mb = first_m_at_or_after(sb);
     if (mb > ma)
-      RES_TRY(synth_rows(1, nw, pl.P, pl.w0 * h, +1, btab, G, ncols, pl.pfirst + ma * pl.pstride, pl.pstride, mb - ma,
-                         inj, st));
+      RES_TRY(synth_rows(r64, nw, pl.P, pl.w0 * h, +1, btab, G, ncols, pl.pfirst + ma * pl.pstride, pl.pstride,
+                         mb - ma, inj, st));
     // lambda rows: lseg[r] = lambda_{sa + r + 1}, segment c at row (c - cg) C of its group's rows
     const int64_t cg = c / G_seg * G_seg;
     void* lseg = row(lrows, (c - cg) * C);
@@ -1643,12 +1623,13 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         s3 = srow(r, 1);
         s4 = srow(r, 2);
       } else if (fused) {
-        if (launch_fwd_step2d(fwd, k, us, nullptr, y2, y3, y4, frc(s, r, 0), frc(s, r, 1), nullptr, h, st))
+        if (launch_fwd_step2d(fwd, k, us, nullptr, y2, y3, y4, frc(s, r, 0), frc(s, r, 1), nullptr, h, st, nullptr,
+                              r64))
           return fail(RES_EINVAL, "fused forward step launch");
       } else {
-        launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st);
-        launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st);
-        launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st);
+        launch_fwd_stage(fwd, k, 1, us, nullptr, us, y2, nullptr, frc(s, r, 0), h, st, nullptr, r64);
+        launch_fwd_stage(fwd, k, 2, us, nullptr, y2, y3, nullptr, frc(s, r, 1), h, st, nullptr, r64);
+        launch_fwd_stage(fwd, k, 3, us, nullptr, y3, y4, nullptr, frc(s, r, 1), h, st, nullptr, r64);
       }
       const void* lp = row(lseg, r);
       const void* seed = nullptr;
@@ -1657,16 +1638,17 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
         if (m < pl.pcount) seed = row(inj, m - ma);
       }
       if (fused) {
-        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lseg, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st))
+        if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lseg, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st,
+                              r64))
           return fail(RES_EINVAL, "fused reverse step launch");
         continue;
       }
       // Kb_3 in ka, Kb_2 in kb, Kb_1 in ub; stage 1 combines the three into lambda
-      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_cols, nullptr, h, st);
-      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_cols, nullptr, h, st);
-      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_cols, nullptr, h, st);
+      launch_rev_stage(rev, k, 4, lp, nullptr, nullptr, s4, ka, nullptr, nullptr, mu_cols, nullptr, h, st, r64);
+      launch_rev_stage(rev, k, 3, lp, nullptr, ka, s3, kb, nullptr, nullptr, mu_cols, nullptr, h, st, r64);
+      launch_rev_stage(rev, k, 2, lp, nullptr, kb, s2, ub, nullptr, nullptr, mu_cols, nullptr, h, st, r64);
       launch_rev_stage(rev, k, 1, lp, r > 0 ? row(lseg, r - 1) : carry, ub, us, nullptr, ka, kb, mu_cols, seed, h,
-                       st);
+                       st, r64);
     }
     HIP_TRY(hipGetLastError());
     // forcing gradient: Fourier sums of lambda_{s+1} over the forced steps of the group, once its first segment
@@ -1674,31 +1656,134 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     if (c == cg) {
       const int64_t ga = cg * C, gb = std::min(S, (cg + G_seg) * C);
       const int64_t nf = std::min(gb, pl.forced_end) - ga;
-      if (f_grad && nf > 0)
-        RES_TRY(project_rows(op, 1, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, ga, 1, nf, 1.0,
+      if (f_out && nf > 0)
+        RES_TRY(project_rows(op, r64, nw, pl.P, pl.w0 * h, +1, btab, lrows, ncols, ncols, ga, 1, nf, 1.0,
                              (double*)facc, st));
     }
   }
   if (mu_cols) launch_sum_columns(mu_cols, mu_rows, nsite, mu_grad, st);
-  // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j
-  if (f_grad) {
-    void *ya, *yb;
-    RES_TRY(ws_get(op, "horner_a", (size_t)nw * rowb, &ya));
-    RES_TRY(ws_get(op, "bw_Gpre", (size_t)nw * rowb, &yb));  // free again after the checkpoint march
-    const double sw0h = -pl.w0 * h, sdwh = -pl.dw * h;
-    if (is_grid(op)) {
-      const GridOpDev& g = op->g64[1];
-      if (launch_grid_horner(g, nullptr, facc, 1, ya, 1, k, nw, sw0h, sdwh, h, 0, st) ||
-          launch_grid_horner(g, (const cx<double>*)ya, facc, 1, yb, 1, k, nw, sw0h, sdwh, h, 1, st) ||
-          launch_grid_horner(g, (const cx<double>*)yb, facc, 1, f_grad, op->fp64(), k, nw, sw0h, sdwh, h, 2, st))
-        return fail(RES_EINVAL, "n_omega * k too large for the forcing pre-filter grid");
-    } else {
-      const cx<double>* tri = (const cx<double>*)op->d_tri[1];
-      launch_tri_horner(tri, nullptr, facc, 1, ya, 1, N, k, nw, sw0h, sdwh, h, 0, st);
-      launch_tri_horner(tri, (const cx<double>*)ya, facc, 1, yb, 1, N, k, nw, sw0h, sdwh, h, 1, st);
-      launch_tri_horner(tri, (const cx<double>*)yb, facc, 1, f_grad, op->fp64(), N, k, nw, sw0h, sdwh, h, 2, st);
-    }
+  // 3. F_grad_j = h Q_{-w_j}(Z^H) facc_j (FP64 Horner passes, written in the working precision)
+  if (f_out) {
+    RES_TRY(prefilter(op, pl, k, facc, 1, f_out, -1, 1, st, op->fp64()));
     launch_finite(facc, 1, (int64_t)nw * ncols, op->d_flag, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return RES_OK;
+}
+
+// Frees the workspace of the forward drivers (state, forcing, snapshot and accumulator blocks), so that the reverse
+// mode can use the memory; every driver sizes its workspace again on its next call.
+int release_forward_workspace(resolvent_op* op) {
+  if (op->capturing || op->arena) return RES_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto& kv : op->ws) {
+    const std::string& name = kv.first;
+    if (name.compare(0, 3, "bw_") == 0 || name.compare(0, 7, "horner_") == 0 || name == "segs") continue;
+    if (kv.second.p) HIP_TRY(hipFree(kv.second.p));
+    kv.second.p = nullptr;
+    kv.second.bytes = 0;
+  }
+  return RES_OK;
+}
+
+// Copies columns [c0, c0 + kc) of a [nw][k][N] block (precision in_fp64) into a [nw][kc][N] block (precision
+// out_fp64), times scale.
+void gather_columns(const void* x, int in_fp64, int64_t k, int64_t c0, int64_t kc, int64_t N, int nw, void* y,
+                    int out_fp64, double scale, hipStream_t st) {
+  const size_t ies = in_fp64 ? sizeof(cd) : sizeof(std::complex<float>);
+  const size_t oes = out_fp64 ? sizeof(cd) : sizeof(std::complex<float>);
+  if (kc == k) {
+    launch_convert(x, in_fp64, y, out_fp64, (int64_t)nw * k * N, scale, st);
+    return;
+  }
+  for (int j = 0; j < nw; ++j)
+    launch_convert((const char*)x + (size_t)((int64_t)j * k + c0) * N * ies, in_fp64,
+                   (char*)y + (size_t)((int64_t)j * kc) * N * oes, out_fp64, kc * N, scale, st);
+}
+
+int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const void* g_hat, void* f_grad,
+             double* mu_grad, int64_t C, hipStream_t st) {
+  const int64_t N = op->N, S = pl.S;
+  const int nw = pl.nw;
+  const int r64 = op->fp64() || op->rev_rows64;
+  const size_t res = r64 ? sizeof(cd) : sizeof(std::complex<float>);
+  if (C <= 0) C = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)S)));
+  C = std::min<int64_t>(C, S);
+  const int64_t ncp = (S + C - 1) / C;
+  // The adjoint recursion for lambda is linear and does not involve the forward trajectory: only the mu gradient
+  // needs the states and stage values, so without it the forcing, the forward march, its checkpoints and the
+  // segment recomputation are skipped (the forcing gradient then costs one adjoint march).
+  const bool need_states = mu_grad != nullptr;
+  const bool f_direct = (op->fp64() ? 1 : 0) == r64;  // the caller's forcing is already in the row precision
+
+  // Columns evolve independently under the march and the mu gradient is a sum over columns, so the columns are
+  // processed in chunks of kc when the rows of all k do not fit: the bytes a chunk holds (the stage rows and the
+  // extra lambda rows are sized later from what is left) against the free memory plus this mode's own workspace.
+  const double horner_budget = env_double("RESOLVENT_HORNER_BUDGET_GB", 8.0) * 1073741824.0;
+  auto need = [&](int64_t kc) {
+    const double row = (double)kc * N * res, blk = nw * row;
+    double b = blk + (double)(2 * C + 12) * row;  // seed, lambda rows, injections, work rows
+    if (f_grad) b += (double)nw * kc * N * sizeof(cd) + std::min(horner_budget, 2.0 * nw * kc * N * sizeof(cd));
+    if (need_states) {
+      b += blk + (kc < k || !f_direct ? blk : 0.0) + (double)(ncp + 3 * C + 1) * row;
+      b += std::min(horner_budget, 2.0 * nw * kc * N * sizeof(cd)) + (double)(k + 1) * adj_op(op, 0).nsite * 8.0;
+    }
+    return b;
+  };
+  auto available = [&](double* out) -> int {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    double a = (double)free_b;
+    for (const auto& kv : op->ws)  // this mode's own slots, except the weighted inputs (in use)
+      if ((kv.first.compare(0, 3, "bw_") == 0 && kv.first.compare(0, 6, "bw_wsc") != 0) ||
+          kv.first.compare(0, 7, "horner_") == 0)
+        a += (double)kv.second.bytes;
+    *out = 0.92 * a - 2.0 * 1073741824.0;
+    return RES_OK;
+  };
+  int64_t kc = k;
+  const long forced = env_long("RESOLVENT_BACKWARD_COLUMNS", 0);
+  if (forced > 0) {
+    kc = std::min<int64_t>(k, forced);
+  } else {
+    double avail = 0;
+    RES_TRY(available(&avail));
+    if (need(k) > avail) {
+      RES_TRY(release_forward_workspace(op));
+      RES_TRY(available(&avail));
+    }
+    while (kc > 1 && need(kc) > avail) --kc;
+  }
+
+  if (mu_grad) RES_TRY(zero_device(mu_grad, (size_t)adj_op(op, 0).nsite * sizeof(double), st));
+  for (int64_t c0 = 0; c0 < k; c0 += kc) {
+    const int64_t kcc = std::min<int64_t>(kc, k - c0);
+    const size_t blk = (size_t)nw * kcc * N * res;
+    void* G;
+    RES_TRY(ws_get(op, "bw_G", blk, &G));
+    gather_columns(g_hat, op->fp64(), k, c0, kcc, N, nw, G, r64, pl.scale, st);
+    const void* F = nullptr;
+    if (need_states) {
+      if (kcc == k && f_direct) {
+        F = f_hat;
+      } else {
+        void* p;
+        RES_TRY(ws_get(op, "bw_F", blk, &p));
+        gather_columns(f_hat, op->fp64(), k, c0, kcc, N, nw, p, r64, 1.0, st);
+        F = p;
+      }
+    }
+    // the chunk's forcing gradient goes straight to f_grad when the chunk is every column, else into the seed
+    // block (no longer read by then) and is scattered from there
+    void* fo = f_grad ? (kcc == k ? f_grad : G) : nullptr;
+    RES_TRY(backward_chunk(op, pl, (int)kcc, r64, F, G, fo, mu_grad, C, st));
+    if (f_grad && kcc < k) {
+      const size_t es = op->wsize();
+      for (int j = 0; j < nw; ++j)
+        HIP_TRY(hipMemcpyAsync((char*)f_grad + (size_t)((int64_t)j * k + c0) * N * es,
+                               (const char*)G + (size_t)((int64_t)j * kcc) * N * es, (size_t)kcc * N * es,
+                               hipMemcpyDeviceToDevice, st));
+    }
   }
   HIP_TRY(hipGetLastError());
   return RES_OK;
@@ -2720,6 +2805,12 @@ int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t 
 int resolvent_op_set_graphs(resolvent_op* op, int32_t enable) {
   if (!op) return fail(RES_EINVAL, "NULL op");
   op->use_graphs = enable != 0;
+  return RES_OK;
+}
+
+int resolvent_op_set_backward_rows(resolvent_op* op, int32_t fp64) {
+  if (!op) return fail(RES_EINVAL, "NULL op");
+  op->rev_rows64 = fp64 != 0;
   return RES_OK;
 }
 

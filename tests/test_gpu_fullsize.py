@@ -229,6 +229,70 @@ def test_adr2d_1024x512_full_size_reverse_mode():
     release()
 
 
+def test_adr3d3c_256x128x128_full_grid_reverse_mode_checkpoint_64():
+    """The reverse mode on the 3-D workload's full grid (256 x 128 x 128, three components, k = 3) with the
+    mixed-precision operator's FP32 rows and a checkpoint every 64 steps, on a short periodic run (4 frequencies,
+    P = 64, three periods projected every 8th step of the last: three 64-step segments) so that the FP64 references
+    stay cheap.  The forcing gradient must satisfy the duality <A^H g, d> = <g, A d> with A d from the FP64
+    operator's apply; the mu gradient must match, along a random direction, central differences of
+    J(mu) = Re <g, A(mu) f> from two FP64 applies with the diagonal moved by -+ eps d.  Bound: 1e-4 relative, the
+    mixed-precision bound (the FP32 rows round every stored value to 2^-24)."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr3d3c_coefficients
+    cfg = W.ADR3D
+    nx, ny, nz, h, k = cfg["nx"], cfg["ny"], cfg["nz"], cfg["h"], cfg["k"]
+    nw, P, w0 = 4, 64, 0.2
+    dw = 2 * np.pi / (P * h)
+    say("case: full-grid 3-D %d x %d x %d reverse mode, mixed (FP32 rows), periodic P=%d x 3, checkpoint 64" % (
+        nx, ny, nz, P))
+    wake = W.wake_parameters(cfg["seed"])
+    mu = np.full((nz, ny, nx), cfg["mu_const"])
+    c = adr3d3c_coefficients(nx, ny, nz, wake, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    N = 3 * nx * ny * nz
+    f = W.random_forcing_device(cfg["seed"], nw, k, N, torch.complex64, "cuda")
+    g = W.random_forcing_device(cfg["seed"] + 100, nw, k, N, torch.complex64, "cuda")
+    opm = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, c, h, precision="mixed")
+    grid, run = opm.grid(w0, dw, nw), opm.run("periodic", periods=3, stride=8)
+    fg, mg = opm.apply_backward(f, g, grid, run, checkpoint_every=64)
+    torch.cuda.synchronize()
+    opm.check()
+    del opm
+    release()
+    say("  backward done")
+    d = W.random_forcing_device(cfg["seed"] + 200, nw, k, N, torch.complex64, "cuda")
+    lhs = complex(torch.vdot(fg.flatten().to(torch.complex128), d.flatten().to(torch.complex128)).item())
+    del fg
+    op = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, c, h, precision="fp64")
+    f64, g64 = f.to(torch.complex128), g.flatten().to(torch.complex128)
+    del f, g
+    ad = op.apply(d.to(torch.complex128), grid, run)
+    del d
+    rhs = complex(torch.vdot(g64, ad.flatten()).item())
+    del ad
+    say("  duality: <A^H g, d> %s  <g, A d> %s  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / abs(rhs)))
+    assert abs(lhs - rhs) < 1e-4 * abs(rhs)
+    mg = mg.cpu().numpy()
+    dfield = np.asarray(c["dfield"], np.float64).ravel()
+    delta = np.random.default_rng(cfg["seed"] + 300).standard_normal(nx * ny * nz)
+    eps = 1e-4
+
+    def J(diag):
+        op.set_diagonal(diag)
+        u = op.apply(f64, grid, run)
+        return float(torch.vdot(g64, u.flatten()).real.item())
+
+    fd = (J(dfield + eps * delta) - J(dfield - eps * delta)) / (2 * eps)
+    op.set_diagonal(dfield)
+    op.check()
+    gd = float(mg @ delta)
+    say("  mu directional: reverse mode %.12e  central differences %.12e  rel %.2e" % (gd, fd, abs(gd - fd) / abs(fd)))
+    assert abs(gd - fd) < 1e-4 * abs(fd)
+    del op, f64, g64
+    release()
+
+
 def test_gl_periodic_n2000_full_size_block_arnoldi(monkeypatch):
     """The Arnoldi line's configuration (N = 2000, k = 4, 256 frequencies, 10 periods per run, 10 blocks of 4
     forcings, FP64, default stepper plan): the four leading gains at sampled frequencies against the singular values
