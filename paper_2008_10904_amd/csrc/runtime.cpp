@@ -1671,14 +1671,16 @@ int backward_chunk(resolvent_op* op, const Plan& pl, int k, int r64, const void*
   return RES_OK;
 }
 
-// Frees the workspace of the forward drivers (state, forcing, snapshot and accumulator blocks), so that the reverse
-// mode can use the memory; every driver sizes its workspace again on its next call.
-int release_forward_workspace(resolvent_op* op) {
+// Frees the handle's workspace (the forward drivers' state, forcing, snapshot and accumulator blocks and the reverse
+// mode's own rows), so that the reverse mode can size its rows to the device memory; every driver sizes its
+// workspace again on its next call.  Kept: the device copy of the stepper regions and the weighted reverse mode's
+// scaled inputs (in use).
+int release_workspace(resolvent_op* op) {
   if (op->capturing || op->arena) return RES_OK;
   HIP_TRY(hipDeviceSynchronize());
   for (auto& kv : op->ws) {
     const std::string& name = kv.first;
-    if (name.compare(0, 3, "bw_") == 0 || name.compare(0, 7, "horner_") == 0 || name == "segs") continue;
+    if (name.compare(0, 6, "bw_wsc") == 0 || name == "segs") continue;
     if (kv.second.p) HIP_TRY(hipFree(kv.second.p));
     kv.second.p = nullptr;
     kv.second.bytes = 0;
@@ -1718,7 +1720,8 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
 
   // Columns evolve independently under the march and the mu gradient is a sum over columns, so the columns are
   // processed in chunks of kc when the rows of all k do not fit: the bytes a chunk holds (the stage rows and the
-  // extra lambda rows are sized later from what is left) against the free memory plus this mode's own workspace.
+  // extra lambda rows are sized later from what is left) against the free device memory, after the handle's
+  // workspace is released when all k columns do not fit beside it.
   const double horner_budget = env_double("RESOLVENT_HORNER_BUDGET_GB", 8.0) * 1073741824.0;
   auto need = [&](int64_t kc) {
     const double row = (double)kc * N * res, blk = nw * row;
@@ -1733,12 +1736,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
   auto available = [&](double* out) -> int {
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    double a = (double)free_b;
-    for (const auto& kv : op->ws)  // this mode's own slots, except the weighted inputs (in use)
-      if ((kv.first.compare(0, 3, "bw_") == 0 && kv.first.compare(0, 6, "bw_wsc") != 0) ||
-          kv.first.compare(0, 7, "horner_") == 0)
-        a += (double)kv.second.bytes;
-    *out = 0.92 * a - 2.0 * 1073741824.0;
+    *out = 0.92 * (double)free_b - 2.0 * 1073741824.0;
     return RES_OK;
   };
   int64_t kc = k;
@@ -1749,7 +1747,7 @@ int backward(resolvent_op* op, const Plan& pl, int k, const void* f_hat, const v
     double avail = 0;
     RES_TRY(available(&avail));
     if (need(k) > avail) {
-      RES_TRY(release_forward_workspace(op));
+      RES_TRY(release_workspace(op));
       RES_TRY(available(&avail));
     }
     while (kc > 1 && need(kc) > avail) --kc;
