@@ -133,11 +133,12 @@ def gl_batched_modes(precision, polished=False):
 
 
 def test_gl_batched_64_modes_mixed():
-    # Mixed precision alone: the batch's smallest gains sit near the FP32 rounding floor of a 2-million-step march
-    # (the suboptimal gains of the stiffest instances), which is where the largest errors are.
+    # Mixed precision alone, to the mixed gain bound 1e-4 (measured on every eighth instance at three frequencies:
+    # gains 2.4e-5, modes 2.2e-5).  The largest errors are on the suboptimal gains of the stiffest instances, whose
+    # values sit closest to the FP32 rounding floor of the 2-million-step march.
     say("case: full-size batched GL (64 instances), k=2, 128 frequencies, 20 iterations, mixed, tuned plan")
     eg, ev, eu = gl_batched_modes("mixed")
-    assert eg < 1e-3 and ev < 1e-1 and eu < 1e-1
+    assert eg < 1e-4 and ev < 1e-2 and eu < 1e-2
 
 
 def test_gl_batched_64_modes_mixed_with_fp64_finish():
