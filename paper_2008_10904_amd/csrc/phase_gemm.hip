@@ -249,6 +249,145 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
       }
 }
 
+// ---- synthesis of a few rows from a short frequency block, FP32 ------------------------------------------------
+// out[r][n] = e^{i sigma w0 h s_r} sum_j A[r][j] G[j][n] for at most 256 rows (forcing tiles, the reverse mode's
+// segment and seed rows) and at most 192 frequencies.  There the GEMM is short in M and K and long in N (the 3-D
+// workload's tile: 64 rows, 96 frequencies, 37.7 M columns), and the tiled kernel above spends its time
+// regenerating the phase operand and staging both operands through LDS for every 64-column tile.  Here a
+// workgroup generates the phase operand of its 64-row tile once, into LDS, and each of its eight waves streams
+// 32-column tiles of G straight from HBM into MFMA operand registers, one 32-frequency chunk ahead of the matrix
+// cores, with the 64 x 32 output tile in accumulators.  A complex product takes three real MFMAs (Gauss):
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2.
+constexpr int SY_ROWS = 64, SY_KMAX = 192, SY_LDA = 80, SY_KC = 8;  // SY_KC: K-steps of 4 per register chunk
+
+__global__ __launch_bounds__(512) void synth_rows_kernel(PhaseGemmArgs a) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  // A planes [k][row] with a row stride of 80 floats (16 mod 32 banks): the 16 rows x 4 k of an operand read
+  // fall in distinct banks for each half-wave
+  __shared__ float Ar[SY_KMAX * SY_LDA], Ai[SY_KMAX * SY_LDA];
+  __shared__ double ph_re[SY_ROWS], ph_im[SY_ROWS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, cl = lane & 15;  // operand lane layout: A[cl][kq], B[kq][cl]
+  const int64_t m0 = (int64_t)blockIdx.y * SY_ROWS;
+  const int K = (int)a.K;
+  const int nkc = (K + 4 * SY_KC - 1) / (4 * SY_KC);  // register chunks per column tile
+  const int Kp = nkc * 4 * SY_KC;
+  const int64_t P = a.P;
+  const int64_t str = a.stride > 0 ? a.stride : 1;
+  const cx<float>* __restrict__ btab = (const cx<float>*)a.btab;
+  const bool conj_a = a.sigma < 0;
+  for (int e = tid; e < Kp * SY_ROWS; e += blockDim.x) {
+    const int k = e / SY_ROWS, r = e - k * SY_ROWS;
+    float re = 0.f, im = 0.f;
+    if (k < K && m0 + r < a.M) {
+      const int64_t smod = (a.s0 + (m0 + r) * str) % P;
+      const cx<float> t = btab[((int64_t)k * smod) % P];  // k < 192 and smod < P: no overflow
+      re = t.re;
+      im = conj_a ? -t.im : t.im;
+    }
+    Ar[k * SY_LDA + r] = re;
+    Ai[k * SY_LDA + r] = im;
+  }
+  if (tid < SY_ROWS) {
+    double sn, cs;
+    sincos((double)a.sigma * a.w0h * (double)(a.s0 + (m0 + tid) * str), &sn, &cs);
+    ph_re[tid] = cs;
+    ph_im[tid] = sn;
+  }
+  __syncthreads();  // the only barrier: from here on the waves are independent
+
+  const cx<float>* __restrict__ B = (const cx<float>*)a.bmat;
+  cx<float>* __restrict__ out = (cx<float>*)a.out;
+  const int64_t ldb = a.ldb > 0 ? a.ldb : a.Ncols;
+  const int64_t ncols = a.Ncols;
+  const int64_t ntiles = (ncols + 31) / 32;
+  const int64_t wstride = (int64_t)gridDim.x * 8;
+  const int64_t t0 = (int64_t)blockIdx.x * 8 + wave;
+  if (t0 >= ntiles) return;
+  const int64_t nq = ((ntiles - 1 - t0) / wstride + 1) * nkc;  // chunks of this wave, in order
+
+  v4 p1[4][2], p2[4][2], p3[4][2];
+  auto zero = [&]() {
+#pragma unroll
+    for (int tr = 0; tr < 4; ++tr)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        p1[tr][c] = v4{0.f, 0.f, 0.f, 0.f};
+        p2[tr][c] = v4{0.f, 0.f, 0.f, 0.f};
+        p3[tr][c] = v4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  // chunk q: column tile t0 + (q / nkc) * wstride, frequencies (q % nkc) * 32 ..; rows past K read row K - 1
+  // (finite data against zero phases), columns past the end read the last column (results not stored)
+  auto load = [&](int64_t q, float (&xr)[SY_KC][2], float (&xi)[SY_KC][2]) {
+    const int64_t n0 = (t0 + (q / nkc) * wstride) * 32;
+    const int kc = (int)(q % nkc);
+#pragma unroll
+    for (int s = 0; s < SY_KC; ++s) {
+      const int k = min(kc * 4 * SY_KC + 4 * s + kq, K - 1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int64_t n = min(n0 + 16 * c + cl, ncols - 1);
+        const cx<float> v = B[(int64_t)k * ldb + n];
+        xr[s][c] = v.re;
+        xi[s][c] = v.im;
+      }
+    }
+  };
+  auto compute = [&](int64_t q, float (&xr)[SY_KC][2], float (&xi)[SY_KC][2]) {
+    const int kc = (int)(q % nkc);
+#pragma unroll
+    for (int s = 0; s < SY_KC; ++s) {
+      const int kr = kc * 4 * SY_KC + 4 * s + kq;
+      float ar[4], ai[4];
+#pragma unroll
+      for (int tr = 0; tr < 4; ++tr) {
+        ar[tr] = Ar[kr * SY_LDA + 16 * tr + cl];
+        ai[tr] = Ai[kr * SY_LDA + 16 * tr + cl];
+      }
+#pragma unroll
+      for (int tr = 0; tr < 4; ++tr)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          p1[tr][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[tr], xr[s][c], p1[tr][c], 0, 0, 0);
+          p2[tr][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[tr], xi[s][c], p2[tr][c], 0, 0, 0);
+          p3[tr][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[tr] + ai[tr], xr[s][c] + xi[s][c], p3[tr][c], 0,
+                                                           0, 0);
+        }
+    }
+    if (kc != nkc - 1) return;
+    // the tile is complete: rows 4 kq + v of each 16 x 16 block, column cl
+    const int64_t n0 = (t0 + (q / nkc) * wstride) * 32;
+#pragma unroll
+    for (int tr = 0; tr < 4; ++tr)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rl = 16 * tr + 4 * kq + v;
+          const int64_t row = m0 + rl, col = n0 + 16 * c + cl;
+          const double x1 = p1[tr][c][v], x2 = p2[tr][c][v], x3 = p3[tr][c][v];
+          const double xr0 = x1 - x2, xi0 = x3 - x1 - x2;
+          const double pr = ph_re[rl], pi = ph_im[rl];
+          if (row < a.M && col < ncols)
+            out[row * ncols + col] = mk<float>((float)(xr0 * pr - xi0 * pi), (float)(xr0 * pi + xi0 * pr));
+        }
+    zero();
+  };
+
+  zero();
+  float xa[SY_KC][2], ya[SY_KC][2], xb[SY_KC][2], yb[SY_KC][2];
+  load(0, xa, ya);
+  int64_t q = 0;
+  for (; q + 1 < nq; q += 2) {
+    load(q + 1, xb, yb);
+    compute(q, xa, ya);
+    if (q + 2 < nq) load(q + 2, xa, ya);
+    compute(q + 1, xb, yb);
+  }
+  if (q < nq) compute(q, xa, ya);
+}
+
 // acc[e] += scale * sum_z partial[z][e]
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const cx<double>* __restrict__ part,
                                                               cx<double>* __restrict__ acc, int64_t count,
@@ -276,6 +415,15 @@ int launch_phase_gemm(const PhaseGemmArgs& a, int fp64, hipStream_t st) {
   const int64_t blocks = (gx + 7) / 8 * 8 * gy;  // column tiles padded to a multiple of 8 (see the tile order)
   if (blocks > 0x7fffffff || gz > 65535) return -1;
   dim3 grid((unsigned)blocks, (unsigned)gz);
+  if (a.mode == 0 && !fp64 && a.K <= SY_KMAX && a.M <= 4 * SY_ROWS && a.k_per_split >= a.K) {
+    // one 512-thread workgroup per CU (123 KB of LDS at most): 256 over the M tiles, a multiple of 8 per M tile so
+    // that the workgroups of one column range sit on one XCD
+    const int64_t mt = (a.M + SY_ROWS - 1) / SY_ROWS;
+    const int64_t per = ((256 / mt) + 7) / 8 * 8;
+    const int64_t gxs = std::max<int64_t>(1, std::min<int64_t>(per, (((a.Ncols + 31) / 32) + 7) / 8));
+    hipLaunchKernelGGL(synth_rows_kernel, dim3((unsigned)gxs, (unsigned)mt), dim3(512), 0, st, a);
+    return 0;
+  }
   if (a.mode == 0) {
     if (fp64) hipLaunchKernelGGL((phase_gemm_kernel<double, 0>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((phase_gemm_kernel<float, 0>), grid, dim3(256), 0, st, a);

@@ -1069,9 +1069,27 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     HIP_TRY(hipGetLastError());
     trace_norm("forcing table", frc, table_rows * ncols, op->fp64(), st);
   } else {
-    const double tile_budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
-    tile_rows = op->arena ? op->arena->sz.tile_rows
-                          : std::max<int64_t>(64, (int64_t)(tile_budget / ((double)ncols * ws)));  // steps per tile
+    // Each tile's synthesis GEMM reads the whole [nw][k N] block G once, so longer tiles amortise that read over
+    // more rows (one row per kernel step; on the 3-D workload G is 29 GB against 302 MB per row).  Default: the
+    // rows of 2 GiB, at least 64, or up to 256 when a third of the free device memory (plus the tile this handle
+    // already holds) has room for them; RESOLVENT_TILE_BUDGET_GB overrides.
+    const double row_b = (double)ncols * (double)ws;
+    const double budget = env_double("RESOLVENT_TILE_BUDGET_GB", 2.0) * 1073741824.0;
+    tile_rows = std::max<int64_t>(64, (int64_t)(budget / row_b));
+    if (op->arena) {
+      tile_rows = op->arena->sz.tile_rows;
+    } else if (!std::getenv("RESOLVENT_TILE_BUDGET_GB")) {
+      size_t free_b = 0, total_b = 0;
+      HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+      const auto held = op->ws.find("forcing");
+      const double held_b = held != op->ws.end() ? (double)held->second.bytes : 0.0;
+      if (op->capturing && held_b > 0) {
+        tile_rows = std::max<int64_t>(1, (int64_t)(held_b / row_b) - 16);  // a captured run reuses its tile
+      } else {
+        const double room = ((double)free_b + held_b - 6.0 * 1073741824.0) / 3.0;
+        tile_rows = std::max<int64_t>(tile_rows, std::min<int64_t>(256, (int64_t)(room / row_b) - 16));
+      }
+    }
     RES_TRY(ws_get(op, "forcing", (size_t)(tile_rows + 16) * ncols * ws, &frc));  // + prefetch padding rows
   }
 
