@@ -134,21 +134,31 @@ def choose_plan(op, k, how, search_power=False):
     return op.set_plan([int(x) for x in how.split(",")])
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON line stays alone on stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def time_steps(op, f0, grid, run, K, W):
     import torch
     from paper_2008_10904_amd import _lib as L
-    for _ in range(W):
+    for i in range(W):
         g, _, _, _ = op.modes(f0, grid, run, 1, want_modes=False, want_hist=False)
+        torch.cuda.synchronize()
+        progress("warmup step %d of %d done" % (i + 1, W))
     torch.cuda.synchronize()
     op.set_timing(True)
     for kind in range(4):
         op.timing(kind)  # reset the counters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(K):
+    for i in range(K):
         g, _, _, _ = op.modes(f0, grid, run, 1, want_modes=False, want_hist=False)
+        if K > 1 and i + 1 < K and (time.perf_counter() - t0) > 30.0:
+            progress("timed step %d of %d queued" % (i + 1, K))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress("%d timed steps done" % K)
     kt = {name: op.timing(kind) for name, kind in (("stepper", L.RES_TIMING_STEPPER),
                                                    ("synthesis", L.RES_TIMING_SYNTHESIS),
                                                    ("projection", L.RES_TIMING_PROJECTION),
@@ -676,6 +686,7 @@ def grad3d(cfg):
     u = op.apply(f, grid, run)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress("gradient: forward apply done")
     J = sum(float(u[j].abs().to(torch.float64).sum().item()) for j in range(nw))
     g = torch.empty_like(u)
     for j in range(nw):  # dJ/du_hat of J = sum |u_hat|, one frequency at a time (no full-size temporaries)
@@ -687,6 +698,7 @@ def grad3d(cfg):
     fg, mg = op.apply_backward(f, g, grid, run, checkpoint_every=cfg["checkpoint_every"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    progress("gradient: backward (forcing and mu) done")
     dual = sum(complex(torch.vdot(fg[j].flatten().to(torch.complex128), f[j].flatten().to(torch.complex128)).item())
                for j in range(nw))
     ok = bool(torch.isfinite(fg).all().item()) and bool(np.isfinite(mg.cpu().numpy()).all())

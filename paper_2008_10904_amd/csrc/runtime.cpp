@@ -1521,12 +1521,18 @@ int backward_chunk(resolvent_op* op, const Plan& pl, int k, int r64, const void*
   // other operators one launch per stage.  The fused step cannot update the state in place, so the checkpoint
   // march ping-pongs between u and a second row.
   const bool fused = fwd.kind == 1 && fwd.ncomp == 1 && fwd.g.nz == 1;
+  // Mixed-precision three-component grids with FP32 rows march the checkpoint states, and the adjoint recursion
+  // when no mu gradient is asked for, with the forward march's fused one-launch step (launch_grid_step3d, FP32
+  // arithmetic): u' = P(Z) u + G_s and lambda_s = P(Z^H) lambda_{s+1} + seed_s, since P(Z)^H = P(Z^H).  Both
+  // need only the states; the stage values of the recomputed segments and the reverse stages of the mu gradient
+  // keep the stage kernels.
+  const bool fused3 = fwd.kind == 1 && fwd.ncomp == 3 && !r64 && !op->fp64();
   void* u2 = nullptr;
   // per-column mu rows of the reverse steps (one row per column, or per grid row of the stage launches), summed at
   // the end: the columns of a node run in different threads, and the sum stays deterministic
   double* mu_cols = nullptr;
   const int mu_rows = fused ? k : rev_stage_rows(k);
-  if (fused) RES_TRY(ws_get(op, "bw_u2", rowb, &u2));
+  if (fused || fused3) RES_TRY(ws_get(op, "bw_u2", rowb, &u2));
   if (mu_grad) {
     void* p;
     RES_TRY(ws_get(op, "bw_mu_cols", (size_t)mu_rows * nsite * sizeof(double), &p));
@@ -1557,6 +1563,13 @@ int backward_chunk(resolvent_op* op, const Plan& pl, int k, int r64, const void*
         if (launch_fwd_step2d(fwd, k, ucur, unext, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h, st, g,
                               r64))
           return fail(RES_EINVAL, "fused forward step launch");
+        ucur = unext;
+        continue;
+      }
+      if (fused3) {
+        void* unext = ucur == u ? u2 : u;
+        if (launch_grid_step3d(op->gw[0], k, ucur, unext, g, 1.0, 0.0, nullptr, st))
+          return fail(RES_EINVAL, "3-D step launch");
         ucur = unext;
         continue;
       }
@@ -1659,6 +1672,11 @@ int backward_chunk(resolvent_op* op, const Plan& pl, int k, int r64, const void*
         if (launch_rev_step2d(rev, k, lp, r > 0 ? row(lseg, r - 1) : carry, s2, s3, s4, us, mu_cols, seed, h, st,
                               r64))
           return fail(RES_EINVAL, "fused reverse step launch");
+        continue;
+      }
+      if (fused3 && !need_states) {
+        if (launch_grid_step3d(op->gw[1], k, lp, r > 0 ? row(lseg, r - 1) : carry, seed, 1.0, 0.0, nullptr, st))
+          return fail(RES_EINVAL, "3-D step launch");
         continue;
       }
       // Kb_3 in ka, Kb_2 in kb, Kb_1 in ub; stage 1 combines the three into lambda

@@ -263,34 +263,43 @@ def test_backward_in_column_chunks_matches_all_columns(case, precision, monkeypa
     assert maxrel(whole[0], ref) < (1e-10 if precision == "fp64" else 1e-4)
 
 
-@pytest.mark.parametrize("case", ["gl", "2d", "3d"])
+@pytest.mark.parametrize("case", ["gl", "2d", "3d", "3d-mixed"])
 def test_forcing_gradient_alone_skips_the_forward_trajectory(case):
     """Without the mu gradient the reverse mode runs the adjoint recursion alone (no forward march, checkpoints or
     recomputation: lambda does not depend on the trajectory).  Its forcing gradient must equal the one computed
-    beside the mu gradient (to rounding), and match the oracle's stepped VJP."""
+    beside the mu gradient (to rounding), and match the oracle's stepped VJP.  The mixed 3-D operator runs that
+    recursion as lambda_s = P(Z^H) lambda_{s+1} + seed_s with the forward march's fused FP32 step, against the
+    FP64-arithmetic stage kernels beside the mu gradient: 1e-5 between the two, 1e-4 against the oracle."""
     import torch
     say("case: forcing gradient without mu,", case)
     h, P, nw, k, w0 = 0.1, 50, 3, 2, 0.1
     dw = 2 * np.pi / (P * h)
     run = dict(periods=2, stride=5)
+    mixed = case.endswith("mixed")
     if case == "gl":
         op = gpu_gl(40, 0.2, h)
         L0 = O_ops.gl_operator(40, 0.2, -0.01, xl=XL_T, xr=XR_T)[0]
     else:
-        op, L0, _, _ = grid_case(case, h)
+        op, L0, _, _ = grid_case(case.split("-")[0], h, "mixed" if mixed else "fp64")
     F, G = forcing(59, nw, k, op.n), forcing(60, nw, k, op.n)
+    dt = None
+    if mixed:
+        F = F.astype(np.complex64).astype(np.complex128)
+        G = G.astype(np.complex64).astype(np.complex128)
+        dt = torch.complex64
     grid, rn = op.grid(w0, dw, nw), op.run("periodic", **run)
-    f, g = gpu_tensor(F), gpu_tensor(G)
+    f, g = gpu_tensor(F, dt), gpu_tensor(G, dt)
     fg_both, _ = op.apply_backward(f, g, grid, rn, checkpoint_every=16)
     fg_alone, mg = op.apply_backward(f, g, grid, rn, checkpoint_every=16, want_mu=False)
     torch.cuda.synchronize()
     op.check()
     assert mg is None
     say("  alone vs with mu: %.3e" % maxrel(to_np(fg_alone), to_np(fg_both)))
-    assert maxrel(to_np(fg_alone), to_np(fg_both)) < 1e-13  # same recursion; only the projection grouping may differ
+    # same recursion; only the projection grouping (and, mixed, the arithmetic precision) may differ
+    assert maxrel(to_np(fg_alone), to_np(fg_both)) < (1e-5 if mixed else 1e-13)
     ref = O_grad.stepped_vjp(L0, h, w0, dw, G, "periodic", **run)
     say("  f_grad err %.3e" % maxrel(to_np(fg_alone), ref))
-    assert maxrel(to_np(fg_alone), ref) < 1e-10
+    assert maxrel(to_np(fg_alone), ref) < (1e-4 if mixed else 1e-10)
 
 
 def test_grid_backward_spans_several_tiles():
