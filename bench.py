@@ -38,6 +38,9 @@ def parse():
                     help="iterations of the untimed accuracy pass against the oracle (default: the workload's own "
                          "iteration count; 0 skips it).  The gains and modes at sampled frequencies are compared "
                          "with the CPU oracle's same iteration, which runs in the CPU-baseline leg")
+    ap.add_argument("--accuracy-every", type=int, default=8,
+                    help="gl_batched_64: compare every n-th instance with the oracle (8: eight instances, all four "
+                         "sizes; 1: all 64, a few minutes of oracle work)")
     ap.add_argument("--workload", default="gl_periodic_n2000",
                     choices=["gl_periodic_n2000", "gl_transient_n200", "gl_batched_64", "adr2d_1024x512",
                              "adr3d3c_256x128x128", "gl_paper_n200"],
@@ -403,7 +406,7 @@ def bench_batched(args):
     F = W.random_forcing(cfg["seed"], nw, k, ntot)
     sweeps_per_step = ntot * k * nw * 2 * steps_per_run
     iters = cfg["iters"] if args.accuracy_iters is None else args.accuracy_iters
-    picks = list(range(0, len(inst), 8))  # every eighth instance: all four sizes, the stiffest included
+    picks = list(range(0, len(inst), max(1, args.accuracy_every)))  # default: every eighth, all four sizes
     js = [0, 64, 127]
     res, plans, powers, sampled = {}, {}, {}, {}
     V_mixed = None
@@ -470,9 +473,11 @@ def batched_accuracy(cfg, inst, off, w0, dw, F, picks, js, iters, sampled):
     t = time.perf_counter()
     out = {"iterations": iters, "instances": picks, "sampled_omega_index": js}
     refs = {}
-    for m in picks:
+    for i, m in enumerate(picks):
         n, mu0, mu2 = inst[m]
         L, _ = gl_operator(n, mu0, mu2)
+        if i % 8 == 7:
+            progress("oracle references: %d of %d instances" % (i + 1, len(picks)))
         sl = slice(int(off[m]), int(off[m + 1]))
         om = w0 + dw * np.asarray(js)
         for kind in ("fp64", "mixed"):
