@@ -46,6 +46,41 @@ def build(verbose=True):
     return LIB
 
 
+# Host sanitizer build: the runtime and the ABI driver of tests/host_sanitize with AddressSanitizer and
+# UndefinedBehaviorSanitizer on the host code only (device code is never sanitized), linked with the device objects
+# of the last build().
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-gpu-sanitize",
+            "-fno-sanitize-recover=undefined"]
+ABI_CHECK_SRC = os.path.join(ROOT, "tests", "host_sanitize", "abi_check.cpp")
+ABI_CHECK = os.path.join(HERE, "abi_check_asan")  # beside the library (the object folder stays on this host)
+
+
+def build_abi_check(verbose=True):
+    os.makedirs(OBJ, exist_ok=True)
+    objs = []
+    for src in (os.path.join(CSRC, "runtime.cpp"), ABI_CHECK_SRC):
+        obj = os.path.join(OBJ, os.path.basename(src) + ".asan.o")
+        cmd = [HIPCC, "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+               "--offload-arch=" + ARCH] + SANITIZE + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+        objs.append(obj)
+    kernels = [os.path.join(OBJ, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    missing = [k for k in kernels if not os.path.exists(k)]
+    if missing:
+        raise RuntimeError("run build() first: missing %s" % ", ".join(missing))
+    cmd = [HIPCC, "--offload-arch=" + ARCH] + SANITIZE + ["-o", ABI_CHECK] + objs + kernels
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    if verbose:
+        print("built", ABI_CHECK)
+    return ABI_CHECK
+
+
 if __name__ == "__main__":
     build()
+    if "--abi-check" in sys.argv:
+        build_abi_check()
     sys.exit(0)
