@@ -98,16 +98,19 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step1d_gl_periodic_n2000_traff
 STEPPER_SOURCES = ("step1d_kernel.h", "common.h")  # the stepper kernel and the helpers it inlines
 
 
-def measured_traffic(plan=None, step_power=1):
+def measured_traffic(plan=None, step_power=1, steps_per_launch=None):
     """HBM bytes per stepper launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
     stepper's sources have changed since those counters were taken (their hash is recorded beside the figure) or
-    when the run uses a different stepper plan or step power than the profiled one."""
+    when the run uses a different stepper plan or step power than the profiled one.  The profiled launches march
+    whole periods; launches of another average length (the first period marched in chunks beside the table's
+    synthesis) scale the figure by their RK4 steps (the traffic is the forcing rows and the exchanges, both
+    per step)."""
     import hashlib
     h = hashlib.sha256()
     for f in STEPPER_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_10904_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    value, digest, prof_plan, prof_power = None, None, None, 1
+    value, digest, prof_plan, prof_power, prof_steps = None, None, None, 1, None
     try:
         with open(TRAFFIC_PROFILE) as fh:
             for line in fh:
@@ -119,10 +122,14 @@ def measured_traffic(plan=None, step_power=1):
                     prof_plan = [int(x) for x in line.split(":", 1)[1].split(",")]
                 elif line.startswith("step_power:"):
                     prof_power = int(line.split(":", 1)[1])
+                elif line.startswith("rk4_steps_per_launch:"):
+                    prof_steps = float(line.split(":", 1)[1])
     except OSError:
         return None
     if digest != h.hexdigest() or (plan is not None and list(plan) != prof_plan) or step_power != prof_power:
         return None
+    if steps_per_launch is not None and prof_steps:
+        return value * steps_per_launch / prof_steps
     return value
 
 
@@ -1068,7 +1075,8 @@ def main():
                    "time_steps_per_step": 2 * steps_per_run},
         "roofline": {"bound": "alu", "kernel": "step1d_kernel (fused RK4 step, FP64)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(plan64, power), "avg_launch_ms": avg_launch_s * 1e3, "launches": stepper_n,
+                     "traffic": measured_traffic(plan64, power, steps_per_launch), "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches": stepper_n,
                      "steps_per_launch": steps_per_launch},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
         "stepper_plan": list(plan64),

@@ -149,6 +149,8 @@ struct resolvent_op {
   bool capturing = false;
   bool use_graphs = false;               // resolvent_modes replays its middle iterations from a captured graph
   hipStream_t cap_stream = nullptr;      // private stream for that capture (default priority)
+  hipStream_t side_stream = nullptr;     // forcing-table synthesis beside the march (default priority)
+  std::vector<hipEvent_t> side_ev;       // chunk events of that synthesis
   int plan_version = 0;                  // bumped by every stepper plan change
   int segs_dev_k = -1, segs_dev_version = -1;  // what the device copy of the regions describes
   // diagonal B, C and metrics W_f, W_y (resolvent_op_set_weights): rows of d_wsc, each [N] FP64
@@ -1060,7 +1062,48 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     g_last_error.clear();
     table_mode = false;  // the allocation failed after all: fall back to tiles
   }
-  if (table_mode) {
+  // In table mode the first period's march overlaps the table's synthesis: rows are synthesised in chunks, the
+  // first on the caller's stream and the others on the handle's side stream, which starts once the caller's
+  // earlier work is done (a previous run may still read the table buffer); the march of the first period waits
+  // for each chunk's event before it reaches the chunk's rows.  A row is synthesised in about half the time the
+  // 1-D march takes to consume it, so the chunks double in size from 1,024 rows: only the first one is not
+  // hidden.  Rows are independent, so every row gets the same value as from one GEMM over the whole table (chunk
+  // bounds are whole 64-row tiles).  Off under graph capture and in the no-allocation entry point, and for grid
+  // operators, whose step kernels occupy every CU; RESOLVENT_SYNTH_OVERLAP=0 turns it off.
+  std::vector<int64_t> ov_bound;  // chunk c holds table rows [ov_bound[c], ov_bound[c + 1])
+  int nov = 0;
+  if (table_mode && !op->capturing && !op->arena && !is_grid(op) && env_long("RESOLVENT_SYNTH_OVERLAP", 1) != 0 &&
+      table_rows >= 4096) {
+    ov_bound.push_back(0);
+    for (int64_t len = 1024; ov_bound.back() < table_rows; len *= 2)
+      ov_bound.push_back(std::min(table_rows, ov_bound.back() + len));
+    nov = (int)ov_bound.size() - 1;
+  }
+  if (table_mode && nov > 0) {
+    if (!op->side_stream) HIP_TRY(hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking));
+    while ((int)op->side_ev.size() < nov) {
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      op->side_ev.push_back(ev);
+    }
+    auto chunk = [&](int c, hipStream_t sc) -> int {
+      const int64_t r0 = ov_bound[c];
+      syn.M = ov_bound[c + 1] - r0;
+      syn.s0 = r0 * M;
+      syn.out = (char*)frc + (size_t)r0 * ncols * ws;
+      TimedLaunch tl(op, RES_TIMING_SYNTHESIS, sc);
+      if (launch_phase_gemm(syn, op->fp64(), sc)) return fail(RES_EINVAL, "synthesis GEMM launch");
+      HIP_TRY(hipGetLastError());
+      return RES_OK;
+    };
+    RES_TRY(chunk(0, st));
+    HIP_TRY(hipEventRecord(op->side_ev[0], st));
+    HIP_TRY(hipStreamWaitEvent(op->side_stream, op->side_ev[0], 0));
+    for (int c = 1; c < nov; ++c) {
+      RES_TRY(chunk(c, op->side_stream));
+      HIP_TRY(hipEventRecord(op->side_ev[c], op->side_stream));
+    }
+  } else if (table_mode) {
     syn.M = table_rows;
     syn.s0 = 0;
     syn.out = frc;
@@ -1099,6 +1142,17 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
 
   int64_t buffered = 0, buf_m0 = 0;  // rows in the snapshot buffer and the sample index of the first
   int64_t s0 = 0;
+  int ov_waited = 1;  // synthesis chunks below this one are ordered before the caller's stream's next work
+  // however the run ends, the caller's stream waits for every chunk (the next run rewrites the table)
+  struct OverlapJoin {
+    resolvent_op* op;
+    hipStream_t st;
+    const int& nov;
+    int& waited;
+    ~OverlapJoin() {
+      for (; waited < nov; ++waited) (void)hipStreamWaitEvent(st, op->side_ev[waited], 0);
+    }
+  } ov_join{op, st, nov, ov_waited};
   auto first_m_at_or_after = [&](int64_t t) -> int64_t {
     if (t <= pl.pfirst) return 0;
     return std::min(pl.pcount, (t - pl.pfirst + pl.pstride - 1) / pl.pstride);
@@ -1108,6 +1162,13 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
     int64_t e = pl.S;
     if (table_mode) e = std::min(e, (s0 / pl.P + 1) * pl.P);
     else e = std::min(e, s0 + tile_rows * M);
+    if (nov > 0 && s0 < pl.P && s0 < pl.forced_end) {  // first period: up to the end of the synthesised chunk
+      int c = 0;
+      while (ov_bound[c + 1] * M <= s0) ++c;
+      for (; ov_waited <= c && ov_waited < nov; ++ov_waited)
+        HIP_TRY(hipStreamWaitEvent(st, op->side_ev[ov_waited], 0));
+      e = std::min(e, ov_bound[c + 1] * M);
+    }
     if (s0 < pl.forced_end) e = std::min(e, pl.forced_end);
     int64_t ma = first_m_at_or_after(s0), mb = first_m_at_or_after(e);
     if (mb - ma > snap_cap - buffered) {
@@ -2417,6 +2478,8 @@ void resolvent_op_destroy(resolvent_op* op) {
   }
   if (op->d_wsc) (void)hipFree(op->d_wsc);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
+  if (op->side_stream) (void)hipStreamDestroy(op->side_stream);
+  for (hipEvent_t e : op->side_ev) (void)hipEventDestroy(e);
   if (op->d_off) (void)hipFree(op->d_off);
   if (op->xch) retired_exchange_areas().push_back(op->xch);  // uncached memory is not freed (see march_1d)
   for (void* b : op->gbufs) (void)hipFree(b);

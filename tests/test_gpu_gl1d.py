@@ -385,3 +385,36 @@ def test_forcing_tiles_and_snapshot_flushes_match_oracle(method, precision, nw, 
         assert e[0] < 1e-10 and e[1] < 1e-10 and e[2] < 1e-12
     else:
         assert e[0] < 1e-3 and e[1] < 1e-3 and e[2] < 1e-5
+
+
+@pytest.mark.parametrize("method", ["periodic", "transient"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_table_synthesis_overlapping_the_march(method, precision, monkeypatch):
+    """The forcing table synthesised in chunks on a side stream while the first period's march consumes the chunks
+    already there (4,096 rows: chunks of 1,024, 2,048 and 1,024 rows) against the table synthesised whole before
+    the march (RESOLVENT_SYNTH_OVERLAP=0): the same bits (the chunks are whole tiles of the same GEMM), and the
+    oracle's run (1e-10, mixed 1e-3)."""
+    import torch
+    say("case: table synthesis overlapping the march,", method, precision)
+    n, h, P, nw, k = 300, 0.02, 4096, 5, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(15, nw, k, n)
+    dt = None
+    if precision == "mixed":
+        F = F.astype(np.complex64).astype(np.complex128)
+        dt = torch.complex64
+    kw = dict(periods=3, stride=16) if method == "periodic" else dict(tail=500)
+    outs = []
+    for overlap in ("0", "1"):
+        monkeypatch.setenv("RESOLVENT_SYNTH_OVERLAP", overlap)
+        op = gpu_gl(n, 0.2, -0.01, h, xl=-50.0, xr=50.0, precision=precision)
+        op.set_step_power(1)  # one table row per RK4 step: 4,096 rows
+        outs.append(to_np(op.apply(gpu_tensor(F, dt), op.grid(-0.4, dw, nw), op.run(method, **kw))))
+        torch.cuda.synchronize()
+        op.check()
+    L, _ = O_ops.gl_operator(n, 0.2, -0.01, xl=-50.0, xr=50.0)
+    ref = O_st.run(L, h, -0.4, dw, F, method, **kw)
+    e = per_freq_relerr(outs[1], ref)
+    say("  overlapped equals serial: %s, overlapped vs oracle %.2e" % (np.array_equal(outs[1], outs[0]), e))
+    assert np.array_equal(outs[1], outs[0])
+    assert e < (1e-10 if precision == "fp64" else 1e-3)
