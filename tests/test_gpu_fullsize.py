@@ -179,6 +179,61 @@ def test_adr3d3c_256x128x128_full_size_steady_state(precision):
     assert worst < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adr3d3c_256x128x128_full_size_modes(precision):
+    """Gains and modes of the block power iteration on the 3-D workload's full grid (k = 3, two frequencies,
+    periodic method with P = 100 and 60 periods: the transient is below e^-30 when the last period is projected;
+    one iteration in FP64, two in mixed precision so that the amplitude weighting runs).  R_d cannot be formed
+    here, so each returned triple is checked through what holds at any size: sigma u = R_d v, i.e. the RK4
+    steady-state equation e^{iwh}(sigma u) - P(Z)(sigma u) = h Q_w(Z) v evaluated by the oracle's sparse products
+    (relative to h Q_w(Z) v: 1e-10 FP64, 1e-4 mixed); V and U orthonormal per frequency (1e-12, 1e-5); gains
+    descending."""
+    import torch
+    import workloads as W
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import adr3d3c_coefficients
+    cfg = W.ADR3D
+    nx, ny, nz, h, k = cfg["nx"], cfg["ny"], cfg["nz"], cfg["h"], cfg["k"]
+    P, periods, nw, w0 = 100, 60, 2, 0.3
+    iters = 1 if precision == "fp64" else 2
+    dw = 2 * np.pi / (P * h)
+    say("case: full-size 3-D %d x %d x %d modes (P=%d, %d periods, %d iterations), %s" % (nx, ny, nz, P, periods,
+                                                                                        iters, precision))
+    wake = W.wake_parameters(cfg["seed"])
+    mu = np.full((nz, ny, nx), cfg["mu_const"])
+    c = adr3d3c_coefficients(nx, ny, nz, wake, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    op = ResolventOp.grid_operator("adr3d3c", nx, ny, nz, c, h, precision=precision)
+    N = 3 * nx * ny * nz
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    f0 = W.random_forcing_device(cfg["seed"] + 7, nw, k, N, dt, "cuda")
+    gains, V, U, _ = op.modes(f0, op.grid(w0, dw, nw), op.run("periodic", periods=periods, stride=1), iters,
+                              want_hist=False)
+    V = V.cpu().numpy().astype(np.complex128)
+    U = U.cpu().numpy().astype(np.complex128)
+    op.check()
+    del op, f0
+    release()
+    L, _ = O_ops.adr3d3c_operator(nx, ny, nz, wake, Re=cfg["Re"], mu=mu, nu_s=cfg["nu_s"])
+    tol_res, tol_orth = (1e-10, 1e-12) if precision == "fp64" else (1e-4, 1e-5)
+    worst_res = worst_orth = 0.0
+    for j in range(nw):
+        w = w0 + j * dw
+        g = gains[0, j]
+        say("  j=%d gains %s" % (j, np.array2string(g, precision=6)))
+        assert np.all(np.diff(g) <= 0) and np.all(g > 0)
+        for M in (V[j], U[j]):
+            G = M.conj() @ M.T
+            worst_orth = max(worst_orth, float(np.abs(G - np.eye(k)).max()))
+        for col in range(k):
+            r = O_dense.rk4_steady_residual(L, w, h, g[col] * U[j, col], V[j, col])
+            q = O_dense.rk4_steady_residual(L, w, h, np.zeros(N, np.complex128), V[j, col])  # -h Q_w(Z) v
+            e = float(np.linalg.norm(r) / np.linalg.norm(q))
+            worst_res = max(worst_res, e)
+            say("  j=%d col=%d  residual of sigma u = R_d v: %.2e" % (j, col, e))
+    say("  worst residual %.2e, worst orthonormality %.2e" % (worst_res, worst_orth))
+    assert worst_res < tol_res and worst_orth < tol_orth
+
+
 def test_adr2d_1024x512_full_size_reverse_mode():
     """The reverse mode at the 2-D workload's full size, in the run the bench times (transient method, 19,949
     forced steps and a tail of 15,000, 128 frequencies, k = 2, default checkpoints), on the FP64 operator.  The
