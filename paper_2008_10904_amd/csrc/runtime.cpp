@@ -123,6 +123,7 @@ struct resolvent_op {
   int64_t step_chunk = 0;                // owned unknowns per workgroup (0: whole column in one workgroup)
   int cur_state = 0;                     // which of the two state buffers holds the current state
   bool step_persist = false;             // one cooperative launch per march, neighbour exchange in-kernel
+  bool coop_refused = false;             // the device refused a cooperative launch: relaunch at every exchange
   void* xch = nullptr;                   // uncached exchange rows of the persistent stepper
   size_t xch_bytes = 0;
   // 2-D / 3-D structured-grid operator: host coefficients of Z = h L (FP64) and device copies of Z and Z^H
@@ -748,7 +749,7 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
   const bool halo = op->step_block > 0;
   if (op->step_block % mstep != 0) return fail(RES_EINVAL, "exchange interval not a multiple of the step power");
   const int64_t kblock = op->step_block / mstep;  // kernel steps between exchanges
-  bool persist = op->step_persist && kblock % step1d_prefetch(op->step_cfg) == 0;
+  bool persist = op->step_persist && kblock % step1d_prefetch(op->step_cfg) == 0 && !op->coop_refused;
   void* xbuf = nullptr;
   if (persist) {
     int dev = 0;
@@ -816,11 +817,22 @@ int march_1d(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Snap
     a.spin_ns = 2000000000ull;
     a.err = op->d_flag;
     int rc;
-    {
+    if (persist && env_long("RESOLVENT_REFUSE_COOPERATIVE", 0) != 0) {
+      rc = -2;  // the refusal a device can give, forced from the host (tests of the fallback below)
+    } else {
       TimedLaunch tl(op, RES_TIMING_STEPPER, st);
       rc = launch_step1d(a, st);
     }
-    if (rc) return fail(RES_EHIP, "stepper launch failed (" + std::to_string(rc) + ")");
+    if (rc) {
+      (void)hipGetLastError();  // report the failed launch once, not again from the next call's error check
+      if (persist && rc == -2 && !op->capturing) {
+        // The device refused the cooperative launch (its co-residency resources may be held by another process):
+        // nothing ran, so march with a relaunch at every exchange instead, for the rest of the handle's life.
+        op->coop_refused = true;
+        return march_1d(op, k, n, fs, ss, dsegs, nseg, st, mstep);
+      }
+      return fail(RES_EHIP, "stepper launch failed (" + std::to_string(rc) + ")");
+    }
     if (halo && !persist) op->cur_state = 1 - op->cur_state;
   }
   HIP_TRY(hipGetLastError());
@@ -1446,6 +1458,9 @@ int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best
   HIP_TRY(hipEventCreate(&e1));
   double best_ms = -1;
   int rc = RES_OK;
+  // a candidate whose launch the device refuses (a persistent grid that cannot be co-resident beside other work)
+  // is skipped; the plan in effect before the search comes back if none runs
+  const PlanCand before{op->step_cfg, op->step_chunk, op->step_block, op->step_persist ? 1 : 0};
   for (const PlanCand& c : plan_candidates(op)) {
     if (c.block % M != 0) continue;
     if (apply_plan(op, c.cfg, c.chunk, c.block, c.persist) != RES_OK) {
@@ -1455,7 +1470,12 @@ int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best
     void* dsegs;
     int64_t nseg;
     if ((rc = upload_regions(op, k, &dsegs, &nseg, st)) != RES_OK) break;
-    if ((rc = march_1d(op, k, ksteps, fs, SnapSpec(), dsegs, nseg, st, M)) != RES_OK) break;  // warm-up
+    if ((rc = march_1d(op, k, ksteps, fs, SnapSpec(), dsegs, nseg, st, M)) != RES_OK) {  // warm-up
+      if (rc != RES_EHIP || g_last_error.compare(0, 21, "stepper launch failed") != 0) break;
+      g_last_error.clear();
+      rc = RES_OK;
+      continue;
+    }
     double ms = -1;
     for (int rep = 0; rep < 2 && rc == RES_OK; ++rep) {  // the faster of two timed marches
       if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(RES_EHIP, "event record"); break; }
@@ -1477,8 +1497,13 @@ int tune_1d(resolvent_op* op, int k, int64_t steps, PlanCand* best, double* best
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   op->timing = timing;
-  if (rc != RES_OK) return rc;
-  if (best_ms < 0) return fail(RES_ENOTSUP, "no stepper plan fits this operator");
+  if (rc != RES_OK || best_ms < 0) {
+    const std::string err = g_last_error;
+    (void)apply_plan(op, before.cfg, before.chunk, before.block, before.persist);
+    g_last_error = err;
+    if (rc != RES_OK) return rc;
+    return fail(RES_ENOTSUP, "no stepper plan fits this operator");
+  }
   *best_us = best_ms * 1e3 / (double)steps;
   return apply_plan(op, best->cfg, best->chunk, best->block, best->persist);
 }

@@ -418,3 +418,33 @@ def test_table_synthesis_overlapping_the_march(method, precision, monkeypatch):
     say("  overlapped equals serial: %s, overlapped vs oracle %.2e" % (np.array_equal(outs[1], outs[0]), e))
     assert np.array_equal(outs[1], outs[0])
     assert e < (1e-10 if precision == "fp64" else 1e-3)
+
+
+def test_refused_cooperative_launch_falls_back_to_relaunches(monkeypatch):
+    """When the device refuses the persistent (cooperative) launch, which it may when another process holds its
+    co-residency resources, the march relaunches at every exchange instead, for the rest of the handle's life:
+    the same bits as the persistent form.  The refusal is forced from the host (RESOLVENT_REFUSE_COOPERATIVE)."""
+    import torch
+    from paper_2008_10904_amd import ResolventOp
+    from paper_2008_10904_amd.operators import gl_coefficients
+    say("case: refused cooperative launch, plan 13,256,32")
+    n, h, P, nw, k = 2000, 0.001, 4096, 4, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(13, nw, k, n)
+    lo, d, up = gl_coefficients(n, 0.38, -0.01)
+    monkeypatch.setenv("RESOLVENT_STEP1D", "13,256,32")
+    outs = []
+    for refuse in ("0", "1"):
+        monkeypatch.setenv("RESOLVENT_REFUSE_COOPERATIVE", refuse)
+        op = ResolventOp.tridiagonal(lo, d, up, h)
+        assert op.get_plan()[3] == 1  # persistent plan asked for
+        grid, run = op.grid(-3.0, dw, nw), op.run("periodic", periods=2, stride=64)
+        outs.append(to_np(op.apply(gpu_tensor(F), grid, run)))
+        if refuse == "1":  # the handle keeps relaunching once refused
+            monkeypatch.setenv("RESOLVENT_REFUSE_COOPERATIVE", "0")
+            again = to_np(op.apply(gpu_tensor(F), grid, run))
+            assert np.array_equal(again, outs[0])
+        torch.cuda.synchronize()
+        op.check()
+    say("  refused vs persistent identical:", np.array_equal(outs[1], outs[0]))
+    assert np.array_equal(outs[1], outs[0])

@@ -46,6 +46,13 @@ def test_host_part_under_sanitizers():
 
 @pytest.mark.gpu
 def test_every_entry_point_under_host_sanitizers():
+    """The driver runs in a process of its own beside this one, which may already hold device memory and the
+    device's cooperative-launch resources from earlier tests: the library then marches without persistent
+    launches (it falls back to a relaunch at every exchange when the device refuses one)."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
     print("case: sanitized ABI driver, GPU part", flush=True)
     out = run(["--gpu"], 300)
     assert "host and GPU parts: 0 failure(s)" in out
