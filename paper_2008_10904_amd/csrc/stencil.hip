@@ -13,6 +13,9 @@
 // G_j = h Q_j(Z) F_j, built by three Horner passes of the same stencil; see step1d.hip).  2-D one-component
 // operators run the whole step in one launch (grid_step2d_kernel); 3-D three-component operators run two launches
 // of two stages each, marching along z (grid_pair3d_kernel).
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 #include "gridz.h"
@@ -343,13 +346,13 @@ template <int DIR> __device__ __forceinline__ float lane_shift(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), DIR == 0 ? 0x138 : 0x130, 0xf, 0xf, true));
 }
 
-template <int TY, int KV>
+template <int TY, int KV, bool ZS>
 __global__ __launch_bounds__(64 * TY) void grid_step3d_kernel(GridCoef<float> Cf, const LineCoef8* __restrict__ lc,
                                                               int64_t nx, int64_t ny, int64_t nz, int64_t ncol,
                                                               const cx<float>* __restrict__ u,
                                                               cx<float>* __restrict__ out,
                                                               const cx<float>* __restrict__ frc, float phr, float phi,
-                                                              cx<float>* __restrict__ snap) {
+                                                              cx<float>* __restrict__ snap, int nzc) {
   constexpr int H = 4, TX = 64, OX = TX - 2 * H, OY = TY - 2 * H, NC = 3;
   __shared__ cx<float> Ls[4][NC][TY][TX];
   __shared__ cx<float> Us[2][NC][TY][TX];
@@ -358,12 +361,24 @@ __global__ __launch_bounds__(64 * TY) void grid_step3d_kernel(GridCoef<float> Cf
   // 32-bit offsets inside one column (the launcher checks 3 * nodes < 2^31); 64-bit only for the column base
   const int nodes = (int)(nx * ny * nz), sz = (int)(nx * ny), nx32 = (int)nx, ny32 = (int)ny, nz32 = (int)nz;
   // Tile order: workgroups are dealt to the eight XCDs in turn (id mod 8); each XCD takes a contiguous run of
-  // tiles (x fastest, then y, then column), so tiles whose halos overlap march side by side and share its L2.
-  const int64_t gx = (nx + OX - 1) / OX, gy = (ny + OY - 1) / OY, ntile = gx * gy * ncol;
+  // tiles (z chunk fastest, then x, then y, then column), so tiles whose halos overlap march side by side and
+  // share its L2.
+  // (ZS: the planes are split into nzc chunks; without it nzc is 1 and the chunk logic compiles away)
+  if (!ZS) nzc = 1;
+  const int64_t gx = (nx + OX - 1) / OX, gy = (ny + OY - 1) / OY, ntile = gx * gy * ncol * nzc;
   const int64_t tile = (int64_t)(blockIdx.x & 7) * ((ntile + 7) / 8) + (blockIdx.x >> 3);
   if (tile >= ntile) return;  // padding of the grid to a multiple of 8 (whole workgroup)
-  const int tx = (int)(tile % gx), ty = (int)((tile / gx) % gy);
-  const int64_t b = tile / (gx * gy);
+  const int zcix = ZS ? (int)(tile % nzc) : 0;
+  const int64_t xyb = ZS ? tile / nzc : tile;
+  const int tx = (int)(xyb % gx), ty = (int)((xyb / gx) % gy);
+  const int64_t b = xyb / (gx * gy);
+  // z chunk [z0, z1) of the output planes; a chunk after the first starts its march two planes early and
+  // discards the outputs below z0 (stage 4 at plane z0 needs stage 1 from plane z0 - 3 on, which needs u from
+  // plane z0 - 4); every output node gets the same arithmetic as in a single chunk
+  const int zlen = ZS ? (int)((nz + nzc - 1) / nzc) : (int)nz;
+  const int z0 = ZS ? zcix * zlen : 0, z1 = ZS ? min((int)nz, z0 + zlen) : (int)nz;
+  if (ZS && z0 >= (int)nz) return;  // whole workgroup
+  const int a_start = (!ZS || zcix == 0) ? 0 : z0 - 2, a_end = z1 + 4;
   const int x0w = tx * OX - H;                      // first window column (uniform)
   const int ix = x0w + lx, iy = ty * OY - H + wy;   // iy uniform
   const bool yin = iy >= 0 && iy < ny32;            // uniform
@@ -479,7 +494,7 @@ __global__ __launch_bounds__(64 * TY) void grid_step3d_kernel(GridCoef<float> Cf
     else zero3(v3N);
     if (row_ok(4) && zin(a - 4)) {
       V3 r = stage(3, a - 4, v3Zm, v3C, v3N, u4, d4, 1.f);
-      if (interior) {
+      if (interior && (!ZS || a - 4 >= z0)) {
         const int e = (a - 4) * sz;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -515,16 +530,25 @@ __global__ __launch_bounds__(64 * TY) void grid_step3d_kernel(GridCoef<float> Cf
   V3 A, B, C, P1, Q1, R1, P2, Q2, R2, P3, Q3, R3;
   zero3(A); zero3(B); zero3(C);
   zero3(P1); zero3(Q1); zero3(R1); zero3(P2); zero3(Q2); zero3(R2); zero3(P3); zero3(Q3); zero3(R3);
+  // entry state of step a_start: u(a_start), u(a_start - 1), u(a_start - 2) (zero outside the grid), stage buffer 0
+  // = u(a_start - 1), the diagonal of plane a_start - 1
   if (yin) {
-    A = ld3(ucol, 0);  // u(0); u(-1) = u(-2) = 0
+    if (zin(a_start)) A = ld3(ucol, a_start);
+    if (zin(a_start - 1)) B = ld3(ucol, a_start - 1);
+    if (zin(a_start - 2)) C = ld3(ucol, a_start - 2);
     mask_x(A);
+    mask_x(B);
+    mask_x(C);
   }
+  if (zin(a_start - 1)) d1 = Cf.d[(int64_t)(a_start - 1) * sz + pxy];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < NC; ++c) {
+    Ls[0][c][wy][lx] = B.c[c];
 #pragma unroll
-    for (int S = 0; S < 4; ++S) Ls[S][c][wy][lx] = zero;
-  const int steps = nz32 + 4;
-  int a = 0;
+    for (int S = 1; S < 4; ++S) Ls[S][c][wy][lx] = zero;
+  }
+  const int steps = a_end;
+  int a = a_start;
   for (; a + 2 < steps; a += 3) {
     step(a, A, B, C, P1, Q1, R1, P2, Q2, R2, P3, Q3, R3);
     step(a + 1, C, A, B, Q1, R1, P1, Q2, R2, P2, Q3, R3, P3);
@@ -669,14 +693,32 @@ int launch_grid_step3d(const GridOpDev& g, int k, const void* uin, void* uout, c
                        double phi, void* snap, hipStream_t st) {
   constexpr int TY = 16;  // 16 waves: a 64 x 16 window, 56 x 8 output nodes per plane
   if (g.ncomp != 3 || k < 1 || 3 * g.nx * g.ny * g.nz >= ((int64_t)1 << 31)) return -1;
-  const int64_t tiles = ((g.nx + 55) / 56) * ((g.ny + TY - 9) / (TY - 8)) * k;
+  const int64_t xy_tiles = ((g.nx + 55) / 56) * ((g.ny + TY - 9) / (TY - 8)) * k;
+  // A workgroup marches all the planes of its tile, one workgroup per CU: when the tiles do not fill the CUs (one
+  // column of the full 3-D grid: 80 tiles), the planes are split into chunks of at least 16 so that they do.
+  // RESOLVENT_STEP3D_ZCHUNKS fixes the number of chunks.
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(cus / std::max<int64_t>(1, xy_tiles), g.nz / 16));
+  if (const char* e = std::getenv("RESOLVENT_STEP3D_ZCHUNKS")) nzc = std::max(1, std::atoi(e));
+  nzc = (int)std::min<int64_t>(nzc, g.nz);
+  const int64_t tiles = xy_tiles * nzc;
   if (tiles > 0x7ffffff0) return -1;
   if (g.lc == nullptr) return -1;
   const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
 #define RES_S3(KV)                                                                                                \
-  hipLaunchKernelGGL((grid_step3d_kernel<TY, KV>), grid, dim3(64 * TY), 0, st, coef_of<float>(g, 0),             \
+  if (nzc > 1) RES_S3Z(KV, true); else RES_S3Z(KV, false)
+#define RES_S3Z(KV, ZS)                                                                                           \
+  hipLaunchKernelGGL((grid_step3d_kernel<TY, KV, ZS>), grid, dim3(64 * TY), 0, st, coef_of<float>(g, 0),         \
                      (const LineCoef8*)g.lc, g.nx, g.ny, g.nz, (int64_t)k, (const cx<float>*)uin, (cx<float>*)uout, \
-                     (const cx<float>*)frc, (float)phr, (float)phi, (cx<float>*)snap)
+                     (const cx<float>*)frc, (float)phr, (float)phi, (cx<float>*)snap, nzc)
   // coupling pattern: the shear terms of the first component (Z), their transpose (Z^H), none, or general
   switch (g.kv) {
     case 0: RES_S3(0); break;
@@ -685,6 +727,7 @@ int launch_grid_step3d(const GridOpDev& g, int k, const void* uin, void* uout, c
     default: RES_S3(3); break;
   }
 #undef RES_S3
+#undef RES_S3Z
   return 0;
 }
 

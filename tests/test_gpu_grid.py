@@ -126,6 +126,35 @@ def test_3d_fused_step_matches_oracle(shape):
     assert max(e) < 1e-4
 
 
+@pytest.mark.parametrize("shape,chunks", [((60, 9, 40), 3), ((70, 12, 64), 4), ((130, 21, 5), 2)])
+def test_3d_fused_step_in_z_chunks(shape, chunks, monkeypatch):
+    """The one-launch 3-D step with the planes split among workgroups (each chunk after the first starts its
+    march two planes early and discards the outputs below its first plane): the same bits as one chunk per tile,
+    for chunks of 14, 16 and 3 planes (the last one shorter than the pipeline depth), and the oracle's run."""
+    import torch
+    nx, ny, nz = shape
+    say("case: 3-D fused step in z chunks", shape, chunks)
+    op, L = make3d(nx, ny, nz, 0.1, "mixed")
+    h, P, nw, k = 0.1, 100, 2, 1
+    dw = 2 * np.pi / (P * h)
+    F = forcing(26, nw, k, op.n)
+    grid, run = op.grid(0.1, dw, nw), op.run("periodic", periods=2, stride=25)
+    outs = []
+    for nzc in ("1", str(chunks)):
+        monkeypatch.setenv("RESOLVENT_STEP3D_ZCHUNKS", nzc)
+        outs.append(to_np(op.apply(gpu_tensor(F, torch.complex64), grid, run)))
+        outs.append(to_np(op.adjoint_apply(gpu_tensor(F, torch.complex64), grid, run)))
+        torch.cuda.synchronize()
+    op.check()
+    Fr = F.astype(np.complex64).astype(np.complex128)
+    ref = O_st.run(L, h, 0.1, dw, Fr, "periodic", periods=2, stride=25)
+    e = per_freq_relerr(outs[2], ref)
+    say("  chunked equals one chunk: %s %s, vs oracle %.2e" % (np.array_equal(outs[2], outs[0]),
+                                                             np.array_equal(outs[3], outs[1]), e))
+    assert np.array_equal(outs[2], outs[0]) and np.array_equal(outs[3], outs[1])
+    assert e < 1e-4
+
+
 @pytest.mark.parametrize("case", ["2d", "3d"])
 def test_modes_match_oracle(case):
     import torch
