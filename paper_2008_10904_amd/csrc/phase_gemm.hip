@@ -12,7 +12,9 @@
 // incrementally (no division in the inner loop).
 //
 // Tiling: one 256-thread workgroup computes a 64 x 64 tile of the (complex) output; each wave owns a 32 x 32
-// quarter = 2 x 2 MFMA tiles, each complex tile being four real MFMAs (re*re - im*im, re*im + im*re).
+// quarter = 2 x 2 MFMA tiles.  In FP32 a complex tile is three real MFMAs (Gauss: P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2, formed in FP64 in the epilogue); in FP64 four
+// (re*re - im*im, re*im + im*re), since a third FP64 accumulator set would halve the waves per SIMD.
 // The generated phase operand and the data operand are staged through LDS 16 deep in K, loaded into registers
 // one chunk ahead of the matrix-core work.  Workgroups walk the M tiles of one column tile on one XCD.  The
 // projection can split K over gridDim.y, writing FP64 partial tiles that a reduction adds into the FP64
@@ -110,13 +112,15 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
     ph_im[tid] = sn;
   }
 
-  v4 cre[2][2], cim[2][2];
+  constexpr bool kGauss = sizeof(R) == 4;
+  v4 c1[2][2], c2[2][2], c3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      cre[i][j] = v4{0, 0, 0, 0};
-      cim[i][j] = v4{0, 0, 0, 0};
+      c1[i][j] = v4{0, 0, 0, 0};
+      c2[i][j] = v4{0, 0, 0, 0};
+      c3[i][j] = v4{0, 0, 0, 0};
     }
 
   // Operands of one K chunk are loaded into registers one chunk ahead, so that the table gathers and data loads
@@ -196,13 +200,12 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of this chunk's matrix-core work
 #pragma unroll
     for (int k4 = 0; k4 < GKC; k4 += 4) {
-      R are[2], aim[2], nai[2], bre[2], bim[2];
+      R are[2], aim[2], bre[2], bim[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int r = wm * 32 + t * 16 + (lane & 15);
         are[t] = As[0][r][k4 + (lane >> 4)];
         aim[t] = As[1][r][k4 + (lane >> 4)];
-        nai[t] = -aim[t];
         const int c = wn * 32 + t * 16 + (lane & 15);
         bre[t] = Bs[0][k4 + (lane >> 4)][c];
         bim[t] = Bs[1][k4 + (lane >> 4)][c];
@@ -211,10 +214,16 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          cre[i][j] = Mfma<R>::mac(are[i], bre[j], cre[i][j]);
-          cre[i][j] = Mfma<R>::mac(nai[i], bim[j], cre[i][j]);
-          cim[i][j] = Mfma<R>::mac(are[i], bim[j], cim[i][j]);
-          cim[i][j] = Mfma<R>::mac(aim[i], bre[j], cim[i][j]);
+          if (kGauss) {  // c1 = ArBr, c2 = AiBi, c3 = (Ar + Ai)(Br + Bi)
+            c1[i][j] = Mfma<R>::mac(are[i], bre[j], c1[i][j]);
+            c2[i][j] = Mfma<R>::mac(aim[i], bim[j], c2[i][j]);
+            c3[i][j] = Mfma<R>::mac(are[i] + aim[i], bre[j] + bim[j], c3[i][j]);
+          } else {  // c1 = re, c2 = im
+            c1[i][j] = Mfma<R>::mac(are[i], bre[j], c1[i][j]);
+            c1[i][j] = Mfma<R>::mac(-aim[i], bim[j], c1[i][j]);
+            c2[i][j] = Mfma<R>::mac(are[i], bim[j], c2[i][j]);
+            c2[i][j] = Mfma<R>::mac(aim[i], bre[j], c2[i][j]);
+          }
         }
     }
     __syncthreads();
@@ -231,7 +240,8 @@ __global__ __launch_bounds__(256) void phase_gemm_kernel(PhaseGemmArgs a) {
         const int cl = wn * 32 + j * 16 + (lane & 15);
         const int64_t row = m0 + rl, col = n0 + cl;
         if (row >= a.M || col >= a.Ncols) continue;
-        const double xr = (double)cre[i][j][v], xi = (double)cim[i][j][v];
+        const double p1 = (double)c1[i][j][v], p2 = (double)c2[i][j][v];
+        const double xr = kGauss ? p1 - p2 : p1, xi = kGauss ? (double)c3[i][j][v] - p1 - p2 : p2;
         if (MODE == 0) {
           const double pr = ph_re[rl], pi = ph_im[rl];
           cx<R>* out = (cx<R>*)a.out;
