@@ -21,6 +21,17 @@ template <> struct EmptyMark<float> {
   static constexpr U bits = 0x7FA5EA1Du;
 };
 
+// DS read instructions of the band product kept in flight per lane (V = 1 configurations), FP64 and FP32; 0 leaves
+// the schedule to the compiler.
+#ifndef RES_LDS_AHEAD64
+#define RES_LDS_AHEAD64 4
+#endif
+#ifndef RES_LDS_AHEAD32
+#define RES_LDS_AHEAD32 0
+#endif
+constexpr int kLdsAhead64 = RES_LDS_AHEAD64;
+constexpr int kLdsAhead32 = RES_LDS_AHEAD32;
+
 // One workgroup marches its region for n_steps kernel steps of MS RK4 steps each: the band is P(Z)^MS (radius
 // 4*MS) and each forcing row is the combined forcing of the MS steps it covers (see the pre-filter in
 // step1d.hip), so a kernel step is one exchange through LDS and one band product whatever MS is.  Thread t holds V consecutive unknowns of the region in
@@ -143,6 +154,22 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
       cx<R> acc = cadd(a[0], a[1]);
       if (NACC == 4) acc = cadd(acc, cadd(a[2], a[3]));
       u[v] = csel(valid[v], acc, zero);
+    }
+    constexpr int want = sizeof(R) == 8 ? kLdsAhead64 : kLdsAhead32;
+    if constexpr (V == 1 && want > 0) {
+      // Keep the next neighbour reads in flight: the first `ahead` DS reads go out together and each one after
+      // them follows the complex FMAs of one read's values (four VALU instructions per value).  Left to itself
+      // the scheduler keeps one read ahead, and every read's LDS latency then stalls the band product.  FP32
+      // pairs two values in one read (ds_read2_b64).
+      constexpr int per = sizeof(R) == 8 ? 1 : 2;
+      constexpr int nds = (BW + per - 1) / per;
+      constexpr int ahead = want < nds ? want : nds;
+      __builtin_amdgcn_sched_group_barrier(0x100, ahead, 0);  // DS reads
+#pragma unroll
+      for (int d = 0; d < nds - ahead; ++d) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 4 * per, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);        // DS read
+      }
     }
   };
 
