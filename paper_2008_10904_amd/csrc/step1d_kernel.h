@@ -21,8 +21,8 @@ template <> struct EmptyMark<float> {
   static constexpr U bits = 0x7FA5EA1Du;
 };
 
-// DS read instructions of the band product kept in flight per lane (V = 1 configurations), FP64 and FP32; 0 leaves
-// the schedule to the compiler.
+// DS read instructions of the band product kept in flight per lane (one unknown per thread, four RK4 steps per
+// kernel step, at most 512 threads), FP64 and FP32; 0 leaves the schedule to the compiler.
 #ifndef RES_LDS_AHEAD64
 #define RES_LDS_AHEAD64 4
 #endif
@@ -156,11 +156,13 @@ __global__ __launch_bounds__(NT) void step1d_kernel(const Seg1D* __restrict__ se
       u[v] = csel(valid[v], acc, zero);
     }
     constexpr int want = sizeof(R) == 8 ? kLdsAhead64 : kLdsAhead32;
-    if constexpr (V == 1 && want > 0) {
+    if constexpr (V == 1 && MS == 4 && NT <= 512 && want > 0) {
       // Keep the next neighbour reads in flight: the first `ahead` DS reads go out together and each one after
       // them follows the complex FMAs of one read's values (four VALU instructions per value).  Left to itself
       // the scheduler keeps one read ahead, and every read's LDS latency then stalls the band product.  FP32
-      // pairs two values in one read (ds_read2_b64).
+      // pairs two values in one read (ds_read2_b64).  Only the 33-diagonal band of four steps, with at least
+      // 256 VGPRs per lane: the shorter bands and the 1,024-thread workgroups (128 VGPRs, which already spill)
+      // ran slower with it.
       constexpr int per = sizeof(R) == 8 ? 1 : 2;
       constexpr int nds = (BW + per - 1) / per;
       constexpr int ahead = want < nds ? want : nds;
