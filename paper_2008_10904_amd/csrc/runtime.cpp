@@ -1080,12 +1080,18 @@ int run_1d(resolvent_op* op, const Plan& pl, int k, const void* in, int in_fp64,
   // for each chunk's event before it reaches the chunk's rows.  A row is synthesised in about half the time the
   // 1-D march takes to consume it, so the chunks double in size from 1,024 rows: only the first one is not
   // hidden.  Rows are independent, so every row gets the same value as from one GEMM over the whole table (chunk
-  // bounds are whole 64-row tiles).  Off under graph capture and in the no-allocation entry point, and for grid
-  // operators, whose step kernels occupy every CU; RESOLVENT_SYNTH_OVERLAP=0 turns it off.
+  // bounds are whole 64-row tiles).  Off under graph capture and in the no-allocation entry point, for grid
+  // operators, whose step kernels occupy every CU, and for marches whose workgroups take more than half the CUs:
+  // there the synthesis slows the march by more than it saves (the 64-instance batch in FP64: 2.84 s per iteration
+  // overlapped, 2.62 s not).  RESOLVENT_SYNTH_OVERLAP=0 turns it off.
   std::vector<int64_t> ov_bound;  // chunk c holds table rows [ov_bound[c], ov_bound[c + 1])
   int nov = 0;
-  if (table_mode && !op->capturing && !op->arena && !is_grid(op) && env_long("RESOLVENT_SYNTH_OVERLAP", 1) != 0 &&
-      table_rows >= 4096) {
+  int cus = 0;
+  if (table_mode && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, op->device) != hipSuccess)
+    cus = 0;
+  const bool cus_free = 2 * (int64_t)k * (int64_t)op->segs.size() <= (int64_t)cus;
+  if (table_mode && !op->capturing && !op->arena && !is_grid(op) && cus_free &&
+      env_long("RESOLVENT_SYNTH_OVERLAP", 1) != 0 && table_rows >= 4096) {
     ov_bound.push_back(0);
     for (int64_t len = 1024; ov_bound.back() < table_rows; len *= 2)
       ov_bound.push_back(std::min(table_rows, ov_bound.back() + len));
