@@ -108,6 +108,17 @@ typedef struct {
   int32_t n_omega;
 } resolvent_grid;
 
+/* The grid of an array of n_omega >= 2 analysis frequencies (host, ascending or descending): the array must be
+ * uniform (every entry within 1e-9 |domega| of omega[0] + j domega with domega = (omega[n-1] - omega[0]) / (n - 1)).
+ * The spacing is snapped to 2 pi / (P h) with P the multiple of `stride` (>= 1, the projection stride of a
+ * periodic run; 1 otherwise) nearest 2 pi / (|domega| h), as the time grid of Sec. 2.3 requires (eq. fourier's
+ * frequencies are the harmonics of the period P h); omega0 = omega[0].  *out gets the snapped grid and *P_out
+ * (may be NULL) the period in steps.  Host only, no device call.  RES_EINVAL for NULL arguments, h <= 0 or
+ * stride < 1; RES_EGRID for n_omega < 2, a non-uniform or non-finite array, equal end points, or a snapped P
+ * with fewer than n_omega steps. */
+int resolvent_grid_from_omegas(const double* omega, int32_t n_omega, double h, int64_t stride,
+                               resolvent_grid* out, int64_t* P_out);
+
 /* Schedule of one run (one application of R_d or R_d^H). */
 typedef struct {
   int32_t method;            /* RES_TRANSIENT or RES_PERIODIC                                          */
@@ -154,6 +165,13 @@ int resolvent_apply(resolvent_op* op, const resolvent_grid* grid, const resolven
 int resolvent_apply_noalloc(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                             const void* f_hat, void* u_hat, void* stream);
 
+/* Smallest device workspace, in bytes, that resolvent_apply_noalloc needs for this grid, run and k (the layout
+ * with the shortest tiles and flushes; given more room, it takes longer ones), so that a caller can tell before
+ * the call whether the run fits RESOLVENT_NOALLOC_SCRATCH_BYTES.  Host only: no device call, no allocation.
+ * Errors as resolvent_apply's argument checks (RES_EINVAL, RES_EGRID). */
+int resolvent_workspace_size(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                             size_t* bytes);
+
 /* z_hat[j] = R_d(w_j)^H g_hat[j]: the adjoint run (Sec. 2.1, eq. adsystemFreqDomain): L^H marched with the
  * frequencies negated (equivalent to the paper's backward integration in reversed time). */
 int resolvent_adjoint_apply(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
@@ -168,7 +186,8 @@ int resolvent_adjoint_apply(resolvent_op* op, const resolvent_grid* grid, const 
  * V, U:   device [n_omega][k][N] force and response modes (each up to a common unit-modulus factor), or NULL.
  * hist:   host double [iters][ninst][n_omega][k][2] or NULL: per iteration the Rayleigh-Ritz gains and the
  *         norm-ratio estimate sqrt(||F_hat_i||) of eq. tildeSig.
- * Synchronises `stream`.  k <= 8. */
+ * Synchronises `stream`.  k <= 8.  Returns what the device flagged during the call, as resolvent_op_check
+ * does: RES_ENONFINITE for non-finite values or a rank-deficient QR block, RES_EHIP for an abandoned exchange. */
 int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                     int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
                     void* stream);
@@ -185,7 +204,7 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
  * V, U:   device [n_omega][k][N] force and response modes (each up to a unit-modulus factor), or NULL.
  * hist:   host double [blocks][ninst][n_omega][k] or NULL: the estimates after each block.
  * Synchronises `stream`.  k <= 8, blocks * k <= 40 and at most the unknowns of every instance; RES_EINVAL
- * otherwise. */
+ * otherwise.  Reports the device's flags as resolvent_modes does. */
 int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
                      int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
                      void* stream);
@@ -334,7 +353,7 @@ int resolvent_op_get_timing(resolvent_op* op, int32_t kind, double* total_ms, in
  * may be NULL) receive the force and response modes of the last iteration, F(w_j) / ||F(w_j)|| and
  * Y(w_j) / ||Y(w_j)|| (for k = 1 the leading modes at any analysis frequency).  The flattening response spans the square of the gain range,
  * more than one windowed filter realises when gains differ by 1e3 (passes = 2 realises 1e6).  Synchronises
- * `stream` every iteration and cannot be captured.  Errors as resolvent_signal_run, and RES_EINVAL for
+ * `stream` every iteration and cannot be captured; reports the device's flags as resolvent_modes does.  Errors as resolvent_signal_run, and RES_EINVAL for
  * n_omega < 1, iters < 1, a bad order, a taper that leaves no sample at one or frequencies beyond Nyquist. */
 int resolvent_signal_run(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
                          int32_t adjoint, const void* f, void* y, void* stream);

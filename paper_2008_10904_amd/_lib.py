@@ -2,7 +2,7 @@
 library).  The structures mirror include/resolvent.h field for field."""
 import ctypes
 import os
-from ctypes import POINTER, c_double, c_int32, c_int64, c_uint64, c_void_p
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libresolvent.so")
@@ -12,6 +12,7 @@ RES_OP_TRIDIAG, RES_OP_ADR2D, RES_OP_ADR3D3C = 1, 2, 3
 RES_FP64, RES_MIXED = 0, 1
 RES_TRANSIENT, RES_PERIODIC = 0, 1
 RES_TIMING_STEPPER, RES_TIMING_SYNTHESIS, RES_TIMING_PROJECTION, RES_TIMING_QR = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 256 << 20  # RESOLVENT_NOALLOC_SCRATCH_BYTES: the no-allocation apply's fixed workspace
 
 _dp = POINTER(c_double)
 
@@ -43,6 +44,8 @@ SIGNATURES = {
     "resolvent_apply": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p, c_void_p]),
     "resolvent_apply_noalloc": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                           c_void_p]),
+    "resolvent_workspace_size": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, POINTER(c_size_t)]),
+    "resolvent_grid_from_omegas": (c_int32, [_dp, c_int32, c_double, c_int64, POINTER(Grid), POINTER(c_int64)]),
     "resolvent_adjoint_apply": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_void_p, c_void_p,
                                           c_void_p]),
     "resolvent_modes": (c_int32, [c_void_p, POINTER(Grid), POINTER(Run), c_int32, c_int32, c_void_p, _dp,

@@ -147,6 +147,14 @@ class ResolventOp:
                                                 self._stream_ptr()))
         return out
 
+    def workspace_size(self, grid, run, k):
+        """Smallest device workspace (bytes) apply_noalloc needs for this grid, run and column count (host
+        computation; compare with _lib.NOALLOC_SCRATCH_BYTES)."""
+        n = ctypes.c_size_t(0)
+        check(self._lib.resolvent_workspace_size(self._h, ctypes.byref(grid), ctypes.byref(run), int(k),
+                                                 ctypes.byref(n)))
+        return int(n.value)
+
     def adjoint_apply(self, g_hat, grid, run, out=None):
         """z_hat[j] = R_d(w_j)^H g_hat[j] in one adjoint run."""
         return self._apply(g_hat, grid, run, out, adjoint=True)
@@ -369,6 +377,17 @@ class ResolventOp:
         if want_modes:
             return gains, amps, fo, V, U
         return gains, amps, fo
+
+
+def grid_from_omegas(omegas, h, stride=1):
+    """(Grid, P) for an array of uniformly spaced analysis frequencies: the spacing snapped to 2 pi / (P h) with P
+    the multiple of `stride` nearest 2 pi / (|domega| h); host computation in the library."""
+    lib = _lib.load()
+    w = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64).ravel())
+    g = Grid()
+    P = ctypes.c_int64(0)
+    check(lib.resolvent_grid_from_omegas(_dptr(w), len(w), float(h), int(stride), ctypes.byref(g), ctypes.byref(P)))
+    return g, int(P.value)
 
 
 def fir_design(order, nu, gain):

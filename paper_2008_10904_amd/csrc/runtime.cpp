@@ -2568,8 +2568,8 @@ int resolvent_adjoint_apply(resolvent_op* op, const resolvent_grid* grid, const 
   return apply_common(op, grid, run, k, g_hat, z_hat, -1, (hipStream_t)stream);
 }
 
-int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
-                    int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+static int modes_body(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                      int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
                     void* stream) {
   g_last_error.clear();
   if (!op || !f0_hat || !gains) return fail(RES_EINVAL, "NULL argument");
@@ -2717,8 +2717,8 @@ int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolven
 // W_i = R_d^H R_d B_i and the coefficients C_b = B_b^H W_i taken twice (classical Gram-Schmidt, two passes).  The
 // first-pass coefficients fill the upper block triangle of H = B^H R_d^H R_d B; the estimates come from the
 // eigen-decomposition of its Hermitian completion: gains sqrt(lambda), V = B psi, U = R_d B psi / gain.
-int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
-                     int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+static int krylov_body(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                       int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
                      void* stream) {
   g_last_error.clear();
   if (!op || !f0_hat || !gains) return fail(RES_EINVAL, "NULL argument");
@@ -2882,6 +2882,60 @@ int resolvent_signal_run(resolvent_op* op, int32_t k, int64_t n_samples, int32_t
   return RES_OK;
 }
 
+int resolvent_grid_from_omegas(const double* omega, int32_t n_omega, double h, int64_t stride,
+                               resolvent_grid* out, int64_t* P_out) {
+  g_last_error.clear();
+  if (!omega || !out) return fail(RES_EINVAL, "NULL argument");
+  if (!(h > 0) || !std::isfinite(h)) return fail(RES_EINVAL, "h must be positive");
+  if (stride < 1) return fail(RES_EINVAL, "stride must be >= 1");
+  if (n_omega < 2) return fail(RES_EGRID, "an array of fewer than two frequencies fixes no spacing");
+  for (int32_t j = 0; j < n_omega; ++j)
+    if (!std::isfinite(omega[j])) return fail(RES_EGRID, "non-finite frequency");
+  const double dw_nom = (omega[n_omega - 1] - omega[0]) / (double)(n_omega - 1);
+  if (dw_nom == 0) return fail(RES_EGRID, "equal end frequencies");
+  for (int32_t j = 0; j < n_omega; ++j)
+    if (std::fabs(omega[j] - (omega[0] + j * dw_nom)) > 1e-9 * std::fabs(dw_nom))
+      return fail(RES_EGRID, "frequency " + std::to_string(j) + " is off the uniform grid of its end points");
+  // the period P h of the time grid must be 2 pi / |domega|: P is the multiple of the stride nearest that
+  const double per = 2.0 * M_PI / (std::fabs(dw_nom) * h * (double)stride);
+  if (!(per < 4e18)) return fail(RES_EGRID, "spacing too small for the time step");
+  const int64_t P = stride * std::max<int64_t>(1, std::llround(per));
+  if (P < n_omega) return fail(RES_EGRID, "more frequencies than steps per period (aliasing)");
+  out->omega0 = omega[0];
+  out->domega = std::copysign(2.0 * M_PI / ((double)P * h), dw_nom);
+  out->n_omega = n_omega;
+  if (P_out) *P_out = P;
+  return RES_OK;
+}
+
+int resolvent_workspace_size(resolvent_op* op, const resolvent_grid* g, const resolvent_run* r, int32_t k,
+                             size_t* bytes) {
+  g_last_error.clear();
+  if (!op || !g || !r || !bytes) return fail(RES_EINVAL, "NULL argument");
+  if (k < 1) return fail(RES_EINVAL, "k must be >= 1");
+  Plan pl;
+  RES_TRY(make_plan(op, g, r, &pl));
+  // The no-allocation apply fits its flexible buffers (forcing tiles, snapshot rows, pre-filter chunks) to the
+  // capacity it is given and refuses a capacity below the smallest layout: find the smallest capacity (to 256
+  // bytes) it accepts, by doubling and then bisection.
+  ArenaSizes z;
+  size_t lo = 0, hi = (size_t)1 << 20;
+  while (arena_sizes(op, pl, k, hi, &z) != RES_OK) {
+    if (hi >= ((size_t)1 << 52)) return fail(RES_EINVAL, "workspace size out of range");
+    lo = hi;
+    hi *= 2;
+  }
+  while (hi - lo > 256) {
+    size_t mid = lo + (hi - lo) / 2;
+    mid -= mid % 256;
+    if (mid <= lo) break;
+    if (arena_sizes(op, pl, k, mid, &z) == RES_OK) hi = mid; else lo = mid;
+  }
+  g_last_error.clear();
+  *bytes = hi;
+  return RES_OK;
+}
+
 int resolvent_fir_design(int32_t order, int32_t npts, const double* nu, const double* gain, double* taps) {
   g_last_error.clear();
   if (!taps) return fail(RES_EINVAL, "NULL argument");
@@ -2905,7 +2959,7 @@ int resolvent_fir_apply(int32_t fp64, int64_t n_t, int64_t ncols, int32_t order,
   return RES_OK;
 }
 
-int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
+static int trm_modes_body(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
                         const void* f0, int32_t n_omega, const double* omegas, int32_t iters, int32_t order,
                         int32_t passes, int64_t pad, int64_t ramp, double margin, double* gains, double* amps,
                         void* f_out, void* V, void* U, void* stream) {
@@ -3062,6 +3116,31 @@ int resolvent_op_check(resolvent_op* op, void* stream) {
     return fail(RES_ENONFINITE, "non-finite values in a result");
   }
   return RES_OK;
+}
+
+// The iterations return host data and synchronise their stream anyway, so they report what the device flagged
+// during the call (non-finite values, a rank-deficient QR block, an abandoned neighbour exchange) themselves.
+int resolvent_modes(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                    int32_t iters, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                    void* stream) {
+  const int rc = modes_body(op, grid, run, k, iters, f0_hat, gains, V, U, hist, stream);
+  return rc == RES_OK ? resolvent_op_check(op, stream) : rc;
+}
+
+int resolvent_krylov(resolvent_op* op, const resolvent_grid* grid, const resolvent_run* run, int32_t k,
+                     int32_t blocks, const void* f0_hat, double* gains, void* V, void* U, double* hist,
+                     void* stream) {
+  const int rc = krylov_body(op, grid, run, k, blocks, f0_hat, gains, V, U, hist, stream);
+  return rc == RES_OK ? resolvent_op_check(op, stream) : rc;
+}
+
+int resolvent_trm_modes(resolvent_op* op, int32_t k, int64_t n_samples, int32_t every, int32_t scheme,
+                        const void* f0, int32_t n_omega, const double* omegas, int32_t iters, int32_t order,
+                        int32_t passes, int64_t pad, int64_t ramp, double margin, double* gains, double* amps,
+                        void* f_out, void* V, void* U, void* stream) {
+  const int rc = trm_modes_body(op, k, n_samples, every, scheme, f0, n_omega, omegas, iters, order, passes, pad,
+                                ramp, margin, gains, amps, f_out, V, U, stream);
+  return rc == RES_OK ? resolvent_op_check(op, stream) : rc;
 }
 
 }  // extern "C"

@@ -49,6 +49,24 @@ void check_host_part() {
   expect("fir_design NULL taps", resolvent_fir_design(64, 4, nu, gain, nullptr), RES_EINVAL);
   const double bad_nu[4] = {-1.0, 0.5, -0.5, 1.0};
   expect("fir_design unordered breakpoints", resolvent_fir_design(64, 4, bad_nu, gain, taps.data()), RES_EINVAL);
+  // grid of an array of frequencies (host only)
+  {
+    std::vector<double> w(256);
+    for (int j = 0; j < 256; ++j) w[j] = -3.0 + j * (6.0 / 255.0);
+    resolvent_grid g;
+    int64_t P = 0;
+    expect("grid_from_omegas", resolvent_grid_from_omegas(w.data(), 256, 0.001, 256, &g, &P), RES_OK);
+    if (P % 256 != 0 || g.n_omega != 256 || std::fabs(std::fabs(g.domega) * P * 0.001 - 2.0 * M_PI) > 1e-12) {
+      std::printf("FAIL grid_from_omegas: P %lld, domega %.17g\n", (long long)P, g.domega);
+      ++g_failures;
+    }
+    expect("grid_from_omegas one frequency", resolvent_grid_from_omegas(w.data(), 1, 0.001, 1, &g, &P), RES_EGRID);
+    expect("grid_from_omegas NULL out", resolvent_grid_from_omegas(w.data(), 256, 0.001, 1, nullptr, &P),
+           RES_EINVAL);
+    w[100] += 1e-3;
+    expect("grid_from_omegas non-uniform", resolvent_grid_from_omegas(w.data(), 256, 0.001, 1, &g, nullptr),
+           RES_EGRID);
+  }
   // descriptors rejected before any device work
   resolvent_op* op = nullptr;
   expect("op_create NULL desc", resolvent_op_create(nullptr, nullptr, &op), RES_EINVAL);
@@ -131,6 +149,13 @@ void exercise_runs(resolvent_op* op, const char* name, int64_t N, int fp64, int6
          RES_OK);
   std::snprintf(what, sizeof(what), "%s backward, forcing only", name);
   expect(what, resolvent_apply_backward(op, &g, &per, k, f.p, z.p, fg.p, nullptr, 0, nullptr), RES_OK);
+  size_t wsb = 0;
+  std::snprintf(what, sizeof(what), "%s workspace size", name);
+  expect(what, resolvent_workspace_size(op, &g, &per, k, &wsb), RES_OK);
+  if (wsb == 0 || wsb > RESOLVENT_NOALLOC_SCRATCH_BYTES) {
+    std::printf("FAIL %s: %zu bytes\n", what, wsb);
+    ++g_failures;
+  }
   std::snprintf(what, sizeof(what), "%s noalloc apply", name);
   expect(what, resolvent_apply_noalloc(op, &g, &per, k, f.p, u.p, nullptr), RES_OK);
   std::snprintf(what, sizeof(what), "%s check", name);
