@@ -10,7 +10,9 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libresolvent.so")
 SOURCES = ["step1d.hip", "step1d_m2.hip", "step1d_m4.hip", "stencil.hip", "phase_gemm.hip", "qr.hip", "krylov.hip", "adjoint.hip",
-           "trm.hip", "noalloc.hip", "runtime.cpp"]
+           "trm.hip", "noalloc.hip", "runtime.cpp", "runs.cpp", "iterations.cpp", "backward.cpp", "trm_host.cpp"]
+HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]  # the host runtime
+EXPORTS = os.path.join(CSRC, "exports.map")  # the library exports the C ABI only
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RESOLVENT_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
@@ -36,7 +38,7 @@ def build(verbose=True):
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Wl,--version-script=" + EXPORTS, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
@@ -58,7 +60,7 @@ ABI_CHECK = os.path.join(HERE, "abi_check_asan")  # beside the library (the obje
 def build_abi_check(verbose=True):
     os.makedirs(OBJ, exist_ok=True)
     objs = []
-    for src in (os.path.join(CSRC, "runtime.cpp"), ABI_CHECK_SRC):
+    for src in [os.path.join(CSRC, h) for h in HOST_SOURCES] + [ABI_CHECK_SRC]:
         obj = os.path.join(OBJ, os.path.basename(src) + ".asan.o")
         cmd = [HIPCC, "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
                "--offload-arch=" + ARCH] + SANITIZE + ["-c", src, "-o", obj]
