@@ -237,9 +237,11 @@ def test_adr3d3c_256x128x128_full_size_modes(precision):
 def test_adr2d_1024x512_full_size_reverse_mode():
     """The reverse mode at the 2-D workload's full size, in the run the bench times (transient method, 19,949
     forced steps and a tail of 15,000, 128 frequencies, k = 2, default checkpoints), on the FP64 operator.  The
-    forcing gradient A^H g must satisfy the duality <A^H g, d> = <g, A d> with the library's own forward apply; the
-    mu gradient must match, along a random direction, central differences of J(mu) = Re <g, A(mu) f> from two
-    forward applies with the diagonal moved by -+ eps d."""
+    forcing gradient A^H g must satisfy the duality <A^H g, d> = <g, A d> with the library's own forward apply, and
+    at four sampled elements equal conj(<g, A e>) for the unit forcing e (1e-9 of the frequency's rms; measured
+    2e-15); the mu gradient must match central differences of J(mu) = Re <g, A(mu) f> from two forward applies with
+    the diagonal moved by -+ eps d, along a random direction and along three 32 x 32-node patches (1e-5; measured
+    1.9e-7 at most)."""
     import torch
     import workloads as W
     from paper_2008_10904_amd import ResolventOp
@@ -263,7 +265,25 @@ def test_adr2d_1024x512_full_size_reverse_mode():
     rhs = complex(torch.vdot(g.flatten(), ad.flatten()).item())
     say("  duality: <A^H g, d> %s  <g, A d> %s  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / abs(rhs)))
     assert abs(lhs - rhs) < 1e-10 * abs(rhs)
-    del fg, ad, d
+    del ad, d
+    # Element by element: the forcing gradient at a (frequency, column, node) equals conj(<g, A e>) for the unit
+    # forcing e there (A is complex-linear, so J(e) = Re <g, A e> and J(i e) = -Im <g, A e>): one forward apply per
+    # sampled element, through the forward march, synthesis and projection instead of the reverse mode.
+    node = lambda ix, iy: iy * nx + ix  # noqa: E731
+    picks = [(0, 0, node(10, 200)), (64, 1, node(300, 256)), (127, 0, node(1000, 30)), (100, 1, node(512, 500))]
+    worst = 0.0
+    for j, col, n in picks:
+        e = torch.zeros_like(f)
+        e[j, col, n] = 1.0
+        ref = complex(torch.vdot(g.flatten(), op.apply(e, grid, run).flatten()).item()).conjugate()
+        got = complex(fg[j, col, n].item())
+        rms = float(torch.linalg.vector_norm(fg[j]).item()) / np.sqrt(fg[j].numel())
+        err = abs(got - ref) / rms
+        worst = max(worst, err)
+        say("  forcing gradient [%d, %d, %d]: %s against %s, error %.2e of the frequency's rms" % (j, col, n, got,
+                                                                                              ref, err))
+    assert worst < 1e-9
+    del fg, e
     mg = mg.cpu().numpy()
     dfield = np.asarray(c["dfield"], np.float64).ravel()
     delta = np.random.default_rng(cfg["seed"] + 300).standard_normal(N)
@@ -275,11 +295,22 @@ def test_adr2d_1024x512_full_size_reverse_mode():
         return float(torch.vdot(g.flatten(), u.flatten()).real.item())
 
     fd = (J(dfield + eps * delta) - J(dfield - eps * delta)) / (2 * eps)
-    op.set_diagonal(dfield)
-    op.check()
     gd = float(mg @ delta)
     say("  mu directional: reverse mode %.12e  central differences %.12e  rel %.2e" % (gd, fd, abs(gd - fd) / abs(fd)))
     assert abs(gd - fd) < 1e-6 * abs(fd)  # measured 5.7e-9: the O(eps^2) truncation of the central difference
+    # Local structure of the mu gradient: 32 x 32-node patches (0.2 % of the domain) in the mu bump, in the sponge
+    # and near the inflow corner, each against central differences along the patch's indicator.
+    for cx, cy in ((256, 256), (960, 256), (40, 40)):
+        patch = np.zeros((ny, nx))
+        patch[cy - 16:cy + 16, cx - 16:cx + 16] = 1.0
+        patch = patch.ravel()
+        fdp = (J(dfield + eps * patch) - J(dfield - eps * patch)) / (2 * eps)
+        gdp = float(mg @ patch)
+        say("  mu on the patch at (%d, %d): reverse mode %.12e  central differences %.12e  rel %.2e" % (
+            cx, cy, gdp, fdp, abs(gdp - fdp) / abs(fdp)))
+        assert abs(gdp - fdp) < 1e-5 * abs(fdp)
+    op.set_diagonal(dfield)
+    op.check()
     del op
     release()
 
@@ -289,9 +320,11 @@ def test_adr3d3c_256x128x128_full_grid_reverse_mode_checkpoint_64():
     mixed-precision operator's FP32 rows and a checkpoint every 64 steps, on a short periodic run (4 frequencies,
     P = 64, three periods projected every 8th step of the last: three 64-step segments) so that the FP64 references
     stay cheap.  The forcing gradient must satisfy the duality <A^H g, d> = <g, A d> with A d from the FP64
-    operator's apply; the mu gradient must match, along a random direction, central differences of
-    J(mu) = Re <g, A(mu) f> from two FP64 applies with the diagonal moved by -+ eps d.  Bound: 1e-4 relative, the
-    mixed-precision bound (the FP32 rows round every stored value to 2^-24)."""
+    operator's apply, and at three sampled elements equal conj(<g, A e>) for the unit forcing e (relative to the
+    frequency's rms); the mu gradient must match central differences of J(mu) = Re <g, A(mu) f> from two FP64
+    applies with the diagonal moved by -+ eps d, along a random direction and along three 16 x 16 x 16-node
+    patches.  Bound: 1e-4 relative, the mixed-precision bound (the FP32 rows round every stored value to 2^-24;
+    measured 2e-7 at most)."""
     import torch
     import workloads as W
     from paper_2008_10904_amd import ResolventOp
@@ -316,6 +349,12 @@ def test_adr3d3c_256x128x128_full_grid_reverse_mode_checkpoint_64():
     del opm
     release()
     say("  backward done")
+    nodes = nx * ny * nz
+    node = lambda comp, ix, iy, iz: comp * nodes + (iz * ny + iy) * nx + ix  # noqa: E731
+    picks = [(0, 0, node(0, 40, 64, 64)), (2, 1, node(1, 128, 20, 100)), (3, 2, node(2, 250, 100, 10))]
+    fg_picks = [complex(fg[j, col, n].item()) for j, col, n in picks]
+    fg_rms = [float(torch.linalg.vector_norm(fg[j].to(torch.complex128)).item()) / np.sqrt(fg[j].numel())
+              for j, _, _ in picks]
     d = W.random_forcing_device(cfg["seed"] + 200, nw, k, N, torch.complex64, "cuda")
     lhs = complex(torch.vdot(fg.flatten().to(torch.complex128), d.flatten().to(torch.complex128)).item())
     del fg
@@ -328,6 +367,17 @@ def test_adr3d3c_256x128x128_full_grid_reverse_mode_checkpoint_64():
     del ad
     say("  duality: <A^H g, d> %s  <g, A d> %s  rel %.2e" % (lhs, rhs, abs(lhs - rhs) / abs(rhs)))
     assert abs(lhs - rhs) < 1e-4 * abs(rhs)
+    # Element by element: conj(<g, A e>) for the unit forcing e at sampled (frequency, column, component and node),
+    # from the FP64 operator's forward apply.
+    for (j, col, n), got, rms in zip(picks, fg_picks, fg_rms):
+        e = torch.zeros_like(f64)
+        e[j, col, n] = 1.0
+        ref = complex(torch.vdot(g64, op.apply(e, grid, run).flatten()).item()).conjugate()
+        err = abs(got - ref) / rms
+        say("  forcing gradient [%d, %d, %d]: %s against %s, error %.2e of the frequency's rms" % (j, col, n, got,
+                                                                                              ref, err))
+        assert err < 1e-4
+        del e
     mg = mg.cpu().numpy()
     dfield = np.asarray(c["dfield"], np.float64).ravel()
     delta = np.random.default_rng(cfg["seed"] + 300).standard_normal(nx * ny * nz)
@@ -339,11 +389,21 @@ def test_adr3d3c_256x128x128_full_grid_reverse_mode_checkpoint_64():
         return float(torch.vdot(g64, u.flatten()).real.item())
 
     fd = (J(dfield + eps * delta) - J(dfield - eps * delta)) / (2 * eps)
-    op.set_diagonal(dfield)
-    op.check()
     gd = float(mg @ delta)
     say("  mu directional: reverse mode %.12e  central differences %.12e  rel %.2e" % (gd, fd, abs(gd - fd) / abs(fd)))
     assert abs(gd - fd) < 1e-4 * abs(fd)
+    # Local structure: 16 x 16 x 16-node patches (0.1 % of the grid) in the wake, in the sponge and in a corner.
+    for cx, cy, cz in ((64, 64, 64), (240, 64, 64), (20, 20, 20)):
+        patch = np.zeros((nz, ny, nx))
+        patch[cz - 8:cz + 8, cy - 8:cy + 8, cx - 8:cx + 8] = 1.0
+        patch = patch.ravel()
+        fdp = (J(dfield + eps * patch) - J(dfield - eps * patch)) / (2 * eps)
+        gdp = float(mg @ patch)
+        say("  mu on the patch at (%d, %d, %d): reverse mode %.12e  central differences %.12e  rel %.2e" % (
+            cx, cy, cz, gdp, fdp, abs(gdp - fdp) / abs(fdp)))
+        assert abs(gdp - fdp) < 1e-4 * abs(fdp)
+    op.set_diagonal(dfield)
+    op.check()
     del op, f64, g64
     release()
 
