@@ -607,7 +607,7 @@ def bench_grid(args):
         autograd = {"forward_s": t1 - t0, "backward_s": t2 - t1, "backward_forcing_only_s": t3 - t2,
                     "note": "one apply and one apply_backward (forcing and mu gradients) of the full workload; "
                             "then the forcing gradient alone (adjoint recursion only)"}
-    kernel_name = ("grid_step2d_kernel (one RK4 step per launch)" if not three
+    kernel_name = ("grid_step2d_kernel (two RK4 steps per launch)" if not three
                    else "grid_step3d_kernel (one RK4 step per launch: the four Horner stages pipelined along z)")
     step_s = kt["stepper"][0] / 1e3 / time_steps_total
     alg_bytes = 3 * csize * N * k  # read u, write u, read one forcing row

@@ -79,6 +79,12 @@ int launch_grid_step3d(const GridOpDev& g, int k, const void* uin, void* uout, c
 // Whole RK4 step of a 2-D one-component operator in one launch (LDS temporal blocking); uout != uin.
 int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, void* uout, const void* frc, double phr,
                        double phi, void* snap, hipStream_t st);
+// Two RK4 steps of a 2-D one-component operator (FP32) in one launch: frc/snap belong to the first step,
+// frc2/snap2 to the second (each may be NULL); wy = 48 or 64 (window rows).  The same bits as two launches of
+// launch_grid_step2d.
+int launch_grid_step2d_pair(const GridOpDev& g, int k, const void* uin, void* uout, const void* frc,
+                            const void* frc2, double phr, double phi, void* snap, void* snap2, int wy,
+                            hipStream_t st);
 int launch_grid_horner(const GridOpDev& g64, const cx<double>* yin, const void* F, int f_fp64, void* yout,
                        int out_fp64, int k, int nw, double sw0h, double sdwh, double h, int pass, hipStream_t st,
                        int j0 = 0);

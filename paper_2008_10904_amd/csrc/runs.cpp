@@ -335,22 +335,35 @@ int march_grid(resolvent_op* op, int k, int64_t n, const ForceSpec& fs, const Sn
   if (!fused && !fused3) RES_TRY(ws_get(op, "gv1", (size_t)ncols * ws, &v2));
   TimedLaunch tl(op, RES_TIMING_STEPPER, st);
   int64_t next = (ss.snap != nullptr && ss.count > 0) ? ss.first : -1, m = 0;
+  auto force_row = [&](int64_t t) -> const void* {
+    if (fs.frc == nullptr) return nullptr;
+    int64_t row = fs.row0 + t;
+    if (fs.period > 0) row %= fs.period;
+    return (const char*)fs.frc + (size_t)row * ncols * ws;
+  };
+  auto snap_row = [&](int64_t t) -> void* {  // consumes the snapshot of step t if it is sampled
+    if (t != next) return nullptr;
+    void* p = (char*)ss.snap + (size_t)(ss.row0 + m) * ss.ld * ws;
+    ++m;
+    next = m < ss.count ? next + ss.stride : -1;
+    return p;
+  };
+  // FP32 2-D steps go in pairs, two per launch (window rows 64, or 48; RESOLVENT_STEP2D_PAIR = 0 keeps one step
+  // per launch): the same bits, half the launches and half the state's trips through memory.
+  const long pair_wy = fused && !op->fp64() ? env_long("RESOLVENT_STEP2D_PAIR", 64) : 0;
   for (int64_t t = 0; t < n; ++t) {
-    const void* frow = nullptr;
-    if (fs.frc != nullptr) {
-      int64_t row = fs.row0 + t;
-      if (fs.period > 0) row %= fs.period;
-      frow = (const char*)fs.frc + (size_t)row * ncols * ws;
-    }
-    void* srow = nullptr;
-    if (t == next) {
-      srow = (char*)ss.snap + (size_t)(ss.row0 + m) * ss.ld * ws;
-      ++m;
-      next = m < ss.count ? next + ss.stride : -1;
-    }
+    const void* frow = force_row(t);
+    void* srow = snap_row(t);
     void* uin = sb[op->cur_state];
     void* uout = sb[1 - op->cur_state];
-    if (fused) {
+    if (pair_wy != 0 && t + 1 < n) {
+      const void* frow2 = force_row(t + 1);
+      void* srow2 = snap_row(t + 1);
+      if (launch_grid_step2d_pair(g, k, uin, uout, frow, frow2, fs.phi.real(), fs.phi.imag(), srow, srow2,
+                                  (int)pair_wy, st))
+        return fail(RES_EINVAL, "2-D step pair launch (window rows must be 48 or 64)");
+      ++t;
+    } else if (fused) {
       if (launch_grid_step2d(g, op->fp64(), k, uin, uout, frow, fs.phi.real(), fs.phi.imag(), srow, st))
         return fail(RES_EINVAL, "2-D step launch");
     } else if (fused3) {

@@ -31,12 +31,20 @@ namespace res {
 // (homogeneous Dirichlet).  The new state goes to uout (a different buffer: neighbouring tiles read this step's u
 // as their halo).  HBM traffic per step: the state once (plus halo rows, mostly from L2), the forcing row once,
 // the new state once.
-template <typename R, int NWAVE, int WY>
+//
+// NSTEP = 2 takes two steps per launch on a window with a halo of 8: after the first step's four stages the new
+// state (with the first step's forcing row frc, and the snapshot of u into snap) replaces u on the region the
+// second step still reads, and the second step ends with frc2 and snap2.  Every node gets the arithmetic of two
+// one-step launches in the same order, so the results are the same bits; the state between the steps never
+// leaves the registers, and the launches and the state's round trip through memory are halved.
+template <typename R, int NWAVE, int WY, int NSTEP = 1>
 __global__ __launch_bounds__(64 * NWAVE) void grid_step2d_kernel(GridCoef<R> Cf, int64_t nx, int64_t ny,
                                                           const cx<R>* __restrict__ uin, cx<R>* __restrict__ uout,
                                                           const cx<R>* __restrict__ frc, R phr, R phi,
-                                                          cx<R>* __restrict__ snap) {
-  constexpr int H = 4, WX = 64, TX = WX - 2 * H, TY = WY - 2 * H, RS = WY / NWAVE;
+                                                          cx<R>* __restrict__ snap,
+                                                          const cx<R>* __restrict__ frc2,
+                                                          cx<R>* __restrict__ snap2) {
+  constexpr int H = 4 * NSTEP, WX = 64, TX = WX - 2 * H, TY = WY - 2 * H, RS = WY / NWAVE;
   __shared__ cx<R> Lw[2][WY][WX];
   __shared__ R cxm[WY], cxp[WY], cym[WY], cyp[WY];
   const int tid = threadIdx.x;
@@ -68,12 +76,13 @@ __global__ __launch_bounds__(64 * NWAVE) void grid_step2d_kernel(GridCoef<R> Cf,
   // stage m = 1..4: y = u + s (Z x) on the valid region (m <= lx < WX - m, m <= ly < WY - m), zero elsewhere;
   // the last stage has s = 1 and adds the forcing.  Operation order as apply_z: diagonal, -x, +x, -y, +y.
 #pragma unroll
-  for (int m = 1; m <= 4; ++m) {
+  for (int m = 1; m <= 4 * NSTEP; ++m) {
     cx<R>(*Lm)[WX] = Lw[m & 1];
 #pragma unroll
     for (int r = 0; r < RS; ++r) Lm[ly0 + r][lx] = x[r];
     __syncthreads();
-    const R s = m == 1 ? R(0.25) : m == 2 ? R(1) / R(3) : m == 3 ? R(0.5) : R(1);
+    const int mm = (m - 1) % 4 + 1;  // stage within its step
+    const R s = mm == 1 ? R(0.25) : mm == 2 ? R(1) / R(3) : mm == 3 ? R(0.5) : R(1);
     const bool xok = lx >= m && lx < WX - m;
     cx<R> y[RS];
 #pragma unroll
@@ -93,18 +102,42 @@ __global__ __launch_bounds__(64 * NWAVE) void grid_step2d_kernel(GridCoef<R> Cf,
     }
 #pragma unroll
     for (int r = 0; r < RS; ++r) x[r] = y[r];
+    if (NSTEP == 2 && m == 4) {
+      // end of the first step on the region the second one reads (the window less a ring of 4): forcing, the
+      // snapshot of u at the tile interior, and the new state as the second step's u and stage input
+      const bool xok1 = lx >= 4 && lx < WX - 4;
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        const int ly = ly0 + r;
+        cx<R> v = mk<R>(R(0), R(0));
+        if (xok1 && ly >= 4 && ly < WY - 4 && in[r]) {
+          const int64_t e = cb + (y0 + ly) * nx + ix;
+          if (snap != nullptr && lx >= H && lx < WX - H && ly >= H && ly < WY - H) snap[e] = u[r];
+          v = x[r];
+          if (frc != nullptr) {
+            const cx<R> f = frc[e];
+            v.re += phr * f.re - phi * f.im;
+            v.im += phr * f.im + phi * f.re;
+          }
+        }
+        u[r] = v;
+        x[r] = v;
+      }
+    }
   }
-  // interior of the tile: forcing, snapshot of u (the state before the step) and the new state
+  // interior of the tile: forcing, snapshot of u (the state before the last step) and the new state
+  const cx<R>* fl = NSTEP == 2 ? frc2 : frc;
+  cx<R>* sl = NSTEP == 2 ? snap2 : snap;
   if (lx < H || lx >= WX - H) return;
 #pragma unroll
   for (int r = 0; r < RS; ++r) {
     const int ly = ly0 + r;
     if (ly < H || ly >= WY - H || !in[r]) continue;
     const int64_t e = cb + (y0 + ly) * nx + ix;
-    if (snap != nullptr) snap[e] = u[r];
+    if (sl != nullptr) sl[e] = u[r];
     cx<R> v = x[r];
-    if (frc != nullptr) {
-      const cx<R> f = frc[e];
+    if (fl != nullptr) {
+      const cx<R> f = fl[e];
       v.re += phr * f.re - phi * f.im;
       v.im += phr * f.im + phi * f.re;
     }
@@ -657,11 +690,26 @@ int launch_grid_step2d(const GridOpDev& g, int fp64, int k, const void* uin, voi
     hipLaunchKernelGGL((grid_step2d_kernel<double, 4, 40>), dim3((unsigned)((g.nx + 55) / 56),
                        (unsigned)((g.ny + 31) / 32), (unsigned)k), dim3(256), 0, st, coef_of<double>(g, 1), g.nx,
                        g.ny, (const cx<double>*)uin, (cx<double>*)uout, (const cx<double>*)frc, phr, phi,
-                       (cx<double>*)snap);
+                       (cx<double>*)snap, nullptr, nullptr);
   else
     hipLaunchKernelGGL((grid_step2d_kernel<float, 16, WY>), grid, dim3(1024), 0, st, coef_of<float>(g, 0), g.nx,
                        g.ny, (const cx<float>*)uin, (cx<float>*)uout, (const cx<float>*)frc, (float)phr, (float)phi,
-                       (cx<float>*)snap);
+                       (cx<float>*)snap, nullptr, nullptr);
+  return 0;
+}
+
+int launch_grid_step2d_pair(const GridOpDev& g, int k, const void* uin, void* uout, const void* frc,
+                            const void* frc2, double phr, double phi, void* snap, void* snap2, int wy,
+                            hipStream_t st) {
+  if (g.ncomp != 1 || g.nz != 1 || k < 1 || k > 65535 || (wy != 48 && wy != 64)) return -1;
+  // 16 waves on a 64 x wy window, halo 8: output tiles of 48 x (wy - 16)
+  const dim3 grid((unsigned)((g.nx + 47) / 48), (unsigned)((g.ny + wy - 17) / (wy - 16)), (unsigned)k);
+#define RES_S2P(W)                                                                                                 \
+  hipLaunchKernelGGL((grid_step2d_kernel<float, 16, W, 2>), grid, dim3(1024), 0, st, coef_of<float>(g, 0), g.nx,   \
+                     g.ny, (const cx<float>*)uin, (cx<float>*)uout, (const cx<float>*)frc, (float)phr, (float)phi, \
+                     (cx<float>*)snap, (const cx<float>*)frc2, (cx<float>*)snap2)
+  if (wy == 48) RES_S2P(48); else RES_S2P(64);
+#undef RES_S2P
   return 0;
 }
 

@@ -214,3 +214,37 @@ def test_grid_operator_has_no_stepper_plan():
         op.tune(1)
     with pytest.raises(ResolventError):
         op.set_step_power(2)
+
+
+@pytest.mark.parametrize("shape", [(130, 70), (50, 21)])
+def test_2d_step_pairs_match_single_steps(shape, monkeypatch):
+    """FP32 2-D steps two per launch (windows of 64 and of 48 rows, halo 8) against one step per launch: the same
+    bits for a periodic run (snapshots every third step, so sampled steps fall on both halves of a pair) and a
+    transient run of an odd number of steps (the last one alone), direct and adjoint, with several tiles per
+    direction and ragged edges; and the oracle's periodic run."""
+    import torch
+    nx, ny = shape
+    say("case: 2-D step pairs against single steps", shape)
+    op, L = make2d(nx, ny, 0.1, "mixed")
+    h, P, nw, k = 0.1, 60, 3, 2
+    dw = 2 * np.pi / (P * h)
+    F = forcing(31, nw, k, op.n)
+    grid = op.grid(-0.2, dw, nw)
+    runs = [op.run("periodic", periods=3, stride=3), op.run("transient", tail=37)]
+    outs = {}
+    for wy in ("0", "64", "48"):
+        monkeypatch.setenv("RESOLVENT_STEP2D_PAIR", wy)
+        res = []
+        for run in runs:
+            res.append(to_np(op.apply(gpu_tensor(F, torch.complex64), grid, run)))
+            res.append(to_np(op.adjoint_apply(gpu_tensor(F, torch.complex64), grid, run)))
+        torch.cuda.synchronize()
+        outs[wy] = res
+    op.check()
+    Fr = F.astype(np.complex64).astype(np.complex128)
+    ref = O_st.run(L, h, -0.2, dw, Fr, "periodic", periods=3, stride=3)
+    e = per_freq_relerr(outs["64"][0], ref)
+    same = {wy: all(np.array_equal(a, b) for a, b in zip(outs[wy], outs["0"])) for wy in ("64", "48")}
+    say("  pairs equal single steps: %s, periodic direct vs oracle %.2e" % (same, e))
+    assert same["64"] and same["48"]
+    assert e < 1e-4
