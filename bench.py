@@ -177,6 +177,29 @@ def time_steps(op, f0, grid, run, K, W):
     return (t1 - t0) / K, g, kt
 
 
+def graph_replay(op, f0, grid, run, iters):
+    """Wall time per iteration of one resolvent_modes call of `iters` iterations, eager and with the middle
+    iterations replayed from one captured HIP graph (resolvent_op_set_graphs), each after a warm call of two
+    iterations; and whether the two give the same gains bit for bit."""
+    import numpy as np
+    import torch
+    out = {"iterations": iters}
+    gains = {}
+    for name, on in (("eager", False), ("graph", True)):
+        op.set_graphs(on)
+        op.modes(f0, grid, run, 2, want_modes=False, want_hist=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, _, _, _ = op.modes(f0, grid, run, iters, want_modes=False, want_hist=False)
+        torch.cuda.synchronize()
+        out[name + "_ms_per_iteration"] = (time.perf_counter() - t0) / iters * 1e3
+        gains[name] = g
+    op.set_graphs(False)
+    out["same_gains"] = bool(np.array_equal(gains["eager"], gains["graph"]))
+    progress("graph replay timed")
+    return out
+
+
 def cpu_baseline(cfg, w0, dw, F, seconds):
     """The oracle's explicit RK4 march of the same operator and forcing, timed for a bounded sample of steps."""
     import numpy as np
@@ -325,6 +348,8 @@ def bench_transient(args):
         run = op.run("transient", tail=cfg["tail"])
         f = torch.from_numpy(F).to(dtype).cuda()
         dt, _, kt = time_steps(op, f, grid, run, args.steps, args.warmup)
+        if prec == "fp64":
+            replay = graph_replay(op, f, grid, run, 20)
         acc = None
         if iters == ref["iters"]:
             g, V, U, _ = op.modes(f, grid, run, iters, want_hist=False)
@@ -360,6 +385,7 @@ def bench_transient(args):
                   "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in ktm.items()}, "stepper_plan": list(planm)},
         "accuracy_vs_oracle": {"iterations": iters, "sampled_omega_index": js, "fp64": acc64, "mixed": accm,
                                "reference": "tests/golden/gl_transient_reference.json (the oracle's 20 iterations)"},
+        "graph_replay_fp64": replay,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_transient(cfg, w0, dw, F, args.cpu_seconds)
@@ -427,6 +453,8 @@ def bench_batched(args):
         run = op.run("periodic", periods=cfg["periods"], stride=cfg["stride"])
         f = torch.from_numpy(F).to(dtype).cuda()
         res[prec] = time_steps(op, f, grid, run, args.steps, args.warmup)
+        if prec == "mixed":
+            replay = graph_replay(op, f, grid, run, 6)
         if iters > 0:
             g, V, U, _ = op.modes(f, grid, run, iters, want_hist=False)
             if prec == "mixed":
@@ -464,6 +492,7 @@ def bench_batched(args):
         "fp64": {"value": sweeps_per_step / dt64, "ms_per_step": dt64 * 1e3, "dtype": "f64",
                  "kernel_ms_per_step": {k_: v[0] / args.steps for k_, v in kt64.items()}},
         "stepper_plan": {k_: list(v) for k_, v in plans.items()},
+        "graph_replay_mixed": replay,
         "step_power": powers,
     }
     if not args.no_cpu_baseline:
@@ -840,6 +869,7 @@ def bench_paper(args):
     steps_per_launch = 2 * steps_per_run * args.steps / max(stepper_n, 1)
     achieved = STEP_FLOP_PER_UNKNOWN * N * k * steps_per_launch / avg_launch_s / 1e12
     peak = FP64_VECTOR_PEAK / 1e12
+    replay = graph_replay(op, f, grid, run, 50)
     n = cfg["iters"]
     study = {"runs": n}
     for name, call in (("power", lambda: op.modes(f, grid, run, n, want_modes=False)),
@@ -866,6 +896,7 @@ def bench_paper(args):
         "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in kt.items()},
         "stepper_plan": list(plan), "step_power": op.get_step_power(),
         "power_vs_arnoldi_same_runs": study,
+        "graph_replay": replay,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, cfg["w0"], cfg["dw"], F, args.cpu_seconds)
