@@ -844,9 +844,9 @@ int resolvent_grid_from_omegas(const double* omega, int32_t n_omega, double h, i
     if (std::fabs(omega[j] - (omega[0] + j * dw_nom)) > 1e-9 * std::fabs(dw_nom))
       return fail(RES_EGRID, "frequency " + std::to_string(j) + " is off the uniform grid of its end points");
   // the period P h of the time grid must be 2 pi / |domega|: P is the multiple of the stride nearest that
-  const double per = 2.0 * M_PI / (std::fabs(dw_nom) * h * (double)stride);
-  if (!(per < 4e18)) return fail(RES_EGRID, "spacing too small for the time step");
-  const int64_t P = stride * std::max<int64_t>(1, std::llround(per));
+  const double steps = 2.0 * M_PI / (std::fabs(dw_nom) * h);  // the array's own period in steps
+  if (!(steps < 1e15)) return fail(RES_EGRID, "spacing too small for the time step");
+  const int64_t P = stride * std::max<int64_t>(1, std::llround(steps / (double)stride));
   if (P < n_omega) return fail(RES_EGRID, "more frequencies than steps per period (aliasing)");
   out->omega0 = omega[0];
   out->domega = std::copysign(2.0 * M_PI / ((double)P * h), dw_nom);

@@ -51,7 +51,8 @@ def test_grid_from_omegas_errors():
              (np.array([0.0, np.nan, 2.0]), 0.01, 1, L.RES_EGRID),
              (w, 0.0, 1, L.RES_EINVAL),                      # h <= 0
              (w, 0.01, 0, L.RES_EINVAL),                     # stride < 1
-             (np.linspace(-100, 100, 50), 0.5, 1, L.RES_EGRID)]  # P = 2 steps for 50 frequencies: aliasing
+             (np.linspace(-100, 100, 50), 0.5, 1, L.RES_EGRID),  # P = 2 steps for 50 frequencies: aliasing
+             (np.array([0.0, 1e-17]), 1.0, 1 << 40, L.RES_EGRID)]   # a period beyond any step count
     for arr, h, stride, code in cases:
         with pytest.raises(ResolventError) as e:
             grid_from_omegas(arr, h, stride)
